@@ -1,0 +1,618 @@
+"""CPU reference ("oracle") for the 3D Gabor splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import or call
+this module; it exists so that tests, the smoke check and the CPU-baseline leg
+of the benchmark can check the GPU path against a plain, slow, obviously
+correct definition.  It shares no code with the GPU path.
+
+Everything is computed in float64 with plain PyTorch CPU ops, except the
+three decisions the method takes on float32 data (the depth key, the near-plane
+cull and the opacity cull), which are taken on float32 values here as well.
+The exact derivative of the whole forward is obtained with torch.autograd on
+this float64 definition (the backward is therefore not a second hand-written
+formula that could share a mistake with the forward).
+
+Per-primitive steps follow the paper:
+  * 3D envelope and covariance Sigma = R S S^T R^T (Sec. 3.1, Eq. 3d_gaussian).
+  * Gabor filter bank G(x) [(1 - sum w) + sum w cos(2 pi f^T (x - mu))]
+    (Sec. 3.2, the 3D Gabor-based primitive).
+  * EWA projection Sigma' = J W Sigma W^T J^T with the 2x2 block as the 2D
+    covariance (Sec. 3.1).
+  * Frequency projection f_proj = (JW)^{-T} f (Sec. 3.3.1; supplementary A.1)
+    followed by the z-integration f2d = f_proj,xy - (S_xy,z / S_zz) f_proj,z
+    with S the inverse ray-space covariance (Sec. 3.3.2; supplementary A.2).
+    Written out, this equals (T Sigma T^T)^{-1} T Sigma f where T is the first
+    two rows of JW, for any full-rank completion of J; that closed form is
+    what is evaluated here (tests check it against the paper's two-step form).
+  * 2D Gabor primitive and front-to-back alpha blending (Sec. 3.3.2 and 3.3.3).
+The per-pixel blend takes every visible primitive sorted by (fp32 depth,
+index): alpha = min(0.99, o G B); skip if alpha < 1/255; stop without blending
+when T (1 - alpha) < 1e-4; background added with the final transmittance.
+
+Readings where the paper is silent (tile rasterizer conventions adopted from
+3DGS, which the paper says it adapts in Sec. 3.3.3): 0.3 px^2 dilation of the
+2D covariance, 1.3x guard band on the Jacobian's evaluation point, near plane
+0.2 on camera z, opacity-aware support radius sqrt(2 ln(255 o)), pixel centres
+at (px + 0.5, py + 0.5), real spherical harmonics of degree <= 3 with +0.5 and
+a clamp at 0, 16x16 tiles, ties in depth broken by primitive index.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+DT = torch.float64
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+DILATION = 0.3
+TILE = 16
+
+
+# --------------------------------------------------------------------------
+# input marshalling (scene / camera objects -> fp64 tensors)
+# --------------------------------------------------------------------------
+def scene_tensors(scene, requires_grad: bool = False) -> Dict[str, torch.Tensor]:
+    """fp64 leaf tensors for the activated primitive attributes."""
+    out = {}
+    for name in ("means", "scales", "quats", "opacities", "freqs", "weights", "colors", "sh"):
+        a = getattr(scene, name)
+        if a is None:
+            continue
+        t = torch.tensor(np.asarray(a, np.float64), dtype=DT)
+        if requires_grad:
+            t.requires_grad_(True)
+        out[name] = t
+    return out
+
+
+def camera_tensors(cam) -> Dict[str, object]:
+    return dict(
+        R=torch.tensor(np.asarray(cam.R, np.float64), dtype=DT),
+        t=torch.tensor(np.asarray(cam.t, np.float64), dtype=DT),
+        eye=torch.tensor(np.asarray(cam.eye, np.float64), dtype=DT),
+        fx=float(cam.fx), fy=float(cam.fy), cx=float(cam.cx), cy=float(cam.cy),
+        W=int(cam.width), H=int(cam.height), near=float(cam.near),
+        bg=torch.tensor(cam.bg, dtype=DT),
+    )
+
+
+# --------------------------------------------------------------------------
+# 3D primitive (Sec. 3.1 / 3.2)
+# --------------------------------------------------------------------------
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix of the (normalised) quaternion (w, x, y, z)."""
+    q = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    r0 = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1)
+    r1 = torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1)
+    r2 = torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)
+    return torch.stack([r0, r1, r2], -2)
+
+
+def covariance_3d(scales: torch.Tensor, quats: torch.Tensor) -> torch.Tensor:
+    """Sigma = R S S^T R^T with S = diag(scales) (Sec. 3.1)."""
+    M = quat_to_rotmat(quats) * scales[..., None, :]
+    return M @ M.transpose(-1, -2)
+
+
+# --------------------------------------------------------------------------
+# real spherical harmonics (colour), written from the closed form
+# Y_l^m ~ K_l^m * {Re, Im}((x + i y)^|m|) * d^|m| P_l / dz^|m|  (no Condon-Shortley phase)
+# --------------------------------------------------------------------------
+def _sh_norm(l: int, m: int) -> float:
+    return math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - abs(m)) / math.factorial(l + abs(m)))
+
+
+def _legendre_derivative_coeffs(l: int, m: int) -> np.ndarray:
+    """Power-series coefficients (ascending) of d^m/dz^m P_l(z)."""
+    c = np.polynomial.legendre.leg2poly(np.eye(l + 1)[l])
+    for _ in range(m):
+        c = np.polynomial.polynomial.polyder(c)
+    return c
+
+
+def sh_basis(dirs: torch.Tensor, degree: int) -> torch.Tensor:
+    """[..., (degree+1)^2] real SH basis at unit directions dirs [..., 3];
+    order l = 0..degree, m = -l..l."""
+    x, y, z = dirs.unbind(-1)
+    A = [torch.ones_like(x)]
+    B = [torch.zeros_like(x)]
+    for m in range(1, degree + 1):  # Re / Im of (x + i y)^m = (x + i y)(A + i B)
+        a_prev, b_prev = A[-1], B[-1]
+        A.append(x * a_prev - y * b_prev)
+        B.append(x * b_prev + y * a_prev)
+    out = []
+    for l in range(degree + 1):
+        for m in range(-l, l + 1):
+            coeffs = _legendre_derivative_coeffs(l, abs(m))
+            q = torch.zeros_like(z)
+            for c in coeffs[::-1]:  # Horner
+                q = q * z + float(c)
+            k = _sh_norm(l, m)
+            if m > 0:
+                out.append(math.sqrt(2.0) * k * A[m] * q)
+            elif m < 0:
+                out.append(math.sqrt(2.0) * k * B[-m] * q)
+            else:
+                out.append(k * q)
+    return torch.stack(out, -1)
+
+
+def sh_to_rgb(sh: torch.Tensor, means: torch.Tensor, eye: torch.Tensor) -> torch.Tensor:
+    """Colour = max(0, sum_d sh[d] Y_d(dir) + 0.5), dir = (mu - eye)/|mu - eye|."""
+    d = means - eye
+    d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
+    deg = int(round(math.sqrt(sh.shape[-2]))) - 1
+    Y = sh_basis(d, deg)  # [n, D]
+    rgb = torch.einsum("nd,ndc->nc", Y, sh) + 0.5
+    return torch.clamp(rgb, min=0.0)
+
+
+# --------------------------------------------------------------------------
+# projection (Sec. 3.1 EWA, Sec. 3.3 frequency projection + z-integration)
+# --------------------------------------------------------------------------
+def depth_fp32(means_f32: np.ndarray, R_f32: np.ndarray, t_f32: np.ndarray) -> np.ndarray:
+    """Camera-space z as a float32 key, fixed evaluation order, one IEEE
+    rounding per operation: ((r20 x + r21 y) + r22 z) + t2."""
+    m = np.asarray(means_f32, np.float32)
+    r = np.asarray(R_f32, np.float32)
+    t2 = np.float32(np.asarray(t_f32, np.float32)[2])
+    a = r[2, 0] * m[:, 0]
+    b = r[2, 1] * m[:, 1]
+    c = r[2, 2] * m[:, 2]
+    return ((a + b) + c) + t2
+
+
+@dataclass
+class Projected:
+    visible: torch.Tensor       # [n] bool
+    depth32: np.ndarray         # [n] float32
+    mu2d: torch.Tensor          # [n,2]
+    cov2d_raw: torch.Tensor     # [n,2,2]
+    conic: torch.Tensor         # [n,3] (xx, xy, yy) of (cov2d_raw + 0.3 I)^-1
+    opac: torch.Tensor          # [n]
+    rgb: torch.Tensor           # [n,3]
+    f2d: torch.Tensor           # [n,K,2] cycles per pixel
+    w: torch.Tensor             # [n,K]
+    rect: np.ndarray            # [n,4] int64 tile rect x0,y0,x1,y1 (exclusive)
+    tiles: np.ndarray           # [n] tiles touched (0 if invisible)
+    fragile_rect: np.ndarray    # [n] bool: rect boundary within 2e-3 px of a pixel centre
+    fragile_prim: np.ndarray    # [n] bool: ill-conditioned 2D frequency solve
+
+
+def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None) -> Projected:
+    """Per-primitive projection.  ``p`` holds fp64 tensors (possibly requiring
+    grad); ``scene_f32`` supplies the float32 means/opacities for the fp32
+    decisions (defaults to rounding p's values, which are exact copies)."""
+    R, t = cam["R"], cam["t"]
+    fx, fy, cx, cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+    W, H = cam["W"], cam["H"]
+    means = p["means"]
+    n = means.shape[0]
+    if scene_f32 is None:
+        m32 = means.detach().numpy().astype(np.float32)
+        o32 = p["opacities"].detach().numpy().astype(np.float32)
+    else:
+        m32, o32 = np.asarray(scene_f32.means, np.float32), np.asarray(scene_f32.opacities, np.float32)
+    R32 = R.numpy().astype(np.float32)
+    t32 = t.numpy().astype(np.float32)
+
+    # camera space (W of the paper is [R | t])
+    tc = means @ R.T + t
+    tx, ty, tz = tc.unbind(-1)
+    depth32 = depth_fp32(m32, R32, t32)
+    in_front = torch.from_numpy(depth32 > np.float32(cam["near"]))
+    opac_ok = torch.from_numpy(o32 * np.float32(255.0) > np.float32(1.0))
+
+    # keep culled entries finite: evaluate them at a harmless depth
+    tz_safe = torch.where(in_front, tz, torch.ones_like(tz))
+    mu2d = torch.stack([fx * tx / tz_safe + cx, fy * ty / tz_safe + cy], -1)
+
+    # Jacobian of the perspective map at the guard-band-clamped point
+    lo_x, hi_x = (-0.15 * W - cx) / fx, (1.15 * W - cx) / fx
+    lo_y, hi_y = (-0.15 * H - cy) / fy, (1.15 * H - cy) / fy
+    txc = torch.clamp(tx / tz_safe, lo_x, hi_x) * tz_safe
+    tyc = torch.clamp(ty / tz_safe, lo_y, hi_y) * tz_safe
+    zero = torch.zeros_like(tz_safe)
+    J2 = torch.stack([
+        torch.stack([fx / tz_safe, zero, -fx * txc / (tz_safe * tz_safe)], -1),
+        torch.stack([zero, fy / tz_safe, -fy * tyc / (tz_safe * tz_safe)], -1),
+    ], -2)                                   # [n,2,3]
+    T = J2 @ R                               # first two rows of J W
+    Sig = covariance_3d(p["scales"], p["quats"])
+    cov_raw = T @ Sig @ T.transpose(-1, -2)  # [n,2,2]
+    a = cov_raw[:, 0, 0] + DILATION
+    b = cov_raw[:, 0, 1]
+    c = cov_raw[:, 1, 1] + DILATION
+    det = a * c - b * b
+    det_ok = det > 0
+    det_safe = torch.where(det_ok, det, torch.ones_like(det))
+    conic = torch.stack([c / det_safe, -b / det_safe, a / det_safe], -1)
+
+    # 2D frequencies: f2d_k = (T Sigma T^T)^-1 (T Sigma f_k)
+    K = p["weights"].shape[1]
+    ra, rb, rc = cov_raw[:, 0, 0], cov_raw[:, 0, 1], cov_raw[:, 1, 1]
+    det_raw = ra * rc - rb * rb
+    scale_raw = ra * rc
+    cond_bad = (det_raw.detach() <= 1e-6 * scale_raw.detach()) | (det_raw.detach() <= 0)
+    det_raw_safe = torch.where(det_raw > 0, det_raw, torch.ones_like(det_raw))
+    if K > 0:
+        g = torch.einsum("nij,njk,nck->nci", T, Sig, p["freqs"])   # [n,K,2] = T Sigma f_k
+        fxp = (rc[:, None] * g[..., 0] - rb[:, None] * g[..., 1]) / det_raw_safe[:, None]
+        fyp = (-rb[:, None] * g[..., 0] + ra[:, None] * g[..., 1]) / det_raw_safe[:, None]
+        f2d = torch.stack([fxp, fyp], -1)
+        f2d = torch.where((det_raw > 0)[:, None, None], f2d, torch.zeros_like(f2d))
+    else:
+        f2d = torch.zeros((n, 0, 2), dtype=DT)
+
+    # colour
+    if "sh" in p:
+        rgb = sh_to_rgb(p["sh"], means, cam["eye"])
+    else:
+        rgb = p["colors"]
+
+    # support: o * G >= 1/255 inside the ellipse d^T conic d <= 2 ln(255 o)
+    with torch.no_grad():
+        o64 = p["opacities"].detach()
+        kk = torch.sqrt(torch.clamp(2.0 * torch.log(255.0 * o64), min=0.0))
+        rx = kk * torch.sqrt(torch.clamp(a.detach(), min=0.0))
+        ry = kk * torch.sqrt(torch.clamp(c.detach(), min=0.0))
+        mx, my = mu2d[:, 0].detach(), mu2d[:, 1].detach()
+        bx0, bx1 = (mx - rx - 0.5).numpy(), (mx + rx - 0.5).numpy()
+        by0, by1 = (my - ry - 0.5).numpy(), (my + ry - 0.5).numpy()
+        with np.errstate(invalid="ignore", over="ignore"):
+            px0 = np.maximum(np.ceil(bx0), 0)
+            px1 = np.minimum(np.floor(bx1), W - 1)
+            py0 = np.maximum(np.ceil(by0), 0)
+            py1 = np.minimum(np.floor(by1), H - 1)
+        ok = (px0 <= px1) & (py0 <= py1) & np.isfinite(bx0) & np.isfinite(by0)
+        vis = in_front.numpy() & opac_ok.numpy() & det_ok.numpy() & ok
+        rect = np.zeros((n, 4), np.int64)
+        rect[vis, 0] = (px0[vis] // TILE).astype(np.int64)
+        rect[vis, 1] = (py0[vis] // TILE).astype(np.int64)
+        rect[vis, 2] = (px1[vis] // TILE).astype(np.int64) + 1
+        rect[vis, 3] = (py1[vis] // TILE).astype(np.int64) + 1
+        tiles = np.where(vis, (rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1]), 0)
+
+        def near_int(v):
+            with np.errstate(invalid="ignore"):
+                return np.abs(v - np.round(v)) < 2e-3
+        fr = vis & (near_int(bx0) | near_int(bx1) | near_int(by0) | near_int(by1))
+        fp = vis & cond_bad.numpy()
+    return Projected(visible=torch.from_numpy(vis), depth32=depth32, mu2d=mu2d, cov2d_raw=cov_raw,
+                     conic=conic, opac=p["opacities"], rgb=rgb, f2d=f2d, w=p["weights"],
+                     rect=rect, tiles=tiles.astype(np.int64), fragile_rect=fr, fragile_prim=fp)
+
+
+# --------------------------------------------------------------------------
+# depth order, tile binning and the (tile, depth) key sort
+# --------------------------------------------------------------------------
+def depth_order(depth32: np.ndarray, visible: np.ndarray) -> np.ndarray:
+    """Indices of visible primitives sorted by (fp32 depth bit pattern, index)."""
+    idx = np.nonzero(np.asarray(visible))[0]
+    bits = np.asarray(depth32, np.float32).view(np.uint32)[idx]
+    return idx[np.lexsort((idx, bits))]
+
+
+def bin_sort(rect: np.ndarray, depth32: np.ndarray, visible: np.ndarray, tiles_x: int,
+             num_tiles: int, tile_offset: int = 0, index_offset: int = 0):
+    """Emit one (key, value) per (primitive, overlapped tile) in primitive
+    order and, within a primitive, row-major tile order; key = tile << 32 |
+    depth bits, value = primitive index.  Sort stably by key (library stable
+    sort) and derive the [start, end) range of every tile; empty tiles get
+    (0, 0).  Returns keys uint64, vals uint32, ranges [num_tiles, 2] uint32."""
+    keys, vals = [], []
+    bits = np.asarray(depth32, np.float32).view(np.uint32).astype(np.uint64)
+    for i in np.nonzero(np.asarray(visible))[0]:
+        x0, y0, x1, y1 = (int(v) for v in rect[i])
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                tile = tile_offset + ty * tiles_x + tx
+                keys.append((np.uint64(tile) << np.uint64(32)) | bits[i])
+                vals.append(index_offset + i)
+    keys = np.asarray(keys, np.uint64)
+    vals = np.asarray(vals, np.uint32)
+    order = np.argsort(keys, kind="stable")
+    keys, vals = keys[order], vals[order]
+    ranges = np.zeros((num_tiles, 2), np.uint32)
+    tl = (keys >> np.uint64(32)).astype(np.int64) - tile_offset
+    for pos in range(len(tl)):
+        t_ = tl[pos]
+        if pos == 0 or tl[pos - 1] != t_:
+            ranges[t_, 0] = pos
+        if pos == len(tl) - 1 or tl[pos + 1] != t_:
+            ranges[t_, 1] = pos + 1
+    return keys, vals, ranges
+
+
+# --------------------------------------------------------------------------
+# per-pixel blending (Sec. 3.3.2 2D Gabor primitive, Sec. 3.3.3 blend)
+# --------------------------------------------------------------------------
+@dataclass
+class PixelResult:
+    color: torch.Tensor      # [P,3]
+    final_T: torch.Tensor    # [P]
+    last_id: np.ndarray      # [P] primitive index of the last blended primitive, -1 if none
+    n_blended: np.ndarray    # [P] number of blended primitives
+    fragile: np.ndarray      # [P] bool
+
+
+def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Tensor,
+                 bg: torch.Tensor, tau_alpha=1e-4, tau_T=1e-3) -> PixelResult:
+    """Blend the candidates ``cand`` (already sorted front to back) at the
+    sample points (px, py), vectorised over pixels and candidates."""
+    P = px.shape[0]
+    m = len(cand)
+    if m == 0:
+        col = bg[None, :].expand(P, 3).clone()
+        return PixelResult(col, torch.ones(P, dtype=DT), -np.ones(P, np.int64),
+                           np.zeros(P, np.int64), np.zeros(P, bool))
+    ci = torch.from_numpy(np.asarray(cand, np.int64))
+    mu = pr.mu2d[ci]
+    con = pr.conic[ci]
+    dx = px[:, None] - mu[None, :, 0]
+    dy = py[:, None] - mu[None, :, 1]
+    G = torch.exp(-0.5 * (con[None, :, 0] * dx * dx + 2.0 * con[None, :, 1] * dx * dy
+                          + con[None, :, 2] * dy * dy))
+    w = pr.w[ci]
+    if w.shape[1] > 0:
+        f = pr.f2d[ci]
+        phase = f[None, :, :, 0] * dx[..., None] + f[None, :, :, 1] * dy[..., None]
+        Bk = (1.0 - w.sum(-1))[None, :] + (w[None] * torch.cos(2.0 * math.pi * phase)).sum(-1)
+    else:
+        Bk = torch.ones_like(G)
+    a_raw = pr.opac[ci][None, :] * G * Bk
+    alpha = torch.clamp(a_raw, max=ALPHA_MAX)
+    with torch.no_grad():
+        valid = alpha >= ALPHA_MIN
+        one_m = torch.where(valid, 1.0 - alpha, torch.ones_like(alpha))
+        T_after = torch.cumprod(one_m, dim=1)
+        keep = valid & (T_after >= T_MIN)
+    factor = torch.where(keep, 1.0 - alpha, torch.ones_like(alpha))
+    T_incl = torch.cumprod(factor, dim=1)
+    T_before = torch.cat([torch.ones((P, 1), dtype=DT), T_incl[:, :-1]], 1)
+    wgt = torch.where(keep, alpha * T_before, torch.zeros_like(alpha))
+    color = wgt @ pr.rgb[ci] + T_incl[:, -1:] * bg[None, :]
+    with torch.no_grad():
+        kn = keep.numpy()
+        n_bl = kn.sum(1)
+        has = kn.any(1)
+        last_pos = np.where(has, m - 1 - np.argmax(kn[:, ::-1], axis=1), -1)
+        last_id = np.where(has, np.asarray(cand)[np.maximum(last_pos, 0)], -1)
+        # fragility: decisions within tolerance of their thresholds, up to the stop point
+        vn, Ta = valid.numpy(), T_after.numpy()
+        stopped = vn & (Ta < T_MIN)
+        stop_pos = np.where(stopped.any(1), np.argmax(stopped, axis=1), m - 1)
+        upto = np.arange(m)[None, :] <= stop_pos[:, None]
+        ar = a_raw.detach().numpy()
+        fa = np.abs(ar - ALPHA_MIN) <= tau_alpha * ALPHA_MIN
+        ft = vn & (np.abs(Ta - T_MIN) <= tau_T * T_MIN)
+        fprim = (pr.fragile_prim[np.asarray(cand)][None, :]) & (ar >= ALPHA_MIN * (1 - tau_alpha))
+        fragile = ((fa | ft | fprim) & upto).any(1)
+    return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile)
+
+
+def blend_pixel_loop(pr: Projected, cand: Sequence[int], x: float, y: float, bg) -> tuple:
+    """The same blend for ONE pixel as a literal sequential loop (small cases
+    only).  Returns (rgb list, final T, last primitive id, count)."""
+    T = 1.0
+    C = [0.0, 0.0, 0.0]
+    last, cnt = -1, 0
+    for i in cand:
+        mx, my = float(pr.mu2d[i, 0]), float(pr.mu2d[i, 1])
+        a, b, c = (float(v) for v in pr.conic[i])
+        dx, dy = x - mx, y - my
+        G = math.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+        Bv = 1.0
+        for k in range(pr.w.shape[1]):
+            wk = float(pr.w[i, k])
+            ph = float(pr.f2d[i, k, 0]) * dx + float(pr.f2d[i, k, 1]) * dy
+            Bv += wk * (math.cos(2 * math.pi * ph) - 1.0)
+        alpha = min(ALPHA_MAX, float(pr.opac[i]) * G * Bv)
+        if alpha < ALPHA_MIN:
+            continue
+        if T * (1.0 - alpha) < T_MIN:
+            break
+        for ch in range(3):
+            C[ch] += float(pr.rgb[i, ch]) * alpha * T
+        T *= 1.0 - alpha
+        last, cnt = i, cnt + 1
+    return [C[ch] + T * float(bg[ch]) for ch in range(3)], T, last, cnt
+
+
+# --------------------------------------------------------------------------
+# whole-image drivers
+# --------------------------------------------------------------------------
+@dataclass
+class Image:
+    color: torch.Tensor    # [3,H,W]
+    final_T: torch.Tensor  # [H,W]
+    last_id: np.ndarray    # [H,W]
+    n_blended: np.ndarray  # [H,W]
+    fragile: np.ndarray    # [H,W]
+
+
+def _tile_pixels(tx, ty, W, H):
+    xs = np.arange(tx * TILE, min((tx + 1) * TILE, W))
+    ys = np.arange(ty * TILE, min((ty + 1) * TILE, H))
+    gy, gx = np.meshgrid(ys, xs, indexing="ij")
+    return gx.ravel(), gy.ravel()
+
+
+def tile_candidates(pr: Projected, order: np.ndarray, tx: int, ty: int) -> np.ndarray:
+    """Visible primitives (in depth order) whose tile rect contains tile (tx, ty)."""
+    r = pr.rect[order]
+    m = (r[:, 0] <= tx) & (tx < r[:, 2]) & (r[:, 1] <= ty) & (ty < r[:, 3])
+    return order[m]
+
+
+def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binned",
+           tiles: Optional[Sequence[tuple]] = None, scene_f32=None, pr: Optional[Projected] = None,
+           chunk: int = 4096) -> Image:
+    """Render the whole image (or only the listed tiles; other pixels are NaN).
+    mode 'brute': every visible primitive at every pixel; 'binned': per-tile
+    candidate lists from the tile rects (exact culling: the rect covers every
+    pixel where o G >= 1/255)."""
+    if pr is None:
+        pr = project(p, cam, scene_f32)
+    W, H = cam["W"], cam["H"]
+    bg = cam["bg"]
+    order = depth_order(pr.depth32, pr.visible.numpy())
+    tx_n, ty_n = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
+    color = torch.full((H * W, 3), float("nan"), dtype=DT)
+    fT = torch.full((H * W,), float("nan"), dtype=DT)
+    last = np.full(H * W, -2, np.int64)
+    nbl = np.zeros(H * W, np.int64)
+    frag = np.zeros(H * W, bool)
+    if tiles is None:
+        tiles = [(tx, ty) for ty in range(ty_n) for tx in range(tx_n)]
+    parts = []
+    if mode == "brute":
+        xs, ys = [], []
+        for (tx, ty) in tiles:
+            gx, gy = _tile_pixels(tx, ty, W, H)
+            xs.append(gx); ys.append(gy)
+        gx, gy = np.concatenate(xs), np.concatenate(ys)
+        for s in range(0, len(gx), chunk):
+            parts.append((gx[s:s + chunk], gy[s:s + chunk], order))
+    else:
+        for (tx, ty) in tiles:
+            gx, gy = _tile_pixels(tx, ty, W, H)
+            parts.append((gx, gy, tile_candidates(pr, order, tx, ty)))
+    cols, fts, idxs = [], [], []
+    for gx, gy, cand in parts:
+        res = blend_pixels(pr, cand, torch.from_numpy(gx + 0.5).to(DT),
+                           torch.from_numpy(gy + 0.5).to(DT), bg)
+        idx = gy * W + gx
+        cols.append(res.color); fts.append(res.final_T); idxs.append(torch.from_numpy(idx))
+        last[idx] = res.last_id
+        nbl[idx] = res.n_blended
+        frag[idx] = res.fragile
+    if idxs:
+        ii = torch.cat(idxs)
+        color = color.index_put((ii,), torch.cat(cols))
+        fT = fT.index_put((ii,), torch.cat(fts))
+    return Image(color.T.reshape(3, H, W), fT.reshape(H, W), last.reshape(H, W),
+                 nbl.reshape(H, W), frag.reshape(H, W))
+
+
+def render_scene(scene, cam, mode="binned", tiles=None) -> Image:
+    """Convenience: numpy scene/camera objects -> fp64 image."""
+    with torch.no_grad():
+        return render(scene_tensors(scene), camera_tensors(cam), mode, tiles, scene_f32=scene)
+
+
+# --------------------------------------------------------------------------
+# gradients: exact derivative of the definition above (autograd, fp64)
+# --------------------------------------------------------------------------
+GRAD_NAMES = ("means", "scales", "quats", "opacities", "colors", "sh", "freqs", "weights")
+
+
+def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned") -> Dict[str, np.ndarray]:
+    """d(sum dl_dimage * C)/d(params) for every activated attribute (fp64)."""
+    p = scene_tensors(scene, requires_grad=True)
+    ct = camera_tensors(cam)
+    img = render(p, ct, mode, scene_f32=scene)
+    g = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+    (img.color * g).sum().backward()
+    return {k: v.grad.numpy() for k, v in p.items()}
+
+
+def _take(pr: Projected, rows: np.ndarray, local_i: int, one: Projected) -> Projected:
+    """Rows ``rows`` of a projection (detached), with row ``local_i`` replaced
+    by the differentiable single-primitive projection ``one``."""
+    r = torch.from_numpy(rows)
+
+    def pick(full, single):
+        f = full.detach()[r].clone()
+        return torch.cat([f[:local_i], single, f[local_i + 1:]], 0)
+    return Projected(visible=pr.visible[r], depth32=pr.depth32[rows],
+                     mu2d=pick(pr.mu2d, one.mu2d), cov2d_raw=pr.cov2d_raw.detach()[r],
+                     conic=pick(pr.conic, one.conic), opac=pick(pr.opac, one.opac),
+                     rgb=pick(pr.rgb, one.rgb), f2d=pick(pr.f2d, one.f2d), w=pick(pr.w, one.w),
+                     rect=pr.rect[rows], tiles=pr.tiles[rows], fragile_rect=pr.fragile_rect[rows],
+                     fragile_prim=pr.fragile_prim[rows])
+
+
+def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[int],
+                             pr_all: Optional[Projected] = None) -> List[Dict[str, np.ndarray]]:
+    """Gradients of sum(dl_dimage * C) w.r.t. the attributes of each listed
+    primitive, evaluated exactly by re-rendering only the tiles in that
+    primitive's rect (outside them its alpha is below 1/255 and it is skipped,
+    so no other pixel depends on it)."""
+    ct = camera_tensors(cam)
+    W, H = ct["W"], ct["H"]
+    with torch.no_grad():
+        if pr_all is None:
+            pr_all = project(scene_tensors(scene), ct, scene)
+    order = depth_order(pr_all.depth32, pr_all.visible.numpy())
+    g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+    out = []
+    for i in prims:
+        sub = scene.subset(np.array([i]))
+        pi = scene_tensors(sub, requires_grad=True)
+        pri = project(pi, ct, sub)
+        total = torch.zeros((), dtype=DT)
+        if bool(pr_all.visible[i]):
+            x0, y0, x1, y1 = (int(v) for v in pr_all.rect[i])
+            tiles = [(tx, ty) for ty in range(y0, y1) for tx in range(x0, x1)]
+            cands = [tile_candidates(pr_all, order, tx, ty) for (tx, ty) in tiles]
+            rows = np.unique(np.concatenate(cands + [np.array([i])]))
+            local_i = int(np.searchsorted(rows, i))
+            pr = _take(pr_all, rows, local_i, pri)
+            for (tx, ty), cand in zip(tiles, cands):
+                gx, gy = _tile_pixels(tx, ty, W, H)
+                loc = np.searchsorted(rows, cand)
+                res = blend_pixels(pr, loc, torch.from_numpy(gx + 0.5).to(DT),
+                                   torch.from_numpy(gy + 0.5).to(DT), ct["bg"])
+                gsel = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
+                total = total + (res.color * gsel).sum()
+        if total.requires_grad:
+            total.backward()
+        grads = {}
+        for k, v in pi.items():
+            grads[k] = (v.grad.numpy()[0] if v.grad is not None else np.zeros(v.shape[1:]))
+        out.append(grads)
+    return out
+
+
+# --------------------------------------------------------------------------
+# photometric loss (Sec. 3.4.1): (1 - lambda) L1 + lambda (1 - SSIM), lambda = 0.2
+# --------------------------------------------------------------------------
+def gaussian_window(size=11, sigma=1.5) -> torch.Tensor:
+    x = torch.arange(size, dtype=DT) - size // 2
+    g = torch.exp(-(x * x) / (2 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim_map(img: torch.Tensor, ref: torch.Tensor, size=11, sigma=1.5) -> torch.Tensor:
+    """SSIM index map (Wang et al. 2004) with an 11x11 Gaussian window,
+    sigma 1.5, zero-padded 'same' filtering, C1 = 0.01^2, C2 = 0.03^2."""
+    C1, C2 = 0.01 ** 2, 0.03 ** 2
+    g1 = gaussian_window(size, sigma)
+    win = (g1[:, None] * g1[None, :])[None, None].expand(img.shape[0], 1, size, size)
+    pad = size // 2
+    f = lambda z: torch.nn.functional.conv2d(z[None], win, padding=pad, groups=img.shape[0])[0]  # noqa: E731
+    mx, my = f(img), f(ref)
+    sxx = f(img * img) - mx * mx
+    syy = f(ref * ref) - my * my
+    sxy = f(img * ref) - mx * my
+    return ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sxx + syy + C2))
+
+
+def photometric_loss(img: torch.Tensor, ref: torch.Tensor, lam=0.2) -> torch.Tensor:
+    l1 = (img - ref).abs().mean()
+    return (1.0 - lam) * l1 + lam * (1.0 - ssim_map(img, ref).mean())
+
+
+def loss_and_grad(img: np.ndarray, ref: np.ndarray, lam=0.2):
+    x = torch.tensor(np.asarray(img, np.float64), dtype=DT, requires_grad=True)
+    r = torch.tensor(np.asarray(ref, np.float64), dtype=DT)
+    L = photometric_loss(x, r, lam)
+    L.backward()
+    return float(L.detach()), x.grad.numpy()
