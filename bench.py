@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Gabor splatting rasterizer.
+
+Default workload: forward render of 1,000,000 Gabor primitives (K = 4, SH
+degree 3, 64 seeded clusters in a 20-unit box) through a 1297x840 pinhole
+camera inside the scene, fp32.  One step = preprocess -> bin sort -> blend on
+inputs resident in HBM.  Also reported: the training step on the same scene
+(forward, L1 + 0.2 D-SSIM loss against a seeded target, backward to every
+attribute), per-stage times, the roofline of the dominant kernel, and the CPU
+oracle timed on a bounded sample of the same frame.
+
+Prints one JSON line (rank 0).  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles of the frame blended by the CPU oracle")
+    ap.add_argument("--profile", action="store_true", help="few steps, no CPU baseline (for rocprofv3)")
+    return ap.parse_args()
+
+
+class StageTimer:
+    """HIP events around each entry point on the stream the kernels run on."""
+
+    def __init__(self, torch, names):
+        self.torch = torch
+        self.names = names
+        self.ev = {n: [] for n in names}
+
+    def pair(self, name):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        self.ev[name].append((s, e))
+        return s, e
+
+    def totals_ms(self):
+        return {n: sum(s.elapsed_time(e) for s, e in v) for n, v in self.ev.items()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this rasterizer build has no multi-GPU path "
+              "(see the sharding note in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.profile:
+        args.steps, args.warmup, args.no_cpu_baseline = min(args.steps, 5), min(args.warmup, 2), True
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2508_05343_amd import _lib
+    from paper_2508_05343_amd.rasterize import DeviceScene, LossBuffers, RenderPlan
+
+    _lib.gabsplat_check_device()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    scene = synth.config2_scene()
+    cam = synth.config2_camera()
+    ds = DeviceScene.from_host(scene)
+    plan = RenderPlan([ds], [cam])
+    # establish the pair capacity (host sync allowed outside the timed region)
+    plan.forward(check_overflow=True)
+    torch.cuda.synchronize()
+    P = int(plan.num_pairs.item())
+    vis = int((plan.tiles_touched[:plan.items] > 0).sum().item())
+    pix = cam.width * cam.height
+
+    timer = StageTimer(torch, ["preprocess", "bin_sort", "render_fwd"])
+
+    def fwd_step(record):
+        if record:
+            a, b = timer.pair("preprocess"); a.record(stream)
+        plan.preprocess()
+        if record:
+            b.record(stream); a, b = timer.pair("bin_sort"); a.record(stream)
+        plan.bin_sort()
+        if record:
+            b.record(stream); a, b = timer.pair("render_fwd"); a.record(stream)
+        plan.render_fwd()
+        if record:
+            b.record(stream)
+
+    for _ in range(args.warmup):
+        fwd_step(False)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        fwd_step(True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    assert int(plan.overflow.item()) == 0, "pair capacity overflow during the timed steps"
+    total_ms = t0.elapsed_time(t1)
+    ms_step = total_ms / args.steps
+    stage = {k: v / args.steps for k, v in timer.totals_ms().items()}
+
+    # ---- the timed region again without per-stage events (pure throughput)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        fwd_step(False)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_step_clean = t0.elapsed_time(t1) / args.steps
+
+    # ---- dominant kernel roofline: render_fwd is one kernel launch
+    n_contrib = plan.n_contrib[:pix].to(torch.int64)
+    ranges = plan.ranges[:cam.num_tiles].to(torch.int64)
+    tile_len = (ranges[:, 1] - ranges[:, 0])
+    # pairs the blend reads: each tile reads its list up to the batch holding
+    # the furthest pixel's stop; bounded by the list length (upper bound used)
+    p_read = int(tile_len.sum().item())
+    rec_bytes = 4 * (10 + 3 * plan.k)  # used record floats
+    render_bytes = p_read * (4 + rec_bytes) + pix * (12 + 4 + 4) + cam.num_tiles * 8
+    stage_ms = dict(stage)
+    dom = max(stage_ms, key=stage_ms.get)
+    # pass-aware algorithmic bytes of the whole forward (byte model in the design doc)
+    N, V = scene.n, vis
+    K = plan.k
+    params_visible = 4 * (3 + 4 + 1 + 48 + 4 * K)
+    b_pre = 12 * N + params_visible * V + 4 * (10 + 3 * K) * V + 4 * 4 * N
+    b_scan = 8 * N
+    b_dup = 16 * V + 12 * P
+    b_sort = 8 * P + 24 * P * 6
+    b_ranges = 8 * P + 8 * cam.num_tiles
+    b_fwd = b_pre + b_scan + b_dup + b_sort + b_ranges + render_bytes
+    hbm_frac_fwd = (b_fwd / 1e9) / (ms_step_clean * 1e-3) / HBM_PEAK_GBS
+    render_gbs = (render_bytes / 1e9) / (stage_ms["render_fwd"] * 1e-3)
+
+    out = {
+        "metric": "Mpix/s fwd, fwd+bwd step ms @1M Gabor prims; serve p50/p99 latency",
+        "value": round(pix / (ms_step_clean * 1e-3) / 1e6, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step_clean, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded clustered scene, random-init attributes)",
+        "config": {"workload": "forward render, 1,000,000 Gabor primitives, K=4, SH degree 3, 1297x840",
+                   "primitives": N, "k": K, "sh_degree": 3, "width": cam.width, "height": cam.height,
+                   "visible": V, "pairs": P, "parallelism": "single GPU"},
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "fwd_pass_aware_bytes": int(b_fwd),
+        "fwd_hbm_fraction": round(hbm_frac_fwd, 4),
+        "roofline": {"kernel": "k_render_fwd<4>", "bound": "hbm", "achieved": round(render_gbs, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(render_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "dominant_stage": dom},
+    }
+
+    # ---- training step (forward + loss + backward)
+    if not args.no_train:
+        target = torch.from_numpy(synth.random_target(1003, (3, cam.height, cam.width))).to(dev)
+        lossb = LossBuffers(3, cam.height, cam.width)
+        grads = {n: torch.zeros_like(getattr(ds, n)) for n in
+                 ("means", "scales", "quats", "opacities", "sh", "freqs", "weights")}
+        img = plan.view_image(0)
+
+        def train_step():
+            fwd_step(False)
+            lossb(img, target)
+            plan.backward(lossb.grad.view(-1), [grads], accumulate=False)
+
+        for _ in range(max(2, args.warmup // 2)):
+            train_step()
+        torch.cuda.synchronize()
+        ts = max(5, args.steps // 2)
+        t0.record(stream)
+        for _ in range(ts):
+            train_step()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        out["train_step_ms"] = round(t0.elapsed_time(t1) / ts, 4)
+        out["train_loss"] = round(float(lossb.loss.item()), 6)
+
+    # ---- CPU oracle on a bounded sample of the same frame
+    if not args.no_cpu_baseline:
+        from oracle import gabor_oracle as O
+        ncores = torch.get_num_threads()
+        t = time.perf_counter()
+        with torch.no_grad():
+            pr = O.project(O.scene_tensors(scene), O.camera_tensors(cam), scene)
+        t_proj = time.perf_counter() - t
+        rng = np.random.Generator(np.random.PCG64(7))
+        sel = rng.choice(cam.num_tiles, size=min(args.cpu_tiles, cam.num_tiles), replace=False)
+        tiles = [(int(s % cam.tiles_x), int(s // cam.tiles_x)) for s in sel]
+        t = time.perf_counter()
+        with torch.no_grad():
+            O.render(None, O.camera_tensors(cam), "binned", tiles=tiles, scene_f32=scene, pr=pr)
+        t_blend = time.perf_counter() - t
+        spix = sum(min(16, cam.width - 16 * tx) * min(16, cam.height - 16 * ty) for tx, ty in tiles)
+        t_sample = t_blend + t_proj * spix / pix
+        out["cpu_baseline"] = {"value": round(spix / t_sample / 1e6, 5), "unit": "Mpix/s", "cores": ncores,
+                               "kind": "oracle",
+                               "sample": f"fp64 projection of all {N} primitives ({t_proj:.1f} s, charged pro rata) "
+                                         f"+ blend of {len(tiles)} seeded tiles of {cam.num_tiles} ({spix} px, "
+                                         f"{t_blend:.1f} s)"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,266 @@
+/*
+ * gabsplat.h -- C ABI of the MI355X (gfx950) 3D Gabor splatting rasterizer.
+ *
+ * The library implements the tile-based differentiable rasterizer for 3D Gabor
+ * primitives: each primitive is a 3D Gaussian envelope (Sec. 3.1, Eq.
+ * 3d_gaussian) modulated by a bank of K directional cosine terms (Sec. 3.2,
+ * the 3D Gabor-based primitive), projected to the image plane with the EWA
+ * covariance (Sec. 3.1) and the frequency projection + z-integration of
+ * Sec. 3.3.1-3.3.2 (derived in supplementary A.1-A.2), and alpha-blended front
+ * to back (Sec. 3.3.3).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers unless stated otherwise; the
+ *    struct arguments themselves (gabsplat_scene, gabsplat_camera,
+ *    gabsplat_geom) live in HOST memory.
+ *  - The caller owns every buffer.  The library never allocates, frees or
+ *    synchronises; every call only enqueues work on `stream` (a hipStream_t,
+ *    passed as void*; NULL = the default stream) and returns.
+ *  - Calls return a gabsplat_status; no C++ exception crosses the ABI.  On an
+ *    error status nothing has been enqueued unless stated otherwise.
+ *  - Attribute values are ACTIVATED: scales > 0, opacities in (0,1), weights
+ *    >= 0 (the paper applies exp / sigmoid before rasterizing, Sec. 3.4.1).
+ *    Quaternions are normalised inside and gradients are taken w.r.t. the
+ *    unnormalised input.
+ *  - Layouts are planar structure-of-arrays, fp32, attribute-major: element
+ *    (attribute a, primitive i) of an array with A attributes is at a*n + i.
+ *  - An "item" is a (view, primitive) pair; item = view_item_offset + i where
+ *    views are laid out back to back in the order given.
+ *  - Pixel (px, py) samples the image point (px + 0.5, py + 0.5).  Tiles are
+ *    16x16 pixels, row-major inside a view; the global tile id of a view's
+ *    tile t is (sum of the tile counts of the earlier views) + t.
+ */
+#ifndef GABSPLAT_H
+#define GABSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GABSPLAT_ABI_VERSION 1
+#define GABSPLAT_TILE 16
+#define GABSPLAT_MAX_K 8
+#define GABSPLAT_MAX_SH_DEGREE 3
+#define GABSPLAT_MAX_VIEWS 4096
+
+typedef enum {
+  GABSPLAT_OK = 0,
+  GABSPLAT_ERR_INVALID_ARGUMENT = 1,
+  GABSPLAT_ERR_WORKSPACE_TOO_SMALL = 2,
+  GABSPLAT_ERR_CAPACITY_EXCEEDED = 3,
+  GABSPLAT_ERR_HIP = 4,
+  GABSPLAT_ERR_UNSUPPORTED_DEVICE = 5
+} gabsplat_status;
+
+/* A set of N primitives (Sec. 3.2: mean, covariance via scale and rotation,
+ * opacity, colour, and F = k pairs (frequency f_i, weight w_i)).
+ *   means     [3][n]   world space
+ *   scales    [3][n]   > 0; Sigma = R S S^T R^T with S = diag(scales)
+ *   quats     [4][n]   (w, x, y, z), any non-zero norm
+ *   opacities [n]      in (0, 1)
+ *   sh        [(deg+1)^2][3][n]  real SH coefficients, coefficient-major then
+ *                      channel (element (d, c, i) at (d*3 + c)*n + i); or NULL
+ *   colors    [3][n]   precomputed RGB; or NULL (exactly one of sh/colors)
+ *   freqs     [k][3][n] cycles per world unit (element (j, axis, i) at
+ *                      (j*3 + axis)*n + i)
+ *   weights   [k][n]   >= 0 (the DC weight is 1 - sum_j w_j)
+ * Limits: 0 <= k <= GABSPLAT_MAX_K, sh_degree in [0, 3] when sh != NULL,
+ * 0 <= n < 2^31. */
+typedef struct {
+  int64_t n;
+  int32_t k;
+  int32_t sh_degree;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  const float* colors;
+  const float* freqs;
+  const float* weights;
+} gabsplat_scene;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point x
+ * maps to camera space as R x + t with world_to_cam = [R | t] row-major
+ * (R at [0..2], [4..6], [8..10]; t at [3], [7], [11]).  cam_pos is the camera
+ * centre in world space (view direction of the SH colour).  Primitives with
+ * camera z <= near_plane are culled.  bg is added with the final
+ * transmittance.  1 <= width, height <= 16384. */
+typedef struct {
+  int32_t width;
+  int32_t height;
+  float fx, fy, cx, cy;
+  float world_to_cam[12];
+  float cam_pos[3];
+  float near_plane;
+  float bg[3];
+} gabsplat_camera;
+
+/* Per-item projected data, caller-allocated device buffers of `items` rows.
+ *   rec    [items][gabsplat_record_floats(k)] render record:
+ *            [0,1]  mu2d (pixels)
+ *            [2..4] quadratic form q = a dx^2 + b dx dy + c dy^2 in log2
+ *                   units: (a, b, c) = -log2(e) * (C_xx/2, C_xy, C_yy/2),
+ *                   C = (Sigma2d + 0.3 I)^-1 the conic
+ *            [5]    log2(opacity)
+ *            [6..8] RGB colour
+ *            [9]    DC weight 1 - sum_j w_j
+ *            [10+3j .. 12+3j]  2D frequency (cycles/pixel, x then y) and
+ *                   weight w_j of component j
+ *          so o * G(p) = exp2(q(p - mu2d) + rec[5]).
+ *   depth  [items] fp32 camera z, computed as ((r20 x + r21 y) + r22 z) + t2
+ *          with one IEEE rounding per operation
+ *   rect   [items][2] tile rectangle: word 0 = x0 | y0 << 16, word 1 =
+ *          x1 | y1 << 16 (x1, y1 exclusive)
+ *   tiles  [items] number of tiles in rect; 0 means culled
+ *   k      number of Gabor components of the scenes (record layout)
+ *   views  view table, gabsplat_views_bytes(num_views, num_scenes) bytes,
+ *          written by gabsplat_preprocess; gabsplat_bin_sort,
+ *          gabsplat_render_fwd and gabsplat_render_bwd read it, so they must
+ *          be given the same views as the preprocess call that wrote it. */
+typedef struct {
+  int32_t k;
+  int32_t pad;
+  float* rec;
+  float* depth;
+  uint32_t* rect;
+  uint32_t* tiles;
+  void* views;
+} gabsplat_geom;
+
+/* Gradient buffers, same layouts as gabsplat_scene.  With accumulate != 0 the
+ * gradients are added (+=) to the buffers (views and calls accumulate);
+ * with accumulate == 0 they are overwritten, every primitive included (culled
+ * ones get 0).  Entries may be NULL to skip that gradient (sh or colors must
+ * match the scene's colour mode).  grad2d [items][gabsplat_grad2d_floats(k)]
+ * is scratch that receives the image-plane gradients (mu2d, conic record
+ * terms, log2 opacity, RGB, per component 2D frequency and weight); the call
+ * clears it first, and it may be read afterwards (e.g. the view-space
+ * positional gradient used by density control).  All scenes of one call
+ * share the same grad2d buffer. */
+typedef struct {
+  int32_t accumulate;
+  int32_t pad;
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+  float* colors;
+  float* freqs;
+  float* weights;
+  float* grad2d;
+} gabsplat_scene_grads;
+
+/* ---------------------------------------------------------------- helpers */
+int32_t gabsplat_abi_version(void);
+const char* gabsplat_status_string(gabsplat_status s);
+/* Floats per render record for k components: round_up(10 + 3k, 4). */
+int32_t gabsplat_record_floats(int32_t k);
+/* Floats per item of the image-plane gradient: round_up(9 + 3k, 4). */
+int32_t gabsplat_grad2d_floats(int32_t k);
+/* Bytes for gabsplat_geom.views. */
+size_t gabsplat_views_bytes(int32_t num_views, int32_t num_scenes);
+/* Device workspace for gabsplat_bin_sort: `items` = total items, `pair_capacity`
+ * = room for (primitive, tile) pairs, `total_tiles` = sum of tile counts. */
+size_t gabsplat_bin_sort_workspace_size(int64_t items, int64_t pair_capacity, int64_t total_tiles);
+/* 0 if the current HIP device is gfx950, else GABSPLAT_ERR_UNSUPPORTED_DEVICE. */
+gabsplat_status gabsplat_check_device(void);
+
+/* ------------------------------------------------------------ entry points */
+
+/* K1, projection and culling of every (view, primitive) item: camera-space
+ * transform and near cull (camera z <= near_plane), opacity cull (255 o <= 1),
+ * EWA 2D covariance J W Sigma W^T J^T (Sec. 3.1) with J evaluated at the
+ * point clamped to 1.3x the frustum, dilated by 0.3 px^2 and inverted; the
+ * 2D frequency of every component, f2d = (T Sigma T^T)^-1 T Sigma f with T
+ * the first two rows of J W, which equals the paper's f_proj = (JW)^-T f
+ * followed by the z-integration of Sec. 3.3.2 for any completion of J; the
+ * SH colour (real SH, degree <= 3, + 0.5, clamped at 0); and the tile
+ * rectangle of the exact support o G >= 1/255 (half-widths sqrt(2 ln(255 o))
+ * sqrt(Sigma2d_xx), resp. yy).
+ *   scenes[num_scenes] (host), scene_of_view[num_views] (host, index into
+ *   scenes; NULL means all views use scenes[0]), cams[num_views] (host).
+ * All scenes of one call must share k and the colour mode (sh / colors and
+ * sh_degree).  geom rows: items = sum over views of that view's scene n. */
+gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_scenes,
+                                    const int32_t* scene_of_view, const gabsplat_camera* cams,
+                                    int32_t num_views, const gabsplat_geom* geom, void* stream);
+
+/* K2-K5, binning: compact the visible items, stably sort them by fp32 depth
+ * bits, emit one (global tile, item) pair per overlapped tile, stably sort the
+ * pairs by tile (an LSD radix sort on the key tile << 32 | depth bits whose
+ * depth passes run on the primitives before duplication), and write each
+ * global tile's [start, end) range (empty tiles = (0, 0)).
+ *   vals [pair_capacity]      sorted item ids (output)
+ *   keys [pair_capacity]      sorted 64-bit keys tile << 32 | depth bits, or
+ *                             NULL to skip writing them
+ *   tile_ranges [total_tiles][2] (output)
+ *   d_num_pairs  device int64 (output): number of pairs
+ *   d_overflow   device int32 (output): 1 if pairs > pair_capacity, else 0.
+ *                On overflow vals/keys/ranges are undefined and
+ *                gabsplat_render_fwd / _bwd become no-ops; call again with a
+ *                larger capacity (gabsplat_read_overflow reports it).
+ *   ws / ws_bytes  device workspace >= gabsplat_bin_sort_workspace_size(). */
+gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_camera* cams,
+                                  int32_t num_views, int64_t items, void* ws, size_t ws_bytes,
+                                  uint64_t* keys, uint32_t* vals, int64_t pair_capacity,
+                                  uint32_t* tile_ranges, int64_t* d_num_pairs, int32_t* d_overflow,
+                                  void* stream);
+
+/* K6, forward blend (Sec. 3.3.3 with the 2D Gabor primitive of Sec. 3.3.2):
+ * per pixel, front to back over its tile's list, alpha = min(0.99, o G B)
+ * with B = (1 - sum w) + sum_j w_j cos(2 pi f2d_j . (p - mu2d)); primitives
+ * with alpha < 1/255 are skipped; the walk stops, without blending, at the
+ * first primitive that would leave T (1 - alpha) < 1e-4; C += c alpha T;
+ * finally C += T bg.  Deterministic (no atomics).
+ *   image     [sum over views of 3*H*W]  view-major, then channel, row, column
+ *   final_T   [sum over views of H*W]
+ *   n_contrib [sum over views of H*W]  1-based position, in the tile's list,
+ *             of the last blended primitive (0 = none)
+ *   d_overflow  from gabsplat_bin_sort (device). */
+gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals,
+                                    const uint32_t* tile_ranges, const gabsplat_camera* cams,
+                                    int32_t num_views, float* image, float* final_T,
+                                    uint32_t* n_contrib, const int32_t* d_overflow, void* stream);
+
+/* K7 + K8, backward of the forward above w.r.t. every attribute.  K7 walks
+ * each tile back to front from n_contrib, recovers the transmittance by
+ * division, reduces each primitive's per-pixel contributions within the
+ * wavefront and adds them atomically into grads->grad2d; K8 chains the
+ * image-plane gradients through the projection of every view into the scene
+ * gradients (+=).  Not bitwise deterministic (fp32 atomics).
+ *   scenes / scene_of_view / cams / num_views exactly as given to
+ *   gabsplat_preprocess; grads[num_scenes] (host array of structs);
+ *   dl_dimage has the layout of `image`. */
+gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_scenes,
+                                    const int32_t* scene_of_view, const gabsplat_camera* cams,
+                                    int32_t num_views, const gabsplat_geom* geom,
+                                    const uint32_t* vals, const uint32_t* tile_ranges,
+                                    const float* final_T, const uint32_t* n_contrib,
+                                    const float* dl_dimage, const gabsplat_scene_grads* grads,
+                                    const int32_t* d_overflow, void* stream);
+
+/* K9, photometric loss of Sec. 3.4.1 for one image: L = (1 - lambda) mean|x - y|
+ * + lambda (1 - mean SSIM(x, y)), SSIM with an 11x11 Gaussian window
+ * (sigma 1.5), zero-padded, C1 = 0.01^2, C2 = 0.03^2, means over all channels
+ * and pixels.  x, y [channels][H][W]; writes d_loss (device float, one
+ * value) and dl_dx [channels][H][W].  ws >= gabsplat_loss_workspace_size().
+ * The L1 gradient at x == y is 0. */
+size_t gabsplat_loss_workspace_size(int32_t channels, int32_t height, int32_t width);
+gabsplat_status gabsplat_loss_l1_dssim(const float* x, const float* y, int32_t channels,
+                                       int32_t height, int32_t width, float lambda, float* d_loss,
+                                       float* dl_dx, void* ws, size_t ws_bytes, void* stream);
+
+/* Reads *d_overflow synchronously (waits for `stream`); returns
+ * GABSPLAT_ERR_CAPACITY_EXCEEDED if it is set, GABSPLAT_OK otherwise. */
+gabsplat_status gabsplat_read_overflow(const int32_t* d_overflow, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABSPLAT_H */

@@ -1,0 +1,209 @@
+"""ctypes binding of libgabsplat.so (argument marshalling only).
+
+The functions below carry the names of the C entry points declared in
+include/gabsplat.h.  They take torch tensors (device memory) and small host
+structs, pass raw pointers and the current HIP stream, and raise GabsplatError
+on a non-OK status.  There is no fallback: if the library has not been built
+(``python -m paper_2508_05343_amd.build``) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+from typing import Optional, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgabsplat.so")
+
+EXPORTS = (
+    "gabsplat_abi_version", "gabsplat_status_string", "gabsplat_record_floats", "gabsplat_grad2d_floats",
+    "gabsplat_views_bytes", "gabsplat_bin_sort_workspace_size", "gabsplat_check_device",
+    "gabsplat_preprocess", "gabsplat_bin_sort", "gabsplat_render_fwd", "gabsplat_render_bwd",
+    "gabsplat_loss_workspace_size", "gabsplat_loss_l1_dssim", "gabsplat_read_overflow",
+)
+
+OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE = range(6)
+
+
+class GabsplatError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32),
+                ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+                ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("world_to_cam", c_float * 12), ("cam_pos", c_float * 3),
+                ("near_plane", c_float), ("bg", c_float * 3)]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("pad", c_int32), ("rec", c_void_p), ("depth", c_void_p), ("rect", c_void_p),
+                ("tiles", c_void_p), ("views", c_void_p)]
+
+
+class SceneGrads(ctypes.Structure):
+    _fields_ = [("accumulate", c_int32), ("pad", c_int32), ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+                ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p),
+                ("grad2d", c_void_p)]
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise GabsplatError(HIP_ERROR, f"{LIB_PATH} not found: build it with `python -m paper_2508_05343_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.gabsplat_abi_version.restype = c_int32
+    L.gabsplat_status_string.restype = ctypes.c_char_p
+    L.gabsplat_status_string.argtypes = [c_int32]
+    L.gabsplat_record_floats.restype = c_int32
+    L.gabsplat_record_floats.argtypes = [c_int32]
+    L.gabsplat_grad2d_floats.restype = c_int32
+    L.gabsplat_grad2d_floats.argtypes = [c_int32]
+    L.gabsplat_views_bytes.restype = c_size_t
+    L.gabsplat_views_bytes.argtypes = [c_int32, c_int32]
+    L.gabsplat_bin_sort_workspace_size.restype = c_size_t
+    L.gabsplat_bin_sort_workspace_size.argtypes = [c_int64, c_int64, c_int64]
+    L.gabsplat_check_device.restype = c_int32
+    L.gabsplat_preprocess.restype = c_int32
+    L.gabsplat_preprocess.argtypes = [POINTER(Scene), c_int32, POINTER(c_int32), POINTER(Camera), c_int32,
+                                      POINTER(Geom), c_void_p]
+    L.gabsplat_bin_sort.restype = c_int32
+    L.gabsplat_bin_sort.argtypes = [POINTER(Geom), POINTER(Camera), c_int32, c_int64, c_void_p, c_size_t,
+                                    c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gabsplat_render_fwd.restype = c_int32
+    L.gabsplat_render_fwd.argtypes = [POINTER(Geom), c_void_p, c_void_p, POINTER(Camera), c_int32, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gabsplat_render_bwd.restype = c_int32
+    L.gabsplat_render_bwd.argtypes = [POINTER(Scene), c_int32, POINTER(c_int32), POINTER(Camera), c_int32,
+                                      POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      POINTER(SceneGrads), c_void_p, c_void_p]
+    L.gabsplat_loss_workspace_size.restype = c_size_t
+    L.gabsplat_loss_workspace_size.argtypes = [c_int32, c_int32, c_int32]
+    L.gabsplat_loss_l1_dssim.restype = c_int32
+    L.gabsplat_loss_l1_dssim.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p,
+                                         c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gabsplat_read_overflow.restype = c_int32
+    L.gabsplat_read_overflow.argtypes = [c_void_p, c_void_p]
+    _LIB = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        msg = lib().gabsplat_status_string(status).decode()
+        raise GabsplatError(status, f"{what}: {msg}")
+
+
+def ptr(t) -> Optional[int]:
+    """Raw device pointer of a tensor (None for None)."""
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def stream_handle(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream) or None
+
+
+def _arr(ctype, items):
+    items = list(items)
+    return (ctype * max(1, len(items)))(*items)
+
+
+# ------------------------------------------------------------------ helpers
+def gabsplat_abi_version() -> int:
+    return int(lib().gabsplat_abi_version())
+
+
+def gabsplat_record_floats(k: int) -> int:
+    return int(lib().gabsplat_record_floats(k))
+
+
+def gabsplat_grad2d_floats(k: int) -> int:
+    return int(lib().gabsplat_grad2d_floats(k))
+
+
+def gabsplat_views_bytes(num_views: int, num_scenes: int) -> int:
+    return int(lib().gabsplat_views_bytes(num_views, num_scenes))
+
+
+def gabsplat_bin_sort_workspace_size(items: int, pair_capacity: int, total_tiles: int) -> int:
+    return int(lib().gabsplat_bin_sort_workspace_size(items, pair_capacity, total_tiles))
+
+
+def gabsplat_loss_workspace_size(c: int, h: int, w: int) -> int:
+    return int(lib().gabsplat_loss_workspace_size(c, h, w))
+
+
+def gabsplat_check_device():
+    _check(lib().gabsplat_check_device(), "gabsplat_check_device")
+
+
+# -------------------------------------------------------------- entry points
+def gabsplat_preprocess(scenes: Sequence[Scene], scene_of_view: Optional[Sequence[int]], cams: Sequence[Camera],
+                        geom: Geom, stream=None):
+    sa = _arr(Scene, scenes)
+    sv = None if scene_of_view is None else _arr(c_int32, scene_of_view)
+    ca = _arr(Camera, cams)
+    _check(lib().gabsplat_preprocess(sa, len(scenes), sv, ca, len(cams), ctypes.byref(geom),
+                                     stream_handle(stream)), "gabsplat_preprocess")
+
+
+def gabsplat_bin_sort(geom: Geom, cams: Sequence[Camera], items: int, ws, keys, vals, pair_capacity: int,
+                      tile_ranges, d_num_pairs, d_overflow, stream=None):
+    ca = _arr(Camera, cams)
+    _check(lib().gabsplat_bin_sort(ctypes.byref(geom), ca, len(cams), items, ptr(ws), ws.numel() * ws.element_size(),
+                                   ptr(keys), ptr(vals), pair_capacity, ptr(tile_ranges), ptr(d_num_pairs),
+                                   ptr(d_overflow), stream_handle(stream)), "gabsplat_bin_sort")
+
+
+def gabsplat_render_fwd(geom: Geom, vals, tile_ranges, cams: Sequence[Camera], image, final_T, n_contrib,
+                        d_overflow, stream=None):
+    ca = _arr(Camera, cams)
+    _check(lib().gabsplat_render_fwd(ctypes.byref(geom), ptr(vals), ptr(tile_ranges), ca, len(cams), ptr(image),
+                                     ptr(final_T), ptr(n_contrib), ptr(d_overflow), stream_handle(stream)),
+           "gabsplat_render_fwd")
+
+
+def gabsplat_render_bwd(scenes: Sequence[Scene], scene_of_view, cams: Sequence[Camera], geom: Geom, vals,
+                        tile_ranges, final_T, n_contrib, dl_dimage, grads: Sequence[SceneGrads], d_overflow,
+                        stream=None):
+    sa = _arr(Scene, scenes)
+    sv = None if scene_of_view is None else _arr(c_int32, scene_of_view)
+    ca = _arr(Camera, cams)
+    ga = _arr(SceneGrads, grads)
+    _check(lib().gabsplat_render_bwd(sa, len(scenes), sv, ca, len(cams), ctypes.byref(geom), ptr(vals),
+                                     ptr(tile_ranges), ptr(final_T), ptr(n_contrib), ptr(dl_dimage), ga,
+                                     ptr(d_overflow), stream_handle(stream)), "gabsplat_render_bwd")
+
+
+def gabsplat_loss_l1_dssim(x, y, lam: float, d_loss, dl_dx, ws, stream=None):
+    c, h, w = x.shape
+    _check(lib().gabsplat_loss_l1_dssim(ptr(x), ptr(y), c, h, w, float(lam), ptr(d_loss), ptr(dl_dx), ptr(ws),
+                                        ws.numel() * ws.element_size(), stream_handle(stream)),
+           "gabsplat_loss_l1_dssim")
+
+
+def gabsplat_read_overflow(d_overflow, stream=None) -> bool:
+    """True if the last bin sort overflowed its pair capacity (synchronises)."""
+    st = lib().gabsplat_read_overflow(ptr(d_overflow), stream_handle(stream))
+    if st == CAPACITY_EXCEEDED:
+        return True
+    _check(st, "gabsplat_read_overflow")
+    return False

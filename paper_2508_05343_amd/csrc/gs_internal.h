@@ -1,0 +1,128 @@
+// Internal declarations of the gfx950 Gabor splatting kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gabsplat.h"
+
+namespace gs {
+
+constexpr int kTile = 16;
+constexpr int kBlock = 256;                    // threads per tile workgroup (4 wave64)
+constexpr float kAlphaMin = 1.0f / 255.0f;     // skip threshold on alpha
+constexpr float kAlphaMax = 0.99f;             // alpha clamp
+constexpr float kTMin = 1e-4f;                 // transmittance stop
+constexpr float kDilation = 0.3f;              // px^2 added to the 2D covariance
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+// log2(1/255): o G < 1/255  <=>  q + log2 o < kLog2AlphaMin
+constexpr float kLog2AlphaMin = -7.9943534368588578f;
+
+// One scene as seen by the kernels (device copy of gabsplat_scene).
+struct SceneEntry {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  const float* colors;
+  const float* freqs;
+  const float* weights;
+  int64_t n;
+  int32_t k;
+  int32_t sh_degree;  // -1 for precomputed colours
+};
+
+// One view (camera + where its items, tiles and pixels live).
+struct ViewEntry {
+  float R[9];
+  float t[3];
+  float campos[3];
+  float fx, fy, cx, cy, near_plane;
+  float bg[3];
+  int32_t width, height, tiles_x, tiles_y;
+  int32_t tile_offset;   // first global tile id of this view
+  int32_t scene;         // index into the scene table
+  int64_t item_offset;   // first item of this view
+  int64_t pixel_offset;  // first pixel of this view (image uses 3x)
+};
+
+// Device view table: header, then views, then scenes.
+struct ViewTableHeader {
+  int32_t num_views;
+  int32_t num_scenes;
+  int32_t total_tiles;
+  int32_t pad;
+  int64_t total_items;
+  int64_t total_pixels;
+};
+
+inline size_t view_table_bytes(int num_views, int num_scenes) {
+  return sizeof(ViewTableHeader) + sizeof(ViewEntry) * (size_t)num_views +
+         sizeof(SceneEntry) * (size_t)num_scenes;
+}
+
+__host__ __device__ inline const ViewEntry* table_views(const void* t) {
+  return reinterpret_cast<const ViewEntry*>(reinterpret_cast<const char*>(t) + sizeof(ViewTableHeader));
+}
+__host__ __device__ inline const SceneEntry* table_scenes(const void* t, int num_views) {
+  return reinterpret_cast<const SceneEntry*>(reinterpret_cast<const char*>(t) + sizeof(ViewTableHeader) +
+                                             sizeof(ViewEntry) * (size_t)num_views);
+}
+
+inline int record_floats(int k) { return (10 + 3 * k + 3) & ~3; }
+inline int grad2d_floats(int k) { return (9 + 3 * k + 3) & ~3; }
+
+// Host-side packed copy of the table (built by the API layer).
+struct HostTable {
+  ViewTableHeader hdr;
+  ViewEntry* views;    // host array [num_views]
+  SceneEntry* scenes;  // host array [num_scenes]
+};
+
+// --- launchers (each returns hipSuccess or the first launch error) ---------
+hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s);
+
+hipError_t launch_preprocess(const void* d_table, const HostTable& h, const gabsplat_geom& g,
+                             hipStream_t s);
+
+struct BinSortPlan {
+  int64_t items;
+  int64_t capacity;
+  int32_t total_tiles;
+  int32_t tile_bits;
+  size_t bytes;
+  // offsets of each workspace region
+  size_t off_counters, off_dkeys_a, off_dkeys_b, off_dvals_a, off_dvals_b, off_offsets;
+  size_t off_tkeys_a, off_tkeys_b, off_pvals_b, off_hist, off_look_sort, off_look_scan;
+  int64_t parts_items, parts_pairs;
+};
+BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles);
+
+hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* ws, uint64_t* keys,
+                           uint32_t* vals, uint32_t* ranges, int64_t* d_num_pairs, int32_t* d_overflow,
+                           hipStream_t s);
+
+hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
+                             int k, const uint32_t* vals, const uint32_t* ranges, float* image,
+                             float* final_T, uint32_t* n_contrib, const int32_t* d_overflow,
+                             hipStream_t s);
+
+hipError_t launch_render_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
+                             int k, const uint32_t* vals, const uint32_t* ranges,
+                             const float* final_T, const uint32_t* n_contrib, const float* dl_dimage,
+                             float* grad2d, const int32_t* d_overflow, hipStream_t s);
+
+hipError_t launch_preprocess_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
+                                 int scene_index, const gabsplat_scene_grads& gr,
+                                 const int32_t* d_overflow, hipStream_t s);
+
+size_t loss_workspace_bytes(int c, int h, int w);
+hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, float lambda,
+                       float* d_loss, float* dl_dx, void* ws, hipStream_t s);
+
+// generic fill kernel (used instead of memset so that callers may capture)
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,591 @@
+// K1 (projection of every (view, primitive) item) and K8 (its backward).
+//
+// Geometry (Sec. 3.1 EWA splatting, Sec. 3.3 frequency projection): with
+// T the first two rows of J W and M = R(q) diag(s) (so Sigma = M M^T), the
+// rows r0, r1 of A = T M give the raw 2D covariance A A^T = [[r0.r0, r0.r1],
+// [r0.r1, r1.r1]] and, by the Lagrange identity, its determinant |r0 x r1|^2
+// without cancellation.  The 2D frequency (T Sigma T^T)^-1 T Sigma f is
+// evaluated as (v_x . f, v_y . f) with v_x = M (r1 x c) / |c|^2 and
+// v_y = M (c x r0) / |c|^2, c = r0 x r1 (the adjugate of A A^T written with
+// cross products), so each component costs two dot products.
+#include <hip/hip_runtime.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- helpers
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross3(V3 a, V3 b) {
+  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 add3(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 scale3(V3 a, float s) { return v3(a.x * s, a.y * s, a.z * s); }
+
+// Real spherical harmonics, degree <= 3, ordered l = 0..3, m = -l..l, without
+// the Condon-Shortley phase.  Constants are K_l^m (times sqrt 2 for m != 0)
+// times the leading factor of d^|m| P_l / dz^|m| for the polynomial written.
+constexpr float kY00 = 0.28209479177387814f;
+constexpr float kY1 = 0.48860251190291992f;
+constexpr float kY2a = 1.0925484305920792f;   // xy, yz, xz
+constexpr float kY2b = 0.31539156525252005f;  // 3z^2 - 1
+constexpr float kY2c = 0.54627421529603959f;  // x^2 - y^2
+constexpr float kY3a = 0.59004358992664352f;  // y(3x^2 - y^2), x(x^2 - 3y^2)
+constexpr float kY3b = 2.8906114426405538f;   // xyz
+constexpr float kY3c = 0.45704579946446572f;  // y(5z^2 - 1), x(5z^2 - 1)
+constexpr float kY3d = 0.37317633259011540f;  // z(5z^2 - 3)
+constexpr float kY3e = 1.4453057213202769f;   // z(x^2 - y^2)
+
+__device__ __forceinline__ void sh_basis(float x, float y, float z, int deg, float* Y) {
+  Y[0] = kY00;
+  if (deg < 1) return;
+  Y[1] = kY1 * y;
+  Y[2] = kY1 * z;
+  Y[3] = kY1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kY2a * x * y;
+  Y[5] = kY2a * y * z;
+  Y[6] = kY2b * (3.0f * zz - 1.0f);
+  Y[7] = kY2a * x * z;
+  Y[8] = kY2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = kY3a * y * (3.0f * xx - yy);
+  Y[10] = kY3b * x * y * z;
+  Y[11] = kY3c * y * (5.0f * zz - 1.0f);
+  Y[12] = kY3d * z * (5.0f * zz - 3.0f);
+  Y[13] = kY3c * x * (5.0f * zz - 1.0f);
+  Y[14] = kY3e * z * (xx - yy);
+  Y[15] = kY3a * x * (xx - 3.0f * yy);
+}
+
+// Ambient gradient of each basis polynomial w.r.t. (x, y, z).
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int deg, V3* dY) {
+  dY[0] = v3(0.f, 0.f, 0.f);
+  if (deg < 1) return;
+  dY[1] = v3(0.f, kY1, 0.f);
+  dY[2] = v3(0.f, 0.f, kY1);
+  dY[3] = v3(kY1, 0.f, 0.f);
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  dY[4] = v3(kY2a * y, kY2a * x, 0.f);
+  dY[5] = v3(0.f, kY2a * z, kY2a * y);
+  dY[6] = v3(0.f, 0.f, 6.0f * kY2b * z);
+  dY[7] = v3(kY2a * z, 0.f, kY2a * x);
+  dY[8] = v3(2.0f * kY2c * x, -2.0f * kY2c * y, 0.f);
+  if (deg < 3) return;
+  dY[9] = v3(6.0f * kY3a * x * y, kY3a * (3.0f * xx - 3.0f * yy), 0.f);
+  dY[10] = v3(kY3b * y * z, kY3b * x * z, kY3b * x * y);
+  dY[11] = v3(0.f, kY3c * (5.0f * zz - 1.0f), 10.0f * kY3c * y * z);
+  dY[12] = v3(0.f, 0.f, kY3d * (15.0f * zz - 3.0f));
+  dY[13] = v3(kY3c * (5.0f * zz - 1.0f), 0.f, 10.0f * kY3c * x * z);
+  dY[14] = v3(2.0f * kY3e * x * z, -2.0f * kY3e * y * z, kY3e * (xx - yy));
+  dY[15] = v3(kY3a * (3.0f * xx - 3.0f * yy), -6.0f * kY3a * x * y, 0.f);
+}
+
+// Everything the forward computes for one item, kept for the backward.
+struct Geo {
+  float tx, ty, tz, inv_tz;
+  float ux, uy, uxc, uyc;
+  bool clamp_x, clamp_y;
+  float a0, a1;        // fx / tz, fy / tz
+  V3 T0, T1;           // rows of J W
+  float qn[4], qlen;
+  float Rq[3][3];
+  float s[3];
+  V3 r0, r1;           // rows of T M
+  float ra, rb, rc;    // raw 2D covariance
+  V3 c;                // r0 x r1
+  float D;             // |c|^2 = det of the raw covariance
+  float det;           // det of the dilated covariance
+  float conic[3];
+  V3 ux_, uy_;         // r1 x c, c x r0
+  V3 vx, vy;           // M ux_ / D, M uy_ / D
+  float M[3][3];
+};
+
+__device__ __forceinline__ float depth_key(const float* R, const float* t, float x, float y, float z) {
+  return __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(R[6], x), __fmul_rn(R[7], y)), __fmul_rn(R[8], z)), t[2]);
+}
+
+// Geometry of one item; `tz` is the fp32 depth key.
+__device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my, float mz, float tz,
+                                         const float* q, const float* s, Geo& g) {
+  const float* R = V.R;
+  g.tx = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
+  g.ty = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
+  g.tz = tz;
+  g.inv_tz = 1.0f / tz;
+  const float Wf = (float)V.width, Hf = (float)V.height;
+  const float lox = (-0.15f * Wf - V.cx) / V.fx, hix = (1.15f * Wf - V.cx) / V.fx;
+  const float loy = (-0.15f * Hf - V.cy) / V.fy, hiy = (1.15f * Hf - V.cy) / V.fy;
+  g.ux = g.tx * g.inv_tz;
+  g.uy = g.ty * g.inv_tz;
+  g.clamp_x = !(g.ux > lox && g.ux < hix);
+  g.clamp_y = !(g.uy > loy && g.uy < hiy);
+  g.uxc = fminf(fmaxf(g.ux, lox), hix);
+  g.uyc = fminf(fmaxf(g.uy, loy), hiy);
+  g.a0 = V.fx * g.inv_tz;
+  g.a1 = V.fy * g.inv_tz;
+  g.T0 = v3(g.a0 * (R[0] - g.uxc * R[6]), g.a0 * (R[1] - g.uxc * R[7]), g.a0 * (R[2] - g.uxc * R[8]));
+  g.T1 = v3(g.a1 * (R[3] - g.uyc * R[6]), g.a1 * (R[4] - g.uyc * R[7]), g.a1 * (R[5] - g.uyc * R[8]));
+
+  const float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  g.qlen = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float iq = 1.0f / g.qlen;
+  const float w = qw * iq, x = qx * iq, y = qy * iq, z = qz * iq;
+  g.qn[0] = w; g.qn[1] = x; g.qn[2] = y; g.qn[3] = z;
+  g.Rq[0][0] = 1.f - 2.f * (y * y + z * z);
+  g.Rq[0][1] = 2.f * (x * y - w * z);
+  g.Rq[0][2] = 2.f * (x * z + w * y);
+  g.Rq[1][0] = 2.f * (x * y + w * z);
+  g.Rq[1][1] = 1.f - 2.f * (x * x + z * z);
+  g.Rq[1][2] = 2.f * (y * z - w * x);
+  g.Rq[2][0] = 2.f * (x * z - w * y);
+  g.Rq[2][1] = 2.f * (y * z + w * x);
+  g.Rq[2][2] = 1.f - 2.f * (x * x + y * y);
+  g.s[0] = s[0]; g.s[1] = s[1]; g.s[2] = s[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g.M[i][j] = g.Rq[i][j] * s[j];
+  const float T0a[3] = {g.T0.x, g.T0.y, g.T0.z}, T1a[3] = {g.T1.x, g.T1.y, g.T1.z};
+  float r0[3], r1[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    r0[j] = T0a[0] * g.M[0][j] + T0a[1] * g.M[1][j] + T0a[2] * g.M[2][j];
+    r1[j] = T1a[0] * g.M[0][j] + T1a[1] * g.M[1][j] + T1a[2] * g.M[2][j];
+  }
+  g.r0 = v3(r0[0], r0[1], r0[2]);
+  g.r1 = v3(r1[0], r1[1], r1[2]);
+  g.ra = dot3(g.r0, g.r0);
+  g.rb = dot3(g.r0, g.r1);
+  g.rc = dot3(g.r1, g.r1);
+  g.c = cross3(g.r0, g.r1);
+  g.D = dot3(g.c, g.c);
+  g.det = g.D + kDilation * (g.ra + g.rc) + kDilation * kDilation;
+  const float idet = 1.0f / g.det;
+  g.conic[0] = (g.rc + kDilation) * idet;
+  g.conic[1] = -g.rb * idet;
+  g.conic[2] = (g.ra + kDilation) * idet;
+  g.ux_ = cross3(g.r1, g.c);
+  g.uy_ = cross3(g.c, g.r0);
+  if (g.D > 0.f) {
+    const float iD = 1.0f / g.D;
+    g.vx = v3((g.M[0][0] * g.ux_.x + g.M[0][1] * g.ux_.y + g.M[0][2] * g.ux_.z) * iD,
+              (g.M[1][0] * g.ux_.x + g.M[1][1] * g.ux_.y + g.M[1][2] * g.ux_.z) * iD,
+              (g.M[2][0] * g.ux_.x + g.M[2][1] * g.ux_.y + g.M[2][2] * g.ux_.z) * iD);
+    g.vy = v3((g.M[0][0] * g.uy_.x + g.M[0][1] * g.uy_.y + g.M[0][2] * g.uy_.z) * iD,
+              (g.M[1][0] * g.uy_.x + g.M[1][1] * g.uy_.y + g.M[1][2] * g.uy_.z) * iD,
+              (g.M[2][0] * g.uy_.x + g.M[2][1] * g.uy_.y + g.M[2][2] * g.uy_.z) * iD);
+  } else {
+    g.vx = v3(0.f, 0.f, 0.f);
+    g.vy = v3(0.f, 0.f, 0.f);
+  }
+}
+
+// ------------------------------------------------------------------ K1
+template <int K>
+__global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ table,
+                                                    float* __restrict__ rec,
+                                                    float* __restrict__ depth_out,
+                                                    uint32_t* __restrict__ rect_out,
+                                                    uint32_t* __restrict__ tiles_out) {
+  constexpr int RF = (10 + 3 * K + 3) & ~3;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry& V = table_views(table)[blockIdx.y];
+  const SceneEntry& S = table_scenes(table, hdr->num_views)[V.scene];
+  const int64_t n = S.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t item = V.item_offset + i;
+
+  const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+  const float tz = depth_key(V.R, V.t, mx, my, mz);
+  depth_out[item] = tz;
+  const float o = S.opac[i];
+  bool ok = (tz > V.near_plane) && (o * 255.0f > 1.0f);
+  uint2 rect = make_uint2(0u, 0u);
+  uint32_t ntiles = 0;
+  if (ok) {
+    const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
+    const float s[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+    Geo g;
+    geometry(V, mx, my, mz, tz, q, s, g);
+    const float mux = fmaf(V.fx * g.tx, g.inv_tz, V.cx);
+    const float muy = fmaf(V.fy * g.ty, g.inv_tz, V.cy);
+    // exact support of o G >= 1/255: d^T C d <= 2 ln(255 o)
+    const float kk = sqrtf(2.0f * kLn2 * log2f(255.0f * o));
+    const float rx = kk * sqrtf(g.ra + kDilation), ry = kk * sqrtf(g.rc + kDilation);
+    const float px0 = fmaxf(ceilf(mux - rx - 0.5f), 0.0f);
+    const float px1 = fminf(floorf(mux + rx - 0.5f), (float)(V.width - 1));
+    const float py0 = fmaxf(ceilf(muy - ry - 0.5f), 0.0f);
+    const float py1 = fminf(floorf(muy + ry - 0.5f), (float)(V.height - 1));
+    ok = (g.det > 0.f) && (px0 <= px1) && (py0 <= py1);
+    if (ok) {
+      const uint32_t x0 = (uint32_t)px0 >> 4, x1 = ((uint32_t)px1 >> 4) + 1;
+      const uint32_t y0 = (uint32_t)py0 >> 4, y1 = ((uint32_t)py1 >> 4) + 1;
+      rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+      ntiles = (x1 - x0) * (y1 - y0);
+      float r[RF];
+      r[0] = mux;
+      r[1] = muy;
+      r[2] = -0.5f * kLog2e * g.conic[0];
+      r[3] = -kLog2e * g.conic[1];
+      r[4] = -0.5f * kLog2e * g.conic[2];
+      r[5] = log2f(o);
+      // colour
+      if (S.sh_degree >= 0) {
+        const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
+        const float il = 1.0f / sqrtf(dot3(d, d));
+        float Y[16];
+        const int deg = S.sh_degree;
+        sh_basis(d.x * il, d.y * il, d.z * il, deg, Y);
+        const int nd = (deg + 1) * (deg + 1);
+        float col[3] = {0.5f, 0.5f, 0.5f};
+        for (int b = 0; b < nd; ++b) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+        }
+        r[6] = fmaxf(col[0], 0.f);
+        r[7] = fmaxf(col[1], 0.f);
+        r[8] = fmaxf(col[2], 0.f);
+      } else {
+        r[6] = S.colors[i];
+        r[7] = S.colors[n + i];
+        r[8] = S.colors[2 * n + i];
+      }
+      float wsum = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
+                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
+        const float w = S.weights[(int64_t)k * n + i];
+        r[10 + 3 * k] = dot3(g.vx, f);
+        r[11 + 3 * k] = dot3(g.vy, f);
+        r[12 + 3 * k] = w;
+        wsum += w;
+      }
+      r[9] = 1.0f - wsum;
+#pragma unroll
+      for (int j = 10 + 3 * K; j < RF; ++j) r[j] = 0.f;
+      float4* dst = reinterpret_cast<float4*>(rec + item * RF);
+#pragma unroll
+      for (int j = 0; j < RF / 4; ++j) dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
+    }
+  }
+  reinterpret_cast<uint2*>(rect_out)[item] = rect;
+  tiles_out[item] = ntiles;
+}
+
+// ------------------------------------------------------------------ K8
+// One thread per primitive of scene `scene_index`; loops over that scene's
+// views (deterministic accumulation across views, no atomics).
+template <int K>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
+                                                        const uint32_t* __restrict__ tiles,
+                                                        const float* __restrict__ depth,
+                                                        const float* __restrict__ grad2d,
+                                                        gabsplat_scene_grads gr,
+                                                        const int32_t* __restrict__ d_overflow) {
+  constexpr int GF = (9 + 3 * K + 3) & ~3;
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const int nv = hdr->num_views;
+  const ViewEntry* views = table_views(table);
+  const SceneEntry& S = table_scenes(table, nv)[scene_index];
+  const int64_t n = S.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+
+  const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+  const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
+  const float s[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+  const float o = S.opac[i];
+  const int deg = S.sh_degree;
+  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+
+  V3 gmean = v3(0.f, 0.f, 0.f);
+  float gs[3] = {0.f, 0.f, 0.f};
+  float gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float go = 0.f;
+  float gcol[3] = {0.f, 0.f, 0.f};
+  float gsh[48];
+  for (int b = 0; b < 48; ++b) gsh[b] = 0.f;
+  V3 gf[K > 0 ? K : 1];
+  float gw[K > 0 ? K : 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    gf[k] = v3(0.f, 0.f, 0.f);
+    gw[k] = 0.f;
+  }
+  bool any = false;
+
+  for (int v = 0; v < nv; ++v) {
+    const ViewEntry& V = views[v];
+    if (V.scene != scene_index) continue;
+    const int64_t item = V.item_offset + i;
+    if (tiles[item] == 0) continue;
+    any = true;
+    const float* g2 = grad2d + item * GF;
+    float G2[GF];
+#pragma unroll
+    for (int j = 0; j < GF / 4; ++j) {
+      const float4 t4 = reinterpret_cast<const float4*>(g2)[j];
+      G2[4 * j] = t4.x; G2[4 * j + 1] = t4.y; G2[4 * j + 2] = t4.z; G2[4 * j + 3] = t4.w;
+    }
+    Geo g;
+    geometry(V, mx, my, mz, depth[item], q, s, g);
+
+    // ---- opacity: rec[5] = log2(o)
+    go += G2[5] / (o * kLn2);
+
+    // ---- conic record terms -> dilated covariance (a, b, c)
+    const float dQ00 = -0.5f * kLog2e * G2[2];
+    const float dQ01 = -kLog2e * G2[3];
+    const float dQ11 = -0.5f * kLog2e * G2[4];
+    const float ca = g.ra + kDilation, cb = g.rb, cc = g.rc + kDilation;
+    const float id2 = 1.0f / (g.det * g.det);
+    const float dra = (-cc * cc * dQ00 + cb * cc * dQ01 - cb * cb * dQ11) * id2;
+    const float drc = (-cb * cb * dQ00 + ca * cb * dQ01 - ca * ca * dQ11) * id2;
+    const float drb = (2.f * cb * cc * dQ00 - (ca * cc + cb * cb) * dQ01 + 2.f * ca * cb * dQ11) * id2;
+    V3 gr0 = add3(scale3(g.r0, 2.f * dra), scale3(g.r1, drb));
+    V3 gr1 = add3(scale3(g.r1, 2.f * drc), scale3(g.r0, drb));
+    float gM[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gM[a][b] = 0.f;
+
+    // ---- 2D frequencies f2d_k = (vx . f_k, vy . f_k)
+    if (K > 0 && g.D > 0.f) {
+      V3 gvx = v3(0.f, 0.f, 0.f), gvy = v3(0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
+                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
+        const float gx = G2[9 + 3 * k], gy = G2[10 + 3 * k];
+        gvx = add3(gvx, scale3(f, gx));
+        gvy = add3(gvy, scale3(f, gy));
+        gf[k] = add3(gf[k], add3(scale3(g.vx, gx), scale3(g.vy, gy)));
+        gw[k] += G2[11 + 3 * k];
+      }
+      const float iD = 1.0f / g.D;
+      const float gvxa[3] = {gvx.x, gvx.y, gvx.z}, gvya[3] = {gvy.x, gvy.y, gvy.z};
+      const float uxa[3] = {g.ux_.x, g.ux_.y, g.ux_.z}, uya[3] = {g.uy_.x, g.uy_.y, g.uy_.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gM[a][b] += (gvxa[a] * uxa[b] + gvya[a] * uya[b]) * iD;
+      // M^T gvx / D, M^T gvy / D
+      V3 gux = v3((g.M[0][0] * gvx.x + g.M[1][0] * gvx.y + g.M[2][0] * gvx.z) * iD,
+                  (g.M[0][1] * gvx.x + g.M[1][1] * gvx.y + g.M[2][1] * gvx.z) * iD,
+                  (g.M[0][2] * gvx.x + g.M[1][2] * gvx.y + g.M[2][2] * gvx.z) * iD);
+      V3 guy = v3((g.M[0][0] * gvy.x + g.M[1][0] * gvy.y + g.M[2][0] * gvy.z) * iD,
+                  (g.M[0][1] * gvy.x + g.M[1][1] * gvy.y + g.M[2][1] * gvy.z) * iD,
+                  (g.M[0][2] * gvy.x + g.M[1][2] * gvy.y + g.M[2][2] * gvy.z) * iD);
+      const float gD = -(dot3(g.vx, gvx) + dot3(g.vy, gvy)) * iD;
+      // ux_ = r1 x c ; uy_ = c x r0 ; D = c.c ; c = r0 x r1
+      V3 gc = v3(0.f, 0.f, 0.f);
+      gr1 = add3(gr1, cross3(g.c, gux));
+      gc = add3(gc, cross3(gux, g.r1));
+      gc = add3(gc, cross3(g.r0, guy));
+      gr0 = add3(gr0, cross3(guy, g.c));
+      gc = add3(gc, scale3(g.c, 2.f * gD));
+      gr0 = add3(gr0, cross3(g.r1, gc));
+      gr1 = add3(gr1, cross3(gc, g.r0));
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) gw[k] += G2[11 + 3 * k];
+    }
+
+    // ---- A = T M: rows r0 = T0 M, r1 = T1 M
+    const float T0a[3] = {g.T0.x, g.T0.y, g.T0.z}, T1a[3] = {g.T1.x, g.T1.y, g.T1.z};
+    const float gr0a[3] = {gr0.x, gr0.y, gr0.z}, gr1a[3] = {gr1.x, gr1.y, gr1.z};
+    float gT0[3], gT1[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      gT0[l] = gr0a[0] * g.M[l][0] + gr0a[1] * g.M[l][1] + gr0a[2] * g.M[l][2];
+      gT1[l] = gr1a[0] * g.M[l][0] + gr1a[1] * g.M[l][1] + gr1a[2] * g.M[l][2];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gM[l][j] += T0a[l] * gr0a[j] + T1a[l] * gr1a[j];
+    }
+    // ---- M = Rq diag(s)
+    float gR[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gR[a][b] = gM[a][b] * s[b];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gs[b] += gM[0][b] * g.Rq[0][b] + gM[1][b] * g.Rq[1][b] + gM[2][b] * g.Rq[2][b];
+    {
+      const float w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+      float gqn[4];
+      gqn[0] = 2.f * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+      gqn[1] = 2.f * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - w * gR[1][2] + z * gR[2][0] + w * gR[2][1]) -
+               4.f * x * (gR[1][1] + gR[2][2]);
+      gqn[2] = 2.f * (x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0] + z * gR[2][1]) -
+               4.f * y * (gR[0][0] + gR[2][2]);
+      gqn[3] = 2.f * (-w * gR[0][1] + x * gR[0][2] + w * gR[1][0] + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]) -
+               4.f * z * (gR[0][0] + gR[1][1]);
+      const float pr = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
+      const float il = 1.0f / g.qlen;
+      gq[0] += (gqn[0] - w * pr) * il;
+      gq[1] += (gqn[1] - x * pr) * il;
+      gq[2] += (gqn[2] - y * pr) * il;
+      gq[3] += (gqn[3] - z * pr) * il;
+    }
+    // ---- T = J2 R (depends on t through tz and the clamped ratios)
+    const float* R = V.R;
+    float gtx = 0.f, gty = 0.f, gtz = 0.f;
+    {
+      const float ga0 = (gT0[0] * g.T0.x + gT0[1] * g.T0.y + gT0[2] * g.T0.z) / g.a0;
+      const float ga1 = (gT1[0] * g.T1.x + gT1[1] * g.T1.y + gT1[2] * g.T1.z) / g.a1;
+      const float guxc = -g.a0 * (gT0[0] * R[6] + gT0[1] * R[7] + gT0[2] * R[8]);
+      const float guyc = -g.a1 * (gT1[0] * R[6] + gT1[1] * R[7] + gT1[2] * R[8]);
+      gtz += -(ga0 * g.a0 + ga1 * g.a1) * g.inv_tz;
+      if (!g.clamp_x) {
+        gtx += guxc * g.inv_tz;
+        gtz += -guxc * g.ux * g.inv_tz;
+      }
+      if (!g.clamp_y) {
+        gty += guyc * g.inv_tz;
+        gtz += -guyc * g.uy * g.inv_tz;
+      }
+    }
+    // ---- mu2d = (fx tx / tz + cx, fy ty / tz + cy)
+    gtx += V.fx * g.inv_tz * G2[0];
+    gty += V.fy * g.inv_tz * G2[1];
+    gtz += -(V.fx * g.tx * G2[0] + V.fy * g.ty * G2[1]) * g.inv_tz * g.inv_tz;
+    // ---- t = R mu + t0
+    gmean = add3(gmean, v3(R[0] * gtx + R[3] * gty + R[6] * gtz, R[1] * gtx + R[4] * gty + R[7] * gtz,
+                           R[2] * gtx + R[5] * gty + R[8] * gtz));
+    // ---- colour
+    if (deg >= 0) {
+      const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
+      const float il = 1.0f / sqrtf(dot3(d, d));
+      const V3 dir = scale3(d, il);
+      float Y[16];
+      V3 dY[16];
+      sh_basis(dir.x, dir.y, dir.z, deg, Y);
+      sh_basis_grad(dir.x, dir.y, dir.z, deg, dY);
+      float col[3] = {0.5f, 0.5f, 0.5f};
+      for (int b = 0; b < nd; ++b)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+      float drgb[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) drgb[ch] = col[ch] < 0.f ? 0.f : G2[6 + ch];
+      V3 gdir = v3(0.f, 0.f, 0.f);
+      for (int b = 0; b < nd; ++b) {
+        float acc = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          gsh[b * 3 + ch] += Y[b] * drgb[ch];
+          acc += S.sh[(int64_t)(b * 3 + ch) * n + i] * drgb[ch];
+        }
+        gdir = add3(gdir, scale3(dY[b], acc));
+      }
+      const float pr = dot3(dir, gdir);
+      gmean = add3(gmean, scale3(add3(gdir, scale3(dir, -pr)), il));
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gcol[ch] += G2[6 + ch];
+    }
+  }
+  if (!any && gr.accumulate) return;
+  // accumulate: +=; otherwise overwrite (gradients of culled primitives are 0)
+  const bool acc = gr.accumulate != 0;
+  auto put = [acc](float* p, float v) { *p = acc ? *p + v : v; };
+  if (gr.means) {
+    put(&gr.means[i], gmean.x);
+    put(&gr.means[n + i], gmean.y);
+    put(&gr.means[2 * n + i], gmean.z);
+  }
+  if (gr.scales) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) put(&gr.scales[b * n + i], gs[b]);
+  }
+  if (gr.quats) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) put(&gr.quats[b * n + i], gq[b]);
+  }
+  if (gr.opacities) put(&gr.opacities[i], go);
+  if (deg >= 0) {
+    if (gr.sh)
+      for (int b = 0; b < nd * 3; ++b) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
+  } else if (gr.colors) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) put(&gr.colors[ch * n + i], gcol[ch]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (gr.freqs) {
+      put(&gr.freqs[(int64_t)(3 * k) * n + i], gf[k].x);
+      put(&gr.freqs[(int64_t)(3 * k + 1) * n + i], gf[k].y);
+      put(&gr.freqs[(int64_t)(3 * k + 2) * n + i], gf[k].z);
+    }
+    if (gr.weights) put(&gr.weights[(int64_t)k * n + i], gw[k]);
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <int K>
+static hipError_t pre_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, hipStream_t s) {
+  int64_t max_n = 0;
+  for (int v = 0; v < h.hdr.num_views; ++v) {
+    const int64_t n = h.scenes[h.views[v].scene].n;
+    if (n > max_n) max_n = n;
+  }
+  if (max_n == 0) return hipSuccess;
+  dim3 grid((unsigned)((max_n + 255) / 256), (unsigned)h.hdr.num_views);
+  hipLaunchKernelGGL(k_preprocess<K>, grid, dim3(256), 0, s, d_table, g.rec, g.depth, g.rect, g.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const void* d_table, const HostTable& h, const gabsplat_geom& g, hipStream_t s) {
+  switch (h.scenes[0].k) {
+    case 0: return pre_k<0>(d_table, h, g, s);
+    case 1: return pre_k<1>(d_table, h, g, s);
+    case 2: return pre_k<2>(d_table, h, g, s);
+    case 3: return pre_k<3>(d_table, h, g, s);
+    case 4: return pre_k<4>(d_table, h, g, s);
+    case 5: return pre_k<5>(d_table, h, g, s);
+    case 6: return pre_k<6>(d_table, h, g, s);
+    case 7: return pre_k<7>(d_table, h, g, s);
+    case 8: return pre_k<8>(d_table, h, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int K>
+static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, int sc,
+                         const gabsplat_scene_grads& gr, const int32_t* ov, hipStream_t s) {
+  const int64_t n = h.scenes[sc].n;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_preprocess_bwd<K>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_table, sc,
+                     g.tiles, g.depth, gr.grad2d, gr, ov);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int sc,
+                                 const gabsplat_scene_grads& gr, const int32_t* ov, hipStream_t s) {
+  switch (h.scenes[sc].k) {
+    case 0: return pbwd_k<0>(d_table, h, g, sc, gr, ov, s);
+    case 1: return pbwd_k<1>(d_table, h, g, sc, gr, ov, s);
+    case 2: return pbwd_k<2>(d_table, h, g, sc, gr, ov, s);
+    case 3: return pbwd_k<3>(d_table, h, g, sc, gr, ov, s);
+    case 4: return pbwd_k<4>(d_table, h, g, sc, gr, ov, s);
+    case 5: return pbwd_k<5>(d_table, h, g, sc, gr, ov, s);
+    case 6: return pbwd_k<6>(d_table, h, g, sc, gr, ov, s);
+    case 7: return pbwd_k<7>(d_table, h, g, sc, gr, ov, s);
+    case 8: return pbwd_k<8>(d_table, h, g, sc, gr, ov, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gs

@@ -1,0 +1,366 @@
+// K6 (front-to-back Gabor alpha blending) and K7 (its backward).
+//
+// One 256-lane workgroup per 16x16 tile; wave w covers the 8x8 quadrant
+// (w & 1, w >> 1) of the tile so that a wave's pixels are spatially compact.
+// Batches of 256 render records are staged in LDS (one record per lane) and
+// every lane walks them in order.  Workgroups are mapped to tiles so that each
+// of the 8 XCDs (which receive workgroup ids round-robin) renders one
+// contiguous band of tiles and keeps its records in its own L2.
+//
+// The forward and the backward evaluate alpha with the same inline function
+// and only explicit fused multiply-adds (the library is built without FP
+// contraction), so the backward's skip decisions and its transmittance
+// recovery T_i = T_{i+1} / (1 - alpha_i) reproduce the forward bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
+  const int per = nb / kNumXcd, extra = nb % kNumXcd;
+  const int x = bid % kNumXcd, j = bid / kNumXcd;
+  return x * per + (x < extra ? x : extra) + j;
+}
+
+__device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv, int tile) {
+  int lo = 0, hi = nv - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_offset <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// cos(2 pi x) and sin(2 pi x); the hardware units take revolutions
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(x)); }
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(x)); }
+
+// Record field access (see gabsplat_geom.rec)
+template <int K>
+struct Rec {
+  static constexpr int RF = (10 + 3 * K + 3) & ~3;
+};
+
+// Envelope exponent q + log2 o for offset (dx, dy).
+__device__ __forceinline__ float rec_power(const float* r, float dx, float dy) {
+  const float t1 = fmaf(r[2], dx, r[3] * dy);
+  return fmaf(t1, dx, fmaf(r[4] * dy, dy, r[5]));
+}
+
+// Gabor modulation B = w0 + sum_k w_k cos(2 pi (f_k . d)).
+template <int K>
+__device__ __forceinline__ float rec_modulation(const float* r, float dx, float dy) {
+  float b = r[9];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float ph = fmaf(r[10 + 3 * k], dx, r[11 + 3 * k] * dy);
+    b = fmaf(r[12 + 3 * k], cos_rev(ph), b);
+  }
+  return b;
+}
+
+// --------------------------------------------------------------------- K6
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ table,
+                                                       const float* __restrict__ rec,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ranges,
+                                                       float* __restrict__ image, float* __restrict__ final_T,
+                                                       uint32_t* __restrict__ n_contrib,
+                                                       const int32_t* __restrict__ d_overflow) {
+  constexpr int RF = Rec<K>::RF;
+  __shared__ float4 s_rec[kBlock * (RF / 4)];
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry* views = table_views(table);
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const ViewEntry& V = views[find_view_by_tile(views, hdr->num_views, tile)];
+  const int lt = tile - V.tile_offset;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int px = tx * kTile + (w & 1) * 8 + (l & 7);
+  const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+  const bool inside = px < V.width && py < V.height;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
+
+  float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (uint32_t b = start; b < end; b += kBlock) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t idx = b + t;
+    if (idx < end) {
+      const float4* src = reinterpret_cast<const float4*>(rec + (size_t)vals[idx] * RF);
+#pragma unroll
+      for (int j = 0; j < RF / 4; ++j) s_rec[t * (RF / 4) + j] = src[j];
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kBlock, end - b);
+    if (!done) {
+      for (int j = 0; j < cnt; ++j) {
+        float r[RF];
+#pragma unroll
+        for (int q = 0; q < RF / 4; ++q) {
+          const float4 v = s_rec[j * (RF / 4) + q];
+          r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
+        }
+        const float dx = fx - r[0], dy = fy - r[1];
+        const float pw = rec_power(r, dx, dy);
+        if (pw < kLog2AlphaMin) continue;  // o G < 1/255 and B <= 1: alpha < 1/255
+        const float E = exp2f(pw);
+        const float Bv = rec_modulation<K>(r, dx, dy);
+        const float alpha = fminf(kAlphaMax, E * Bv);
+        if (alpha < kAlphaMin) continue;
+        const float Tn = T * (1.0f - alpha);
+        if (Tn < kTMin) {
+          done = true;
+          break;
+        }
+        const float wt = alpha * T;
+        C0 = fmaf(r[6], wt, C0);
+        C1 = fmaf(r[7], wt, C1);
+        C2 = fmaf(r[8], wt, C2);
+        T = Tn;
+        last = b - start + (uint32_t)j + 1;
+      }
+    }
+  }
+  if (inside) {
+    const size_t hw = (size_t)V.width * V.height;
+    const size_t pix = (size_t)py * V.width + px;
+    float* img = image + 3 * (size_t)V.pixel_offset;
+    img[pix] = fmaf(T, V.bg[0], C0);
+    img[hw + pix] = fmaf(T, V.bg[1], C1);
+    img[2 * hw + pix] = fmaf(T, V.bg[2], C2);
+    final_T[V.pixel_offset + pix] = T;
+    n_contrib[V.pixel_offset + pix] = last;
+  }
+}
+
+// ------------------------------------------------- wave reduce-scatter-add
+// Sums v[0..NP) over the 64 lanes by recursive halving (each stage ships half
+// of the remaining vector to the partner lane), then lane l holds the total of
+// component l >> (6 - log2 NP); one lane per component adds it to dst.
+template <int NP>
+__device__ __forceinline__ void wave_reduce_add(float (&v)[NP], float* dst, int ncomp) {
+  const int l = __lane_id();
+  constexpr int LOGNP = (NP == 64) ? 6 : (NP == 32) ? 5 : (NP == 16) ? 4 : 3;
+  int L = NP;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    if (L > 1) {
+      const bool upper = (l & d) != 0;
+#pragma unroll
+      for (int j = 0; j < NP / 2; ++j) {
+        if (j < L / 2) {
+          const float a = v[j], b = v[j + L / 2];
+          const float send = upper ? a : b;
+          const float keep = upper ? b : a;
+          v[j] = keep + __shfl_xor(send, d, 64);
+        }
+      }
+      L >>= 1;
+    } else {
+      v[0] += __shfl_xor(v[0], d, 64);
+    }
+  }
+  constexpr int SH = 6 - LOGNP;
+  const int comp = l >> SH;
+  if ((l & ((1 << SH) - 1)) == 0 && comp < ncomp) atomicAdd(dst + comp, v[0]);
+}
+
+// --------------------------------------------------------------------- K7
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ table,
+                                                       const float* __restrict__ rec,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ranges,
+                                                       const float* __restrict__ final_T,
+                                                       const uint32_t* __restrict__ n_contrib,
+                                                       const float* __restrict__ dl_dimage,
+                                                       float* __restrict__ grad2d,
+                                                       const int32_t* __restrict__ d_overflow) {
+  constexpr int RF = Rec<K>::RF;
+  constexpr int GS = 9 + 3 * K;            // gradient components per pair
+  constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
+  constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
+  __shared__ float4 s_rec[kBlock * (RF / 4)];
+  __shared__ uint32_t s_id[kBlock];
+  __shared__ uint32_t s_max;
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry* views = table_views(table);
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const ViewEntry& V = views[find_view_by_tile(views, hdr->num_views, tile)];
+  const int lt = tile - V.tile_offset;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int px = tx * kTile + (w & 1) * 8 + (l & 7);
+  const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+  const bool inside = px < V.width && py < V.height;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t start = ranges[2 * (size_t)tile];
+
+  float T = 1.0f, Tf = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  uint32_t last = 0;
+  if (inside) {
+    const size_t hw = (size_t)V.width * V.height;
+    const size_t pix = (size_t)py * V.width + px;
+    Tf = final_T[V.pixel_offset + pix];
+    last = n_contrib[V.pixel_offset + pix];
+    const float* g = dl_dimage + 3 * (size_t)V.pixel_offset;
+    dC0 = g[pix];
+    dC1 = g[hw + pix];
+    dC2 = g[2 * hw + pix];
+  }
+  T = Tf;
+  const float bgdot = V.bg[0] * dC0 + V.bg[1] * dC1 + V.bg[2] * dC2;
+  if (t == 0) s_max = 0;
+  __syncthreads();
+  if (last) atomicMax(&s_max, last);
+  __syncthreads();
+  const uint32_t maxlast = s_max;
+
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, la = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
+  for (uint32_t hi = maxlast; hi > 0;) {
+    const uint32_t lo = hi > (uint32_t)kBlock ? hi - kBlock : 0u;
+    const uint32_t cnt = hi - lo;
+    __syncthreads();
+    if ((uint32_t)t < cnt) {
+      const uint32_t gid = vals[start + lo + t];
+      s_id[t] = gid;
+      const float4* src = reinterpret_cast<const float4*>(rec + (size_t)gid * RF);
+#pragma unroll
+      for (int j = 0; j < RF / 4; ++j) s_rec[t * (RF / 4) + j] = src[j];
+    }
+    __syncthreads();
+    for (int j = (int)cnt - 1; j >= 0; --j) {
+      const uint32_t pos = lo + (uint32_t)j + 1;
+      float r[RF];
+#pragma unroll
+      for (int q = 0; q < RF / 4; ++q) {
+        const float4 v = s_rec[j * (RF / 4) + q];
+        r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
+      }
+      const float dx = fx - r[0], dy = fy - r[1];
+      bool contrib = inside && pos <= last;
+      float pw = 0.f, E = 0.f, Bv = 0.f, alpha = 0.f;
+      if (contrib) {
+        pw = rec_power(r, dx, dy);
+        contrib = !(pw < kLog2AlphaMin);
+      }
+      if (contrib) {
+        E = exp2f(pw);
+        Bv = rec_modulation<K>(r, dx, dy);
+        alpha = fminf(kAlphaMax, E * Bv);
+        contrib = !(alpha < kAlphaMin);
+      }
+      if (__ballot(contrib) == 0ull) continue;
+      float gv[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) gv[q] = 0.f;
+      if (contrib) {
+        const float om = 1.0f - alpha;
+        T = T / om;
+        const float wt = alpha * T;
+        gv[6] = wt * dC0;
+        gv[7] = wt * dC1;
+        gv[8] = wt * dC2;
+        acc0 = fmaf(la, lc0, (1.0f - la) * acc0);
+        acc1 = fmaf(la, lc1, (1.0f - la) * acc1);
+        acc2 = fmaf(la, lc2, (1.0f - la) * acc2);
+        lc0 = r[6]; lc1 = r[7]; lc2 = r[8];
+        la = alpha;
+        float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
+        da = da * T - Tf * bgdot / om;
+        if (E * Bv > kAlphaMax) da = 0.f;  // clamp binds: zero derivative
+        const float dE = da * Bv, dB = da * E;
+        const float dp = dE * E * kLn2;
+        gv[2] = dp * dx * dx;
+        gv[3] = dp * dx * dy;
+        gv[4] = dp * dy * dy;
+        gv[5] = dp;
+        float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
+        float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float fkx = r[10 + 3 * k], fky = r[11 + 3 * k], wk = r[12 + 3 * k];
+          const float ph = fmaf(fkx, dx, fky * dy);
+          const float cs = cos_rev(ph), sn = sin_rev(ph);
+          gv[11 + 3 * k] = dB * (cs - 1.0f);
+          const float dph = -dB * wk * 6.283185307179586f * sn;
+          gv[9 + 3 * k] = dph * dx;
+          gv[10 + 3 * k] = dph * dy;
+          ddx = fmaf(dph, fkx, ddx);
+          ddy = fmaf(dph, fky, ddy);
+        }
+        gv[0] = -ddx;
+        gv[1] = -ddy;
+      }
+      wave_reduce_add<NP>(gv, grad2d + (size_t)s_id[j] * GF, GS);
+    }
+    hi = lo;
+  }
+}
+
+// --------------------------------------------------------------- launchers
+template <int K>
+static hipError_t fwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, const uint32_t* vals,
+                        const uint32_t* ranges, float* image, float* final_T, uint32_t* n_contrib,
+                        const int32_t* ov, hipStream_t s) {
+  if (h.hdr.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_render_fwd<K>, dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table, g.rec, vals,
+                     ranges, image, final_T, n_contrib, ov);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int k,
+                             const uint32_t* vals, const uint32_t* ranges, float* image, float* final_T,
+                             uint32_t* n_contrib, const int32_t* ov, hipStream_t s) {
+  switch (k) {
+    case 0: return fwd_k<0>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 1: return fwd_k<1>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 2: return fwd_k<2>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 3: return fwd_k<3>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 4: return fwd_k<4>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 5: return fwd_k<5>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 6: return fwd_k<6>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 7: return fwd_k<7>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+    case 8: return fwd_k<8>(d_table, h, g, vals, ranges, image, final_T, n_contrib, ov, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int K>
+static hipError_t bwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, const uint32_t* vals,
+                        const uint32_t* ranges, const float* final_T, const uint32_t* n_contrib,
+                        const float* dl, float* grad2d, const int32_t* ov, hipStream_t s) {
+  if (h.hdr.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_render_bwd<K>, dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table, g.rec, vals,
+                     ranges, final_T, n_contrib, dl, grad2d, ov);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int k,
+                             const uint32_t* vals, const uint32_t* ranges, const float* final_T,
+                             const uint32_t* n_contrib, const float* dl, float* grad2d, const int32_t* ov,
+                             hipStream_t s) {
+  switch (k) {
+    case 0: return bwd_k<0>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 1: return bwd_k<1>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 2: return bwd_k<2>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 3: return bwd_k<3>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 4: return bwd_k<4>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 5: return bwd_k<5>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 6: return bwd_k<6>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 7: return bwd_k<7>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 8: return bwd_k<8>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gs

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/gabsplat.h, and rejects invalid arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2508_05343_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2508_05343_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gabsplat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gabsplat_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported(L):
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_helpers(L):
+    assert L.gabsplat_abi_version() == 1
+    assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 16
+    assert L.gabsplat_record_floats(4) == 24 and L.gabsplat_record_floats(8) == 36
+    assert L.gabsplat_record_floats(9) == -1
+    assert L.gabsplat_grad2d_floats(4) == 24 and L.gabsplat_grad2d_floats(2) == 16
+    assert L.gabsplat_views_bytes(1, 1) > 0
+    small = L.gabsplat_bin_sort_workspace_size(1000, 10000, 64)
+    big = L.gabsplat_bin_sort_workspace_size(10 ** 6, 2 * 10 ** 7, 4346)
+    assert 0 < small < big
+    assert L.gabsplat_bin_sort_workspace_size(-1, 10, 10) == 0
+    assert L.gabsplat_loss_workspace_size(3, 840, 1297) >= 3 * 3 * 840 * 1297 * 4
+    for s in range(6):
+        assert L.lib().gabsplat_status_string(s)
+
+
+def test_invalid_arguments_are_rejected_on_the_host(L):
+    lib = L.lib()
+    g = L.Geom()
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy = 16, 16, 10.0, 10.0
+    sc = L.Scene()
+    sc.n, sc.k = 10, 9  # k above the limit
+    st = lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    sc.k = 2  # NULL attribute pointers with n > 0
+    st = lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    st = lib.gabsplat_preprocess(None, 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    bad = L.Camera()  # zero-sized image
+    st = lib.gabsplat_render_fwd(ctypes.byref(g), None, None, ctypes.byref(bad), 1, None, None, None, None, None)
+    assert st == L.INVALID_ARGUMENT
+    st = lib.gabsplat_bin_sort(ctypes.byref(g), ctypes.byref(cam), 1, 10, None, 0, None, None, 10, None, None,
+                               None, None)
+    assert st == L.INVALID_ARGUMENT
+    st = lib.gabsplat_loss_l1_dssim(None, None, 3, 4, 4, 0.2, None, None, None, 0, None)
+    assert st == L.INVALID_ARGUMENT
+    assert lib.gabsplat_read_overflow(None, None) == L.INVALID_ARGUMENT
+
+
+def test_missing_library_fails_loudly(L, monkeypatch):
+    monkeypatch.setattr(L, "_LIB", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libgabsplat.so")
+    with pytest.raises(L.GabsplatError):
+        L.lib()

@@ -1,0 +1,221 @@
+"""GPU forward parity: preprocess (K1), binning (K2-K5) and blend (K6) against
+the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gabor_oracle as O
+
+from gpu_helpers import compare_image, gpu_plan, last_ids_from_gpu, oracle_project, record_fields_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b, floor):
+    return np.abs(a - b) / (np.abs(b) + floor)
+
+
+def test_preprocess_matches_oracle_config1(gpu_lib):
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam])
+    plan.preprocess()
+    torch.cuda.synchronize()
+    pr = oracle_project(sc, cam)
+    depth = plan.depth.cpu().numpy()[:sc.n]
+    assert (depth.view(np.uint32) == pr.depth32.view(np.uint32)).all(), "depth keys must be bit-identical"
+    tiles = plan.tiles_touched.cpu().numpy()[:sc.n]
+    vis_g = tiles > 0
+    vis_o = pr.visible.numpy()
+    frag = pr.fragile_rect
+    assert ((vis_g == vis_o) | frag).all()
+    rect = plan.rect.cpu().numpy()[:sc.n].astype(np.int64)
+    x0, y0, x1, y1 = rect[:, 0] & 0xFFFF, rect[:, 0] >> 16, rect[:, 1] & 0xFFFF, rect[:, 1] >> 16
+    rg = np.stack([x0, y0, x1, y1], 1)
+    sel = vis_o & vis_g & ~frag
+    assert (rg[sel] == pr.rect[sel]).all()
+    f = record_fields_np(plan)
+    m = vis_o & vis_g & ~pr.fragile_prim
+    np.testing.assert_allclose(f["mu2d"][m], pr.mu2d.numpy()[m], rtol=1e-5, atol=1e-4)
+    con = pr.conic.numpy()[m]
+    scale = np.abs(con).max(1, keepdims=True)
+    assert (np.abs(f["conic"][m] - con) <= 1e-5 * scale + 1e-9).all()
+    np.testing.assert_allclose(f["rgb"][m], pr.rgb.numpy()[m], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(f["opacity"][m], pr.opac.numpy()[m], rtol=1e-5)
+    f2 = pr.f2d.numpy()[m]
+    fs = np.abs(f2).max(axis=(1, 2), keepdims=True) + 1e-6
+    assert (np.abs(f["f2d"][m] - f2) <= 1e-5 * fs).all(), np.abs(f["f2d"][m] - f2).max()
+
+
+def _write_synthetic_geom(plan, rect, depth, vis):
+    r = torch.zeros((plan.items, 2), dtype=torch.int64)
+    rr = torch.from_numpy(rect.astype(np.int64))
+    r[:, 0] = rr[:, 0] | (rr[:, 1] << 16)
+    r[:, 1] = rr[:, 2] | (rr[:, 3] << 16)
+    plan.rect.copy_(r.to(torch.int32).cuda())
+    plan.depth.copy_(torch.from_numpy(depth).cuda())
+    t = np.where(vis, (rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1]), 0).astype(np.int32)
+    plan.tiles_touched.copy_(torch.from_numpy(t).cuda())
+
+
+@pytest.mark.parametrize("n,views,seed", [(3000, 1, 1), (20000, 2, 2), (1, 1, 3), (9000, 3, 4)])
+def test_bin_sort_bit_exact_on_synthetic_geometry(gpu_lib, n, views, seed):
+    """Stage-isolated K2-K5: seeded synthetic rects/depths (with ties) go into
+    the GPU bin sort and the oracle's library stable sort; keys, values and
+    ranges must be identical."""
+    sc = synth.uniform_scene(seed, n, 1)
+    cams = [synth.pinhole_camera(200 + 37 * v, 150 + 11 * v, 60.0, (0, 0, -3), (0, 0, 0)) for v in range(views)]
+    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * views)
+    plan.preprocess()  # writes the view table
+    rects, depths, viss = [], [], []
+    for v, c in enumerate(cams):
+        r, d, vi = synth.random_geom(100 * seed + v, n, c.tiles_x, c.tiles_y)
+        rects.append(r); depths.append(d); viss.append(vi)
+    rect, depth, vis = np.concatenate(rects), np.concatenate(depths), np.concatenate(viss)
+    _write_synthetic_geom(plan, rect, depth, vis)
+    plan.bin_sort()
+    torch.cuda.synchronize()
+    P = int(plan.num_pairs.item())
+    assert int(plan.overflow.item()) == 0
+    keys_o, vals_o, ranges_o = [], [], []
+    for v, c in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        k, vv, rg = O.bin_sort(rect[sl], depth[sl], vis[sl], c.tiles_x, c.num_tiles,
+                               tile_offset=plan.layout[v].tile_offset, index_offset=v * n)
+        keys_o.append(k); vals_o.append(vv); ranges_o.append(rg + (sum(len(x) for x in keys_o[:-1])) * (rg[:, 1:] > 0))
+    keys_o = np.concatenate(keys_o)
+    vals_o = np.concatenate(vals_o)
+    assert P == len(keys_o)
+    kg = plan.keys.cpu().numpy()[:P].view(np.uint64)
+    vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
+    assert (kg == keys_o).all()
+    assert (vg == vals_o).all()
+    rg = plan.ranges.cpu().numpy().view(np.uint32)
+    # global ranges: recompute from the oracle's global key order
+    tl = (keys_o >> np.uint64(32)).astype(np.int64)
+    exp = np.zeros((plan.tiles, 2), np.uint32)
+    for t_ in np.unique(tl):
+        idx = np.nonzero(tl == t_)[0]
+        exp[t_] = (idx[0], idx[-1] + 1)
+    assert (rg[:plan.tiles] == exp).all()
+
+
+def test_bin_sort_end_to_end_config1(gpu_lib):
+    """K1 + K2-K5 on config 1: the GPU's sorted keys equal the oracle's
+    (no primitive of this scene sits within the rect tolerance of a tile
+    boundary, so the comparison is exact)."""
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam])
+    plan.preprocess()
+    plan.bin_sort()
+    torch.cuda.synchronize()
+    pr = oracle_project(sc, cam)
+    keys_o, vals_o, ranges_o = O.bin_sort(pr.rect, pr.depth32, pr.visible.numpy(), cam.tiles_x, cam.num_tiles)
+    P = int(plan.num_pairs.item())
+    kg = plan.keys.cpu().numpy()[:P].view(np.uint64)
+    vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
+    if pr.fragile_rect.any():
+        bad = set(np.nonzero(pr.fragile_rect)[0].tolist())
+        keep_o = np.array([int(v) not in bad for v in vals_o])
+        keep_g = np.array([int(v) not in bad for v in vg])
+        kg, vg, keys_o, vals_o = kg[keep_g], vg[keep_g], keys_o[keep_o], vals_o[keep_o]
+    else:
+        assert (plan.ranges.cpu().numpy().view(np.uint32)[:cam.num_tiles] == ranges_o).all()
+    assert (kg == keys_o).all() and (vg == vals_o).all()
+
+
+def test_render_forward_config1(gpu_lib):
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    torch.cuda.synchronize()
+    ref = O.render_scene(sc, cam, "binned")
+    img = plan.view_image(0).cpu().numpy()
+    err, frag, nbad = compare_image(img, ref)
+    print(f"config1: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
+    assert nbad == 0 and err <= 1e-4
+    T = plan.view_final_T(0).cpu().numpy()
+    ok = ~ref.fragile
+    assert np.abs(T - ref.final_T.numpy())[ok].max() <= 1e-4
+    ids = last_ids_from_gpu(plan, 0)
+    assert (ids[ok] == ref.last_id[ok]).all()
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (1.0, 0.5, 0.25)])
+def test_render_forward_sh_and_background(gpu_lib, bg):
+    sc = synth.uniform_scene(31, 3000, 4, sh_degree=3, log_scale_mu=-3.3)
+    cam = synth.pinhole_camera(200, 136, 55.0, eye=(0.3, -0.2, -2.7), target=(0.0, 0.1, 0.0), bg=bg)
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    ref = O.render_scene(sc, cam, "binned")
+    err, frag, nbad = compare_image(plan.view_image(0).cpu().numpy(), ref)
+    print(f"sh3 K4: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
+    assert nbad == 0 and err <= 1e-4
+
+
+def test_render_forward_high_frequency(gpu_lib):
+    """Frequencies scaled so that |f2d| reaches ~0.5 cycles/px."""
+    sc = synth.uniform_scene(32, 2000, 3, sh_degree=-1, log_scale_mu=-2.8)
+    sc.freqs *= 12.0
+    cam = synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    pr = oracle_project(sc, cam)
+    print("max |f2d|", float(pr.f2d.norm(dim=-1).max()))
+    ref = O.render_scene(sc, cam, "binned")
+    err, frag, nbad = compare_image(plan.view_image(0).cpu().numpy(), ref)
+    print(f"high-f: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
+    assert nbad == 0 and err <= 1e-4
+
+
+def test_render_forward_multiview_ragged(gpu_lib):
+    """Several views of different (ragged, non-multiple-of-16) sizes in one
+    launch per stage; each equals its own single-view oracle render."""
+    sc = synth.uniform_scene(33, 1500, 2, sh_degree=1)
+    cams = [synth.pinhole_camera(97, 61, 60.0, (0.0, 0.0, -3.0), (0, 0, 0)),
+            synth.pinhole_camera(33, 130, 50.0, (1.0, 0.5, -2.5), (0, 0, 0), bg=(0.2, 0.2, 0.2)),
+            synth.pinhole_camera(1, 1, 60.0, (0.0, 0.0, -3.0), (0, 0, 0)),
+            synth.pinhole_camera(160, 17, 70.0, (-1.0, 0.0, -2.0), (0, 0, 0))]
+    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * len(cams))
+    plan.forward()
+    for v, c in enumerate(cams):
+        ref = O.render_scene(sc, c, "binned")
+        err, frag, nbad = compare_image(plan.view_image(v).cpu().numpy(), ref)
+        assert nbad == 0 and err <= 1e-4, (v, err, nbad)
+
+
+def test_render_forward_empty_and_culled(gpu_lib):
+    """All primitives behind the camera: background everywhere, no pairs."""
+    sc = synth.uniform_scene(34, 500, 2, sh_degree=-1)
+    sc.means[:, 2] = -5.0
+    cam = synth.pinhole_camera(40, 40, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0), bg=(0.3, 0.6, 0.9))
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    assert int(plan.num_pairs.item()) == 0
+    img = plan.view_image(0).cpu().numpy()
+    np.testing.assert_array_equal(img, np.broadcast_to(np.array([0.3, 0.6, 0.9], np.float32)[:, None, None], img.shape))
+    assert (plan.view_n_contrib(0).cpu().numpy() == 0).all()
+
+
+def test_forward_is_deterministic(gpu_lib):
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam])
+    a = plan.forward().clone()
+    b = plan.forward().clone()
+    assert torch.equal(a, b)
+
+
+def test_capacity_overflow_and_retry(gpu_lib):
+    """A pair capacity that is too small sets the device flag; the plan grows
+    its buffers and reaches the same image."""
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    ds, plan = gpu_plan(sc, [cam], capacity=100)
+    plan.preprocess()
+    plan.bin_sort()
+    torch.cuda.synchronize()
+    assert int(plan.overflow.item()) == 1
+    assert int(plan.num_pairs.item()) > 100
+    img = plan.forward().clone()
+    assert plan.capacity > 100
+    ds2, plan2 = gpu_plan(sc, [cam])
+    assert torch.equal(img, plan2.forward())

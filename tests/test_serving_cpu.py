@@ -1,0 +1,90 @@
+"""Scheduler logic of the serving loop, on the CPU with a fake executor."""
+import numpy as np
+import pytest
+
+import synth
+from paper_2508_05343_amd.serving import FakeExecutor, Job, Scheduler, scratch_bytes, serve
+
+
+class VClock:
+    """Virtual clock: every read advances time a little; sleep jumps."""
+
+    def __init__(self, dt=2e-4):
+        self.t, self.dt = 0.0, dt
+
+    def __call__(self):
+        self.t += self.dt
+        return self.t
+
+    def sleep(self, s):
+        self.t += s
+
+
+def trace(n=120, qps=400.0, seed=3, sizes=(1000, 5000, 20000)):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1 / qps, n))
+    res = [(64, 64), (128, 96), (256, 256)]
+    jobs = []
+    for i in range(n):
+        w, h = res[int(rng.integers(3))]
+        cam = synth.pinhole_camera(w, h, 60.0, (0, 0, -3), (0, 0, 0))
+        jobs.append(Job(i, int(rng.integers(len(sizes))), cam, float(t[i])))
+    return jobs, sizes
+
+
+def test_all_requests_complete_in_fifo_batches_within_budget():
+    jobs, sizes = trace()
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=2)
+    budget = 8 * scratch_bytes(20000, 256 * 256, 200000)
+    sch = Scheduler(sizes, budget, max_slots=16, max_batch=8, max_inflight=2)
+    st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
+    assert st.requests == len(jobs) and len(st.latencies_ms) == len(jobs)
+    assert st.max_bytes_in_use <= budget
+    assert sch.in_use == 0 and sch.slots_used == 0
+    order = [r for b in ex.submitted for r in b]
+    assert order == sorted(order), "admission is FIFO"
+    assert all(len(b) <= 8 for b in ex.submitted)
+    assert all(j.done_s >= j.arrival_s for j in jobs)
+    assert st.max_inflight_jobs <= 16
+
+
+def test_requests_arriving_during_a_batch_join_the_next_one():
+    jobs, sizes = trace(n=60, qps=5000.0)
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=1, fixed_s=0.01)
+    sch = Scheduler(sizes, 1 << 40, max_slots=64, max_batch=64, max_inflight=1)
+    serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
+    # with one stream busy for 10 ms, later arrivals accumulate into large batches
+    assert max(len(b) for b in ex.submitted) > 5
+    assert sum(len(b) for b in ex.submitted) == 60
+
+
+def test_small_budget_defers_but_never_overcommits():
+    jobs, sizes = trace(n=40)
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=4)
+    one = max(Scheduler(sizes, 1 << 40).job_bytes(j) for j in jobs)
+    sch = Scheduler(sizes, int(one * 1.5), max_slots=16, max_batch=16, max_inflight=4)
+    st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
+    assert st.requests == 40
+    assert st.max_bytes_in_use <= int(one * 1.5)
+    # the budget holds at most a couple of jobs: work is spread over many batches
+    assert st.batches >= 20
+
+
+def test_request_larger_than_budget_is_rejected():
+    jobs, sizes = trace(n=3)
+    clk = VClock()
+    sch = Scheduler(sizes, 1000)
+    with pytest.raises(ValueError):
+        serve(jobs, FakeExecutor(clk), sch, clock=clk, sleep=clk.sleep)
+
+
+def test_sequential_baseline_is_one_job_per_batch():
+    jobs, sizes = trace(n=30)
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=1)
+    sch = Scheduler(sizes, 1 << 40, max_slots=1, max_batch=1, max_inflight=1)
+    st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
+    assert all(len(b) == 1 for b in ex.submitted) and st.batches == 30
