@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles of the frame blended by the CPU oracle")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU baseline (for rocprofv3)")
+    ap.add_argument("--no-multiview", action="store_true", help="skip the 64-view training step")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-qps", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -63,6 +67,7 @@ def main():
         sys.exit(2)
     if args.profile:
         args.steps, args.warmup, args.no_cpu_baseline = min(args.steps, 5), min(args.warmup, 2), True
+        args.no_multiview, args.no_serve = True, True
 
     import numpy as np
     import torch
@@ -199,6 +204,16 @@ def main():
         out["train_step_ms"] = round(t0.elapsed_time(t1) / ts, 4)
         out["train_loss"] = round(float(lossb.loss.item()), 6)
 
+    # ---- multi-view training step: 64 views of 800x800, one launch per stage
+    if not args.no_multiview:
+        out["multiview"] = multiview_step(args, torch, synth, DeviceScene, RenderPlan, LossBuffers)
+        print(json.dumps({"progress": "multiview", **out["multiview"]}), file=sys.stderr, flush=True)
+
+    # ---- serving: continuous batching vs one request at a time
+    if not args.no_serve:
+        out["serve"] = serving_run(args, torch, synth)
+        print(json.dumps({"progress": "serve", **out["serve"]}), file=sys.stderr, flush=True)
+
     # ---- CPU oracle on a bounded sample of the same frame
     if not args.no_cpu_baseline:
         from oracle import gabor_oracle as O
@@ -222,6 +237,77 @@ def main():
                                          f"+ blend of {len(tiles)} seeded tiles of {cam.num_tiles} ({spix} px, "
                                          f"{t_blend:.1f} s)"}
     print(json.dumps(out))
+
+
+def multiview_step(args, torch, synth, DeviceScene, RenderPlan, LossBuffers):
+    """300k primitives, K=4, SH3, 64 cameras on an orbit at 800x800: forward
+    over all views (one launch per stage), loss over all views (one launch),
+    backward over all views with the gradients summed over views in fp32."""
+    scene = synth.config4_scene()
+    cams = synth.config4_cameras()
+    ds = DeviceScene.from_host(scene)
+    plan = RenderPlan([ds], cams, [0] * len(cams), pair_capacity=12 * scene.n * len(cams))
+    plan.forward(check_overflow=True)
+    torch.cuda.synchronize()
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    tgt = torch.cat([torch.from_numpy(synth.random_target(1004 + v, (3, H, W))) for v in range(V)]).cuda()
+    lossb = LossBuffers(3 * V, H, W)
+    grads = {n: torch.zeros_like(getattr(ds, n)) for n in
+             ("means", "scales", "quats", "opacities", "sh", "freqs", "weights")}
+    img = plan.image[:3 * V * H * W].view(3 * V, H, W)
+
+    def step():
+        plan.preprocess()
+        plan.bin_sort()
+        plan.render_fwd()
+        lossb(img, tgt)
+        plan.backward(lossb.grad.view(-1), [grads], accumulate=False)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    assert int(plan.overflow.item()) == 0
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "64 views x 800x800 fwd+loss+bwd, 300,000 primitives, K=4, SH3",
+            "step_ms": round(ms, 3), "views_per_s": round(V / (ms * 1e-3), 1),
+            "mpix_s": round(V * H * W / (ms * 1e-3) / 1e6, 1), "pairs": int(plan.num_pairs.item()),
+            "loss": round(float(lossb.loss.item()), 6)}
+
+
+def serving_run(args, torch, synth):
+    """8 resident scenes (100k..2M primitives), Poisson requests, random
+    cameras and resolutions; continuous batching vs one request at a time."""
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
+    scenes = synth.config5_scenes()
+    dss = [DeviceScene.from_host(s) for s in scenes]
+    reqs = synth.config5_requests(scenes, n_requests=args.serve_requests, qps=args.serve_qps)
+    sizes = [s.n for s in scenes]
+    budget = 6 << 30
+
+    def jobs():
+        return [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
+
+    # warm the kernels and the allocator with a few requests of every shape
+    warm = [Job(i, i % 8, r.camera, 0.0) for i, r in enumerate(reqs[:16])]
+    serve(warm, GpuExecutor(dss, 2), Scheduler(sizes, budget, max_slots=16, max_batch=16, max_inflight=2))
+    torch.cuda.synchronize()
+    res = {}
+    for mode, sch, ns in (("continuous", Scheduler(sizes, budget, max_slots=16, max_batch=16, max_inflight=2), 2),
+                          ("sequential", Scheduler(sizes, budget, max_slots=1, max_batch=1, max_inflight=1), 1)):
+        st = serve(jobs(), GpuExecutor(dss, ns), sch)
+        sm = st.summary()
+        res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
+    res["workload"] = (f"8 resident scenes ({sum(sizes)} primitives), {len(reqs)} Poisson requests at "
+                       f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB scratch budget")
+    return res
 
 
 if __name__ == "__main__":
