@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-sweep", type=str, default="1000,4000",
+                    help="extra arrival rates (QPS) run with 600 requests each to find saturation")
     return ap.parse_args()
 
 
@@ -179,6 +181,16 @@ def main():
                      "traffic": None, "dominant_stage": dom},
     }
 
+    # ---- calibration copy of known size for the HBM counters (profile runs)
+    if args.profile:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
+        del src, dst
+
     # ---- training step (forward + loss + backward)
     if not args.no_train:
         target = torch.from_numpy(synth.random_target(1003, (3, cam.height, cam.width))).to(dev)
@@ -307,6 +319,17 @@ def serving_run(args, torch, synth):
         res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
     res["workload"] = (f"8 resident scenes ({sum(sizes)} primitives), {len(reqs)} Poisson requests at "
                        f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB scratch budget")
+    sweep = []
+    for q in [float(x) for x in args.serve_sweep.split(",") if x]:
+        rq = synth.config5_requests(scenes, n_requests=600, qps=q, seed=1005 + int(q))
+        row = {"qps": q}
+        for mode, sch, ns in (("continuous", Scheduler(sizes, budget, max_slots=16, max_batch=16, max_inflight=2), 2),
+                              ("sequential", Scheduler(sizes, budget, max_slots=1, max_batch=1, max_inflight=1), 1)):
+            st = serve([Job(r.rid, r.scene, r.camera, r.arrival_s) for r in rq], GpuExecutor(dss, ns), sch)
+            sm = st.summary()
+            row[mode] = {k: round(sm[k], 3) for k in ("p50_ms", "p99_ms", "throughput_rps", "mpix_s")}
+        sweep.append(row)
+    res["sweep"] = sweep
     return res
 
 

@@ -17,8 +17,8 @@
 // Launch sequence (8 + tile-pass launches): clear the workspace head;
 // compaction of the visible items fused with the depth-digit histograms; 4
 // depth passes; expansion = tiles-touched scan fused with load-balanced pair
-// emission and the tile-digit histograms; the tile passes; per-tile ranges by
-// binary search (so the range array needs no clearing).
+// emission and the tile-digit histograms; the tile passes; per-tile ranges from
+// the boundaries between runs of equal tile keys.
 #include <hip/hip_runtime.h>
 
 #include "gs_internal.h"
@@ -86,27 +86,39 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
   return off + inc - v;
 }
 
-// Decoupled look-back on a single-value status array; returns the exclusive
-// prefix of partition `part` and publishes its inclusive value.
-__device__ __forceinline__ uint32_t lookback_single(uint32_t* look, uint32_t part, uint32_t aggregate) {
-  uint32_t excl = 0;
+// Decoupled look-back on a single-value status array, run by one whole wave:
+// each step reads the status words of 64 predecessors at once (one load per
+// lane), so a walk over p predecessors takes ceil(p / 64) memory round trips
+// instead of p.  Returns the exclusive prefix of partition `part` (to every
+// lane) after publishing its inclusive value.  Must be called by all 64 lanes.
+__device__ __forceinline__ uint32_t lookback_wave(uint32_t* look, uint32_t part, uint32_t aggregate) {
+  const int l = __lane_id();
   if (part == 0) {
-    st_flag(&look[0], kFlagInc | aggregate);
+    if (l == 0) st_flag(&look[0], kFlagInc | aggregate);
     return 0;
   }
-  st_flag(&look[part], kFlagAgg | aggregate);
-  int64_t p = (int64_t)part - 1;
+  if (l == 0) st_flag(&look[part], kFlagAgg | aggregate);
+  uint32_t excl = 0;
+  int64_t hi = (int64_t)part - 1;  // newest predecessor not yet accounted for
   while (true) {
-    const uint32_t v = ld_flag(&look[p]);
-    if ((v & (kFlagAgg | kFlagInc)) == 0) {
+    const int64_t p = hi - l;
+    uint32_t v = (p >= 0) ? ld_flag(&look[p]) : kFlagInc;  // before partition 0: an inclusive zero
+    // wait until every lane's predecessor has published something
+    while (__ballot((v & (kFlagAgg | kFlagInc)) == 0) != 0ull) {
       __builtin_amdgcn_s_sleep(1);
-      continue;
+      if ((v & (kFlagAgg | kFlagInc)) == 0) v = ld_flag(&look[p]);
     }
-    excl += v & kCountMask;
-    if (v & kFlagInc) break;
-    --p;
+    const uint64_t inc = __ballot((v & kFlagInc) != 0);
+    // lanes up to (and including) the nearest inclusive predecessor contribute
+    const int stop = inc ? __builtin_ctzll(inc) : 64;
+    uint32_t c = (l <= stop) ? (v & kCountMask) : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    excl += c;
+    if (inc) break;
+    hi -= 64;
   }
-  st_flag(&look[part], kFlagInc | (excl + aggregate));
+  if (l == 0) st_flag(&look[part], kFlagInc | (excl + aggregate));
   return excl;
 }
 
@@ -114,6 +126,14 @@ __device__ __forceinline__ uint32_t lookback_single(uint32_t* look, uint32_t par
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// two regions in one launch (the workspace head and the tile ranges)
+__global__ void k_fill2_u32(uint32_t* __restrict__ p, size_t n, uint32_t* __restrict__ q, size_t m) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += stride) {
+    if (i < n) p[i] = 0u; else q[i - n] = 0u;
+  }
 }
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
@@ -153,10 +173,12 @@ __global__ __launch_bounds__(kSortThreads) void k_compact(uint32_t n, const uint
   }
   uint32_t block_total;
   const uint32_t tpre = block_excl_scan(sum, s_wave, &block_total);
-  if (t == 0) {
-    const uint32_t excl = lookback_single(look, part, block_total);
-    s_misc[1] = excl;
-    if (base + kPart >= n) counters[C_NUM_VISIBLE] = excl + block_total;
+  if (t < 64) {
+    const uint32_t excl = lookback_wave(look, part, block_total);
+    if (t == 0) {
+      s_misc[1] = excl;
+      if (base + kPart >= n) counters[C_NUM_VISIBLE] = excl + block_total;
+    }
   }
   __syncthreads();
   uint32_t pos = s_misc[1] + tpre;
@@ -260,16 +282,30 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     st_flag(my_look, kFlagInc | tot);
   } else {
     st_flag(my_look, kFlagAgg | tot);
-    int64_t p = (int64_t)part - 1;
-    while (true) {
-      const uint32_t v = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
-      if ((v & (kFlagAgg | kFlagInc)) == 0) {
-        __builtin_amdgcn_s_sleep(1);
-        continue;
+    // walk back 8 predecessors per round trip (independent loads in flight)
+    constexpr int kAhead = 8;
+    int64_t hi = (int64_t)part - 1;
+    bool found = false;
+    while (!found) {
+      uint32_t v[kAhead];
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        const int64_t p = hi - q;
+        v[q] = (p >= 0) ? ld_flag(look + ((size_t)p * npass + pass) * kRadix + d) : kFlagInc;
       }
-      excl += v & kCountMask;
-      if (v & kFlagInc) break;
-      --p;
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        if (found) break;
+        const int64_t p = hi - q;
+        uint32_t x = v[q];
+        while ((x & (kFlagAgg | kFlagInc)) == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
+        }
+        excl += x & kCountMask;
+        found = (x & kFlagInc) != 0;
+      }
+      hi -= kAhead;
     }
     st_flag(my_look, kFlagInc | (excl + tot));
   }
@@ -376,10 +412,10 @@ __global__ __launch_bounds__(kSortThreads) void k_expand(const void* __restrict_
     s_off[t * kExpItems + j] = run;
     run += cnt[j];
   }
-  if (t == 0) {
-    const uint32_t excl = lookback_single(look, part, block_total);
-    s_misc[1] = excl;
-    if (base + kExpPart >= V) {
+  if (t < 64) {
+    const uint32_t excl = lookback_wave(look, part, block_total);
+    if (t == 0) s_misc[1] = excl;
+    if (t == 0 && base + kExpPart >= V) {
       const uint32_t P = excl + block_total;
       const uint32_t ov = P > capacity ? 1u : 0u;
       counters[C_NUM_PAIRS] = P;
@@ -418,29 +454,18 @@ __global__ __launch_bounds__(kSortThreads) void k_expand(const void* __restrict_
 }
 
 // ---------------------------------------------------------------- ranges
-// One thread per tile: [lower_bound(tile), lower_bound(tile + 1)) in the
-// sorted tile keys; empty tiles get (0, 0).
+// One thread per sorted pair: a tile's first pair writes its start, its last
+// pair its end (the range array was cleared, so empty tiles read (0, 0)).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkeys,
-                                                const uint32_t* __restrict__ counters, uint32_t total_tiles,
+                                                const uint32_t* __restrict__ counters,
                                                 uint32_t* __restrict__ ranges) {
   if (counters[C_OVERFLOW]) return;
-  const uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile >= total_tiles) return;
   const uint32_t P = counters[C_NUM_PAIRS];
-  uint32_t lo = 0, hi = P;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tkeys[mid] < tile) lo = mid + 1; else hi = mid;
-  }
-  const uint32_t a = lo;
-  hi = P;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tkeys[mid] <= tile) lo = mid + 1; else hi = mid;
-  }
-  const bool empty = (lo == a);
-  ranges[2 * (size_t)tile] = empty ? 0u : a;
-  ranges[2 * (size_t)tile + 1] = empty ? 0u : lo;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t tk = tkeys[i];
+  if (i == 0 || tkeys[i - 1] != tk) ranges[2 * (size_t)tk] = i;
+  if (i == P - 1 || tkeys[i + 1] != tk) ranges[2 * (size_t)tk + 1] = i + 1;
 }
 
 __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ vals,
@@ -514,8 +539,12 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const uint32_t* depth_bits = reinterpret_cast<const uint32_t*>(g.depth);
   const uint32_t* ov = counters + C_OVERFLOW;
 
-  hipError_t e = fill_u32(counters, 0u, (p.off_dkeys_a - p.off_counters) / 4, s);
-  if (e != hipSuccess) return e;
+  {
+    const size_t nh = (p.off_dkeys_a - p.off_counters) / 4, nr = (size_t)p.total_tiles * 2;
+    size_t blocks = (nh + nr + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill2_u32, dim3((unsigned)blocks), dim3(256), 0, s, counters, nh, ranges, nr);
+  }
   const unsigned parts_i = (unsigned)(p.parts_items > 0 ? p.parts_items : 1);
   const unsigned parts_p = (unsigned)(p.parts_pairs > 0 ? p.parts_pairs : 1);
   const unsigned parts_e = (unsigned)((p.items + kExpPart - 1) / kExpPart > 0 ? (p.items + kExpPart - 1) / kExpPart : 1);
@@ -544,13 +573,10 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   }
   uint32_t* tk_final = tk[tpass & 1];
   // K5: ranges
-  if (p.total_tiles > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((p.total_tiles + 255) / 256)), dim3(256), 0, s, tk_final, counters,
-                       (uint32_t)p.total_tiles, ranges);
-  if (keys) {
-    const unsigned pblocks = (unsigned)((p.capacity + 255) / 256 > 0 ? (p.capacity + 255) / 256 : 1);
+  const unsigned pblocks = (unsigned)((p.capacity + 255) / 256 > 0 ? (p.capacity + 255) / 256 : 1);
+  hipLaunchKernelGGL(k_ranges, dim3(pblocks), dim3(256), 0, s, tk_final, counters, ranges);
+  if (keys)
     hipLaunchKernelGGL(k_keys64, dim3(pblocks), dim3(256), 0, s, tk_final, vals, depth_bits, counters, keys);
-  }
   return hipGetLastError();
 }
 

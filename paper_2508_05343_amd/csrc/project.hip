@@ -189,6 +189,16 @@ __device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my,
 }
 
 // ------------------------------------------------------------------ K1
+// Two phases per block of 1024 items.  Phase 1 (every item, coalesced): depth
+// key, near and opacity culls, and a conservative screen test: the 2D
+// covariance's diagonal is at most |J W|_F^2 max(s)^2 + 0.3 (W orthonormal,
+// the largest eigenvalue of Sigma is max(s)^2), so an item whose box of that
+// half-width misses the image cannot be visible.  Survivors are compacted in
+// LDS so that phase 2 (full EWA projection, SH colour, 2D frequencies, exact
+// rect) runs on dense wavefronts instead of wavefronts that are mostly culled.
+constexpr int kPreItems = 4;
+constexpr int kPreBlock = 256 * kPreItems;
+
 template <int K>
 __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ table,
                                                     float* __restrict__ rec,
@@ -196,26 +206,87 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
                                                     uint32_t* __restrict__ rect_out,
                                                     uint32_t* __restrict__ tiles_out) {
   constexpr int RF = (10 + 3 * K + 3) & ~3;
+  __shared__ uint16_t s_cand[kPreBlock];
+  __shared__ uint32_t s_wave[4];
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry& V = table_views(table)[blockIdx.y];
   const SceneEntry& S = table_scenes(table, hdr->num_views)[V.scene];
   const int64_t n = S.n;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t item = V.item_offset + i;
+  const int64_t base = (int64_t)blockIdx.x * kPreBlock;
+  if (base >= n) return;
+  const int t = threadIdx.x;
+  const float Wf = (float)V.width, Hf = (float)V.height;
 
-  const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
-  const float tz = depth_key(V.R, V.t, mx, my, mz);
-  depth_out[item] = tz;
-  const float o = S.opac[i];
-  bool ok = (tz > V.near_plane) && (o * 255.0f > 1.0f);
-  uint2 rect = make_uint2(0u, 0u);
-  uint32_t ntiles = 0;
-  if (ok) {
+  // ---- phase 1
+  uint32_t cand = 0;
+#pragma unroll
+  for (int j = 0; j < kPreItems; ++j) {
+    const int64_t i = base + j * 256 + t;
+    if (i >= n) continue;
+    const int64_t item = V.item_offset + i;
+    const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+    const float tz = depth_key(V.R, V.t, mx, my, mz);
+    depth_out[item] = tz;
+    const float o = S.opac[i];
+    bool ok = (tz > V.near_plane) && (o * 255.0f > 1.0f);
+    if (ok) {
+      const float smax = fmaxf(fmaxf(S.scales[i], S.scales[n + i]), S.scales[2 * n + i]);
+      const float* R = V.R;
+      const float tx = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
+      const float ty = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
+      const float iz = 1.0f / tz;
+      const float mux = fmaf(V.fx * tx, iz, V.cx), muy = fmaf(V.fy * ty, iz, V.cy);
+      const float lox = (-0.15f * Wf - V.cx) / V.fx, hix = (1.15f * Wf - V.cx) / V.fx;
+      const float loy = (-0.15f * Hf - V.cy) / V.fy, hiy = (1.15f * Hf - V.cy) / V.fy;
+      const float ux = fminf(fmaxf(tx * iz, lox), hix), uy = fminf(fmaxf(ty * iz, loy), hiy);
+      const float a0 = V.fx * iz, a1 = V.fy * iz;
+      const float jf2 = a0 * a0 * (1.0f + ux * ux) + a1 * a1 * (1.0f + uy * uy);
+      const float kk = sqrtf(fmaxf(2.0f * kLn2 * log2f(255.0f * o), 0.0f));
+      const float rb = 1.01f * kk * sqrtf(jf2 * smax * smax + kDilation) + 1.0f;
+      // also keep anything whose numbers are not finite: phase 2 decides
+      ok = !(mux + rb < 0.0f || mux - rb > Wf || muy + rb < 0.0f || muy - rb > Hf);
+    }
+    if (ok) {
+      cand |= 1u << j;
+    } else {
+      reinterpret_cast<uint2*>(rect_out)[item] = make_uint2(0u, 0u);
+      tiles_out[item] = 0;
+    }
+  }
+  // ---- compact the candidates of the block (order does not matter)
+  uint32_t nc = (uint32_t)__popc(cand);
+  const int w = t >> 6, l = t & 63;
+  uint32_t inc = nc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, 64);
+    if (l >= d) inc += o;
+  }
+  if (l == 63) s_wave[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    off += (q < w) ? s_wave[q] : 0u;
+    total += s_wave[q];
+  }
+  uint32_t pos = off + inc - nc;
+#pragma unroll
+  for (int j = 0; j < kPreItems; ++j)
+    if ((cand >> j) & 1u) s_cand[pos++] = (uint16_t)(j * 256 + t);
+  __syncthreads();
+
+  // ---- phase 2
+  for (uint32_t c = t; c < total; c += 256) {
+    const int64_t i = base + s_cand[c];
+    const int64_t item = V.item_offset + i;
+    const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+    const float tz = depth_out[item];
+    const float o = S.opac[i];
     const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
-    const float s[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+    const float sc[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
     Geo g;
-    geometry(V, mx, my, mz, tz, q, s, g);
+    geometry(V, mx, my, mz, tz, q, sc, g);
     const float mux = fmaf(V.fx * g.tx, g.inv_tz, V.cx);
     const float muy = fmaf(V.fy * g.ty, g.inv_tz, V.cy);
     // exact support of o G >= 1/255: d^T C d <= 2 ln(255 o)
@@ -225,8 +296,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     const float px1 = fminf(floorf(mux + rx - 0.5f), (float)(V.width - 1));
     const float py0 = fmaxf(ceilf(muy - ry - 0.5f), 0.0f);
     const float py1 = fminf(floorf(muy + ry - 0.5f), (float)(V.height - 1));
-    ok = (g.det > 0.f) && (px0 <= px1) && (py0 <= py1);
-    if (ok) {
+    const bool vis = (g.det > 0.f) && (px0 <= px1) && (py0 <= py1);
+    uint2 rect = make_uint2(0u, 0u);
+    uint32_t ntiles = 0;
+    if (vis) {
       const uint32_t x0 = (uint32_t)px0 >> 4, x1 = ((uint32_t)px1 >> 4) + 1;
       const uint32_t y0 = (uint32_t)py0 >> 4, y1 = ((uint32_t)py1 >> 4) + 1;
       rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
@@ -238,7 +311,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       r[3] = -kLog2e * g.conic[1];
       r[4] = -0.5f * kLog2e * g.conic[2];
       r[5] = log2f(o);
-      // colour
       if (S.sh_degree >= 0) {
         const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
         const float il = 1.0f / sqrtf(dot3(d, d));
@@ -264,44 +336,43 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       for (int k = 0; k < K; ++k) {
         const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
                         S.freqs[(int64_t)(3 * k + 2) * n + i]);
-        const float w = S.weights[(int64_t)k * n + i];
+        const float wk = S.weights[(int64_t)k * n + i];
         r[10 + 3 * k] = dot3(g.vx, f);
         r[11 + 3 * k] = dot3(g.vy, f);
-        r[12 + 3 * k] = w;
-        wsum += w;
+        r[12 + 3 * k] = wk;
+        wsum += wk;
       }
       r[9] = 1.0f - wsum;
 #pragma unroll
-      for (int j = 10 + 3 * K; j < RF; ++j) r[j] = 0.f;
+      for (int jj = 10 + 3 * K; jj < RF; ++jj) r[jj] = 0.f;
       float4* dst = reinterpret_cast<float4*>(rec + item * RF);
 #pragma unroll
-      for (int j = 0; j < RF / 4; ++j) dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
+      for (int jj = 0; jj < RF / 4; ++jj) dst[jj] = make_float4(r[4 * jj], r[4 * jj + 1], r[4 * jj + 2], r[4 * jj + 3]);
     }
+    reinterpret_cast<uint2*>(rect_out)[item] = rect;
+    tiles_out[item] = ntiles;
   }
-  reinterpret_cast<uint2*>(rect_out)[item] = rect;
-  tiles_out[item] = ntiles;
 }
 
 // ------------------------------------------------------------------ K8
-// One thread per primitive of scene `scene_index`; loops over that scene's
-// views (deterministic accumulation across views, no atomics).
+// One primitive of scene `scene_index` per work item; the primitive's views
+// are looped over (deterministic accumulation across views, no atomics).
+// Like K1 the kernel runs in two phases per block of 1024 primitives: phase 1
+// finds the primitives visible in at least one view (and, when overwriting,
+// zeroes the gradients of the others); phase 2 runs the chain rule on the
+// compacted visible primitives only.
 template <int K>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
-                                                        const uint32_t* __restrict__ tiles,
-                                                        const float* __restrict__ depth,
-                                                        const float* __restrict__ grad2d,
-                                                        gabsplat_scene_grads gr,
-                                                        const int32_t* __restrict__ d_overflow) {
+__device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ table, int scene_index,
+                                                   const uint32_t* __restrict__ tiles,
+                                                   const float* __restrict__ depth,
+                                                   const float* __restrict__ grad2d,
+                                                   const gabsplat_scene_grads& gr, int64_t i) {
   constexpr int GF = (9 + 3 * K + 3) & ~3;
-  if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
   const SceneEntry& S = table_scenes(table, nv)[scene_index];
   const int64_t n = S.n;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-
   const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
   const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
   const float s[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
@@ -533,6 +604,76 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__
   }
 }
 
+template <int K>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
+                                                        const uint32_t* __restrict__ tiles,
+                                                        const float* __restrict__ depth,
+                                                        const float* __restrict__ grad2d,
+                                                        gabsplat_scene_grads gr,
+                                                        const int32_t* __restrict__ d_overflow) {
+  __shared__ uint16_t s_cand[kPreBlock];
+  __shared__ uint32_t s_wave[4];
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const int nv = hdr->num_views;
+  const ViewEntry* views = table_views(table);
+  const SceneEntry& S = table_scenes(table, nv)[scene_index];
+  const int64_t n = S.n;
+  const int64_t base = (int64_t)blockIdx.x * kPreBlock;
+  if (base >= n) return;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int deg = S.sh_degree;
+  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+  uint32_t cand = 0;
+#pragma unroll
+  for (int j = 0; j < kPreItems; ++j) {
+    const int64_t i = base + j * 256 + t;
+    if (i >= n) continue;
+    bool any = false;
+    for (int v = 0; v < nv && !any; ++v)
+      any = views[v].scene == scene_index && tiles[views[v].item_offset + i] != 0;
+    if (any) {
+      cand |= 1u << j;
+    } else if (!gr.accumulate) {
+      if (gr.means) { gr.means[i] = 0.f; gr.means[n + i] = 0.f; gr.means[2 * n + i] = 0.f; }
+      if (gr.scales) { gr.scales[i] = 0.f; gr.scales[n + i] = 0.f; gr.scales[2 * n + i] = 0.f; }
+      if (gr.quats)
+        for (int b = 0; b < 4; ++b) gr.quats[b * n + i] = 0.f;
+      if (gr.opacities) gr.opacities[i] = 0.f;
+      if (deg >= 0 && gr.sh)
+        for (int b = 0; b < nd * 3; ++b) gr.sh[(int64_t)b * n + i] = 0.f;
+      if (deg < 0 && gr.colors)
+        for (int b = 0; b < 3; ++b) gr.colors[b * n + i] = 0.f;
+      if (gr.freqs)
+        for (int b = 0; b < 3 * K; ++b) gr.freqs[(int64_t)b * n + i] = 0.f;
+      if (gr.weights)
+        for (int b = 0; b < K; ++b) gr.weights[(int64_t)b * n + i] = 0.f;
+    }
+  }
+  const uint32_t nc = (uint32_t)__popc(cand);
+  uint32_t inc = nc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, 64);
+    if (l >= d) inc += o;
+  }
+  if (l == 63) s_wave[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    off += (q < w) ? s_wave[q] : 0u;
+    total += s_wave[q];
+  }
+  uint32_t pos = off + inc - nc;
+#pragma unroll
+  for (int j = 0; j < kPreItems; ++j)
+    if ((cand >> j) & 1u) s_cand[pos++] = (uint16_t)(j * 256 + t);
+  __syncthreads();
+  for (uint32_t c = t; c < total; c += 256)
+    preprocess_bwd_one<K>(table, scene_index, tiles, depth, grad2d, gr, base + s_cand[c]);
+}
+
 // ------------------------------------------------------------- launchers
 template <int K>
 static hipError_t pre_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, hipStream_t s) {
@@ -542,7 +683,7 @@ static hipError_t pre_k(const void* d_table, const HostTable& h, const gabsplat_
     if (n > max_n) max_n = n;
   }
   if (max_n == 0) return hipSuccess;
-  dim3 grid((unsigned)((max_n + 255) / 256), (unsigned)h.hdr.num_views);
+  dim3 grid((unsigned)((max_n + kPreBlock - 1) / kPreBlock), (unsigned)h.hdr.num_views);
   hipLaunchKernelGGL(k_preprocess<K>, grid, dim3(256), 0, s, d_table, g.rec, g.depth, g.rect, g.tiles);
   return hipGetLastError();
 }
@@ -567,7 +708,7 @@ static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat
                          const gabsplat_scene_grads& gr, const int32_t* ov, hipStream_t s) {
   const int64_t n = h.scenes[sc].n;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_preprocess_bwd<K>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_table, sc,
+  hipLaunchKernelGGL(k_preprocess_bwd<K>, dim3((unsigned)((n + kPreBlock - 1) / kPreBlock)), dim3(256), 0, s, d_table, sc,
                      g.tiles, g.depth, gr.grad2d, gr, ov);
   return hipGetLastError();
 }

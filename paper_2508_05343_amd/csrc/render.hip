@@ -37,12 +37,36 @@ __device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv,
 // cos(2 pi x) and sin(2 pi x); the hardware units take revolutions
 __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(x)); }
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(x)); }
+// 2^x on the hardware unit; only called with x >= log2(1/255), far from denormals
+__device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Record field access (see gabsplat_geom.rec)
 template <int K>
 struct Rec {
   static constexpr int RF = (10 + 3 * K + 3) & ~3;
 };
+
+// Bit q (q = 0..3, quadrant (q & 1, q >> 1) of 8x8 pixels of the tile whose
+// top-left pixel is (ox, oy)) is set when the record's support o G >= 1/255
+// can reach a pixel centre of that quadrant: the axis-aligned box of the
+// ellipse {q(d) + log2 o >= log2(1/255)} (widened by a small margin so that the
+// per-pixel test stays the only decision) is tested against the quadrant.
+__device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float ox, float oy) {
+  const float a = -r0.z, b = -r0.w, c = -r1.x;  // positive definite form a dx^2 + b dx dy + c dy^2
+  const float R = r1.y - kLog2AlphaMin;         // log2 o - log2(1/255)
+  const float det = a * c - 0.25f * b * b;
+  if (!(R > 0.f) || !(det > 0.f)) return 0u;
+  const float rx = sqrtf(R * c / det) * 1.001f + 1e-3f;
+  const float ry = sqrtf(R * a / det) * 1.001f + 1e-3f;
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float x0 = ox + 8.0f * (q & 1) + 0.5f, y0 = oy + 8.0f * (q >> 1) + 0.5f;
+    const bool hit = (x0 <= r0.x + rx) && (x0 + 7.0f >= r0.x - rx) && (y0 <= r0.y + ry) && (y0 + 7.0f >= r0.y - ry);
+    m |= hit ? (1u << q) : 0u;
+  }
+  return m;
+}
 
 // Envelope exponent q + log2 o for offset (dx, dy).
 __device__ __forceinline__ float rec_power(const float* r, float dx, float dy) {
@@ -72,7 +96,9 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
                                                        uint32_t* __restrict__ n_contrib,
                                                        const int32_t* __restrict__ d_overflow) {
   constexpr int RF = Rec<K>::RF;
-  __shared__ float4 s_rec[kBlock * (RF / 4)];
+  constexpr int R4 = RF / 4;
+  __shared__ float4 s_rec[kBlock * R4];
+  __shared__ uint32_t s_mask[kBlock];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
@@ -85,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -93,32 +120,45 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   for (uint32_t b = start; b < end; b += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = b + t;
+    uint32_t m = 0;
     if (idx < end) {
       const float4* src = reinterpret_cast<const float4*>(rec + (size_t)vals[idx] * RF);
+      float4 q[R4];
 #pragma unroll
-      for (int j = 0; j < RF / 4; ++j) s_rec[t * (RF / 4) + j] = src[j];
+      for (int j = 0; j < R4; ++j) q[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < R4; ++j) s_rec[t * R4 + j] = q[j];
+      m = quadrant_mask(q[0], q[1], ox, oy);
     }
+    s_mask[t] = m;
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBlock, end - b);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      if (__ballot(!done) == 0ull) break;
+      uint64_t bits = __ballot(c0 + l < cnt && ((s_mask[c0 + l] >> w) & 1u));
+      while (bits) {
+        const int j = c0 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        if (done) continue;
+        const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
+        const float dx = fx - r0.x, dy = fy - r0.y;
+        const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
+        if (pw < kLog2AlphaMin) continue;  // o G < 1/255 and B <= 1: alpha < 1/255
         float r[RF];
+        r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
 #pragma unroll
-        for (int q = 0; q < RF / 4; ++q) {
-          const float4 v = s_rec[j * (RF / 4) + q];
+        for (int q = 2; q < R4; ++q) {
+          const float4 v = s_rec[j * R4 + q];
           r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
         }
-        const float dx = fx - r[0], dy = fy - r[1];
-        const float pw = rec_power(r, dx, dy);
-        if (pw < kLog2AlphaMin) continue;  // o G < 1/255 and B <= 1: alpha < 1/255
-        const float E = exp2f(pw);
+        const float E = exp2_hw(pw);
         const float Bv = rec_modulation<K>(r, dx, dy);
         const float alpha = fminf(kAlphaMax, E * Bv);
         if (alpha < kAlphaMin) continue;
         const float Tn = T * (1.0f - alpha);
         if (Tn < kTMin) {
           done = true;
-          break;
+          continue;
         }
         const float wt = alpha * T;
         C0 = fmaf(r[6], wt, C0);
@@ -185,11 +225,13 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
                                                        float* __restrict__ grad2d,
                                                        const int32_t* __restrict__ d_overflow) {
   constexpr int RF = Rec<K>::RF;
+  constexpr int R4 = RF / 4;
   constexpr int GS = 9 + 3 * K;            // gradient components per pair
   constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
   constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
-  __shared__ float4 s_rec[kBlock * (RF / 4)];
+  __shared__ float4 s_rec[kBlock * R4];
   __shared__ uint32_t s_id[kBlock];
+  __shared__ uint32_t s_mask[kBlock];
   __shared__ uint32_t s_max;
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -203,6 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile];
 
   float T = 1.0f, Tf = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
@@ -224,84 +267,107 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   if (last) atomicMax(&s_max, last);
   __syncthreads();
   const uint32_t maxlast = s_max;
+  // the wave's own furthest contributor (positions beyond it are skipped)
+  uint32_t wlast = last;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, d, 64));
 
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, la = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
   for (uint32_t hi = maxlast; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBlock ? hi - kBlock : 0u;
     const uint32_t cnt = hi - lo;
     __syncthreads();
+    uint32_t m = 0;
     if ((uint32_t)t < cnt) {
       const uint32_t gid = vals[start + lo + t];
       s_id[t] = gid;
       const float4* src = reinterpret_cast<const float4*>(rec + (size_t)gid * RF);
+      float4 q[R4];
 #pragma unroll
-      for (int j = 0; j < RF / 4; ++j) s_rec[t * (RF / 4) + j] = src[j];
+      for (int j = 0; j < R4; ++j) q[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < R4; ++j) s_rec[t * R4 + j] = q[j];
+      m = quadrant_mask(q[0], q[1], ox, oy);
     }
+    s_mask[t] = m;
     __syncthreads();
-    for (int j = (int)cnt - 1; j >= 0; --j) {
-      const uint32_t pos = lo + (uint32_t)j + 1;
-      float r[RF];
-#pragma unroll
-      for (int q = 0; q < RF / 4; ++q) {
-        const float4 v = s_rec[j * (RF / 4) + q];
-        r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
-      }
-      const float dx = fx - r[0], dy = fy - r[1];
-      bool contrib = inside && pos <= last;
-      float pw = 0.f, E = 0.f, Bv = 0.f, alpha = 0.f;
-      if (contrib) {
-        pw = rec_power(r, dx, dy);
-        contrib = !(pw < kLog2AlphaMin);
-      }
-      if (contrib) {
-        E = exp2f(pw);
-        Bv = rec_modulation<K>(r, dx, dy);
-        alpha = fminf(kAlphaMax, E * Bv);
-        contrib = !(alpha < kAlphaMin);
-      }
-      if (__ballot(contrib) == 0ull) continue;
-      float gv[NP];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) gv[q] = 0.f;
-      if (contrib) {
-        const float om = 1.0f - alpha;
-        T = T / om;
-        const float wt = alpha * T;
-        gv[6] = wt * dC0;
-        gv[7] = wt * dC1;
-        gv[8] = wt * dC2;
-        acc0 = fmaf(la, lc0, (1.0f - la) * acc0);
-        acc1 = fmaf(la, lc1, (1.0f - la) * acc1);
-        acc2 = fmaf(la, lc2, (1.0f - la) * acc2);
-        lc0 = r[6]; lc1 = r[7]; lc2 = r[8];
-        la = alpha;
-        float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
-        da = da * T - Tf * bgdot / om;
-        if (E * Bv > kAlphaMax) da = 0.f;  // clamp binds: zero derivative
-        const float dE = da * Bv, dB = da * E;
-        const float dp = dE * E * kLn2;
-        gv[2] = dp * dx * dx;
-        gv[3] = dp * dx * dy;
-        gv[4] = dp * dy * dy;
-        gv[5] = dp;
-        float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
-        float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float fkx = r[10 + 3 * k], fky = r[11 + 3 * k], wk = r[12 + 3 * k];
-          const float ph = fmaf(fkx, dx, fky * dy);
-          const float cs = cos_rev(ph), sn = sin_rev(ph);
-          gv[11 + 3 * k] = dB * (cs - 1.0f);
-          const float dph = -dB * wk * 6.283185307179586f * sn;
-          gv[9 + 3 * k] = dph * dx;
-          gv[10 + 3 * k] = dph * dy;
-          ddx = fmaf(dph, fkx, ddx);
-          ddy = fmaf(dph, fky, ddy);
+    // chunks of 64 records, newest first; records past the wave's last contributor are skipped
+    for (int c0 = ((int)cnt - 1) & ~63; c0 >= 0; c0 -= 64) {
+      const uint32_t pos_l = lo + (uint32_t)(c0 + l) + 1;
+      uint64_t bits = __ballot(c0 + l < (int)cnt && pos_l <= wlast && ((s_mask[c0 + l] >> w) & 1u));
+      while (bits) {
+        const int hb = 63 - __builtin_clzll(bits);
+        bits &= ~(1ull << hb);
+        const int j = c0 + hb;
+        const uint32_t pos = lo + (uint32_t)j + 1;
+        const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
+        const float dx = fx - r0.x, dy = fy - r0.y;
+        bool contrib = pos <= last;
+        float pw = 0.f;
+        if (contrib) {
+          pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
+          contrib = !(pw < kLog2AlphaMin);
         }
-        gv[0] = -ddx;
-        gv[1] = -ddy;
+        if (__ballot(contrib) == 0ull) continue;
+        float r[RF];
+        r[0] = r0.x; r[1] = r0.y; r[2] = r0.z; r[3] = r0.w;
+        r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
+#pragma unroll
+        for (int q = 2; q < R4; ++q) {
+          const float4 v = s_rec[j * R4 + q];
+          r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
+        }
+        float E = 0.f, Bv = 0.f, alpha = 0.f;
+        if (contrib) {
+          E = exp2_hw(pw);
+          Bv = rec_modulation<K>(r, dx, dy);
+          alpha = fminf(kAlphaMax, E * Bv);
+          contrib = !(alpha < kAlphaMin);
+        }
+        if (__ballot(contrib) == 0ull) continue;
+        float gv[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) gv[q] = 0.f;
+        if (contrib) {
+          const float om = 1.0f - alpha;
+          T = T / om;
+          const float wt = alpha * T;
+          gv[6] = wt * dC0;
+          gv[7] = wt * dC1;
+          gv[8] = wt * dC2;
+          acc0 = fmaf(la, lc0, (1.0f - la) * acc0);
+          acc1 = fmaf(la, lc1, (1.0f - la) * acc1);
+          acc2 = fmaf(la, lc2, (1.0f - la) * acc2);
+          lc0 = r[6]; lc1 = r[7]; lc2 = r[8];
+          la = alpha;
+          float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
+          da = da * T - Tf * bgdot / om;
+          if (E * Bv > kAlphaMax) da = 0.f;  // clamp binds: zero derivative
+          const float dE = da * Bv, dB = da * E;
+          const float dp = dE * E * kLn2;
+          gv[2] = dp * dx * dx;
+          gv[3] = dp * dx * dy;
+          gv[4] = dp * dy * dy;
+          gv[5] = dp;
+          float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
+          float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float fkx = r[10 + 3 * k], fky = r[11 + 3 * k], wk = r[12 + 3 * k];
+            const float ph = fmaf(fkx, dx, fky * dy);
+            const float cs = cos_rev(ph), sn = sin_rev(ph);
+            gv[11 + 3 * k] = dB * (cs - 1.0f);
+            const float dph = -dB * wk * 6.283185307179586f * sn;
+            gv[9 + 3 * k] = dph * dx;
+            gv[10 + 3 * k] = dph * dy;
+            ddx = fmaf(dph, fkx, ddx);
+            ddy = fmaf(dph, fky, ddy);
+          }
+          gv[0] = -ddx;
+          gv[1] = -ddy;
+        }
+        wave_reduce_add<NP>(gv, grad2d + (size_t)s_id[j] * GF, GS);
       }
-      wave_reduce_add<NP>(gv, grad2d + (size_t)s_id[j] * GF, GS);
     }
     hi = lo;
   }

@@ -75,10 +75,12 @@ def scratch_bytes(n_items: int, pixels: int, pairs: int, k: int = 4) -> int:
 
 
 class PairEstimator:
-    """Pairs per job, learned online per scene (pairs per pixel), with a
-    safety factor; starts from a generous prior."""
+    """Pairs per job, learned online per scene: the largest pairs-per-pixel
+    ratio seen so far times a safety factor, starting from a generous prior
+    (an underestimate costs a retry of that batch's binning, an overestimate
+    only admission headroom)."""
 
-    def __init__(self, prior_pairs_per_pixel=2.0, safety=1.6):
+    def __init__(self, prior_pairs_per_pixel=8.0, safety=1.5):
         self.ppp: Dict[int, float] = {}
         self.prior = prior_pairs_per_pixel
         self.safety = safety
@@ -90,7 +92,7 @@ class PairEstimator:
     def observe(self, scene: int, pixels: int, pairs: int):
         r = pairs / max(1, pixels)
         old = self.ppp.get(scene)
-        self.ppp[scene] = r if old is None else max(r, 0.8 * old + 0.2 * r)
+        self.ppp[scene] = max(r, self.prior / 4) if old is None else max(r, old)
 
 
 # --------------------------------------------------------------- scheduler
