@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# fp32 VALU peak without packed-FP32 instructions (which this build does not
+# use): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -133,20 +136,29 @@ def main():
     torch.cuda.synchronize()
     ms_step_clean = t0.elapsed_time(t1) / args.steps
 
-    # ---- dominant kernel roofline: render_fwd is one kernel launch
-    n_contrib = plan.n_contrib[:pix].to(torch.int64)
+    # ---- roofline of the blend (one kernel launch, k_render_fwd<4>).  Its work
+    # is counted by the kernel itself in a separate, untimed launch: per pixel
+    # the pairs walked up to the stop (each needs the envelope test) and the
+    # pairs that passed it (each needs the full Gabor evaluation).
+    counts = torch.zeros((pix, 2), dtype=torch.int32, device=dev)
+    plan.render_fwd(eval_counts=counts)
+    torch.cuda.synchronize()
+    e_env = int(counts[:, 0].to(torch.int64).sum().item())
+    e_full = int(counts[:, 1].to(torch.int64).sum().item())
+    K = plan.k
+    flops_env, flops_full = 10, 12 + 7 * K  # per evaluation, FMA = 2
+    render_flops = flops_env * e_env + flops_full * e_full
     ranges = plan.ranges[:cam.num_tiles].to(torch.int64)
-    tile_len = (ranges[:, 1] - ranges[:, 0])
-    # pairs the blend reads: each tile reads its list up to the batch holding
-    # the furthest pixel's stop; bounded by the list length (upper bound used)
-    p_read = int(tile_len.sum().item())
-    rec_bytes = 4 * (10 + 3 * plan.k)  # used record floats
+    p_read = int((ranges[:, 1] - ranges[:, 0]).sum().item())
+    rec_bytes = 4 * (10 + 3 * K)  # record floats the blend uses
     render_bytes = p_read * (4 + rec_bytes) + pix * (12 + 4 + 4) + cam.num_tiles * 8
     stage_ms = dict(stage)
     dom = max(stage_ms, key=stage_ms.get)
+    t_render = stage_ms["render_fwd"] * 1e-3
+    render_tflops = render_flops / t_render / 1e12
+    render_gbs = (render_bytes / 1e9) / t_render
     # pass-aware algorithmic bytes of the whole forward (byte model in the design doc)
     N, V = scene.n, vis
-    K = plan.k
     params_visible = 4 * (3 + 4 + 1 + 48 + 4 * K)
     b_pre = 12 * N + params_visible * V + 4 * (10 + 3 * K) * V + 4 * 4 * N
     b_scan = 8 * N
@@ -155,8 +167,6 @@ def main():
     b_ranges = 8 * P + 8 * cam.num_tiles
     b_fwd = b_pre + b_scan + b_dup + b_sort + b_ranges + render_bytes
     hbm_frac_fwd = (b_fwd / 1e9) / (ms_step_clean * 1e-3) / HBM_PEAK_GBS
-    render_gbs = (render_bytes / 1e9) / (stage_ms["render_fwd"] * 1e-3)
-
     out = {
         "metric": "Mpix/s fwd, fwd+bwd step ms @1M Gabor prims; serve p50/p99 latency",
         "value": round(pix / (ms_step_clean * 1e-3) / 1e6, 3),
@@ -176,9 +186,12 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "fwd_pass_aware_bytes": int(b_fwd),
         "fwd_hbm_fraction": round(hbm_frac_fwd, 4),
-        "roofline": {"kernel": "k_render_fwd<4>", "bound": "hbm", "achieved": round(render_gbs, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(render_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "dominant_stage": dom},
+        "roofline": {"kernel": "k_render_fwd<4>", "bound": "alu", "achieved": round(render_tflops, 3),
+                     "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(render_tflops / VALU_PEAK_TFLOPS, 4),
+                     "traffic": None, "evaluations": e_env, "full_evaluations": e_full,
+                     "flops_per_launch": int(render_flops), "kernel_ms": round(stage_ms["render_fwd"], 4),
+                     "hbm_gbs": round(render_gbs, 1), "hbm_frac": round(render_gbs / HBM_PEAK_GBS, 4),
+                     "dominant_stage": dom},
     }
 
     # ---- calibration copy of known size for the HBM counters (profile runs)

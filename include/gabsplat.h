@@ -221,11 +221,16 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
  *   final_T   [sum over views of H*W]
  *   n_contrib [sum over views of H*W]  1-based position, in the tile's list,
  *             of the last blended primitive (0 = none)
+ *   eval_counts  NULL, or [sum over views of H*W][2]: per pixel, the position
+ *             in its tile's list where the walk ended (the stopping primitive,
+ *             else the list length) and how many of those primitives passed
+ *             the envelope test o G >= 1/255 (the work the blend had to do)
  *   d_overflow  from gabsplat_bin_sort (device). */
 gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals,
                                     const uint32_t* tile_ranges, const gabsplat_camera* cams,
                                     int32_t num_views, float* image, float* final_T,
-                                    uint32_t* n_contrib, const int32_t* d_overflow, void* stream);
+                                    uint32_t* n_contrib, uint32_t* eval_counts,
+                                    const int32_t* d_overflow, void* stream);
 
 /* K7 + K8, backward of the forward above w.r.t. every attribute.  K7 walks
  * each tile back to front from n_contrib, recovers the transmittance by

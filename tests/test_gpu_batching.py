@@ -1,0 +1,105 @@
+"""Batched launches: several views of one scene (training) and several scenes
+per launch (serving)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gabor_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "scales", "quats", "opacities", "sh", "freqs", "weights")
+
+
+def test_multiview_backward_sums_views(gpu_lib):
+    """One preprocess / bin sort / blend / backward launch over 3 views: the
+    scene gradients equal the sum over views of the oracle's per-view exact
+    gradients."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    sc = synth.uniform_scene(51, 400, 2, sh_degree=1, log_scale_mu=-2.8)
+    cams = [synth.pinhole_camera(48, 40, 60.0, (0.0, 0.0, -3.0), (0, 0, 0), bg=(0.2, 0.2, 0.2)),
+            synth.pinhole_camera(37, 52, 55.0, (1.5, -0.5, -2.5), (0, 0, 0)),
+            synth.pinhole_camera(64, 33, 50.0, (-2.0, 0.3, -2.0), (0.1, 0, 0), bg=(1.0, 1.0, 1.0))]
+    ds = DeviceScene.from_host(sc)
+    plan = RenderPlan([ds], cams, [0, 0, 0])
+    plan.forward()
+    gs_img = [synth.random_dl_dimage(60 + v, (3, c.height, c.width)) for v, c in enumerate(cams)]
+    flat = np.concatenate([g.reshape(-1) for g in gs_img]).astype(np.float32)
+    grads = {n: torch.zeros_like(getattr(ds, n)) for n in NAMES}
+    plan.backward(torch.from_numpy(flat).cuda(), [grads], accumulate=False)
+    torch.cuda.synchronize()
+    ref = None
+    for c, g in zip(cams, gs_img):
+        r = O.render_grads(sc, c, g, "binned")
+        ref = r if ref is None else {k: ref[k] + r[k] for k in ref}
+    n = sc.n
+    gpu = dict(means=grads["means"].cpu().numpy().T, scales=grads["scales"].cpu().numpy().T,
+               quats=grads["quats"].cpu().numpy().T, opacities=grads["opacities"].cpu().numpy(),
+               sh=grads["sh"].cpu().numpy().reshape(4, 3, n).transpose(2, 0, 1),
+               freqs=grads["freqs"].cpu().numpy().reshape(2, 3, n).transpose(2, 0, 1),
+               weights=grads["weights"].cpu().numpy().T)
+    for k in NAMES:
+        rel = np.linalg.norm(gpu[k] - ref[k]) / np.linalg.norm(ref[k])
+        assert rel <= 1e-3, (k, rel)
+
+
+def test_accumulate_adds_to_existing_gradients(gpu_lib):
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    sc = synth.uniform_scene(52, 300, 2, sh_degree=0)
+    cam = synth.pinhole_camera(40, 40, 60.0, (0.0, 0.0, -3.0), (0, 0, 0))
+    ds = DeviceScene.from_host(sc)
+    plan = RenderPlan([ds], [cam])
+    plan.forward()
+    g = torch.from_numpy(synth.random_dl_dimage(61, (3 * 40 * 40,))).cuda()
+    a = {n: torch.zeros_like(getattr(ds, n)) for n in NAMES}
+    plan.backward(g, [a], accumulate=False)
+    b = {n: torch.full_like(getattr(ds, n), 7.0) for n in NAMES}
+    plan.backward(g, [b], accumulate=False)  # overwrite: the 7s are gone
+    c = {n: torch.ones_like(getattr(ds, n)) for n in NAMES}
+    plan.backward(g, [c], accumulate=True)   # accumulate: 1 + gradient
+    torch.cuda.synchronize()
+    for n in NAMES:
+        assert torch.equal(a[n], b[n]), n
+        assert torch.allclose(c[n], 1.0 + a[n], rtol=0, atol=1e-6), n
+
+
+def test_serving_mix_equals_alone(gpu_lib):
+    """Requests for different scenes and resolutions batched into shared
+    launches render exactly what each renders alone."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
+    scenes = [synth.clustered_scene(3000 + s, n, k=4, sh_degree=3) for s, n in enumerate((20000, 50000, 30000))]
+    dss = [DeviceScene.from_host(s) for s in scenes]
+    reqs = synth.config5_requests(scenes, n_requests=40, qps=20000.0, seed=9,
+                                  resolutions=((64, 64), (100, 75), (160, 96)))
+    jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
+    sch = Scheduler([s.n for s in scenes], 1 << 33, max_slots=16, max_batch=8, max_inflight=2)
+    st = serve(jobs, GpuExecutor(dss, 2), sch, keep_results=True)
+    assert st.requests == 40 and st.batches < 40, "requests must have been batched"
+    for r in reqs:
+        plan = RenderPlan([dss[r.scene]], [r.camera])
+        alone = plan.forward().clone()
+        mixed = st.results[r.rid].reshape(-1)
+        assert torch.equal(alone[:mixed.numel()], mixed), r.rid
+
+
+def test_serving_alone_matches_oracle(gpu_lib):
+    """A served request (different scene per job in one launch) matches the
+    oracle render of its own scene and camera."""
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
+    scenes = [synth.clustered_scene(3100 + s, 3000, k=4, sh_degree=3, centre_box=1.5, box=3.0,
+                                    log_scale_mu=-3.0) for s in range(2)]
+    dss = [DeviceScene.from_host(s) for s in scenes]
+    cams = [synth.pinhole_camera(80, 60, 60.0, (0.0, 0.0, -5.0), (0, 0, 0)),
+            synth.pinhole_camera(72, 72, 50.0, (3.0, 1.0, -4.0), (0, 0, 0), bg=(0.5, 0.5, 0.5))]
+    jobs = [Job(0, 0, cams[0], 0.0), Job(1, 1, cams[1], 0.0), Job(2, 1, cams[0], 0.0)]
+    st = serve(jobs, GpuExecutor(dss, 1), Scheduler([3000, 3000], 1 << 33), keep_results=True)
+    for j in jobs:
+        ref = O.render_scene(scenes[j.scene], j.camera, "binned")
+        img = st.results[j.rid].cpu().numpy()
+        ok = ~ref.fragile
+        assert np.abs(img - ref.color.numpy())[:, ok].max() <= 1e-4
