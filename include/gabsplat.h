@@ -45,6 +45,8 @@ extern "C" {
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
 #define GABSPLAT_MAX_VIEWS 4096
+/* gabsplat_scene.flags */
+#define GABSPLAT_FLAG_ATTENUATION 1
 
 typedef enum {
   GABSPLAT_OK = 0,
@@ -67,12 +69,19 @@ typedef enum {
  *   freqs     [k][3][n] cycles per world unit (element (j, axis, i) at
  *                      (j*3 + axis)*n + i)
  *   weights   [k][n]   >= 0 (the DC weight is 1 - sum_j w_j)
+ *   flags     GABSPLAT_FLAG_ATTENUATION: keep, for every cosine term, the factor
+ *             exp(-2 pi^2 v_j) that the z-integration of supplementary A.2
+ *             produces (v_j the variance of f_j . x along the ray given the
+ *             image point) and the paper's final 2D primitive (Sec. 3.3.2)
+ *             drops; 0 reproduces the paper's primitive.
  * Limits: 0 <= k <= GABSPLAT_MAX_K, sh_degree in [0, 3] when sh != NULL,
- * 0 <= n < 2^31. */
+ * 0 <= n < 2^31.  All scenes of one call share k, the colour mode and flags. */
 typedef struct {
   int64_t n;
   int32_t k;
   int32_t sh_degree;
+  int32_t flags;
+  int32_t pad;
   const float* means;
   const float* scales;
   const float* quats;
@@ -109,7 +118,8 @@ typedef struct {
  *            [6..8] RGB colour
  *            [9]    DC weight 1 - sum_j w_j
  *            [10+3j .. 12+3j]  2D frequency (cycles/pixel, x then y) and
- *                   weight w_j of component j
+ *                   weight of component j's cosine (w_j, times its
+ *                   attenuation when GABSPLAT_FLAG_ATTENUATION is set)
  *          so o * G(p) = exp2(q(p - mu2d) + rec[5]).
  *   depth  [items] fp32 camera z, computed as ((r20 x + r21 y) + r22 z) + t2
  *          with one IEEE rounding per operation
@@ -136,8 +146,8 @@ typedef struct {
  * with accumulate == 0 they are overwritten, every primitive included (culled
  * ones get 0).  Entries may be NULL to skip that gradient (sh or colors must
  * match the scene's colour mode).  grad2d [items][gabsplat_grad2d_floats(k)]
- * is scratch that receives the image-plane gradients (mu2d, conic record
- * terms, log2 opacity, RGB, per component 2D frequency and weight); the call
+ * is scratch that receives the image-plane gradients, i.e. the gradient with
+ * respect to every field of the render record, in the record's order; the call
  * clears it first, and it may be read afterwards (e.g. the view-space
  * positional gradient used by density control).  All scenes of one call
  * share the same grad2d buffer. */
@@ -160,7 +170,7 @@ int32_t gabsplat_abi_version(void);
 const char* gabsplat_status_string(gabsplat_status s);
 /* Floats per render record for k components: round_up(10 + 3k, 4). */
 int32_t gabsplat_record_floats(int32_t k);
-/* Floats per item of the image-plane gradient: round_up(9 + 3k, 4). */
+/* Floats per item of the image-plane gradient: round_up(10 + 3k, 4). */
 int32_t gabsplat_grad2d_floats(int32_t k);
 /* Bytes for gabsplat_geom.views. */
 size_t gabsplat_views_bytes(int32_t num_views, int32_t num_scenes);

@@ -178,17 +178,24 @@ class Projected:
     opac: torch.Tensor          # [n]
     rgb: torch.Tensor           # [n,3]
     f2d: torch.Tensor           # [n,K,2] cycles per pixel
-    w: torch.Tensor             # [n,K]
+    w: torch.Tensor             # [n,K] weights of the cosine terms (attenuated if requested)
     rect: np.ndarray            # [n,4] int64 tile rect x0,y0,x1,y1 (exclusive)
     tiles: np.ndarray           # [n] tiles touched (0 if invisible)
     fragile_rect: np.ndarray    # [n] bool: rect boundary within 2e-3 px of a pixel centre
     fragile_prim: np.ndarray    # [n] bool: ill-conditioned 2D frequency solve
 
 
-def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None) -> Projected:
+def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
+            attenuation: bool = False) -> Projected:
     """Per-primitive projection.  ``p`` holds fp64 tensors (possibly requiring
     grad); ``scene_f32`` supplies the float32 means/opacities for the fp32
-    decisions (defaults to rounding p's values, which are exact copies)."""
+    decisions (defaults to rounding p's values, which are exact copies).
+
+    attenuation=True keeps the factor the z-integration of supplementary A.2
+    produces for every cosine term and the paper's final 2D primitive drops:
+    w_k -> w_k exp(-2 pi^2 v_k), v_k = f_k^T Sigma f_k - (T Sigma f_k)^T
+    (T Sigma T^T)^-1 (T Sigma f_k), the variance of f_k . x along the ray
+    given the image-plane point (the DC weight 1 - sum w is unchanged)."""
     R, t = cam["R"], cam["t"]
     fx, fy, cx, cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
     W, H = cam["W"], cam["H"]
@@ -247,8 +254,15 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None) 
         fyp = (-rb[:, None] * g[..., 0] + ra[:, None] * g[..., 1]) / det_raw_safe[:, None]
         f2d = torch.stack([fxp, fyp], -1)
         f2d = torch.where((det_raw > 0)[:, None, None], f2d, torch.zeros_like(f2d))
+        w_cos = p["weights"]
+        if attenuation:
+            fSf = torch.einsum("nck,nkl,ncl->nc", p["freqs"], Sig, p["freqs"])
+            v = fSf - (g[..., 0] * fxp + g[..., 1] * fyp)  # g^T (T Sigma T^T)^-1 g = g . f2d
+            v = torch.where((det_raw > 0)[:, None], v, fSf)
+            w_cos = p["weights"] * torch.exp(-2.0 * math.pi ** 2 * v)
     else:
         f2d = torch.zeros((n, 0, 2), dtype=DT)
+        w_cos = p["weights"]
 
     # colour
     if "sh" in p:
@@ -284,9 +298,11 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None) 
                 return np.abs(v - np.round(v)) < 2e-3
         fr = vis & (near_int(bx0) | near_int(bx1) | near_int(by0) | near_int(by1))
         fp = vis & cond_bad.numpy()
-    return Projected(visible=torch.from_numpy(vis), depth32=depth32, mu2d=mu2d, cov2d_raw=cov_raw,
-                     conic=conic, opac=p["opacities"], rgb=rgb, f2d=f2d, w=p["weights"],
-                     rect=rect, tiles=tiles.astype(np.int64), fragile_rect=fr, fragile_prim=fp)
+    pr = Projected(visible=torch.from_numpy(vis), depth32=depth32, mu2d=mu2d, cov2d_raw=cov_raw,
+                   conic=conic, opac=p["opacities"], rgb=rgb, f2d=f2d, w=w_cos,
+                   rect=rect, tiles=tiles.astype(np.int64), fragile_rect=fr, fragile_prim=fp)
+    pr.w_dc = 1.0 - p["weights"].sum(-1)  # DC weight, never attenuated
+    return pr
 
 
 # --------------------------------------------------------------------------
@@ -363,7 +379,7 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
     if w.shape[1] > 0:
         f = pr.f2d[ci]
         phase = f[None, :, :, 0] * dx[..., None] + f[None, :, :, 1] * dy[..., None]
-        Bk = (1.0 - w.sum(-1))[None, :] + (w[None] * torch.cos(2.0 * math.pi * phase)).sum(-1)
+        Bk = pr.w_dc[ci][None, :] + (w[None] * torch.cos(2.0 * math.pi * phase)).sum(-1)
     else:
         Bk = torch.ones_like(G)
     a_raw = pr.opac[ci][None, :] * G * Bk
@@ -408,11 +424,11 @@ def blend_pixel_loop(pr: Projected, cand: Sequence[int], x: float, y: float, bg)
         a, b, c = (float(v) for v in pr.conic[i])
         dx, dy = x - mx, y - my
         G = math.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
-        Bv = 1.0
+        Bv = float(pr.w_dc[i])
         for k in range(pr.w.shape[1]):
             wk = float(pr.w[i, k])
             ph = float(pr.f2d[i, k, 0]) * dx + float(pr.f2d[i, k, 1]) * dy
-            Bv += wk * (math.cos(2 * math.pi * ph) - 1.0)
+            Bv += wk * math.cos(2 * math.pi * ph)
         alpha = min(ALPHA_MAX, float(pr.opac[i]) * G * Bv)
         if alpha < ALPHA_MIN:
             continue
@@ -453,13 +469,13 @@ def tile_candidates(pr: Projected, order: np.ndarray, tx: int, ty: int) -> np.nd
 
 def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binned",
            tiles: Optional[Sequence[tuple]] = None, scene_f32=None, pr: Optional[Projected] = None,
-           chunk: int = 4096) -> Image:
+           chunk: int = 4096, attenuation: bool = False) -> Image:
     """Render the whole image (or only the listed tiles; other pixels are NaN).
     mode 'brute': every visible primitive at every pixel; 'binned': per-tile
     candidate lists from the tile rects (exact culling: the rect covers every
     pixel where o G >= 1/255)."""
     if pr is None:
-        pr = project(p, cam, scene_f32)
+        pr = project(p, cam, scene_f32, attenuation)
     W, H = cam["W"], cam["H"]
     bg = cam["bg"]
     order = depth_order(pr.depth32, pr.visible.numpy())
@@ -501,10 +517,11 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
                  nbl.reshape(H, W), frag.reshape(H, W))
 
 
-def render_scene(scene, cam, mode="binned", tiles=None) -> Image:
+def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False) -> Image:
     """Convenience: numpy scene/camera objects -> fp64 image."""
     with torch.no_grad():
-        return render(scene_tensors(scene), camera_tensors(cam), mode, tiles, scene_f32=scene)
+        return render(scene_tensors(scene), camera_tensors(cam), mode, tiles, scene_f32=scene,
+                      attenuation=attenuation)
 
 
 # --------------------------------------------------------------------------
@@ -513,11 +530,11 @@ def render_scene(scene, cam, mode="binned", tiles=None) -> Image:
 GRAD_NAMES = ("means", "scales", "quats", "opacities", "colors", "sh", "freqs", "weights")
 
 
-def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned") -> Dict[str, np.ndarray]:
+def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned", attenuation=False) -> Dict[str, np.ndarray]:
     """d(sum dl_dimage * C)/d(params) for every activated attribute (fp64)."""
     p = scene_tensors(scene, requires_grad=True)
     ct = camera_tensors(cam)
-    img = render(p, ct, mode, scene_f32=scene)
+    img = render(p, ct, mode, scene_f32=scene, attenuation=attenuation)
     g = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
     (img.color * g).sum().backward()
     return {k: v.grad.numpy() for k, v in p.items()}
@@ -531,12 +548,14 @@ def _take(pr: Projected, rows: np.ndarray, local_i: int, one: Projected) -> Proj
     def pick(full, single):
         f = full.detach()[r].clone()
         return torch.cat([f[:local_i], single, f[local_i + 1:]], 0)
-    return Projected(visible=pr.visible[r], depth32=pr.depth32[rows],
-                     mu2d=pick(pr.mu2d, one.mu2d), cov2d_raw=pr.cov2d_raw.detach()[r],
-                     conic=pick(pr.conic, one.conic), opac=pick(pr.opac, one.opac),
-                     rgb=pick(pr.rgb, one.rgb), f2d=pick(pr.f2d, one.f2d), w=pick(pr.w, one.w),
-                     rect=pr.rect[rows], tiles=pr.tiles[rows], fragile_rect=pr.fragile_rect[rows],
-                     fragile_prim=pr.fragile_prim[rows])
+    out = Projected(visible=pr.visible[r], depth32=pr.depth32[rows],
+                    mu2d=pick(pr.mu2d, one.mu2d), cov2d_raw=pr.cov2d_raw.detach()[r],
+                    conic=pick(pr.conic, one.conic), opac=pick(pr.opac, one.opac),
+                    rgb=pick(pr.rgb, one.rgb), f2d=pick(pr.f2d, one.f2d), w=pick(pr.w, one.w),
+                    rect=pr.rect[rows], tiles=pr.tiles[rows], fragile_rect=pr.fragile_rect[rows],
+                    fragile_prim=pr.fragile_prim[rows])
+    out.w_dc = pick(pr.w_dc, one.w_dc)
+    return out
 
 
 def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[int],

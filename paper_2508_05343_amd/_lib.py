@@ -24,6 +24,7 @@ EXPORTS = (
 )
 
 OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE = range(6)
+FLAG_ATTENUATION = 1
 
 
 class GabsplatError(RuntimeError):
@@ -33,7 +34,7 @@ class GabsplatError(RuntimeError):
 
 
 class Scene(ctypes.Structure):
-    _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32),
+    _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32), ("flags", c_int32), ("pad", c_int32),
                 ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
                 ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p)]
 

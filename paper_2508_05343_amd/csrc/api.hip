@@ -89,16 +89,18 @@ gabsplat_status build_table(const gabsplat_scene* scenes, int32_t num_scenes, co
   const int32_t k = scenes[0].k;
   const bool use_sh = scenes[0].sh != nullptr;
   const int32_t deg = use_sh ? scenes[0].sh_degree : -1;
+  const int32_t flags = scenes[0].flags;
   tb.scenes.resize(num_scenes);
   for (int i = 0; i < num_scenes; ++i) {
     const gabsplat_scene& s = scenes[i];
     if (!valid_scene(s)) return GABSPLAT_ERR_INVALID_ARGUMENT;
-    if (s.k != k || (s.sh != nullptr) != use_sh || (use_sh && s.sh_degree != deg))
+    if (s.k != k || (s.sh != nullptr) != use_sh || (use_sh && s.sh_degree != deg) || s.flags != flags ||
+        (s.flags & ~GABSPLAT_FLAG_ATTENUATION) != 0)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     SceneEntry& e = tb.scenes[i];
     e.means = s.means; e.scales = s.scales; e.quats = s.quats; e.opac = s.opacities;
     e.sh = s.sh; e.colors = s.colors; e.freqs = s.freqs; e.weights = s.weights;
-    e.n = s.n; e.k = s.k; e.sh_degree = deg;
+    e.n = s.n; e.k = s.k; e.sh_degree = deg; e.flags = s.flags; e.pad = 0;
   }
   tb.views.resize(num_views);
   int64_t items = 0, pixels = 0, tiles = 0;

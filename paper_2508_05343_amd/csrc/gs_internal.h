@@ -32,6 +32,8 @@ struct SceneEntry {
   int64_t n;
   int32_t k;
   int32_t sh_degree;  // -1 for precomputed colours
+  int32_t flags;      // GABSPLAT_FLAG_*
+  int32_t pad;
 };
 
 // One view (camera + where its items, tiles and pixels live).
@@ -72,7 +74,7 @@ __host__ __device__ inline const SceneEntry* table_scenes(const void* t, int num
 }
 
 inline int record_floats(int k) { return (10 + 3 * k + 3) & ~3; }
-inline int grad2d_floats(int k) { return (9 + 3 * k + 3) & ~3; }
+inline int grad2d_floats(int k) { return (10 + 3 * k + 3) & ~3; }
 
 // Host-side packed copy of the table (built by the API layer).
 struct HostTable {

@@ -188,6 +188,30 @@ __device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my,
   }
 }
 
+constexpr float kTwoPiSq = 19.739208802178716f;  // 2 pi^2
+
+__device__ __forceinline__ V3 mat_vec(const float (&M)[3][3], V3 x) {
+  return v3(M[0][0] * x.x + M[0][1] * x.y + M[0][2] * x.z, M[1][0] * x.x + M[1][1] * x.y + M[1][2] * x.z,
+            M[2][0] * x.x + M[2][1] * x.y + M[2][2] * x.z);
+}
+__device__ __forceinline__ V3 mat_t_vec(const float (&M)[3][3], V3 x) {
+  return v3(M[0][0] * x.x + M[1][0] * x.y + M[2][0] * x.z, M[0][1] * x.x + M[1][1] * x.y + M[2][1] * x.z,
+            M[0][2] * x.x + M[1][2] * x.y + M[2][2] * x.z);
+}
+
+// Variance along the ray of f . x given the image point: with A = T M and
+// c = r0 x r1 spanning A's null space, f^T Sigma f - (T Sigma f)^T (T Sigma
+// T^T)^-1 T Sigma f = (M^T f . c)^2 / |c|^2 = (f . M c)^2 / D.  For a
+// degenerate 2D footprint (D = 0) the whole f^T Sigma f remains.
+__device__ __forceinline__ float ray_variance(const Geo& g, V3 u, V3 f) {
+  if (g.D > 0.f) {
+    const float s = dot3(f, u);
+    return s * s / g.D;
+  }
+  const V3 mf = mat_t_vec(g.M, f);
+  return dot3(mf, mf);
+}
+
 // ------------------------------------------------------------------ K1
 // Two phases per block of 1024 items.  Phase 1 (every item, coalesced): depth
 // key, near and opacity culls, and a conservative screen test: the 2D
@@ -332,6 +356,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         r[8] = S.colors[2 * n + i];
       }
       float wsum = 0.f;
+      const bool atten = (S.flags & GABSPLAT_FLAG_ATTENUATION) != 0;
+      const V3 u = mat_vec(g.M, g.c);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
@@ -339,7 +365,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         const float wk = S.weights[(int64_t)k * n + i];
         r[10 + 3 * k] = dot3(g.vx, f);
         r[11 + 3 * k] = dot3(g.vy, f);
-        r[12 + 3 * k] = wk;
+        r[12 + 3 * k] = atten ? wk * __expf(-kTwoPiSq * ray_variance(g, u, f)) : wk;
         wsum += wk;
       }
       r[9] = 1.0f - wsum;
@@ -367,7 +393,7 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
                                                    const float* __restrict__ depth,
                                                    const float* __restrict__ grad2d,
                                                    const gabsplat_scene_grads& gr, int64_t i) {
-  constexpr int GF = (9 + 3 * K + 3) & ~3;
+  constexpr int GF = (10 + 3 * K + 3) & ~3;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
@@ -432,36 +458,62 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
 #pragma unroll
       for (int b = 0; b < 3; ++b) gM[a][b] = 0.f;
 
-    // ---- 2D frequencies f2d_k = (vx . f_k, vy . f_k)
-    if (K > 0 && g.D > 0.f) {
-      V3 gvx = v3(0.f, 0.f, 0.f), gvy = v3(0.f, 0.f, 0.f);
+    // ---- 2D frequencies f2d_k = (vx . f_k, vy . f_k) and cosine weights
+    // record weight w'_k = w_k a_k (a_k = exp(-2 pi^2 v_k) or 1), DC weight 1 - sum w
+    const bool atten = (S.flags & GABSPLAT_FLAG_ATTENUATION) != 0;
+    const V3 u = mat_vec(g.M, g.c);
+    V3 gu = v3(0.f, 0.f, 0.f);
+    float gD_att = 0.f;
+    V3 gvx = v3(0.f, 0.f, 0.f), gvy = v3(0.f, 0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
-                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
-        const float gx = G2[9 + 3 * k], gy = G2[10 + 3 * k];
-        gvx = add3(gvx, scale3(f, gx));
-        gvy = add3(gvy, scale3(f, gy));
-        gf[k] = add3(gf[k], add3(scale3(g.vx, gx), scale3(g.vy, gy)));
-        gw[k] += G2[11 + 3 * k];
+    for (int k = 0; k < K; ++k) {
+      const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
+                      S.freqs[(int64_t)(3 * k + 2) * n + i]);
+      const float gx = G2[10 + 3 * k], gy = G2[11 + 3 * k], gwr = G2[12 + 3 * k];
+      gvx = add3(gvx, scale3(f, gx));
+      gvy = add3(gvy, scale3(f, gy));
+      gf[k] = add3(gf[k], add3(scale3(g.vx, gx), scale3(g.vy, gy)));
+      if (atten) {
+        const float wk = S.weights[(int64_t)k * n + i];
+        const float v = ray_variance(g, u, f);
+        const float a = __expf(-kTwoPiSq * v);
+        gw[k] += gwr * a - G2[9];
+        const float gv_ = -kTwoPiSq * a * wk * gwr;  // dL/dv_k
+        if (g.D > 0.f) {
+          const float sdot = dot3(f, u);
+          const float c2 = 2.f * sdot / g.D * gv_;
+          gf[k] = add3(gf[k], scale3(u, c2));
+          gu = add3(gu, scale3(f, c2));
+          gD_att += -gv_ * v / g.D;
+        } else {
+          // v = |M^T f|^2: dv/df = 2 M M^T f, dv/dM = 2 f (M^T f)^T
+          const V3 mf = mat_t_vec(g.M, f);
+          gf[k] = add3(gf[k], scale3(mat_vec(g.M, mf), 2.f * gv_));
+          const float fa[3] = {f.x, f.y, f.z}, ma[3] = {mf.x, mf.y, mf.z};
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 3; ++b2) gM[a2][b2] += 2.f * gv_ * fa[a2] * ma[b2];
+        }
+      } else {
+        gw[k] += gwr - G2[9];
       }
+    }
+    if (K > 0 && g.D > 0.f) {
       const float iD = 1.0f / g.D;
       const float gvxa[3] = {gvx.x, gvx.y, gvx.z}, gvya[3] = {gvy.x, gvy.y, gvy.z};
       const float uxa[3] = {g.ux_.x, g.ux_.y, g.ux_.z}, uya[3] = {g.uy_.x, g.uy_.y, g.uy_.z};
+      const float gua[3] = {gu.x, gu.y, gu.z}, ca[3] = {g.c.x, g.c.y, g.c.z};
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) gM[a][b] += (gvxa[a] * uxa[b] + gvya[a] * uya[b]) * iD;
+        for (int b = 0; b < 3; ++b) gM[a][b] += (gvxa[a] * uxa[b] + gvya[a] * uya[b]) * iD + gua[a] * ca[b];
       // M^T gvx / D, M^T gvy / D
-      V3 gux = v3((g.M[0][0] * gvx.x + g.M[1][0] * gvx.y + g.M[2][0] * gvx.z) * iD,
-                  (g.M[0][1] * gvx.x + g.M[1][1] * gvx.y + g.M[2][1] * gvx.z) * iD,
-                  (g.M[0][2] * gvx.x + g.M[1][2] * gvx.y + g.M[2][2] * gvx.z) * iD);
-      V3 guy = v3((g.M[0][0] * gvy.x + g.M[1][0] * gvy.y + g.M[2][0] * gvy.z) * iD,
-                  (g.M[0][1] * gvy.x + g.M[1][1] * gvy.y + g.M[2][1] * gvy.z) * iD,
-                  (g.M[0][2] * gvy.x + g.M[1][2] * gvy.y + g.M[2][2] * gvy.z) * iD);
-      const float gD = -(dot3(g.vx, gvx) + dot3(g.vy, gvy)) * iD;
-      // ux_ = r1 x c ; uy_ = c x r0 ; D = c.c ; c = r0 x r1
-      V3 gc = v3(0.f, 0.f, 0.f);
+      const V3 gux = scale3(mat_t_vec(g.M, gvx), iD);
+      const V3 guy = scale3(mat_t_vec(g.M, gvy), iD);
+      const float gD = -(dot3(g.vx, gvx) + dot3(g.vy, gvy)) * iD + gD_att;
+      // ux_ = r1 x c ; uy_ = c x r0 ; u = M c ; D = c.c ; c = r0 x r1
+      V3 gc = mat_t_vec(g.M, gu);
       gr1 = add3(gr1, cross3(g.c, gux));
       gc = add3(gc, cross3(gux, g.r1));
       gc = add3(gc, cross3(g.r0, guy));
@@ -469,9 +521,6 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
       gc = add3(gc, scale3(g.c, 2.f * gD));
       gr0 = add3(gr0, cross3(g.r1, gc));
       gr1 = add3(gr1, cross3(gc, g.r0));
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) gw[k] += G2[11 + 3 * k];
     }
 
     // ---- A = T M: rows r0 = T0 M, r1 = T1 M

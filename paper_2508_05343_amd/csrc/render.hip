@@ -48,22 +48,40 @@ struct Rec {
 
 // Bit q (q = 0..3, quadrant (q & 1, q >> 1) of 8x8 pixels of the tile whose
 // top-left pixel is (ox, oy)) is set when the record's support o G >= 1/255
-// can reach a pixel centre of that quadrant: the axis-aligned box of the
-// ellipse {q(d) + log2 o >= log2(1/255)} (widened by a small margin so that the
-// per-pixel test stays the only decision) is tested against the quadrant.
+// can reach a pixel centre of that quadrant.  With Q(d) = -(a dx^2 + b dx dy +
+// c dy^2) (positive definite) the support is {Q(d) <= R}, R = log2 o -
+// log2(1/255); the quadrant is reached iff the minimum of Q over its rectangle
+// of pixel centres is <= R.  A convex quadratic attains that minimum at the
+// origin when the origin is inside, else on an edge, where it is the clamped
+// one-dimensional minimiser.  A small relative margin keeps the per-pixel test
+// the only decision.
+__device__ __forceinline__ float edge_min_x(float a, float b, float c, float X, float y0, float y1) {
+  const float y = fminf(fmaxf(-b * X / (2.0f * c), y0), y1);
+  return fmaf(fmaf(a, X, b * y), X, c * y * y);
+}
+__device__ __forceinline__ float edge_min_y(float a, float b, float c, float Y, float x0, float x1) {
+  const float x = fminf(fmaxf(-b * Y / (2.0f * a), x0), x1);
+  return fmaf(fmaf(a, x, b * Y), x, c * Y * Y);
+}
+
 __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float ox, float oy) {
-  const float a = -r0.z, b = -r0.w, c = -r1.x;  // positive definite form a dx^2 + b dx dy + c dy^2
-  const float R = r1.y - kLog2AlphaMin;         // log2 o - log2(1/255)
-  const float det = a * c - 0.25f * b * b;
-  if (!(R > 0.f) || !(det > 0.f)) return 0u;
-  const float rx = sqrtf(R * c / det) * 1.001f + 1e-3f;
-  const float ry = sqrtf(R * a / det) * 1.001f + 1e-3f;
+  const float a = -r0.z, b = -r0.w, c = -r1.x;
+  const float R = r1.y - kLog2AlphaMin;
+  if (!(R > 0.f) || !(a > 0.f) || !(c > 0.f)) return 0u;
+  const float lim = R * 1.002f + 1e-4f;
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float x0 = ox + 8.0f * (q & 1) + 0.5f, y0 = oy + 8.0f * (q >> 1) + 0.5f;
-    const bool hit = (x0 <= r0.x + rx) && (x0 + 7.0f >= r0.x - rx) && (y0 <= r0.y + ry) && (y0 + 7.0f >= r0.y - ry);
-    m |= hit ? (1u << q) : 0u;
+    const float x0 = ox + 8.0f * (q & 1) + 0.5f - r0.x, x1 = x0 + 7.0f;
+    const float y0 = oy + 8.0f * (q >> 1) + 0.5f - r0.y, y1 = y0 + 7.0f;
+    float mn;
+    if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) {
+      mn = 0.f;
+    } else {
+      mn = fminf(fminf(edge_min_x(a, b, c, x0, y0, y1), edge_min_x(a, b, c, x1, y0, y1)),
+                 fminf(edge_min_y(a, b, c, y0, x0, x1), edge_min_y(a, b, c, y1, x0, x1)));
+    }
+    m |= (mn <= lim) ? (1u << q) : 0u;
   }
   return m;
 }
@@ -237,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
                                                        const int32_t* __restrict__ d_overflow) {
   constexpr int RF = Rec<K>::RF;
   constexpr int R4 = RF / 4;
-  constexpr int GS = 9 + 3 * K;            // gradient components per pair
+  constexpr int GS = 10 + 3 * K;           // gradient components per pair (one per record field)
   constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
   constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
   __shared__ float4 s_rec[kBlock * R4];
@@ -362,15 +380,16 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
           gv[5] = dp;
           float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
           float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
+          gv[9] = dB;  // DC weight
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             const float fkx = r[10 + 3 * k], fky = r[11 + 3 * k], wk = r[12 + 3 * k];
             const float ph = fmaf(fkx, dx, fky * dy);
             const float cs = cos_rev(ph), sn = sin_rev(ph);
-            gv[11 + 3 * k] = dB * (cs - 1.0f);
+            gv[12 + 3 * k] = dB * cs;
             const float dph = -dB * wk * 6.283185307179586f * sn;
-            gv[9 + 3 * k] = dph * dx;
-            gv[10 + 3 * k] = dph * dy;
+            gv[10 + 3 * k] = dph * dx;
+            gv[11 + 3 * k] = dph * dy;
             ddx = fmaf(dph, fkx, ddx);
             ddy = fmaf(dph, fky, ddy);
           }

@@ -26,7 +26,9 @@ class DeviceScene:
     means [3,n], scales [3,n], quats [4,n], opacities [n], sh [D*3,n] or
     colors [3,n], freqs [3K,n], weights [K,n]."""
 
-    def __init__(self, means, scales, quats, opacities, freqs, weights, sh=None, colors=None, sh_degree=-1):
+    def __init__(self, means, scales, quats, opacities, freqs, weights, sh=None, colors=None, sh_degree=-1,
+                 attenuation=False):
+        self.attenuation = bool(attenuation)
         self.means, self.scales, self.quats, self.opacities = means, scales, quats, opacities
         self.freqs, self.weights, self.sh, self.colors = freqs, weights, sh, colors
         self.sh_degree = sh_degree if sh is not None else -1
@@ -34,7 +36,7 @@ class DeviceScene:
         self.k = int(weights.shape[0])
 
     @staticmethod
-    def from_host(scene, device="cuda") -> "DeviceScene":
+    def from_host(scene, device="cuda", attenuation=False) -> "DeviceScene":
         """From AoS numpy arrays (synthetic generator layout)."""
         def planar(a):
             a = np.asarray(a, np.float32)
@@ -47,7 +49,7 @@ class DeviceScene:
                            torch.from_numpy(np.ascontiguousarray(scene.opacities, np.float32)).to(device),
                            planar(scene.freqs.reshape(n, -1)), planar(scene.weights), sh=sh,
                            colors=None if scene.colors is None else planar(scene.colors),
-                           sh_degree=scene.sh_degree if scene.sh is not None else -1)
+                           sh_degree=scene.sh_degree if scene.sh is not None else -1, attenuation=attenuation)
 
     def tensors(self):
         return [self.means, self.scales, self.quats, self.opacities, self.sh if self.sh is not None else self.colors,
@@ -56,6 +58,7 @@ class DeviceScene:
     def cstruct(self) -> _lib.Scene:
         s = _lib.Scene()
         s.n, s.k, s.sh_degree = self.n, self.k, max(self.sh_degree, 0)
+        s.flags = _lib.FLAG_ATTENUATION if self.attenuation else 0
         s.means, s.scales, s.quats = _lib.ptr(self.means), _lib.ptr(self.scales), _lib.ptr(self.quats)
         s.opacities = _lib.ptr(self.opacities)
         s.sh = _lib.ptr(self.sh) if self.sh is not None else None

@@ -580,3 +580,80 @@ def test_loss_identity_and_finite_differences():
     l1 = np.abs(x - y).mean()
     ss = O.ssim_map(torch.tensor(x), torch.tensor(y)).numpy().mean()
     assert abs(L - (0.8 * l1 + 0.2 * (1 - ss))) < 1e-14
+
+
+# ------------------------------------------------- attenuation-corrected variant
+def test_attenuation_closed_form_axis_aligned():
+    """Axis-aligned primitive on the optical axis: the z-integration multiplies
+    a cosine term by exp(-2 pi^2 f_z^2 s_z^2) (the variance of f . x along the
+    ray is f_z^2 s_z^2 there)."""
+    cam = axis_camera()
+    f = np.array([1.0, -2.0, 3.0])
+    s = np.array([0.1, 0.2, 0.15])
+    sc = make_scene([[0, 0, 3.0]], [s], [[1, 0, 0, 0]], [0.7], [[1, 1, 1]], [[f]], [[0.5]])
+    pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc, attenuation=True)
+    f32, s32 = f.astype(np.float32).astype(float), s.astype(np.float32).astype(float)
+    w32 = float(np.float32(0.5))
+    np.testing.assert_allclose(float(pr.w[0, 0]), w32 * math.exp(-2 * math.pi ** 2 * (f32[2] * s32[2]) ** 2),
+                               rtol=1e-12)
+    np.testing.assert_allclose(float(pr.w_dc[0]), 1 - w32, rtol=1e-15)
+
+
+def test_attenuated_primitive_equals_the_exact_z_integral():
+    """With attenuation the 2D Gabor primitive is the exact integral of the
+    ray-space 3D primitive along z (supplementary A.2 without dropping the
+    per-component factor), up to the common factor sqrt(2 pi / S_zz) that the
+    opacity absorbs: checked by fp64 quadrature of the whole filter bank."""
+    from scipy.integrate import quad
+    sc = synth.config1_scene()
+    cam = synth.config1_camera()
+    pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc, attenuation=True)
+    R = cam.R.astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(12))
+    for i in [7, 123, 456, 901]:
+        tc = R @ sc.means[i].astype(np.float64) + cam.t.astype(np.float64)
+        A = _full_jacobian(tc, cam.fx, cam.fy, tc / np.linalg.norm(tc)) @ R
+        Sig = O.covariance_3d(torch.tensor(sc.scales[i:i + 1].astype(np.float64)),
+                              torch.tensor(sc.quats[i:i + 1].astype(np.float64))).numpy()[0]
+        S = np.linalg.inv(A @ Sig @ A.T)
+        fps = [np.linalg.inv(A).T @ sc.freqs[i, k].astype(np.float64) for k in range(sc.k)]
+        w = sc.weights[i].astype(np.float64)
+        sd = math.sqrt((A @ Sig @ A.T)[2, 2])
+        for _ in range(3):
+            d = rng.normal(0, 1.0, 2) * np.sqrt(np.diag((A @ Sig @ A.T)[:2, :2]))
+
+            def integrand(z):
+                x = np.array([d[0], d[1], z])
+                bank = (1 - w.sum()) + sum(w[k] * math.cos(2 * math.pi * fps[k] @ x) for k in range(sc.k))
+                return math.exp(-0.5 * x @ S @ x) * bank
+            val, _ = quad(integrand, -12 * sd, 12 * sd, limit=400, epsabs=1e-14, epsrel=1e-12)
+            g2 = math.exp(-0.5 * d @ np.linalg.inv(pr.cov2d_raw[i].numpy()) @ d)
+            bank2 = float(pr.w_dc[i]) + sum(float(pr.w[i, k]) * math.cos(2 * math.pi * pr.f2d[i, k].numpy() @ d)
+                                           for k in range(sc.k))
+            pred = math.sqrt(2 * math.pi / S[2, 2]) * g2 * bank2
+            assert abs(val - pred) <= 1e-9 * math.sqrt(2 * math.pi / S[2, 2])
+
+
+def test_attenuation_gradients_match_finite_differences():
+    sc = tiny_scene(26)
+    cam = axis_camera(bg=(0.1, 0.4, 0.2))
+    g = synth.random_dl_dimage(13, (3, 32, 32))
+    an = O.render_grads(sc, cam, g, mode="brute", attenuation=True)
+    rng = np.random.Generator(np.random.PCG64(14))
+    for name in ("means", "scales", "quats", "freqs", "weights"):
+        arr = getattr(sc, name)
+        for _ in range(5):
+            idx = tuple(rng.integers(0, s_) for s_ in arr.shape)
+            p = O.scene_tensors(sc)
+            base = p[name][idx].item()
+            h = 1e-6 * max(1.0, abs(base))
+            vals = []
+            for sgn in (+1, -1):
+                p2 = {k: v.clone() for k, v in p.items()}
+                p2[name][idx] = base + sgn * h
+                with torch.no_grad():
+                    img = O.render(p2, O.camera_tensors(cam), "brute", scene_f32=sc, attenuation=True)
+                vals.append(float((img.color.numpy() * g).sum()))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            a = an[name][idx]
+            assert abs(fd - a) <= 1e-5 * (abs(a) + 1e-4), (name, idx, fd, a)
