@@ -61,9 +61,11 @@ def test_accumulate_adds_to_existing_gradients(gpu_lib):
     c = {n: torch.ones_like(getattr(ds, n)) for n in NAMES}
     plan.backward(g, [c], accumulate=True)   # accumulate: 1 + gradient
     torch.cuda.synchronize()
+    # fp32 atomics make two backward passes agree only to rounding
     for n in NAMES:
-        assert torch.equal(a[n], b[n]), n
-        assert torch.allclose(c[n], 1.0 + a[n], rtol=0, atol=1e-6), n
+        scale = float(a[n].abs().max())
+        assert float((a[n] - b[n]).abs().max()) <= 1e-5 * scale, n  # no 7s left
+        assert float((c[n] - 1.0 - a[n]).abs().max()) <= 1e-5 * scale + 1e-6, n
 
 
 def test_serving_mix_equals_alone(gpu_lib):
