@@ -270,6 +270,76 @@ gabsplat_status gabsplat_loss_l1_dssim(const float* x, const float* y, int32_t c
                                        int32_t height, int32_t width, float lambda, float* d_loss,
                                        float* dl_dx, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------ density control (Sec. 3.4.2)
+ * The paper densifies as 3DGS does (clone small / split large primitives whose
+ * mean view-space positional gradient exceeds a threshold, prune transparent
+ * ones) and resets the frequencies and frequency weights of every newly
+ * generated child to small values; every few thousand iterations it resets all
+ * frequency weights together with the opacity reset. */
+typedef struct {
+  float grad_threshold;  /* on the mean view-space (NDC) gradient norm, e.g. 0.0002 */
+  float percent_dense;   /* clone if max scale <= percent_dense * extent, else split */
+  float scene_extent;
+  float min_opacity;     /* prune below (0.01 in the paper's supplement) */
+  float max_world_frac;  /* with prune_big: prune if max scale > max_world_frac * extent */
+  int32_t prune_big;
+  float freq_reset;      /* every axis of every frequency of a new child (0.001) */
+  float weight_reset;    /* every frequency weight of a new child (0.01) */
+  float split_shrink;    /* child scale factor (1 / 1.6) */
+  int32_t split_count;   /* children per split primitive (2), 1..8 */
+} gabsplat_densify_params;
+
+/* Writable scene buffers (same layout and meaning as gabsplat_scene). */
+typedef struct {
+  int64_t n;
+  int32_t k;
+  int32_t sh_degree;
+  int32_t flags;
+  int32_t pad;
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+  float* colors;
+  float* freqs;
+  float* weights;
+} gabsplat_scene_out;
+
+/* accum[i] += |dL/d mu2d| in normalised device coordinates (the pixel
+ * gradient from grad2d scaled by (W/2, H/2)) and denom[i] += 1 for every view
+ * of `geom` (one scene of n primitives, views as given to the preprocess that
+ * wrote geom) in which primitive i is visible. */
+gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat_camera* cams,
+                                       int32_t num_views, int64_t n, const float* grad2d, float* accum,
+                                       float* denom, void* stream);
+
+/* Clone / split / prune.  Decision per primitive, in order: prune if opacity <
+ * min_opacity (or too large, with prune_big); else clone if accum/denom >=
+ * grad_threshold and max scale <= percent_dense * extent; split if the
+ * threshold is met and the primitive is larger; keep otherwise.  Output rows:
+ * kept and cloned primitives unchanged (ascending source index), then one copy
+ * of each cloned primitive, then split_count children of each split primitive
+ * with mean + R(q)(s * z_c) (z_c = normals[c][.][i], standard normal draws
+ * supplied by the caller) and scale s * split_shrink.  Every new row (clone
+ * copy or split child) gets frequencies freq_reset and weights weight_reset.
+ * out: arrays of out_capacity rows; they are written with the planar stride
+ * n_out (the output count, written to *d_n_out).  src_index / tag [n_out]:
+ * source primitive and 0 kept, 1 clone copy, 2 + c split child c (use them to
+ * carry per-primitive optimizer state).  *d_overflow = 1 (and nothing
+ * written) if n_out > out_capacity.  ws >= gabsplat_densify_workspace_size(n). */
+size_t gabsplat_densify_workspace_size(int64_t n);
+gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, const float* denom,
+                                 const float* normals, const gabsplat_densify_params* params,
+                                 const gabsplat_scene_out* out, int64_t out_capacity, uint32_t* src_index,
+                                 uint32_t* tag, int64_t* d_n_out, int32_t* d_overflow, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Periodic reset: every frequency weight := weight_value, opacity :=
+ * min(opacity, opacity_cap). */
+gabsplat_status gabsplat_reset_frequency_weights(const gabsplat_scene_out* scene, float weight_value,
+                                                 float opacity_cap, void* stream);
+
 /* Reads *d_overflow synchronously (waits for `stream`); returns
  * GABSPLAT_ERR_CAPACITY_EXCEEDED if it is set, GABSPLAT_OK otherwise. */
 gabsplat_status gabsplat_read_overflow(const int32_t* d_overflow, void* stream);

@@ -21,6 +21,8 @@ EXPORTS = (
     "gabsplat_views_bytes", "gabsplat_bin_sort_workspace_size", "gabsplat_check_device",
     "gabsplat_preprocess", "gabsplat_bin_sort", "gabsplat_render_fwd", "gabsplat_render_bwd",
     "gabsplat_loss_workspace_size", "gabsplat_loss_l1_dssim", "gabsplat_read_overflow",
+    "gabsplat_densify_stats", "gabsplat_densify_workspace_size", "gabsplat_densify",
+    "gabsplat_reset_frequency_weights",
 )
 
 OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE = range(6)
@@ -54,6 +56,19 @@ class SceneGrads(ctypes.Structure):
     _fields_ = [("accumulate", c_int32), ("pad", c_int32), ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
                 ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p),
                 ("grad2d", c_void_p)]
+
+
+class DensifyParams(ctypes.Structure):
+    _fields_ = [("grad_threshold", c_float), ("percent_dense", c_float), ("scene_extent", c_float),
+                ("min_opacity", c_float), ("max_world_frac", c_float), ("prune_big", c_int32),
+                ("freq_reset", c_float), ("weight_reset", c_float), ("split_shrink", c_float),
+                ("split_count", c_int32)]
+
+
+class SceneOut(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32), ("flags", c_int32), ("pad", c_int32),
+                ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+                ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -99,6 +114,17 @@ def lib() -> ctypes.CDLL:
                                          c_void_p, c_void_p, c_size_t, c_void_p]
     L.gabsplat_read_overflow.restype = c_int32
     L.gabsplat_read_overflow.argtypes = [c_void_p, c_void_p]
+    L.gabsplat_densify_stats.restype = c_int32
+    L.gabsplat_densify_stats.argtypes = [POINTER(Geom), POINTER(Camera), c_int32, c_int64, c_void_p, c_void_p,
+                                         c_void_p, c_void_p]
+    L.gabsplat_densify_workspace_size.restype = c_size_t
+    L.gabsplat_densify_workspace_size.argtypes = [c_int64]
+    L.gabsplat_densify.restype = c_int32
+    L.gabsplat_densify.argtypes = [POINTER(Scene), c_void_p, c_void_p, c_void_p, POINTER(DensifyParams),
+                                   POINTER(SceneOut), c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]
+    L.gabsplat_reset_frequency_weights.restype = c_int32
+    L.gabsplat_reset_frequency_weights.argtypes = [POINTER(SceneOut), c_float, c_float, c_void_p]
     _LIB = L
     return L
 
@@ -199,6 +225,29 @@ def gabsplat_loss_l1_dssim(x, y, lam: float, d_loss, dl_dx, ws, stream=None):
     _check(lib().gabsplat_loss_l1_dssim(ptr(x), ptr(y), c, h, w, float(lam), ptr(d_loss), ptr(dl_dx), ptr(ws),
                                         ws.numel() * ws.element_size(), stream_handle(stream)),
            "gabsplat_loss_l1_dssim")
+
+
+def gabsplat_densify_stats(geom: Geom, cams: Sequence[Camera], n: int, grad2d, accum, denom, stream=None):
+    ca = _arr(Camera, cams)
+    _check(lib().gabsplat_densify_stats(ctypes.byref(geom), ca, len(cams), n, ptr(grad2d), ptr(accum), ptr(denom),
+                                        stream_handle(stream)), "gabsplat_densify_stats")
+
+
+def gabsplat_densify_workspace_size(n: int) -> int:
+    return int(lib().gabsplat_densify_workspace_size(n))
+
+
+def gabsplat_densify(scene_in: Scene, accum, denom, normals, params: DensifyParams, out: SceneOut,
+                     out_capacity: int, src_index, tag, d_n_out, d_overflow, ws, stream=None):
+    _check(lib().gabsplat_densify(ctypes.byref(scene_in), ptr(accum), ptr(denom), ptr(normals),
+                                  ctypes.byref(params), ctypes.byref(out), out_capacity, ptr(src_index), ptr(tag),
+                                  ptr(d_n_out), ptr(d_overflow), ptr(ws), ws.numel() * ws.element_size(),
+                                  stream_handle(stream)), "gabsplat_densify")
+
+
+def gabsplat_reset_frequency_weights(scene: SceneOut, weight_value: float, opacity_cap: float, stream=None):
+    _check(lib().gabsplat_reset_frequency_weights(ctypes.byref(scene), float(weight_value), float(opacity_cap),
+                                                  stream_handle(stream)), "gabsplat_reset_frequency_weights")
 
 
 def gabsplat_read_overflow(d_overflow, stream=None) -> bool:
