@@ -235,11 +235,17 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
  *             in its tile's list where the walk ended (the stopping primitive,
  *             else the list length) and how many of those primitives passed
  *             the envelope test o G >= 1/255 (the work the blend had to do)
+ *   freq_map  NULL, or [sum over views of H*W]: the frequency map the paper
+ *             visualises (supplementary C), each primitive's weighted
+ *             image-plane frequency sum_j w_j |f2d_j| (cycles per pixel, w_j
+ *             the record's cosine weights) blended with the weights alpha T of
+ *             its colour, without background
+ *   (eval_counts / freq_map select a separate, slower analysis variant.)
  *   d_overflow  from gabsplat_bin_sort (device). */
 gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals,
                                     const uint32_t* tile_ranges, const gabsplat_camera* cams,
                                     int32_t num_views, float* image, float* final_T,
-                                    uint32_t* n_contrib, uint32_t* eval_counts,
+                                    uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map,
                                     const int32_t* d_overflow, void* stream);
 
 /* K7 + K8, backward of the forward above w.r.t. every attribute.  K7 walks

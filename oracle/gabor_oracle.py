@@ -356,6 +356,7 @@ class PixelResult:
     last_id: np.ndarray      # [P] primitive index of the last blended primitive, -1 if none
     n_blended: np.ndarray    # [P] number of blended primitives
     fragile: np.ndarray      # [P] bool
+    freq_map: Optional[torch.Tensor] = None  # [P] blended sum_k w_k |f2d_k| (cycles/px)
 
 
 def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Tensor,
@@ -367,7 +368,7 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
     if m == 0:
         col = bg[None, :].expand(P, 3).clone()
         return PixelResult(col, torch.ones(P, dtype=DT), -np.ones(P, np.int64),
-                           np.zeros(P, np.int64), np.zeros(P, bool))
+                           np.zeros(P, np.int64), np.zeros(P, bool), torch.zeros(P, dtype=DT))
     ci = torch.from_numpy(np.asarray(cand, np.int64))
     mu = pr.mu2d[ci]
     con = pr.conic[ci]
@@ -394,6 +395,9 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
     T_before = torch.cat([torch.ones((P, 1), dtype=DT), T_incl[:, :-1]], 1)
     wgt = torch.where(keep, alpha * T_before, torch.zeros_like(alpha))
     color = wgt @ pr.rgb[ci] + T_incl[:, -1:] * bg[None, :]
+    # frequency map (supplementary C): per primitive sum_k w_k |f2d_k|, blended like a colour
+    phi = (pr.w[ci] * torch.linalg.norm(pr.f2d[ci], dim=-1)).sum(-1) if pr.w.shape[1] else torch.zeros(m, dtype=DT)
+    fmap = wgt @ phi
     with torch.no_grad():
         kn = keep.numpy()
         n_bl = kn.sum(1)
@@ -410,7 +414,7 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
         ft = vn & (np.abs(Ta - T_MIN) <= tau_T * T_MIN)
         fprim = (pr.fragile_prim[np.asarray(cand)][None, :]) & (ar >= ALPHA_MIN * (1 - tau_alpha))
         fragile = ((fa | ft | fprim) & upto).any(1)
-    return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile)
+    return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile, fmap)
 
 
 def blend_pixel_loop(pr: Projected, cand: Sequence[int], x: float, y: float, bg) -> tuple:
@@ -451,6 +455,7 @@ class Image:
     last_id: np.ndarray    # [H,W]
     n_blended: np.ndarray  # [H,W]
     fragile: np.ndarray    # [H,W]
+    freq_map: Optional[torch.Tensor] = None  # [H,W]
 
 
 def _tile_pixels(tx, ty, W, H):
@@ -500,21 +505,23 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
         for (tx, ty) in tiles:
             gx, gy = _tile_pixels(tx, ty, W, H)
             parts.append((gx, gy, tile_candidates(pr, order, tx, ty)))
-    cols, fts, idxs = [], [], []
+    cols, fts, idxs, fms = [], [], [], []
     for gx, gy, cand in parts:
         res = blend_pixels(pr, cand, torch.from_numpy(gx + 0.5).to(DT),
                            torch.from_numpy(gy + 0.5).to(DT), bg)
         idx = gy * W + gx
-        cols.append(res.color); fts.append(res.final_T); idxs.append(torch.from_numpy(idx))
+        cols.append(res.color); fts.append(res.final_T); idxs.append(torch.from_numpy(idx)); fms.append(res.freq_map)
         last[idx] = res.last_id
         nbl[idx] = res.n_blended
         frag[idx] = res.fragile
+    fm = torch.full((H * W,), float("nan"), dtype=DT)
     if idxs:
         ii = torch.cat(idxs)
         color = color.index_put((ii,), torch.cat(cols))
         fT = fT.index_put((ii,), torch.cat(fts))
+        fm = fm.index_put((ii,), torch.cat(fms))
     return Image(color.T.reshape(3, H, W), fT.reshape(H, W), last.reshape(H, W),
-                 nbl.reshape(H, W), frag.reshape(H, W))
+                 nbl.reshape(H, W), frag.reshape(H, W), fm.reshape(H, W))
 
 
 def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False) -> Image:

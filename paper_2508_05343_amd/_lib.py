@@ -102,7 +102,7 @@ def lib() -> ctypes.CDLL:
                                     c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gabsplat_render_fwd.restype = c_int32
     L.gabsplat_render_fwd.argtypes = [POINTER(Geom), c_void_p, c_void_p, POINTER(Camera), c_int32, c_void_p,
-                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gabsplat_render_bwd.restype = c_int32
     L.gabsplat_render_bwd.argtypes = [POINTER(Scene), c_int32, POINTER(c_int32), POINTER(Camera), c_int32,
                                       POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -201,11 +201,11 @@ def gabsplat_bin_sort(geom: Geom, cams: Sequence[Camera], items: int, ws, keys, 
 
 
 def gabsplat_render_fwd(geom: Geom, vals, tile_ranges, cams: Sequence[Camera], image, final_T, n_contrib,
-                        d_overflow, stream=None, eval_counts=None):
+                        d_overflow, stream=None, eval_counts=None, freq_map=None):
     ca = _arr(Camera, cams)
     _check(lib().gabsplat_render_fwd(ctypes.byref(geom), ptr(vals), ptr(tile_ranges), ca, len(cams), ptr(image),
-                                     ptr(final_T), ptr(n_contrib), ptr(eval_counts), ptr(d_overflow),
-                                     stream_handle(stream)), "gabsplat_render_fwd")
+                                     ptr(final_T), ptr(n_contrib), ptr(eval_counts), ptr(freq_map),
+                                     ptr(d_overflow), stream_handle(stream)), "gabsplat_render_fwd")
 
 
 def gabsplat_render_bwd(scenes: Sequence[Scene], scene_of_view, cams: Sequence[Camera], geom: Geom, vals,

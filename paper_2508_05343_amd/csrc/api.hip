@@ -235,8 +235,8 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
 
 gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals, const uint32_t* tile_ranges,
                                     const gabsplat_camera* cams, int32_t num_views, float* image, float* final_T,
-                                    uint32_t* n_contrib, uint32_t* eval_counts, const int32_t* d_overflow,
-                                    void* stream) {
+                                    uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map,
+                                    const int32_t* d_overflow, void* stream) {
   try {
     if (!geom || !geom->views || !geom->rec || geom->k < 0 || geom->k > GABSPLAT_MAX_K || !cams ||
         num_views < 1 || num_views > GABSPLAT_MAX_VIEWS || !tile_ranges || !image || !final_T || !n_contrib)
@@ -250,7 +250,8 @@ gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* v
     h.hdr.num_views = num_views;
     h.hdr.total_tiles = (int32_t)tiles;
     return hip_status(launch_render_fwd(geom->views, h, *geom, geom->k, vals, tile_ranges, image, final_T,
-                                        n_contrib, eval_counts, d_overflow, static_cast<hipStream_t>(stream)));
+                                        n_contrib, eval_counts, freq_map, d_overflow,
+                                        static_cast<hipStream_t>(stream)));
   } catch (...) {
     return GABSPLAT_ERR_HIP;
   }

@@ -109,7 +109,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
 hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                              int k, const uint32_t* vals, const uint32_t* ranges, float* image,
                              float* final_T, uint32_t* n_contrib, uint32_t* eval_counts,
-                             const int32_t* d_overflow, hipStream_t s);
+                             float* freq_map, const int32_t* d_overflow, hipStream_t s);
 
 hipError_t launch_render_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                              int k, const uint32_t* vals, const uint32_t* ranges,

@@ -105,11 +105,13 @@ __device__ __forceinline__ float rec_modulation(const float* r, float dx, float 
 }
 
 // --------------------------------------------------------------------- K6
-// With STATS the kernel also reports, per pixel, how far down its tile list
-// the blend had to go (the stopping position, or the list length) and how
-// many of those pairs passed the envelope test (full Gabor evaluations): the
-// algorithmic work of the blend, used for its roofline.
-template <int K, bool STATS>
+// The ANALYSIS variant (never the timed one) can also report, per pixel, how
+// far down its tile list the blend had to go (the stopping position, or the
+// list length) and how many of those pairs passed the envelope test (full
+// Gabor evaluations) -- the algorithmic work of the blend -- and a frequency
+// map: each primitive's weighted image-plane frequency sum_k w_k |f2d_k|
+// (cycles per pixel) blended with the same weights alpha_i T_i as its colour.
+template <int K, bool ANALYSIS>
 __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ table,
                                                        const float* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
                                                        float* __restrict__ image, float* __restrict__ final_T,
                                                        uint32_t* __restrict__ n_contrib,
                                                        uint32_t* __restrict__ eval_counts,
+                                                       float* __restrict__ freq_map,
                                                        const int32_t* __restrict__ d_overflow) {
   constexpr int RF = Rec<K>::RF;
   constexpr int R4 = RF / 4;
@@ -139,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0, stop_pos = end - start, n_full = 0;
+  float Fm = 0.f;
   bool done = !inside;
   for (uint32_t b = start; b < end; b += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         const float dx = fx - r0.x, dy = fy - r0.y;
         const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
         if (pw < kLog2AlphaMin) continue;  // o G < 1/255 and B <= 1: alpha < 1/255
-        if (STATS) ++n_full;
+        if (ANALYSIS) ++n_full;
         float r[RF];
         r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
 #pragma unroll
@@ -182,13 +186,20 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         const float Tn = T * (1.0f - alpha);
         if (Tn < kTMin) {
           done = true;
-          if (STATS) stop_pos = b - start + (uint32_t)j + 1;
+          if (ANALYSIS) stop_pos = b - start + (uint32_t)j + 1;
           continue;
         }
         const float wt = alpha * T;
         C0 = fmaf(r[6], wt, C0);
         C1 = fmaf(r[7], wt, C1);
         C2 = fmaf(r[8], wt, C2);
+        if (ANALYSIS) {
+          float phi = 0.f;
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            phi = fmaf(r[12 + 3 * k], sqrtf(r[10 + 3 * k] * r[10 + 3 * k] + r[11 + 3 * k] * r[11 + 3 * k]), phi);
+          Fm = fmaf(phi, wt, Fm);
+        }
         T = Tn;
         last = b - start + (uint32_t)j + 1;
       }
@@ -203,10 +214,11 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
     img[2 * hw + pix] = fmaf(T, V.bg[2], C2);
     final_T[V.pixel_offset + pix] = T;
     n_contrib[V.pixel_offset + pix] = last;
-    if (STATS) {
+    if (ANALYSIS && eval_counts) {
       eval_counts[2 * (V.pixel_offset + pix)] = stop_pos;
       eval_counts[2 * (V.pixel_offset + pix) + 1] = n_full;
     }
+    if (ANALYSIS && freq_map) freq_map[V.pixel_offset + pix] = Fm;
   }
 }
 
@@ -407,30 +419,31 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
 template <int K>
 static hipError_t fwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, const uint32_t* vals,
                         const uint32_t* ranges, float* image, float* final_T, uint32_t* n_contrib,
-                        uint32_t* eval_counts, const int32_t* ov, hipStream_t s) {
+                        uint32_t* eval_counts, float* freq_map, const int32_t* ov, hipStream_t s) {
   if (h.hdr.total_tiles == 0) return hipSuccess;
-  if (eval_counts)
+  if (eval_counts || freq_map)
     hipLaunchKernelGGL((k_render_fwd<K, true>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table, g.rec,
-                       vals, ranges, image, final_T, n_contrib, eval_counts, ov);
+                       vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
   else
     hipLaunchKernelGGL((k_render_fwd<K, false>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table,
-                       g.rec, vals, ranges, image, final_T, n_contrib, eval_counts, ov);
+                       g.rec, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int k,
                              const uint32_t* vals, const uint32_t* ranges, float* image, float* final_T,
-                             uint32_t* n_contrib, uint32_t* eval_counts, const int32_t* ov, hipStream_t s) {
+                             uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map, const int32_t* ov,
+                             hipStream_t s) {
   switch (k) {
-    case 0: return fwd_k<0>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 1: return fwd_k<1>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 2: return fwd_k<2>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 3: return fwd_k<3>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 4: return fwd_k<4>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 5: return fwd_k<5>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 6: return fwd_k<6>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 7: return fwd_k<7>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
-    case 8: return fwd_k<8>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, ov, s);
+    case 0: return fwd_k<0>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 1: return fwd_k<1>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 2: return fwd_k<2>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 3: return fwd_k<3>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 4: return fwd_k<4>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 5: return fwd_k<5>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 6: return fwd_k<6>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 7: return fwd_k<7>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
+    case 8: return fwd_k<8>(d_table, h, g, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov, s);
   }
   return hipErrorInvalidValue;
 }

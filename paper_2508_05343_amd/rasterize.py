@@ -159,9 +159,9 @@ class RenderPlan:
         _lib.gabsplat_bin_sort(self.geom, self.c_cams, self.items, self.ws, self.keys, self.vals, self.capacity,
                                self.ranges, self.num_pairs, self.overflow, stream)
 
-    def render_fwd(self, stream=None, eval_counts=None):
+    def render_fwd(self, stream=None, eval_counts=None, freq_map=None):
         _lib.gabsplat_render_fwd(self.geom, self.vals, self.ranges, self.c_cams, self.image, self.final_T,
-                                 self.n_contrib, self.overflow, stream, eval_counts=eval_counts)
+                                 self.n_contrib, self.overflow, stream, eval_counts=eval_counts, freq_map=freq_map)
 
     def forward(self, check_overflow=True, stream=None):
         """preprocess -> bin_sort -> render_fwd.  With check_overflow the pair

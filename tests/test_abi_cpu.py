@@ -66,7 +66,7 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert st == L.INVALID_ARGUMENT
     bad = L.Camera()  # zero-sized image
     st = lib.gabsplat_render_fwd(ctypes.byref(g), None, None, ctypes.byref(bad), 1, None, None, None, None, None,
-                                 None)
+                                 None, None)
     assert st == L.INVALID_ARGUMENT
     st = lib.gabsplat_bin_sort(ctypes.byref(g), ctypes.byref(cam), 1, 10, None, 0, None, None, 10, None, None,
                                None, None)

@@ -219,3 +219,27 @@ def test_capacity_overflow_and_retry(gpu_lib):
     assert plan.capacity > 100
     ds2, plan2 = gpu_plan(sc, [cam])
     assert torch.equal(img, plan2.forward())
+
+
+def test_frequency_map_and_eval_counts(gpu_lib):
+    """The analysis variant: frequency map against the oracle, and the image
+    it renders is the same as the timed variant's."""
+    sc = synth.uniform_scene(35, 2000, 3, sh_degree=1, log_scale_mu=-3.0)
+    cam = synth.pinhole_camera(96, 64, 60.0, (0.2, 0.1, -3.0), (0, 0, 0))
+    ds, plan = gpu_plan(sc, [cam])
+    img = plan.forward().clone()
+    fm = torch.zeros(96 * 64, dtype=torch.float32, device="cuda")
+    cnt = torch.zeros((96 * 64, 2), dtype=torch.int32, device="cuda")
+    plan.render_fwd(eval_counts=cnt, freq_map=fm)
+    torch.cuda.synchronize()
+    assert torch.equal(img, plan.image)
+    ref = O.render_scene(sc, cam, "binned")
+    ok = ~ref.fragile
+    d = np.abs(fm.cpu().numpy().reshape(64, 96) - ref.freq_map.numpy())
+    assert d[ok].max() <= 1e-4 * max(1.0, float(ref.freq_map.numpy().max()))
+    c = cnt.cpu().numpy()
+    ranges = plan.view_ranges(0).cpu().numpy().astype(np.int64)
+    tile = (np.arange(64)[:, None] // 16) * 6 + (np.arange(96)[None, :] // 16)
+    lens = (ranges[:, 1] - ranges[:, 0])[tile].reshape(-1)
+    assert (c[:, 0] <= lens).all() and (c[:, 1] <= c[:, 0]).all()
+    assert (c[:, 0] >= plan.view_n_contrib(0).cpu().numpy().reshape(-1)).all()

@@ -657,3 +657,35 @@ def test_attenuation_gradients_match_finite_differences():
             fd = (vals[0] - vals[1]) / (2 * h)
             a = an[name][idx]
             assert abs(fd - a) <= 1e-5 * (abs(a) + 1e-4), (name, idx, fd, a)
+
+
+def test_frequency_map_is_a_blended_channel():
+    """The frequency map equals rendering the scene with every primitive's
+    colour set to its weighted frequency sum_k w_k |f2d_k| on a black
+    background (same blending weights); for one primitive it is alpha * phi."""
+    sc = synth.config1_scene()
+    cam = synth.config1_camera()
+    img = O.render_scene(sc, cam, "binned")
+    pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
+    phi = (pr.w * torch.linalg.norm(pr.f2d, dim=-1)).sum(-1).numpy()
+    s2 = sc.subset(np.arange(sc.n))
+    s2.colors = np.repeat(phi[:, None], 3, 1).astype(np.float64)
+    with torch.no_grad():
+        p2 = O.scene_tensors(s2)
+        p2["colors"] = torch.tensor(np.repeat(phi[:, None], 3, 1), dtype=torch.float64)
+        ref = O.render(p2, O.camera_tensors(cam), "binned", scene_f32=sc)
+    np.testing.assert_allclose(img.freq_map.numpy(), ref.color[0].numpy(), rtol=1e-12, atol=1e-15)
+    # one axis-aligned primitive on the axis: alpha * phi at its centre pixel
+    one = make_scene([[0, 0, 2.0]], [[0.05, 0.08, 0.03]], [[1, 0, 0, 0]], [0.8], [[1, 1, 1]],
+                     [[[1.5, -2.0, 7.0], [0.5, 0.5, 0.0]]], [[0.2, 0.3]])
+    c1 = axis_camera(W=32, H=32, f=40.0)
+    im1 = O.render_scene(one, c1, "brute")
+    f2 = np.array([[1.5, -2.0], [0.5, 0.5]], np.float32).astype(float) * 2.0 / 40.0
+    w = np.array([0.2, 0.3], np.float32).astype(float)
+    ph = float((w * np.linalg.norm(f2, axis=1)).sum())
+    dx = dy = 0.5
+    cov = np.diag([(40 * float(np.float32(0.05)) / 2.0) ** 2 + 0.3, (40 * float(np.float32(0.08)) / 2.0) ** 2 + 0.3])
+    G = math.exp(-0.5 * (dx * dx / cov[0, 0] + dy * dy / cov[1, 1]))
+    B = (1 - w.sum()) + sum(w[k] * math.cos(2 * math.pi * (f2[k, 0] * dx + f2[k, 1] * dy)) for k in range(2))
+    a = float(np.float32(0.8)) * G * B
+    np.testing.assert_allclose(float(im1.freq_map[16, 16]), a * ph, rtol=1e-12)
