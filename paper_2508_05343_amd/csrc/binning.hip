@@ -14,11 +14,11 @@
 // already running), ranked in LDS with wave64 ballot matching, and placed
 // with a decoupled look-back over per-(partition, digit) status words.
 //
-// Launch sequence (8 + tile-pass launches): clear the workspace head;
+// Launch sequence (9 + tile-pass launches): clear the workspace head;
 // compaction of the visible items fused with the depth-digit histograms; 4
-// depth passes; expansion = tiles-touched scan fused with load-balanced pair
-// emission and the tile-digit histograms; the tile passes; per-tile ranges from
-// the boundaries between runs of equal tile keys.
+// depth passes; tiles-touched scan; pair emission balanced over fixed chunks
+// of pairs, fused with the tile-digit histograms; the tile passes; per-tile
+// ranges from the boundaries between runs of equal tile keys.
 #include <hip/hip_runtime.h>
 
 #include "gs_block.h"
@@ -29,8 +29,6 @@ namespace gs {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kPart = kSortThreads * kSortItems;   // 4096 keys per partition
-constexpr int kExpItems = 8;
-constexpr int kExpPart = kSortThreads * kExpItems;  // 2048 visible items per expansion partition
 constexpr int kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 1u << 31;
@@ -308,35 +306,24 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 }
 
 // -------------------------------------------------------------- expansion
-// Over the V depth-sorted visible items: exclusive scan of tiles touched
-// (decoupled look-back), then the block's pairs are written cooperatively
-// (thread t writes pairs t, t + 256, ... of the block, finding its item by a
-// binary search over the block's item offsets), and the tile-digit histograms
-// are accumulated.  The last partition writes P and the overflow flag; pairs
-// past the capacity are never written.
-__global__ __launch_bounds__(kSortThreads) void k_expand(const void* __restrict__ table,
-                                                         const uint32_t* __restrict__ tiles,
-                                                         const uint32_t* __restrict__ rect,
-                                                         const uint32_t* __restrict__ ids, uint32_t capacity,
-                                                         int tpass, uint32_t* __restrict__ counters,
-                                                         uint32_t* __restrict__ look, uint32_t* __restrict__ thist,
-                                                         uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pvals,
-                                                         int64_t* __restrict__ d_num_pairs,
-                                                         int32_t* __restrict__ d_overflow) {
-  __shared__ uint32_t s_off[kExpPart];
-  __shared__ uint32_t s_base[kExpPart];
-  __shared__ uint32_t s_wx[kExpPart];  // rect width | tiles_x << 16
-  __shared__ uint32_t s_id[kExpPart];
-  __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
+// k_expand_scan: over the V depth-sorted visible items, exclusive scan of
+// tiles touched (single pass, wave-parallel decoupled look-back) into
+// offsets[]; the last partition writes P and the overflow flag.
+__global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __restrict__ tiles,
+                                                              const uint32_t* __restrict__ ids, uint32_t capacity,
+                                                              uint32_t* __restrict__ counters,
+                                                              uint32_t* __restrict__ look,
+                                                              uint32_t* __restrict__ offsets,
+                                                              int64_t* __restrict__ d_num_pairs,
+                                                              int32_t* __restrict__ d_overflow) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
   __shared__ uint32_t s_misc[2];
   const int t = threadIdx.x;
   if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_EXPAND], 1u);
-  for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
   const uint32_t part = s_misc[0];
   const uint32_t V = counters[C_NUM_VISIBLE];
-  const uint64_t base = (uint64_t)part * kExpPart;
+  const uint64_t base = (uint64_t)part * kPart;
   if (V == 0) {
     if (part == 0 && t == 0) {
       counters[C_NUM_PAIRS] = 0;
@@ -347,75 +334,122 @@ __global__ __launch_bounds__(kSortThreads) void k_expand(const void* __restrict_
     return;
   }
   if (base >= V) return;
-  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
-  const ViewEntry* views = table_views(table);
-  const int nv = hdr->num_views;
-
-  uint32_t cnt[kExpItems];
+  const uint64_t first = base + (uint64_t)t * kSortItems;
+  uint32_t x[kSortItems];
   uint32_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < kExpItems; ++j) {
-    const int li = t * kExpItems + j;
-    const uint64_t jj = base + li;
-    uint32_t c = 0;
-    if (jj < V) {
-      const uint32_t item = ids[jj];
-      c = tiles[item];
-      const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
-      const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu;
-      int lo = 0, hi = nv - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].item_offset <= (int64_t)item) lo = mid; else hi = mid - 1;
-      }
-      const ViewEntry& Vw = views[lo];
-      s_base[li] = (uint32_t)Vw.tile_offset + y0 * (uint32_t)Vw.tiles_x + x0;
-      s_wx[li] = (x1 - x0) | ((uint32_t)Vw.tiles_x << 16);
-      s_id[li] = item;
-    }
-    cnt[j] = c;
-    sum += c;
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint64_t jj = first + j;
+    x[j] = jj < V ? tiles[ids[jj]] : 0u;
+    sum += x[j];
   }
   uint32_t block_total;
-  uint32_t run = block_excl_scan(sum, s_wave, &block_total);
-#pragma unroll
-  for (int j = 0; j < kExpItems; ++j) {
-    s_off[t * kExpItems + j] = run;
-    run += cnt[j];
-  }
+  const uint32_t tpre = block_excl_scan(sum, s_wave, &block_total);
   if (t < 64) {
     const uint32_t excl = lookback_wave(look, part, block_total);
-    if (t == 0) s_misc[1] = excl;
-    if (t == 0 && base + kExpPart >= V) {
-      const uint32_t P = excl + block_total;
-      const uint32_t ov = P > capacity ? 1u : 0u;
-      counters[C_NUM_PAIRS] = P;
-      counters[C_OVERFLOW] = ov;
-      *d_num_pairs = (int64_t)P;
-      *d_overflow = (int32_t)ov;
+    if (t == 0) {
+      s_misc[1] = excl;
+      if (base + kPart >= V) {
+        const uint32_t P = excl + block_total;
+        const uint32_t ov = P > capacity ? 1u : 0u;
+        counters[C_NUM_PAIRS] = P;
+        counters[C_OVERFLOW] = ov;
+        *d_num_pairs = (int64_t)P;
+        *d_overflow = (int32_t)ov;
+      }
     }
   }
   __syncthreads();
-  const uint32_t excl = s_misc[1];
-  const uint32_t nitems = (uint32_t)((V - base) < (uint64_t)kExpPart ? (V - base) : (uint64_t)kExpPart);
-  for (uint32_t m = t; m < block_total; m += kSortThreads) {
-    // last item whose offset is <= m (offsets of real items strictly increase)
-    uint32_t lo = 0, hi = nitems - 1;
+  uint32_t pos = s_misc[1] + tpre;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint64_t jj = first + j;
+    if (jj < V) offsets[jj] = pos;
+    pos += x[j];
+  }
+}
+
+// Adds 1 to s_h[d] for every active lane with `on`, one LDS atomic per group of
+// lanes sharing the digit (ballot matching), so that the common case of a
+// whole wave on one digit costs one atomic instead of 64 serialised ones.
+__device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on) {
+  uint64_t peers = __ballot(on);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  const int l = __lane_id();
+  if (on && (peers >> l) == 1ull) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+}
+
+// k_emit: globally load-balanced pair emission.  Block b writes pairs
+// [4096 b, 4096 (b + 1)); it finds the first item whose range overlaps its
+// chunk by a binary search over offsets[], stages the offsets of the items
+// covering the chunk (at most 4096) in LDS, and every pair finds its item by
+// a binary search there.  Tile-digit histograms are accumulated per block.
+__global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ table,
+                                                       const uint32_t* __restrict__ rect,
+                                                       const uint32_t* __restrict__ ids,
+                                                       const uint32_t* __restrict__ offsets, int tpass,
+                                                       const uint32_t* __restrict__ counters,
+                                                       uint32_t* __restrict__ thist, uint32_t* __restrict__ tkeys,
+                                                       uint32_t* __restrict__ pvals) {
+  __shared__ uint32_t s_off[kPart];
+  __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
+  __shared__ uint32_t s_first;
+  if (counters[C_OVERFLOW]) return;
+  const uint32_t P = counters[C_NUM_PAIRS];
+  const uint32_t V = counters[C_NUM_VISIBLE];
+  const uint64_t p0 = (uint64_t)blockIdx.x * kPart;
+  if (p0 >= P) return;
+  const int t = threadIdx.x;
+  for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
+  if (t == 0) {  // last item with offsets[item] <= p0
+    uint32_t lo = 0, hi = V - 1;
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= m) lo = mid; else hi = mid - 1;
+      if (offsets[mid] <= (uint32_t)p0) lo = mid; else hi = mid - 1;
     }
-    const uint32_t q = m - s_off[lo];
-    const uint32_t wx = s_wx[lo];
-    const uint32_t wdt = wx & 0xffffu, tx = wx >> 16;
-    const uint32_t row = q / wdt, col = q - row * wdt;
-    const uint32_t tile = s_base[lo] + row * tx + col;
-    const uint32_t dst = excl + m;
-    if (dst < capacity) {
-      tkeys[dst] = tile;
-      pvals[dst] = s_id[lo];
+    s_first = lo;
+  }
+  __syncthreads();
+  const uint32_t first = s_first;
+  const uint32_t nitems = min((uint32_t)kPart, V - first);
+  for (uint32_t i = t; i < nitems; i += kSortThreads) s_off[i] = offsets[first + i];
+  __syncthreads();
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry* views = table_views(table);
+  const int nv = hdr->num_views;
+  const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
+  // uniform trip count so that every lane takes part in the ballots
+  for (uint32_t m0 = (uint32_t)p0; m0 < pend; m0 += kSortThreads) {
+    const uint32_t m = m0 + t;
+    const bool on = m < pend;
+    uint32_t tile = 0;
+    if (on) {
+      uint32_t lo = 0, hi = nitems - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= m) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t item = ids[first + lo];
+      const uint32_t q = m - s_off[lo];
+      const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
+      const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu;
+      int vlo = 0, vhi = nv - 1;
+      while (vlo < vhi) {
+        const int mid = (vlo + vhi + 1) >> 1;
+        if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+      }
+      const uint32_t wdt = x1 - x0;
+      const uint32_t row = q / wdt, col = q - row * wdt;
+      tile = (uint32_t)views[vlo].tile_offset + (y0 + row) * (uint32_t)views[vlo].tiles_x + x0 + col;
+      tkeys[m] = tile;
+      pvals[m] = item;
     }
-    for (int p = 0; p < tpass; ++p) atomicAdd(&s_h[p * kRadix + ((tile >> (8 * p)) & 255u)], 1u);
+    for (int ps = 0; ps < tpass; ++ps) wave_hist_add(s_h + ps * kRadix, (tile >> (8 * ps)) & 255u, on);
   }
   __syncthreads();
   for (int i = t; i < tpass * kRadix; i += kSortThreads) {
@@ -462,7 +496,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.tile_bits = bits;
   p.parts_items = (items + kPart - 1) / kPart;
   p.parts_pairs = (capacity + kPart - 1) / kPart;
-  const int64_t parts_exp = (items + kExpPart - 1) / kExpPart;
+  const int64_t parts_exp = (items + kPart - 1) / kPart;
   const int tpass = (bits + 7) / 8;
   size_t off = 0;
   // --- head: cleared at the start of every call
@@ -477,7 +511,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_dkeys_b = off; off = align_up(off + (size_t)items * 4);
   p.off_dvals_a = off; off = align_up(off + (size_t)items * 4);
   p.off_dvals_b = off; off = align_up(off + (size_t)items * 4);
-  p.off_offsets = off;
+  p.off_offsets = off; off = align_up(off + (size_t)items * 4);
   p.off_tkeys_a = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
@@ -518,7 +552,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   }
   const unsigned parts_i = (unsigned)(p.parts_items > 0 ? p.parts_items : 1);
   const unsigned parts_p = (unsigned)(p.parts_pairs > 0 ? p.parts_pairs : 1);
-  const unsigned parts_e = (unsigned)((p.items + kExpPart - 1) / kExpPart > 0 ? (p.items + kExpPart - 1) / kExpPart : 1);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
 
   // K2a: compaction + depth histograms
   if (p.items > 0)
@@ -531,10 +565,13 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
                        counters + C_NUM_VISIBLE, 8 * ps, ps, kDepthPasses, hist + ps * kRadix, look_depth,
                        counters + C_TICKET_DEPTH + ps, nullptr);
   }
-  // K2b + K3: tiles-touched scan, pair emission in depth order, tile histograms
+  // K2b: tiles-touched scan in depth order, P, overflow
   uint32_t* thist = hist + kDepthPasses * kRadix;
-  hipLaunchKernelGGL(k_expand, dim3(parts_e), dim3(kSortThreads), 0, s, g.views, g.tiles, g.rect, dv[0],
-                     (uint32_t)p.capacity, tpass, counters, look_expand, thist, tk[0], pv[0], d_num_pairs, d_overflow);
+  hipLaunchKernelGGL(k_expand_scan, dim3(parts_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
+                     counters, look_expand, offsets, d_num_pairs, d_overflow);
+  // K3: load-balanced pair emission in depth order + tile-digit histograms
+  hipLaunchKernelGGL(k_emit, dim3(parts_p), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, tpass,
+                     counters, thist, tk[0], pv[0]);
   // K4b: tile passes over the P pairs
   for (int ps = 0; ps < tpass; ++ps) {
     const int a = ps & 1;

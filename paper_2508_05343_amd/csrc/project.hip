@@ -41,6 +41,8 @@ constexpr float kY3d = 0.37317633259011540f;  // z(5z^2 - 3)
 constexpr float kY3e = 1.4453057213202769f;   // z(x^2 - y^2)
 
 __device__ __forceinline__ void sh_basis(float x, float y, float z, int deg, float* Y) {
+#pragma unroll
+  for (int b = 1; b < 16; ++b) Y[b] = 0.f;
   Y[0] = kY00;
   if (deg < 1) return;
   Y[1] = kY1 * y;
@@ -65,7 +67,8 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, int deg, flo
 
 // Ambient gradient of each basis polynomial w.r.t. (x, y, z).
 __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int deg, V3* dY) {
-  dY[0] = v3(0.f, 0.f, 0.f);
+#pragma unroll
+  for (int b = 0; b < 16; ++b) dY[b] = v3(0.f, 0.f, 0.f);
   if (deg < 1) return;
   dY[1] = v3(0.f, kY1, 0.f);
   dY[2] = v3(0.f, 0.f, kY1);
@@ -343,9 +346,12 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         sh_basis(d.x * il, d.y * il, d.z * il, deg, Y);
         const int nd = (deg + 1) * (deg + 1);
         float col[3] = {0.5f, 0.5f, 0.5f};
-        for (int b = 0; b < nd; ++b) {
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+        for (int b = 0; b < 16; ++b) {  // compile-time bound keeps Y in registers
+          if (b < nd) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+          }
         }
         r[6] = fmaxf(col[0], 0.f);
         r[7] = fmaxf(col[1], 0.f);
@@ -412,6 +418,7 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
   float go = 0.f;
   float gcol[3] = {0.f, 0.f, 0.f};
   float gsh[48];
+#pragma unroll
   for (int b = 0; b < 48; ++b) gsh[b] = 0.f;
   V3 gf[K > 0 ? K : 1];
   float gw[K > 0 ? K : 1];
@@ -593,22 +600,31 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
       V3 dY[16];
       sh_basis(dir.x, dir.y, dir.z, deg, Y);
       sh_basis_grad(dir.x, dir.y, dir.z, deg, dY);
-      float col[3] = {0.5f, 0.5f, 0.5f};
-      for (int b = 0; b < nd; ++b)
+      float shv[48];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+      for (int b = 0; b < 16; ++b)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) shv[b * 3 + ch] = (b < nd) ? S.sh[(int64_t)(b * 3 + ch) * n + i] : 0.f;
+      float col[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = (b < nd) ? fmaf(Y[b], shv[b * 3 + ch], col[ch]) : col[ch];
       float drgb[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) drgb[ch] = col[ch] < 0.f ? 0.f : G2[6 + ch];
       V3 gdir = v3(0.f, 0.f, 0.f);
-      for (int b = 0; b < nd; ++b) {
-        float acc = 0.f;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          gsh[b * 3 + ch] += Y[b] * drgb[ch];
-          acc += S.sh[(int64_t)(b * 3 + ch) * n + i] * drgb[ch];
+      for (int b = 0; b < 16; ++b) {
+        if (b < nd) {
+          float acc = 0.f;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            gsh[b * 3 + ch] += Y[b] * drgb[ch];
+            acc += shv[b * 3 + ch] * drgb[ch];
+          }
+          gdir = add3(gdir, scale3(dY[b], acc));
         }
-        gdir = add3(gdir, scale3(dY[b], acc));
       }
       const float pr = dot3(dir, gdir);
       gmean = add3(gmean, scale3(add3(gdir, scale3(dir, -pr)), il));
@@ -636,8 +652,11 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
   }
   if (gr.opacities) put(&gr.opacities[i], go);
   if (deg >= 0) {
-    if (gr.sh)
-      for (int b = 0; b < nd * 3; ++b) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
+    if (gr.sh) {
+#pragma unroll
+      for (int b = 0; b < 48; ++b)
+        if (b < nd * 3) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
+    }
   } else if (gr.colors) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) put(&gr.colors[ch * n + i], gcol[ch]);

@@ -223,33 +223,67 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
 }
 
 // ------------------------------------------------- wave reduce-scatter-add
-// Sums v[0..NP) over the 64 lanes by recursive halving (each stage ships half
-// of the remaining vector to the partner lane), then lane l holds the total of
-// component l >> (6 - log2 NP); one lane per component adds it to dst.
+// Sums v[0..NP) over the 64 lanes of a wavefront by recursive halving: at each
+// stage a lane keeps half of its remaining components and adds its partner's
+// partial sums of that half, so after log2 NP stages lane l holds the total of
+// component l >> (6 - log2 NP) (the stages left over when NP < 64 only add) and
+// a single vector atomic writes every component.  Partners, stage by stage:
+// lane l ^ 32 and l ^ 16 through the lane-swap instructions of gfx950 --
+// swapping the upper 32 (odd 16-lane) lanes of x with the lower 32 (even) lanes
+// of y leaves x's pair sums in the lower and y's in the upper lanes of x + y, one
+// add per pair of components -- then the DPP patterns 15 - i within a row of 16,
+// 7 - i within its halves, 3 - i and i ^ 1 within quads.  Each stage pairs lanes
+// that differ in the stage's bit and agree in the bits above it, and the six
+// partner masks 32, 16, 15, 7, 3, 1 together span all six lane bits.  Every
+// lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+template <int N, int L>
+__device__ __forceinline__ void stage_swap32(float (&v)[N]) {
+#pragma unroll
+  for (int j = 0; j < L / 2; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + L / 2]), false, false);
+    v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+template <int N, int L>
+__device__ __forceinline__ void stage_swap16(float (&v)[N]) {
+#pragma unroll
+  for (int j = 0; j < L / 2; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + L / 2]), false, false);
+    v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+template <int N, int L, int CTRL>
+__device__ __forceinline__ void stage_dpp(float (&v)[N], bool upper) {
+  if constexpr (L >= 2) {
+#pragma unroll
+    for (int j = 0; j < L / 2; ++j) {
+      const float keep = upper ? v[j + L / 2] : v[j];
+      const float send = upper ? v[j] : v[j + L / 2];
+      v[j] = keep + dpp_get<CTRL>(send);
+    }
+  } else {
+    v[0] += dpp_get<CTRL>(v[0]);
+  }
+}
+
 template <int NP>
 __device__ __forceinline__ void wave_reduce_add(float (&v)[NP], float* dst, int ncomp) {
+  static_assert(NP == 16 || NP == 32 || NP == 64, "component count");
   const int l = __lane_id();
-  constexpr int LOGNP = (NP == 64) ? 6 : (NP == 32) ? 5 : (NP == 16) ? 4 : 3;
-  int L = NP;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    if (L > 1) {
-      const bool upper = (l & d) != 0;
-#pragma unroll
-      for (int j = 0; j < NP / 2; ++j) {
-        if (j < L / 2) {
-          const float a = v[j], b = v[j + L / 2];
-          const float send = upper ? a : b;
-          const float keep = upper ? b : a;
-          v[j] = keep + __shfl_xor(send, d, 64);
-        }
-      }
-      L >>= 1;
-    } else {
-      v[0] += __shfl_xor(v[0], d, 64);
-    }
-  }
-  constexpr int SH = 6 - LOGNP;
+  stage_swap32<NP, NP>(v);
+  stage_swap16<NP, NP / 2>(v);
+  stage_dpp<NP, NP / 4, 0x140>(v, (l & 8) != 0);   // row mirror
+  stage_dpp<NP, NP / 8, 0x141>(v, (l & 4) != 0);   // half-row mirror
+  stage_dpp<NP, NP / 16, 0x1B>(v, (l & 2) != 0);   // quad (3, 2, 1, 0)
+  stage_dpp<NP, NP / 32, 0xB1>(v, (l & 1) != 0);   // quad (1, 0, 3, 2)
+  constexpr int SH = NP == 64 ? 0 : (NP == 32 ? 1 : 2);
   const int comp = l >> SH;
   if ((l & ((1 << SH) - 1)) == 0 && comp < ncomp) atomicAdd(dst + comp, v[0]);
 }
@@ -343,12 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         const uint32_t pos = lo + (uint32_t)j + 1;
         const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
         const float dx = fx - r0.x, dy = fy - r0.y;
-        bool contrib = pos <= last;
-        float pw = 0.f;
-        if (contrib) {
-          pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
-          contrib = !(pw < kLog2AlphaMin);
-        }
+        const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
+        bool contrib = pos <= last && !(pw < kLog2AlphaMin);
         if (__ballot(contrib) == 0ull) continue;
         float r[RF];
         r[0] = r0.x; r[1] = r0.y; r[2] = r0.z; r[3] = r0.w;
@@ -358,56 +388,67 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
           const float4 v = s_rec[j * R4 + q];
           r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
         }
-        float E = 0.f, Bv = 0.f, alpha = 0.f;
-        if (contrib) {
-          E = exp2_hw(pw);
-          Bv = rec_modulation<K>(r, dx, dy);
-          alpha = fminf(kAlphaMax, E * Bv);
-          contrib = !(alpha < kAlphaMin);
+        // alpha exactly as the forward evaluates it (same operations, same order)
+        const float E = exp2_hw(fmaxf(pw, kLog2AlphaMin));
+        float cs[K > 0 ? K : 1], sn[K > 0 ? K : 1];
+        float Bv = r[9];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float ph = fmaf(r[10 + 3 * k], dx, r[11 + 3 * k] * dy);
+          const float fr = __builtin_amdgcn_fractf(ph);
+          cs[k] = __builtin_amdgcn_cosf(fr);
+          sn[k] = __builtin_amdgcn_sinf(fr);
+          Bv = fmaf(r[12 + 3 * k], cs[k], Bv);
         }
+        const float EB = E * Bv;
+        const float alpha = fminf(kAlphaMax, EB);
+        contrib = contrib && !(alpha < kAlphaMin);
         if (__ballot(contrib) == 0ull) continue;
+        // lanes without a contribution keep their state and produce zero gradients
+        const float om = 1.0f - alpha;
+        const float inv = __builtin_amdgcn_rcpf(om);
+        T = contrib ? T * inv : T;
+        const float na0 = fmaf(la, lc0, (1.0f - la) * acc0);
+        const float na1 = fmaf(la, lc1, (1.0f - la) * acc1);
+        const float na2 = fmaf(la, lc2, (1.0f - la) * acc2);
+        acc0 = contrib ? na0 : acc0;
+        acc1 = contrib ? na1 : acc1;
+        acc2 = contrib ? na2 : acc2;
+        lc0 = contrib ? r[6] : lc0;
+        lc1 = contrib ? r[7] : lc1;
+        lc2 = contrib ? r[8] : lc2;
+        la = contrib ? alpha : la;
+        const float wt = contrib ? alpha * T : 0.f;
+        float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
+        da = da * T - Tf * bgdot * inv;
+        da = (contrib && !(EB > kAlphaMax)) ? da : 0.f;  // a binding clamp has zero derivative
+        const float dB = da * E;
+        const float dp = da * Bv * E * kLn2;
         float gv[NP];
+        gv[2] = dp * dx * dx;
+        gv[3] = dp * dx * dy;
+        gv[4] = dp * dy * dy;
+        gv[5] = dp;
+        gv[6] = wt * dC0;
+        gv[7] = wt * dC1;
+        gv[8] = wt * dC2;
+        gv[9] = dB;  // DC weight
+        float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
+        float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
+        const float dB2pi = -dB * 6.283185307179586f;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) gv[q] = 0.f;
-        if (contrib) {
-          const float om = 1.0f - alpha;
-          T = T / om;
-          const float wt = alpha * T;
-          gv[6] = wt * dC0;
-          gv[7] = wt * dC1;
-          gv[8] = wt * dC2;
-          acc0 = fmaf(la, lc0, (1.0f - la) * acc0);
-          acc1 = fmaf(la, lc1, (1.0f - la) * acc1);
-          acc2 = fmaf(la, lc2, (1.0f - la) * acc2);
-          lc0 = r[6]; lc1 = r[7]; lc2 = r[8];
-          la = alpha;
-          float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
-          da = da * T - Tf * bgdot / om;
-          if (E * Bv > kAlphaMax) da = 0.f;  // clamp binds: zero derivative
-          const float dE = da * Bv, dB = da * E;
-          const float dp = dE * E * kLn2;
-          gv[2] = dp * dx * dx;
-          gv[3] = dp * dx * dy;
-          gv[4] = dp * dy * dy;
-          gv[5] = dp;
-          float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
-          float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
-          gv[9] = dB;  // DC weight
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float fkx = r[10 + 3 * k], fky = r[11 + 3 * k], wk = r[12 + 3 * k];
-            const float ph = fmaf(fkx, dx, fky * dy);
-            const float cs = cos_rev(ph), sn = sin_rev(ph);
-            gv[12 + 3 * k] = dB * cs;
-            const float dph = -dB * wk * 6.283185307179586f * sn;
-            gv[10 + 3 * k] = dph * dx;
-            gv[11 + 3 * k] = dph * dy;
-            ddx = fmaf(dph, fkx, ddx);
-            ddy = fmaf(dph, fky, ddy);
-          }
-          gv[0] = -ddx;
-          gv[1] = -ddy;
+        for (int k = 0; k < K; ++k) {
+          const float dph = dB2pi * r[12 + 3 * k] * sn[k];
+          gv[10 + 3 * k] = dph * dx;
+          gv[11 + 3 * k] = dph * dy;
+          gv[12 + 3 * k] = dB * cs[k];
+          ddx = fmaf(dph, r[10 + 3 * k], ddx);
+          ddy = fmaf(dph, r[11 + 3 * k], ddy);
         }
+        gv[0] = -ddx;
+        gv[1] = -ddy;
+#pragma unroll
+        for (int q = GS; q < NP; ++q) gv[q] = 0.f;
         wave_reduce_add<NP>(gv, grad2d + (size_t)s_id[j] * GF, GS);
       }
     }
