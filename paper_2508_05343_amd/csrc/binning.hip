@@ -251,8 +251,9 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     st_flag(my_look, kFlagInc | tot);
   } else {
     st_flag(my_look, kFlagAgg | tot);
-    // walk back 8 predecessors per round trip (independent loads in flight)
-    constexpr int kAhead = 8;
+    // walk back 64 predecessors per round trip (independent loads in flight):
+    // a walk over p predecessors costs ceil(p / 64) memory latencies
+    constexpr int kAhead = 64;
     int64_t hi = (int64_t)part - 1;
     bool found = false;
     while (!found) {
@@ -264,15 +265,16 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
       }
 #pragma unroll
       for (int q = 0; q < kAhead; ++q) {
-        if (found) break;
-        const int64_t p = hi - q;
-        uint32_t x = v[q];
-        while ((x & (kFlagAgg | kFlagInc)) == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
+        if (!found) {
+          const int64_t p = hi - q;
+          uint32_t x = v[q];
+          while ((x & (kFlagAgg | kFlagInc)) == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
+          }
+          excl += x & kCountMask;
+          found = (x & kFlagInc) != 0;
         }
-        excl += x & kCountMask;
-        found = (x & kFlagInc) != 0;
       }
       hi -= kAhead;
     }
@@ -308,12 +310,16 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 // -------------------------------------------------------------- expansion
 // k_expand_scan: over the V depth-sorted visible items, exclusive scan of
 // tiles touched (single pass, wave-parallel decoupled look-back) into
-// offsets[]; the last partition writes P and the overflow flag.
+// offsets[]; the last partition writes P and the overflow flag.  Every
+// visible item touches at least one tile, so pair index c * kPart lies in
+// exactly one item's range: that item's position is stored as chunk_first[c]
+// (c < max_chunks) for the emission kernel.
 __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __restrict__ tiles,
                                                               const uint32_t* __restrict__ ids, uint32_t capacity,
                                                               uint32_t* __restrict__ counters,
                                                               uint32_t* __restrict__ look,
                                                               uint32_t* __restrict__ offsets,
+                                                              uint32_t* __restrict__ chunk_first, uint32_t max_chunks,
                                                               int64_t* __restrict__ d_num_pairs,
                                                               int32_t* __restrict__ d_overflow) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
@@ -364,7 +370,11 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const uint64_t jj = first + j;
-    if (jj < V) offsets[jj] = pos;
+    if (jj < V) {
+      offsets[jj] = pos;
+      for (uint32_t c = (pos + kPart - 1) / kPart; c < max_chunks && (uint64_t)c * kPart < (uint64_t)pos + x[j]; ++c)
+        chunk_first[c] = (uint32_t)jj;
+    }
     pos += x[j];
   }
 }
@@ -385,20 +395,26 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
 }
 
 // k_emit: globally load-balanced pair emission.  Block b writes pairs
-// [4096 b, 4096 (b + 1)); it finds the first item whose range overlaps its
-// chunk by a binary search over offsets[], stages the offsets of the items
-// covering the chunk (at most 4096) in LDS, and every pair finds its item by
-// a binary search there.  Tile-digit histograms are accumulated per block.
+// [b * kPart, (b + 1) * kPart) of the depth-ordered pair sequence: it stages
+// the offsets of the items from chunk_first[b] on in LDS, every thread finds
+// the item of its first pair (one binary search) and walks its 16 consecutive
+// pairs item by item and tile by tile (row-major inside the item's tile
+// rectangle), and the block writes the (tile, item) pairs coalesced from LDS
+// while accumulating the tile-digit histograms of the tile passes.
+constexpr int kPad = kPart + kPart / kSortItems;  // LDS index i + i / 16: conflict-free per-thread runs
+
 __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ table,
                                                        const uint32_t* __restrict__ rect,
                                                        const uint32_t* __restrict__ ids,
-                                                       const uint32_t* __restrict__ offsets, int tpass,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ chunk_first, int tpass,
                                                        const uint32_t* __restrict__ counters,
                                                        uint32_t* __restrict__ thist, uint32_t* __restrict__ tkeys,
                                                        uint32_t* __restrict__ pvals) {
   __shared__ uint32_t s_off[kPart];
+  __shared__ uint32_t s_tile[kPad];
+  __shared__ uint32_t s_item[kPad];
   __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
-  __shared__ uint32_t s_first;
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
   const uint32_t V = counters[C_NUM_VISIBLE];
@@ -406,16 +422,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
   if (p0 >= P) return;
   const int t = threadIdx.x;
   for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
-  if (t == 0) {  // last item with offsets[item] <= p0
-    uint32_t lo = 0, hi = V - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (offsets[mid] <= (uint32_t)p0) lo = mid; else hi = mid - 1;
-    }
-    s_first = lo;
-  }
-  __syncthreads();
-  const uint32_t first = s_first;
+  const uint32_t first = chunk_first[blockIdx.x];
   const uint32_t nitems = min((uint32_t)kPart, V - first);
   for (uint32_t i = t; i < nitems; i += kSortThreads) s_off[i] = offsets[first + i];
   __syncthreads();
@@ -423,31 +430,63 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
   const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
+  const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kSortItems;
+  if (mb < pend) {
+    uint32_t lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= mb) lo = mid; else hi = mid - 1;
+    }
+    uint32_t cur = lo, item = 0, x0 = 0, y0 = 0, wdt = 1, row = 0, col = 0, tiles_x = 0, toff = 0;
+    uint32_t next = 0;
+    bool fresh = true;
+#pragma unroll 1
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint32_t m = mb + (uint32_t)j;
+      if (m >= pend) break;
+      if (!fresh && m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
+        ++cur;
+        fresh = true;
+      }
+      if (fresh) {
+        item = ids[first + cur];
+        next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
+        const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
+        x0 = r.x & 0xffffu;
+        y0 = r.x >> 16;
+        wdt = (r.y & 0xffffu) - x0;
+        const uint32_t q = m - s_off[cur];
+        row = q / wdt;
+        col = q - row * wdt;
+        int vlo = 0, vhi = nv - 1;
+        while (vlo < vhi) {
+          const int mid = (vlo + vhi + 1) >> 1;
+          if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+        }
+        toff = (uint32_t)views[vlo].tile_offset;
+        tiles_x = (uint32_t)views[vlo].tiles_x;
+        fresh = false;
+      }
+      const uint32_t li = (uint32_t)t * (kSortItems + 1) + (uint32_t)j;
+      s_tile[li] = toff + (y0 + row) * tiles_x + x0 + col;
+      s_item[li] = item;
+      if (++col == wdt) {
+        col = 0;
+        ++row;
+      }
+    }
+  }
+  __syncthreads();
   // uniform trip count so that every lane takes part in the ballots
-  for (uint32_t m0 = (uint32_t)p0; m0 < pend; m0 += kSortThreads) {
-    const uint32_t m = m0 + t;
+  for (uint32_t i = t; i < (uint32_t)kPart; i += kSortThreads) {
+    const uint32_t m = (uint32_t)p0 + i;
     const bool on = m < pend;
     uint32_t tile = 0;
     if (on) {
-      uint32_t lo = 0, hi = nitems - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= m) lo = mid; else hi = mid - 1;
-      }
-      const uint32_t item = ids[first + lo];
-      const uint32_t q = m - s_off[lo];
-      const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
-      const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu;
-      int vlo = 0, vhi = nv - 1;
-      while (vlo < vhi) {
-        const int mid = (vlo + vhi + 1) >> 1;
-        if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
-      }
-      const uint32_t wdt = x1 - x0;
-      const uint32_t row = q / wdt, col = q - row * wdt;
-      tile = (uint32_t)views[vlo].tile_offset + (y0 + row) * (uint32_t)views[vlo].tiles_x + x0 + col;
+      const uint32_t li = i + i / kSortItems;
+      tile = s_tile[li];
       tkeys[m] = tile;
-      pvals[m] = item;
+      pvals[m] = s_item[li];
     }
     for (int ps = 0; ps < tpass; ++ps) wave_hist_add(s_h + ps * kRadix, (tile >> (8 * ps)) & 255u, on);
   }
@@ -458,19 +497,16 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
   }
 }
 
-// ---------------------------------------------------------------- ranges
-// One thread per sorted pair: a tile's first pair writes its start, its last
-// pair its end (the range array was cleared, so empty tiles read (0, 0)).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkeys,
                                                 const uint32_t* __restrict__ counters,
                                                 uint32_t* __restrict__ ranges) {
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const uint32_t tk = tkeys[i];
-  if (i == 0 || tkeys[i - 1] != tk) ranges[2 * (size_t)tk] = i;
-  if (i == P - 1 || tkeys[i + 1] != tk) ranges[2 * (size_t)tk + 1] = i + 1;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+    const uint32_t tk = tkeys[i];
+    if (i == 0 || tkeys[i - 1] != tk) ranges[2 * (size_t)tk] = i;
+    if (i == P - 1 || tkeys[i + 1] != tk) ranges[2 * (size_t)tk + 1] = i + 1;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ vals,
@@ -478,9 +514,8 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
                                                 const uint32_t* __restrict__ counters, uint64_t* __restrict__ keys) {
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  keys[i] = ((uint64_t)tkeys[i] << 32) | (uint64_t)depth_bits[vals[i]];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x)
+    keys[i] = ((uint64_t)tkeys[i] << 32) | (uint64_t)depth_bits[vals[i]];
 }
 
 // ------------------------------------------------------------------ plan
@@ -512,6 +547,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_dvals_a = off; off = align_up(off + (size_t)items * 4);
   p.off_dvals_b = off; off = align_up(off + (size_t)items * 4);
   p.off_offsets = off; off = align_up(off + (size_t)items * 4);
+  p.off_chunks = off; off = align_up(off + (size_t)(p.parts_pairs + 1) * 4);
   p.off_tkeys_a = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
@@ -553,6 +589,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const unsigned parts_i = (unsigned)(p.parts_items > 0 ? p.parts_items : 1);
   const unsigned parts_p = (unsigned)(p.parts_pairs > 0 ? p.parts_pairs : 1);
   uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
+  uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 
   // K2a: compaction + depth histograms
   if (p.items > 0)
@@ -568,9 +605,9 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K2b: tiles-touched scan in depth order, P, overflow
   uint32_t* thist = hist + kDepthPasses * kRadix;
   hipLaunchKernelGGL(k_expand_scan, dim3(parts_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
-                     counters, look_expand, offsets, d_num_pairs, d_overflow);
+                     counters, look_expand, offsets, chunk_first, parts_p, d_num_pairs, d_overflow);
   // K3: load-balanced pair emission in depth order + tile-digit histograms
-  hipLaunchKernelGGL(k_emit, dim3(parts_p), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, tpass,
+  hipLaunchKernelGGL(k_emit, dim3(parts_p), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first, tpass,
                      counters, thist, tk[0], pv[0]);
   // K4b: tile passes over the P pairs
   for (int ps = 0; ps < tpass; ++ps) {
@@ -581,7 +618,8 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   }
   uint32_t* tk_final = tk[tpass & 1];
   // K5: ranges
-  const unsigned pblocks = (unsigned)((p.capacity + 255) / 256 > 0 ? (p.capacity + 255) / 256 : 1);
+  const int64_t pb = (p.capacity + 255) / 256;
+  const unsigned pblocks = (unsigned)(pb < 1 ? 1 : (pb > 2048 ? 2048 : pb));
   hipLaunchKernelGGL(k_ranges, dim3(pblocks), dim3(256), 0, s, tk_final, counters, ranges);
   if (keys)
     hipLaunchKernelGGL(k_keys64, dim3(pblocks), dim3(256), 0, s, tk_final, vals, depth_bits, counters, keys);
