@@ -27,6 +27,39 @@ HBM_PEAK_GBS = 8000.0
 # use): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 78.6
 
+# HBM traffic of one k_render_fwd<4, false> launch on the default workload,
+# from two rocprofv3 --pmc runs of `bench.py --profile --no-train` (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch, mean over the dispatches), each scaled by
+# what the same counter reads for the 256 MiB device copy that run also makes
+# (FETCH_SIZE reads 131,088 KiB for 262,144 KiB moved: x2.0; WRITE_SIZE reads
+# 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
+# taken on (hash of the blend's source text); otherwise traffic is null.
+RENDER_FWD_COUNTERS = {
+    "source_sha256": "c3be92b9370e6411a6f04c36501ca58b7aab490730b0243b66549c450f6dfd34",
+    "fetch_kib": 20367.25, "write_kib": 21496.92, "fetch_scale": 2.0, "write_scale": 1.0,
+}
+
+
+def render_fwd_source_sha():
+    """sha256 over the blend kernel's source: render.hip up to the backward
+    helpers, plus the shared internal header."""
+    import hashlib
+    base = os.path.join(ROOT, "paper_2508_05343_amd", "csrc")
+    with open(os.path.join(base, "render.hip")) as f:
+        txt = f.read()
+    cut = txt.index("// ------------------------------------------------- wave reduce-scatter-add")
+    h = hashlib.sha256(txt[:cut].encode())
+    with open(os.path.join(base, "gs_internal.h")) as f:
+        h.update(f.read().encode())
+    return h.hexdigest()
+
+
+def render_fwd_traffic():
+    c = RENDER_FWD_COUNTERS
+    if render_fwd_source_sha() != c["source_sha256"]:
+        return None
+    return int(1024 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -188,7 +221,7 @@ def main():
         "fwd_hbm_fraction": round(hbm_frac_fwd, 4),
         "roofline": {"kernel": "k_render_fwd<4>", "bound": "alu", "achieved": round(render_tflops, 3),
                      "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(render_tflops / VALU_PEAK_TFLOPS, 4),
-                     "traffic": None, "evaluations": e_env, "full_evaluations": e_full,
+                     "traffic": render_fwd_traffic(), "evaluations": e_env, "full_evaluations": e_full,
                      "flops_per_launch": int(render_flops), "kernel_ms": round(stage_ms["render_fwd"], 4),
                      "hbm_gbs": round(render_gbs, 1), "hbm_frac": round(render_gbs / HBM_PEAK_GBS, 4),
                      "dominant_stage": dom},

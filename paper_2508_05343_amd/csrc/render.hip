@@ -7,10 +7,10 @@
 // of the 8 XCDs (which receive workgroup ids round-robin) renders one
 // contiguous band of tiles and keeps its records in its own L2.
 //
-// The forward and the backward evaluate alpha with the same inline function
-// and only explicit fused multiply-adds (the library is built without FP
-// contraction), so the backward's skip decisions and its transmittance
-// recovery T_i = T_{i+1} / (1 - alpha_i) reproduce the forward bit for bit.
+// The forward and the backward evaluate alpha with the same sequence of
+// operations and only explicit fused multiply-adds (the library is built
+// without FP contraction), so the backward takes exactly the forward's skip
+// decisions; it recovers T_i = T_{i+1} / (1 - alpha_i) up to rounding.
 #include <hip/hip_runtime.h>
 
 #include "gs_internal.h"
@@ -37,7 +37,8 @@ __device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv,
 // cos(2 pi x) and sin(2 pi x); the hardware units take revolutions
 __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(x)); }
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(x)); }
-// 2^x on the hardware unit; only called with x >= log2(1/255), far from denormals
+// 2^x on the hardware unit.  Every result that is used has x >= log2(1/255);
+// lanes with smaller x (whose results are discarded) get 0 or a denormal.
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Record field access (see gabsplat_geom.rec)
@@ -166,12 +167,13 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
       while (bits) {
         const int j = c0 + __builtin_ctzll(bits);
         bits &= bits - 1;
-        if (done) continue;
         const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
         const float dx = fx - r0.x, dy = fy - r0.y;
         const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
-        if (pw < kLog2AlphaMin) continue;  // o G < 1/255 and B <= 1: alpha < 1/255
-        if (ANALYSIS) ++n_full;
+        // o G < 1/255 with B <= 1 means alpha < 1/255: no full evaluation
+        bool live = !done && !(pw < kLog2AlphaMin);
+        if (__ballot(live) == 0ull) continue;
+        if (ANALYSIS) n_full += live ? 1u : 0u;
         float r[RF];
         r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
 #pragma unroll
@@ -179,17 +181,17 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
           const float4 v = s_rec[j * R4 + q];
           r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
         }
+        // straight-line update: lanes that do not take the record keep their state
         const float E = exp2_hw(pw);
         const float Bv = rec_modulation<K>(r, dx, dy);
         const float alpha = fminf(kAlphaMax, E * Bv);
-        if (alpha < kAlphaMin) continue;
+        live = live && !(alpha < kAlphaMin);
         const float Tn = T * (1.0f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          if (ANALYSIS) stop_pos = b - start + (uint32_t)j + 1;
-          continue;
-        }
-        const float wt = alpha * T;
+        const bool stop = live && Tn < kTMin;
+        const bool take = live && !stop;
+        if (ANALYSIS && stop) stop_pos = b - start + (uint32_t)j + 1;
+        done = done || stop;
+        const float wt = take ? alpha * T : 0.f;
         C0 = fmaf(r[6], wt, C0);
         C1 = fmaf(r[7], wt, C1);
         C2 = fmaf(r[8], wt, C2);
@@ -200,8 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
             phi = fmaf(r[12 + 3 * k], sqrtf(r[10 + 3 * k] * r[10 + 3 * k] + r[11 + 3 * k] * r[11 + 3 * k]), phi);
           Fm = fmaf(phi, wt, Fm);
         }
-        T = Tn;
-        last = b - start + (uint32_t)j + 1;
+        T = take ? Tn : T;
+        last = take ? b - start + (uint32_t)j + 1 : last;
       }
     }
   }
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
           r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
         }
         // alpha exactly as the forward evaluates it (same operations, same order)
-        const float E = exp2_hw(fmaxf(pw, kLog2AlphaMin));
+        const float E = exp2_hw(pw);
         float cs[K > 0 ? K : 1], sn[K > 0 ? K : 1];
         float Bv = r[9];
 #pragma unroll
