@@ -35,6 +35,7 @@ constexpr uint32_t kFlagInc = 1u << 31;
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr int kDepthPasses = 4;
 constexpr int kMaxTilePasses = 4;
+constexpr unsigned kLoopBlocks = 512;  // two 256-lane blocks per CU
 
 // counters (u32) at the start of the workspace
 enum {
@@ -192,118 +193,122 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  if (t == 0) s_part = atomicAdd(ticket, 1u);
-  for (int i = t; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&s_wh[0][0])[i] = 0;
-  __syncthreads();
-  const uint32_t part = s_part;
   const uint32_t n = *d_count;
-  const uint64_t base = (uint64_t)part * kPart;
-  if (base >= n) return;
-
   // exclusive digit offsets of this pass
   uint32_t dummy;
   const uint32_t goff = block_excl_scan(hist[t], s_wave, &dummy);
+  // partitions are taken from the ticket until they run past the key count;
+  // a block only ever waits on partitions that running blocks hold
+  for (;;) {
+    __syncthreads();
+    if (t == 0) s_part = atomicAdd(ticket, 1u);
+    for (int i = t; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&s_wh[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t part = s_part;
+    const uint64_t base = (uint64_t)part * kPart;
+    if (base >= n) return;
 
-  // warp-striped load: wave w owns [w*1024, (w+1)*1024), item j of lane l at j*64 + l
-  uint32_t key[kSortItems], val[kSortItems];
-  uint16_t rank[kSortItems];
-  const uint64_t wbase = base + (uint64_t)w * (64 * kSortItems);
+    // warp-striped load: wave w owns [w*1024, (w+1)*1024), item j of lane l at j*64 + l
+    uint32_t key[kSortItems], val[kSortItems];
+    uint16_t rank[kSortItems];
+    const uint64_t wbase = base + (uint64_t)w * (64 * kSortItems);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t i = wbase + (uint64_t)j * 64 + l;
-    const bool ok = i < n;
-    key[j] = ok ? keys_in[i] : 0xffffffffu;
-    val[j] = ok ? vals_in[i] : 0u;
-  }
-  const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t i = wbase + (uint64_t)j * 64 + l;
-    const bool ok = i < n;
-    const uint32_t d = (key[j] >> shift) & 255u;
-    uint64_t peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      const bool ok = i < n;
+      key[j] = ok ? keys_in[i] : 0xffffffffu;
+      val[j] = ok ? vals_in[i] : 0u;
     }
-    const uint32_t lower = (uint32_t)__popcll(peers & lt_mask);
-    const uint32_t cur = s_wh[w][d];
-    rank[j] = (uint16_t)(cur + lower);
-    const bool leader = ok && ((peers >> l) == 1ull);
-    if (leader) s_wh[w][d] = cur + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-
-  // per digit: wave prefix, block count, publish, look back
-  const int d = t;
-  uint32_t tot = 0;
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
 #pragma unroll
-  for (int i = 0; i < kSortThreads / 64; ++i) {
-    const uint32_t c = s_wh[i][d];
-    s_wh[i][d] = tot;
-    tot += c;
-  }
-  uint32_t* my_look = look + ((size_t)part * npass + pass) * kRadix + d;
-  uint32_t excl = 0;
-  if (part == 0) {
-    st_flag(my_look, kFlagInc | tot);
-  } else {
-    st_flag(my_look, kFlagAgg | tot);
-    // walk back 64 predecessors per round trip (independent loads in flight):
-    // a walk over p predecessors costs ceil(p / 64) memory latencies
-    constexpr int kAhead = 64;
-    int64_t hi = (int64_t)part - 1;
-    bool found = false;
-    while (!found) {
-      uint32_t v[kAhead];
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      const bool ok = i < n;
+      const uint32_t d = (key[j] >> shift) & 255u;
+      uint64_t peers = __ballot(ok);
 #pragma unroll
-      for (int q = 0; q < kAhead; ++q) {
-        const int64_t p = hi - q;
-        v[q] = (p >= 0) ? ld_flag(look + ((size_t)p * npass + pass) * kRadix + d) : kFlagInc;
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
       }
+      const uint32_t lower = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t cur = s_wh[w][d];
+      rank[j] = (uint16_t)(cur + lower);
+      const bool leader = ok && ((peers >> l) == 1ull);
+      if (leader) s_wh[w][d] = cur + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // per digit: wave prefix, block count, publish, look back
+    const int d = t;
+    uint32_t tot = 0;
 #pragma unroll
-      for (int q = 0; q < kAhead; ++q) {
-        if (!found) {
+    for (int i = 0; i < kSortThreads / 64; ++i) {
+      const uint32_t c = s_wh[i][d];
+      s_wh[i][d] = tot;
+      tot += c;
+    }
+    uint32_t* my_look = look + ((size_t)part * npass + pass) * kRadix + d;
+    uint32_t excl = 0;
+    if (part == 0) {
+      st_flag(my_look, kFlagInc | tot);
+    } else {
+      st_flag(my_look, kFlagAgg | tot);
+      // walk back 64 predecessors per round trip (independent loads in flight):
+      // a walk over p predecessors costs ceil(p / 64) memory latencies
+      constexpr int kAhead = 64;
+      int64_t hi = (int64_t)part - 1;
+      bool found = false;
+      while (!found) {
+        uint32_t v[kAhead];
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q) {
           const int64_t p = hi - q;
-          uint32_t x = v[q];
-          while ((x & (kFlagAgg | kFlagInc)) == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
-          }
-          excl += x & kCountMask;
-          found = (x & kFlagInc) != 0;
+          v[q] = (p >= 0) ? ld_flag(look + ((size_t)p * npass + pass) * kRadix + d) : kFlagInc;
         }
-      }
-      hi -= kAhead;
-    }
-    st_flag(my_look, kFlagInc | (excl + tot));
-  }
-  s_gbase[d] = goff + excl;
-  const uint32_t lstart = block_excl_scan(tot, s_wave, &dummy);
-  s_local[d] = lstart;
-  __syncthreads();
-
-  // scatter into LDS in digit order
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t i = wbase + (uint64_t)j * 64 + l;
-    if (i < n) {
-      const uint32_t dd = (key[j] >> shift) & 255u;
-      const uint32_t lp = s_local[dd] + s_wh[w][dd] + rank[j];
-      s_keys[lp] = key[j];
-      s_vals[lp] = val[j];
+        for (int q = 0; q < kAhead; ++q) {
+          if (!found) {
+            const int64_t p = hi - q;
+            uint32_t x = v[q];
+            while ((x & (kFlagAgg | kFlagInc)) == 0) {
+              __builtin_amdgcn_s_sleep(1);
+              x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
+            }
+            excl += x & kCountMask;
+            found = (x & kFlagInc) != 0;
+          }
+        }
+        hi -= kAhead;
+      }
+      st_flag(my_look, kFlagInc | (excl + tot));
     }
-  }
-  __syncthreads();
-  const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)kPart ? (n - base) : (uint64_t)kPart);
-  for (uint32_t i = t; i < nvalid; i += kSortThreads) {
-    const uint32_t k = s_keys[i];
-    const uint32_t dd = (k >> shift) & 255u;
-    const uint32_t dst = s_gbase[dd] + (i - s_local[dd]);
-    keys_out[dst] = k;
-    vals_out[dst] = s_vals[i];
+    s_gbase[d] = goff + excl;
+    const uint32_t lstart = block_excl_scan(tot, s_wave, &dummy);
+    s_local[d] = lstart;
+    __syncthreads();
+
+    // scatter into LDS in digit order
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      if (i < n) {
+        const uint32_t dd = (key[j] >> shift) & 255u;
+        const uint32_t lp = s_local[dd] + s_wh[w][dd] + rank[j];
+        s_keys[lp] = key[j];
+        s_vals[lp] = val[j];
+      }
+    }
+    __syncthreads();
+    const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)kPart ? (n - base) : (uint64_t)kPart);
+    for (uint32_t i = t; i < nvalid; i += kSortThreads) {
+      const uint32_t k = s_keys[i];
+      const uint32_t dd = (k >> shift) & 255u;
+      const uint32_t dst = s_gbase[dd] + (i - s_local[dd]);
+      keys_out[dst] = k;
+      vals_out[dst] = s_vals[i];
+    }
   }
 }
 
@@ -313,7 +318,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 // offsets[]; the last partition writes P and the overflow flag.  Every
 // visible item touches at least one tile, so pair index c * kPart lies in
 // exactly one item's range: that item's position is stored as chunk_first[c]
-// (c < max_chunks) for the emission kernel.
+// (c < max_chunks) for the emission kernel.  Blocks take partitions from a
+// ticket until they run past V.
 __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __restrict__ tiles,
                                                               const uint32_t* __restrict__ ids, uint32_t capacity,
                                                               uint32_t* __restrict__ counters,
@@ -325,57 +331,60 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
   __shared__ uint32_t s_wave[kSortThreads / 64];
   __shared__ uint32_t s_misc[2];
   const int t = threadIdx.x;
-  if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_EXPAND], 1u);
-  __syncthreads();
-  const uint32_t part = s_misc[0];
   const uint32_t V = counters[C_NUM_VISIBLE];
-  const uint64_t base = (uint64_t)part * kPart;
-  if (V == 0) {
-    if (part == 0 && t == 0) {
-      counters[C_NUM_PAIRS] = 0;
-      counters[C_OVERFLOW] = 0;
-      *d_num_pairs = 0;
-      *d_overflow = 0;
+  for (;;) {
+    __syncthreads();
+    if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_EXPAND], 1u);
+    __syncthreads();
+    const uint32_t part = s_misc[0];
+    const uint64_t base = (uint64_t)part * kPart;
+    if (V == 0) {
+      if (part == 0 && t == 0) {
+        counters[C_NUM_PAIRS] = 0;
+        counters[C_OVERFLOW] = 0;
+        *d_num_pairs = 0;
+        *d_overflow = 0;
+      }
+      return;
     }
-    return;
-  }
-  if (base >= V) return;
-  const uint64_t first = base + (uint64_t)t * kSortItems;
-  uint32_t x[kSortItems];
-  uint32_t sum = 0;
+    if (base >= V) return;
+    const uint64_t first = base + (uint64_t)t * kSortItems;
+    uint32_t x[kSortItems];
+    uint32_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t jj = first + j;
-    x[j] = jj < V ? tiles[ids[jj]] : 0u;
-    sum += x[j];
-  }
-  uint32_t block_total;
-  const uint32_t tpre = block_excl_scan(sum, s_wave, &block_total);
-  if (t < 64) {
-    const uint32_t excl = lookback_wave(look, part, block_total);
-    if (t == 0) {
-      s_misc[1] = excl;
-      if (base + kPart >= V) {
-        const uint32_t P = excl + block_total;
-        const uint32_t ov = P > capacity ? 1u : 0u;
-        counters[C_NUM_PAIRS] = P;
-        counters[C_OVERFLOW] = ov;
-        *d_num_pairs = (int64_t)P;
-        *d_overflow = (int32_t)ov;
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t jj = first + j;
+      x[j] = jj < V ? tiles[ids[jj]] : 0u;
+      sum += x[j];
+    }
+    uint32_t block_total;
+    const uint32_t tpre = block_excl_scan(sum, s_wave, &block_total);
+    if (t < 64) {
+      const uint32_t excl = lookback_wave(look, part, block_total);
+      if (t == 0) {
+        s_misc[1] = excl;
+        if (base + kPart >= V) {
+          const uint32_t P = excl + block_total;
+          const uint32_t ov = P > capacity ? 1u : 0u;
+          counters[C_NUM_PAIRS] = P;
+          counters[C_OVERFLOW] = ov;
+          *d_num_pairs = (int64_t)P;
+          *d_overflow = (int32_t)ov;
+        }
       }
     }
-  }
-  __syncthreads();
-  uint32_t pos = s_misc[1] + tpre;
+    __syncthreads();
+    uint32_t pos = s_misc[1] + tpre;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t jj = first + j;
-    if (jj < V) {
-      offsets[jj] = pos;
-      for (uint32_t c = (pos + kPart - 1) / kPart; c < max_chunks && (uint64_t)c * kPart < (uint64_t)pos + x[j]; ++c)
-        chunk_first[c] = (uint32_t)jj;
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t jj = first + j;
+      if (jj < V) {
+        offsets[jj] = pos;
+        for (uint32_t c = (pos + kPart - 1) / kPart; c < max_chunks && (uint64_t)c * kPart < (uint64_t)pos + x[j]; ++c)
+          chunk_first[c] = (uint32_t)jj;
+      }
+      pos += x[j];
     }
-    pos += x[j];
   }
 }
 
@@ -394,8 +403,9 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
   if (on && (peers >> l) == 1ull) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
 }
 
-// k_emit: globally load-balanced pair emission.  Block b writes pairs
-// [b * kPart, (b + 1) * kPart) of the depth-ordered pair sequence: it stages
+// k_emit: globally load-balanced pair emission.  Chunk c holds pairs
+// [c * kPart, (c + 1) * kPart) of the depth-ordered pair sequence; blocks
+// stride over the chunks.  For one chunk a block stages
 // the offsets of the items from chunk_first[b] on in LDS, every thread finds
 // the item of its first pair (one binary search) and walks its 16 consecutive
 // pairs item by item and tile by tile (row-major inside the item's tile
@@ -418,77 +428,80 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
   const uint32_t V = counters[C_NUM_VISIBLE];
-  const uint64_t p0 = (uint64_t)blockIdx.x * kPart;
-  if (p0 >= P) return;
+  if ((uint64_t)blockIdx.x * kPart >= P) return;
   const int t = threadIdx.x;
   for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
-  const uint32_t first = chunk_first[blockIdx.x];
-  const uint32_t nitems = min((uint32_t)kPart, V - first);
-  for (uint32_t i = t; i < nitems; i += kSortThreads) s_off[i] = offsets[first + i];
-  __syncthreads();
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
-  const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
-  const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kSortItems;
-  if (mb < pend) {
-    uint32_t lo = 0, hi = nitems - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= mb) lo = mid; else hi = mid - 1;
-    }
-    uint32_t cur = lo, item = 0, x0 = 0, y0 = 0, wdt = 1, row = 0, col = 0, tiles_x = 0, toff = 0;
-    uint32_t next = 0;
-    bool fresh = true;
+  for (uint64_t chunk = blockIdx.x; chunk * kPart < P; chunk += gridDim.x) {
+    const uint64_t p0 = chunk * kPart;
+    __syncthreads();
+    const uint32_t first = chunk_first[chunk];
+    const uint32_t nitems = min((uint32_t)kPart, V - first);
+    for (uint32_t i = t; i < nitems; i += kSortThreads) s_off[i] = offsets[first + i];
+    __syncthreads();
+    const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
+    const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kSortItems;
+    if (mb < pend) {
+      uint32_t lo = 0, hi = nitems - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= mb) lo = mid; else hi = mid - 1;
+      }
+      uint32_t cur = lo, item = 0, x0 = 0, y0 = 0, wdt = 1, row = 0, col = 0, tiles_x = 0, toff = 0;
+      uint32_t next = 0;
+      bool fresh = true;
 #pragma unroll 1
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint32_t m = mb + (uint32_t)j;
-      if (m >= pend) break;
-      if (!fresh && m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
-        ++cur;
-        fresh = true;
-      }
-      if (fresh) {
-        item = ids[first + cur];
-        next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
-        const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
-        x0 = r.x & 0xffffu;
-        y0 = r.x >> 16;
-        wdt = (r.y & 0xffffu) - x0;
-        const uint32_t q = m - s_off[cur];
-        row = q / wdt;
-        col = q - row * wdt;
-        int vlo = 0, vhi = nv - 1;
-        while (vlo < vhi) {
-          const int mid = (vlo + vhi + 1) >> 1;
-          if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+      for (int j = 0; j < kSortItems; ++j) {
+        const uint32_t m = mb + (uint32_t)j;
+        if (m >= pend) break;
+        if (!fresh && m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
+          ++cur;
+          fresh = true;
         }
-        toff = (uint32_t)views[vlo].tile_offset;
-        tiles_x = (uint32_t)views[vlo].tiles_x;
-        fresh = false;
-      }
-      const uint32_t li = (uint32_t)t * (kSortItems + 1) + (uint32_t)j;
-      s_tile[li] = toff + (y0 + row) * tiles_x + x0 + col;
-      s_item[li] = item;
-      if (++col == wdt) {
-        col = 0;
-        ++row;
+        if (fresh) {
+          item = ids[first + cur];
+          next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
+          const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
+          x0 = r.x & 0xffffu;
+          y0 = r.x >> 16;
+          wdt = (r.y & 0xffffu) - x0;
+          const uint32_t q = m - s_off[cur];
+          row = q / wdt;
+          col = q - row * wdt;
+          int vlo = 0, vhi = nv - 1;
+          while (vlo < vhi) {
+            const int mid = (vlo + vhi + 1) >> 1;
+            if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+          }
+          toff = (uint32_t)views[vlo].tile_offset;
+          tiles_x = (uint32_t)views[vlo].tiles_x;
+          fresh = false;
+        }
+        const uint32_t li = (uint32_t)t * (kSortItems + 1) + (uint32_t)j;
+        s_tile[li] = toff + (y0 + row) * tiles_x + x0 + col;
+        s_item[li] = item;
+        if (++col == wdt) {
+          col = 0;
+          ++row;
+        }
       }
     }
-  }
-  __syncthreads();
-  // uniform trip count so that every lane takes part in the ballots
-  for (uint32_t i = t; i < (uint32_t)kPart; i += kSortThreads) {
-    const uint32_t m = (uint32_t)p0 + i;
-    const bool on = m < pend;
-    uint32_t tile = 0;
-    if (on) {
-      const uint32_t li = i + i / kSortItems;
-      tile = s_tile[li];
-      tkeys[m] = tile;
-      pvals[m] = s_item[li];
+    __syncthreads();
+    // uniform trip count so that every lane takes part in the ballots
+    for (uint32_t i = t; i < (uint32_t)kPart; i += kSortThreads) {
+      const uint32_t m = (uint32_t)p0 + i;
+      const bool on = m < pend;
+      uint32_t tile = 0;
+      if (on) {
+        const uint32_t li = i + i / kSortItems;
+        tile = s_tile[li];
+        tkeys[m] = tile;
+        pvals[m] = s_item[li];
+      }
+      for (int ps = 0; ps < tpass; ++ps) wave_hist_add(s_h + ps * kRadix, (tile >> (8 * ps)) & 255u, on);
     }
-    for (int ps = 0; ps < tpass; ++ps) wave_hist_add(s_h + ps * kRadix, (tile >> (8 * ps)) & 255u, on);
   }
   __syncthreads();
   for (int i = t; i < tpass * kRadix; i += kSortThreads) {
@@ -588,6 +601,10 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   }
   const unsigned parts_i = (unsigned)(p.parts_items > 0 ? p.parts_items : 1);
   const unsigned parts_p = (unsigned)(p.parts_pairs > 0 ? p.parts_pairs : 1);
+  // grids of the ticket / stride loops: bounded, independent of the capacity
+  const unsigned grid_i = parts_i < kLoopBlocks ? parts_i : kLoopBlocks;
+  const unsigned grid_p = parts_p < kLoopBlocks ? parts_p : kLoopBlocks;
+  const unsigned grid_e = parts_p < 2 * kLoopBlocks ? parts_p : 2 * kLoopBlocks;
   uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
   uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 
@@ -598,21 +615,21 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K4a: depth passes over the V visible items (even count: result in dk[0], dv[0])
   for (int ps = 0; ps < kDepthPasses; ++ps) {
     const int a = ps & 1;
-    hipLaunchKernelGGL(k_onesweep, dim3(parts_i), dim3(kSortThreads), 0, s, dk[a], dv[a], dk[a ^ 1], dv[a ^ 1],
+    hipLaunchKernelGGL(k_onesweep, dim3(grid_i), dim3(kSortThreads), 0, s, dk[a], dv[a], dk[a ^ 1], dv[a ^ 1],
                        counters + C_NUM_VISIBLE, 8 * ps, ps, kDepthPasses, hist + ps * kRadix, look_depth,
                        counters + C_TICKET_DEPTH + ps, nullptr);
   }
   // K2b: tiles-touched scan in depth order, P, overflow
   uint32_t* thist = hist + kDepthPasses * kRadix;
-  hipLaunchKernelGGL(k_expand_scan, dim3(parts_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
+  hipLaunchKernelGGL(k_expand_scan, dim3(grid_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
                      counters, look_expand, offsets, chunk_first, parts_p, d_num_pairs, d_overflow);
   // K3: load-balanced pair emission in depth order + tile-digit histograms
-  hipLaunchKernelGGL(k_emit, dim3(parts_p), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first, tpass,
+  hipLaunchKernelGGL(k_emit, dim3(grid_e), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first, tpass,
                      counters, thist, tk[0], pv[0]);
   // K4b: tile passes over the P pairs
   for (int ps = 0; ps < tpass; ++ps) {
     const int a = ps & 1;
-    hipLaunchKernelGGL(k_onesweep, dim3(parts_p), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1], pv[a ^ 1],
+    hipLaunchKernelGGL(k_onesweep, dim3(grid_p), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1], pv[a ^ 1],
                        counters + C_NUM_PAIRS, 8 * ps, ps, tpass, thist + ps * kRadix, look_tile,
                        counters + C_TICKET_TILE + ps, ov);
   }

@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
 // finds the primitives visible in at least one view (and, when overwriting,
 // zeroes the gradients of the others); phase 2 runs the chain rule on the
 // compacted visible primitives only.
-template <int K>
+template <int K, bool COLOUR>
 __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ table, int scene_index,
                                                    const uint32_t* __restrict__ tiles,
                                                    const float* __restrict__ depth,
@@ -436,6 +436,7 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
     if (tiles[item] == 0) continue;
     any = true;
     const float* g2 = grad2d + item * GF;
+    if constexpr (!COLOUR) {
     float G2[GF];
 #pragma unroll
     for (int j = 0; j < GF / 4; ++j) {
@@ -591,7 +592,9 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
     // ---- t = R mu + t0
     gmean = add3(gmean, v3(R[0] * gtx + R[3] * gty + R[6] * gtz, R[1] * gtx + R[4] * gty + R[7] * gtz,
                            R[2] * gtx + R[5] * gty + R[8] * gtz));
+    } else {
     // ---- colour
+    const float G2c[3] = {g2[6], g2[7], g2[8]};
     if (deg >= 0) {
       const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
       const float il = 1.0f / sqrtf(dot3(d, d));
@@ -612,7 +615,7 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
         for (int ch = 0; ch < 3; ++ch) col[ch] = (b < nd) ? fmaf(Y[b], shv[b * 3 + ch], col[ch]) : col[ch];
       float drgb[3];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) drgb[ch] = col[ch] < 0.f ? 0.f : G2[6 + ch];
+      for (int ch = 0; ch < 3; ++ch) drgb[ch] = col[ch] < 0.f ? 0.f : G2c[ch];
       V3 gdir = v3(0.f, 0.f, 0.f);
 #pragma unroll
       for (int b = 0; b < 16; ++b) {
@@ -630,49 +633,60 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
       gmean = add3(gmean, scale3(add3(gdir, scale3(dir, -pr)), il));
     } else {
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gcol[ch] += G2[6 + ch];
+      for (int ch = 0; ch < 3; ++ch) gcol[ch] += G2c[ch];
+    }
     }
   }
   if (!any && gr.accumulate) return;
-  // accumulate: +=; otherwise overwrite (gradients of culled primitives are 0)
+  // accumulate: +=; otherwise overwrite (gradients of culled primitives are 0).
+  // The colour part runs second and adds its view-direction term to the mean
+  // gradient that the geometry part has just written.
   const bool acc = gr.accumulate != 0;
   auto put = [acc](float* p, float v) { *p = acc ? *p + v : v; };
-  if (gr.means) {
-    put(&gr.means[i], gmean.x);
-    put(&gr.means[n + i], gmean.y);
-    put(&gr.means[2 * n + i], gmean.z);
-  }
-  if (gr.scales) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b) put(&gr.scales[b * n + i], gs[b]);
-  }
-  if (gr.quats) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) put(&gr.quats[b * n + i], gq[b]);
-  }
-  if (gr.opacities) put(&gr.opacities[i], go);
-  if (deg >= 0) {
-    if (gr.sh) {
-#pragma unroll
-      for (int b = 0; b < 48; ++b)
-        if (b < nd * 3) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
+  if constexpr (COLOUR) {
+    if (gr.means) {
+      gr.means[i] += gmean.x;
+      gr.means[n + i] += gmean.y;
+      gr.means[2 * n + i] += gmean.z;
     }
-  } else if (gr.colors) {
+    if (deg >= 0) {
+      if (gr.sh) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) put(&gr.colors[ch * n + i], gcol[ch]);
-  }
+        for (int b = 0; b < 48; ++b)
+          if (b < nd * 3) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
+      }
+    } else if (gr.colors) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (gr.freqs) {
-      put(&gr.freqs[(int64_t)(3 * k) * n + i], gf[k].x);
-      put(&gr.freqs[(int64_t)(3 * k + 1) * n + i], gf[k].y);
-      put(&gr.freqs[(int64_t)(3 * k + 2) * n + i], gf[k].z);
+      for (int ch = 0; ch < 3; ++ch) put(&gr.colors[ch * n + i], gcol[ch]);
     }
-    if (gr.weights) put(&gr.weights[(int64_t)k * n + i], gw[k]);
+  } else {
+    if (gr.means) {
+      put(&gr.means[i], gmean.x);
+      put(&gr.means[n + i], gmean.y);
+      put(&gr.means[2 * n + i], gmean.z);
+    }
+    if (gr.scales) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) put(&gr.scales[b * n + i], gs[b]);
+    }
+    if (gr.quats) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) put(&gr.quats[b * n + i], gq[b]);
+    }
+    if (gr.opacities) put(&gr.opacities[i], go);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (gr.freqs) {
+        put(&gr.freqs[(int64_t)(3 * k) * n + i], gf[k].x);
+        put(&gr.freqs[(int64_t)(3 * k + 1) * n + i], gf[k].y);
+        put(&gr.freqs[(int64_t)(3 * k + 2) * n + i], gf[k].z);
+      }
+      if (gr.weights) put(&gr.weights[(int64_t)k * n + i], gw[k]);
+    }
   }
 }
 
-template <int K>
+template <int K, bool COLOUR>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
                                                         const uint32_t* __restrict__ tiles,
                                                         const float* __restrict__ depth,
@@ -703,19 +717,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__
     if (any) {
       cand |= 1u << j;
     } else if (!gr.accumulate) {
-      if (gr.means) { gr.means[i] = 0.f; gr.means[n + i] = 0.f; gr.means[2 * n + i] = 0.f; }
-      if (gr.scales) { gr.scales[i] = 0.f; gr.scales[n + i] = 0.f; gr.scales[2 * n + i] = 0.f; }
-      if (gr.quats)
-        for (int b = 0; b < 4; ++b) gr.quats[b * n + i] = 0.f;
-      if (gr.opacities) gr.opacities[i] = 0.f;
-      if (deg >= 0 && gr.sh)
-        for (int b = 0; b < nd * 3; ++b) gr.sh[(int64_t)b * n + i] = 0.f;
-      if (deg < 0 && gr.colors)
-        for (int b = 0; b < 3; ++b) gr.colors[b * n + i] = 0.f;
-      if (gr.freqs)
-        for (int b = 0; b < 3 * K; ++b) gr.freqs[(int64_t)b * n + i] = 0.f;
-      if (gr.weights)
-        for (int b = 0; b < K; ++b) gr.weights[(int64_t)b * n + i] = 0.f;
+      if constexpr (COLOUR) {
+        if (deg >= 0 && gr.sh)
+          for (int b = 0; b < nd * 3; ++b) gr.sh[(int64_t)b * n + i] = 0.f;
+        if (deg < 0 && gr.colors)
+          for (int b = 0; b < 3; ++b) gr.colors[b * n + i] = 0.f;
+      } else {
+        if (gr.means) { gr.means[i] = 0.f; gr.means[n + i] = 0.f; gr.means[2 * n + i] = 0.f; }
+        if (gr.scales) { gr.scales[i] = 0.f; gr.scales[n + i] = 0.f; gr.scales[2 * n + i] = 0.f; }
+        if (gr.quats)
+          for (int b = 0; b < 4; ++b) gr.quats[b * n + i] = 0.f;
+        if (gr.opacities) gr.opacities[i] = 0.f;
+        if (gr.freqs)
+          for (int b = 0; b < 3 * K; ++b) gr.freqs[(int64_t)b * n + i] = 0.f;
+        if (gr.weights)
+          for (int b = 0; b < K; ++b) gr.weights[(int64_t)b * n + i] = 0.f;
+      }
     }
   }
   const uint32_t nc = (uint32_t)__popc(cand);
@@ -739,7 +756,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__
     if ((cand >> j) & 1u) s_cand[pos++] = (uint16_t)(j * 256 + t);
   __syncthreads();
   for (uint32_t c = t; c < total; c += 256)
-    preprocess_bwd_one<K>(table, scene_index, tiles, depth, grad2d, gr, base + s_cand[c]);
+    preprocess_bwd_one<K, COLOUR>(table, scene_index, tiles, depth, grad2d, gr, base + s_cand[c]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -776,8 +793,13 @@ static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat
                          const gabsplat_scene_grads& gr, const int32_t* ov, hipStream_t s) {
   const int64_t n = h.scenes[sc].n;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_preprocess_bwd<K>, dim3((unsigned)((n + kPreBlock - 1) / kPreBlock)), dim3(256), 0, s, d_table, sc,
-                     g.tiles, g.depth, gr.grad2d, gr, ov);
+  // geometry / frequency / opacity part, then the colour part (which adds
+  // its view-direction term to the mean gradient): two register budgets
+  const dim3 grid((unsigned)((n + kPreBlock - 1) / kPreBlock));
+  hipLaunchKernelGGL((k_preprocess_bwd<K, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
+                     gr, ov);
+  hipLaunchKernelGGL((k_preprocess_bwd<K, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
+                     gr, ov);
   return hipGetLastError();
 }
 
