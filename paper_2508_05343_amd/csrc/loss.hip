@@ -1,7 +1,8 @@
 // K9: photometric loss (1 - lambda) L1 + lambda (1 - SSIM) and its gradient
 // (Sec. 3.4.1, lambda = 0.2).  SSIM uses an 11x11 Gaussian window (sigma 1.5)
 // with zero padding; the five local moments are separable filters staged in
-// LDS per 16x16 tile.  With A1 = 2 mx my + C1, A2 = 2 sxy + C2,
+// LDS per 32x16 output tile (horizontal pass: runs of 4 outputs per lane from
+// registers; vertical pass: pairs of rows per lane).  With A1 = 2 mx my + C1, A2 = 2 sxy + C2,
 // B1 = mx^2 + my^2 + C1, B2 = sxx + syy + C2 and s = A1 A2 / (B1 B2):
 //   ds/dmx  = s (2 my / A1 - 2 my / A2 - 2 mx / B1 + 2 mx / B2)
 //   ds/dExx = -s / B2,   ds/dExy = 2 s / A2
@@ -18,8 +19,13 @@ namespace gs {
 
 constexpr int kWin = 11;
 constexpr int kHalo = 5;
-constexpr int kLT = 16;                 // output tile
-constexpr int kLS = kLT + 2 * kHalo;    // staged region 26x26
+constexpr int kTX = 32, kTY = 16;        // output tile of one 256-lane block
+constexpr int kSY = kTY + 2 * kHalo;     // staged rows (26)
+constexpr int kSX = kTX + 2 * kHalo;     // staged columns (42)
+constexpr int kSP = 44;                  // LDS row pitch: 16-byte aligned rows
+constexpr int kRun = 4;                  // horizontal outputs per lane
+constexpr int kRuns = kTX / kRun;        // runs per row (8)
+constexpr int kHLanes = kSY * kRuns;     // lanes busy in the horizontal pass (208)
 
 struct Window {
   float g[kWin];
@@ -48,75 +54,120 @@ __device__ __forceinline__ float block_sum(float v, float* s_red) {
   return tot;
 }
 
+// Stages the (kSY x kSX) neighbourhood of the block's output tile of NM
+// planes (zero outside the image) into LDS rows of pitch kSP.
+template <int NM>
+__device__ __forceinline__ void stage_planes(const float* const (&src)[NM], int H, int W, int ox, int oy,
+                                             float (*dst)[kSY][kSP]) {
+  for (int i = threadIdx.x; i < kSY * kSX; i += 256) {
+    const int r = i / kSX, q = i - r * kSX;
+    const int gy = oy + r - kHalo, gx = ox + q - kHalo;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const size_t o = (size_t)gy * W + gx;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) dst[m][r][q] = in ? src[m][o] : 0.f;
+  }
+}
+
+// The kRun + kWin - 1 = 14 staged values a run of 4 outputs reads, from a row
+// position that is a multiple of 4 (three 16-byte and one 8-byte LDS read).
+constexpr int kRunIn = kRun + kWin - 1;
+__device__ __forceinline__ void load_run(const float* row, float (&v)[kRunIn]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float4 t = reinterpret_cast<const float4*>(row)[j];
+    v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
+  }
+  const float2 t = reinterpret_cast<const float2*>(row)[6];
+  v[12] = t.x;
+  v[13] = t.y;
+}
+
 // pass 1: moments, SSIM map, per-pixel factors for the backward, partial sums
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Window win, float lambda, float inv_n,
                                                   float* __restrict__ f3, float* __restrict__ partial) {
-  __shared__ float s_x[kLS][kLS], s_y[kLS][kLS];
-  __shared__ float s_h[5][kLS][kLT];
+  __shared__ __align__(16) float s_in[2][kSY][kSP];
+  __shared__ __align__(16) float s_h[5][kSY][kTX];
   __shared__ float s_red[4];
   const int c = blockIdx.z;
-  const int ox = blockIdx.x * kLT, oy = blockIdx.y * kLT;
+  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY;
   const size_t plane = (size_t)H * W;
-  const float* xc = x + c * plane;
-  const float* yc = y + c * plane;
-  for (int i = threadIdx.x; i < kLS * kLS; i += 256) {
-    const int r = i / kLS, q = i % kLS;
-    const int gy = oy + r - kHalo, gx = ox + q - kHalo;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    s_x[r][q] = in ? xc[(size_t)gy * W + gx] : 0.f;
-    s_y[r][q] = in ? yc[(size_t)gy * W + gx] : 0.f;
-  }
+  const float* const src[2] = {x + c * plane, y + c * plane};
+  stage_planes<2>(src, H, W, ox, oy, s_in);
   __syncthreads();
-  for (int i = threadIdx.x; i < kLS * kLT; i += 256) {
-    const int r = i / kLT, q = i % kLT;
-    float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+  const int t = threadIdx.x;
+  if (t < kHLanes) {  // horizontal pass: lane = (row, run of 4 outputs)
+    const int r = t / kRuns, q0 = (t % kRuns) * kRun;
+    float xv[kRunIn], yv[kRunIn];
+    load_run(&s_in[0][r][q0], xv);
+    load_run(&s_in[1][r][q0], yv);
+    float a[kRun], b[kRun], aa[kRun], bb[kRun], ab[kRun];
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float xv = s_x[r][q + k], yv = s_y[r][q + k], g = win.g[k];
-      a = fmaf(g, xv, a);
-      b = fmaf(g, yv, b);
-      aa = fmaf(g, xv * xv, aa);
-      bb = fmaf(g, yv * yv, bb);
-      ab = fmaf(g, xv * yv, ab);
+    for (int o = 0; o < kRun; ++o) a[o] = b[o] = aa[o] = bb[o] = ab[o] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kRunIn; ++j) {
+      const float xx = xv[j] * xv[j], yy = yv[j] * yv[j], xy = xv[j] * yv[j];
+#pragma unroll
+      for (int o = 0; o < kRun; ++o) {
+        const int k = j - o;
+        if (k >= 0 && k < kWin) {
+          const float g = win.g[k];
+          a[o] = fmaf(g, xv[j], a[o]);
+          b[o] = fmaf(g, yv[j], b[o]);
+          aa[o] = fmaf(g, xx, aa[o]);
+          bb[o] = fmaf(g, yy, bb[o]);
+          ab[o] = fmaf(g, xy, ab[o]);
+        }
+      }
     }
-    s_h[0][r][q] = a; s_h[1][r][q] = b; s_h[2][r][q] = aa; s_h[3][r][q] = bb; s_h[4][r][q] = ab;
+    *reinterpret_cast<float4*>(&s_h[0][r][q0]) = make_float4(a[0], a[1], a[2], a[3]);
+    *reinterpret_cast<float4*>(&s_h[1][r][q0]) = make_float4(b[0], b[1], b[2], b[3]);
+    *reinterpret_cast<float4*>(&s_h[2][r][q0]) = make_float4(aa[0], aa[1], aa[2], aa[3]);
+    *reinterpret_cast<float4*>(&s_h[3][r][q0]) = make_float4(bb[0], bb[1], bb[2], bb[3]);
+    *reinterpret_cast<float4*>(&s_h[4][r][q0]) = make_float4(ab[0], ab[1], ab[2], ab[3]);
   }
   __syncthreads();
-  const int r = threadIdx.x / kLT, q = threadIdx.x % kLT;
-  const int gy = oy + r, gx = ox + q;
-  float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+  // vertical pass: lane = (column, pair of rows)
+  const int q = t % kTX, r0 = (t / kTX) * 2;
+  float m[5][2];
 #pragma unroll
-  for (int k = 0; k < kWin; ++k) {
-    const float g = win.g[k];
-    mx = fmaf(g, s_h[0][r + k][q], mx);
-    my = fmaf(g, s_h[1][r + k][q], my);
-    exx = fmaf(g, s_h[2][r + k][q], exx);
-    eyy = fmaf(g, s_h[3][r + k][q], eyy);
-    exy = fmaf(g, s_h[4][r + k][q], exy);
+  for (int mm = 0; mm < 5; ++mm) {
+    m[mm][0] = m[mm][1] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kWin + 1; ++j) {
+      const float v = s_h[mm][r0 + j][q];
+      if (j < kWin) m[mm][0] = fmaf(win.g[j], v, m[mm][0]);
+      if (j >= 1) m[mm][1] = fmaf(win.g[j - 1], v, m[mm][1]);
+    }
   }
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
+  const float g = -lambda * inv_n;
+  const size_t nn = plane * gridDim.z;
   float ssim = 0.f, l1 = 0.f;
-  if (gy < H && gx < W) {
-    const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-    const float A1 = 2.f * mx * my + C1, A2 = 2.f * sxy + C2;
-    const float B1 = mx * mx + my * my + C1, B2 = sxx + syy + C2;
-    const float s = (A1 * A2) / (B1 * B2);
-    ssim = s;
-    l1 = fabsf(s_x[r + kHalo][q + kHalo] - s_y[r + kHalo][q + kHalo]);
-    const float g = -lambda * inv_n;
-    const size_t o = c * plane + (size_t)gy * W + gx;
-    const size_t nn = plane * gridDim.z;
-    f3[o] = g * s * (2.f * my / A1 - 2.f * my / A2 - 2.f * mx / B1 + 2.f * mx / B2);
-    f3[nn + o] = g * (-s / B2);
-    f3[2 * nn + o] = g * (2.f * s / A2);
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const int gy = oy + r0 + o, gx = ox + q;
+    if (gy < H && gx < W) {
+      const float mx = m[0][o], my = m[1][o];
+      const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
+      const float A1 = 2.f * mx * my + C1, A2 = 2.f * sxy + C2;
+      const float B1 = mx * mx + my * my + C1, B2 = sxx + syy + C2;
+      const float s = (A1 * A2) / (B1 * B2);
+      ssim += s;
+      l1 += fabsf(s_in[0][r0 + o + kHalo][q + kHalo] - s_in[1][r0 + o + kHalo][q + kHalo]);
+      const size_t off = c * plane + (size_t)gy * W + gx;
+      f3[off] = g * s * (2.f * my / A1 - 2.f * my / A2 - 2.f * mx / B1 + 2.f * mx / B2);
+      f3[nn + off] = g * (-s / B2);
+      f3[2 * nn + off] = g * (2.f * s / A2);
+    }
   }
   const float ts = block_sum(ssim, s_red);
   const float tl = block_sum(l1, s_red);
   if (threadIdx.x == 0) {
-    const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    partial[2 * b] = tl;
-    partial[2 * b + 1] = ts;
+    const size_t bi = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partial[2 * bi] = tl;
+    partial[2 * bi + 1] = ts;
   }
 }
 
@@ -124,51 +175,56 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Window win, float lambda, float inv_n,
                                                   const float* __restrict__ f3, float* __restrict__ dl_dx) {
-  __shared__ float s_f[3][kLS][kLS];
-  __shared__ float s_h[3][kLS][kLT];
+  __shared__ __align__(16) float s_f[3][kSY][kSP];
+  __shared__ __align__(16) float s_h[3][kSY][kTX];
   const int c = blockIdx.z;
-  const int ox = blockIdx.x * kLT, oy = blockIdx.y * kLT;
+  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY;
   const size_t plane = (size_t)H * W;
   const size_t nn = plane * gridDim.z;
-  for (int i = threadIdx.x; i < kLS * kLS; i += 256) {
-    const int r = i / kLS, q = i % kLS;
-    const int gy = oy + r - kHalo, gx = ox + q - kHalo;
-    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    const size_t o = c * plane + (size_t)gy * W + gx;
-    s_f[0][r][q] = in ? f3[o] : 0.f;
-    s_f[1][r][q] = in ? f3[nn + o] : 0.f;
-    s_f[2][r][q] = in ? f3[2 * nn + o] : 0.f;
-  }
+  const float* const src[3] = {f3 + c * plane, f3 + nn + c * plane, f3 + 2 * nn + c * plane};
+  stage_planes<3>(src, H, W, ox, oy, s_f);
   __syncthreads();
-  for (int i = threadIdx.x; i < kLS * kLT; i += 256) {
-    const int r = i / kLT, q = i % kLT;
-    float a = 0.f, b = 0.f, d = 0.f;
+  const int t = threadIdx.x;
+  if (t < kHLanes) {
+    const int r = t / kRuns, q0 = (t % kRuns) * kRun;
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float g = win.g[k];
-      a = fmaf(g, s_f[0][r][q + k], a);
-      b = fmaf(g, s_f[1][r][q + k], b);
-      d = fmaf(g, s_f[2][r][q + k], d);
+    for (int mm = 0; mm < 3; ++mm) {
+      float v[kRunIn];
+      load_run(&s_f[mm][r][q0], v);
+      float acc[kRun];
+#pragma unroll
+      for (int o = 0; o < kRun; ++o) {
+        acc[o] = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc[o] = fmaf(win.g[k], v[o + k], acc[o]);
+      }
+      *reinterpret_cast<float4*>(&s_h[mm][r][q0]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
-    s_h[0][r][q] = a; s_h[1][r][q] = b; s_h[2][r][q] = d;
   }
   __syncthreads();
-  const int r = threadIdx.x / kLT, q = threadIdx.x % kLT;
-  const int gy = oy + r, gx = ox + q;
-  if (gy >= H || gx >= W) return;
-  float a = 0.f, b = 0.f, d = 0.f;
+  const int q = t % kTX, r0 = (t / kTX) * 2;
+  float m[3][2];
 #pragma unroll
-  for (int k = 0; k < kWin; ++k) {
-    const float g = win.g[k];
-    a = fmaf(g, s_h[0][r + k][q], a);
-    b = fmaf(g, s_h[1][r + k][q], b);
-    d = fmaf(g, s_h[2][r + k][q], d);
+  for (int mm = 0; mm < 3; ++mm) {
+    m[mm][0] = m[mm][1] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kWin + 1; ++j) {
+      const float v = s_h[mm][r0 + j][q];
+      if (j < kWin) m[mm][0] = fmaf(win.g[j], v, m[mm][0]);
+      if (j >= 1) m[mm][1] = fmaf(win.g[j - 1], v, m[mm][1]);
+    }
   }
-  const size_t o = c * plane + (size_t)gy * W + gx;
-  const float xv = x[o], yv = y[o];
-  const float diff = xv - yv;
-  const float sgn = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
-  dl_dx[o] = (1.f - lambda) * inv_n * sgn + a + 2.f * xv * b + yv * d;
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const int gy = oy + r0 + o, gx = ox + q;
+    if (gy < H && gx < W) {
+      const size_t off = c * plane + (size_t)gy * W + gx;
+      const float xv = x[off], yv = y[off];
+      const float diff = xv - yv;
+      const float sgn = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
+      dl_dx[off] = (1.f - lambda) * inv_n * sgn + m[0][o] + 2.f * xv * m[1][o] + yv * m[2][o];
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ partial, int nb, float lambda,
@@ -185,14 +241,14 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
 }
 
 size_t loss_workspace_bytes(int c, int h, int w) {
-  const size_t nb = (size_t)((w + kLT - 1) / kLT) * ((h + kLT - 1) / kLT) * c;
+  const size_t nb = (size_t)((w + kTX - 1) / kTX) * ((h + kTY - 1) / kTY) * c;
   return (size_t)3 * c * h * w * 4 + nb * 2 * 4 + 256;
 }
 
 hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, float lambda, float* d_loss,
                        float* dl_dx, void* ws, hipStream_t s) {
   const Window win = gaussian_window();
-  const dim3 grid((w + kLT - 1) / kLT, (h + kLT - 1) / kLT, c);
+  const dim3 grid((w + kTX - 1) / kTX, (h + kTY - 1) / kTY, c);
   const int nb = grid.x * grid.y * grid.z;
   float* f3 = static_cast<float*>(ws);
   float* partial = f3 + (size_t)3 * c * h * w;
