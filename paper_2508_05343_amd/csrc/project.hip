@@ -387,39 +387,66 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
 }
 
 // ------------------------------------------------------------------ K8
-// One primitive of scene `scene_index` per work item; the primitive's views
-// are looped over (deterministic accumulation across views, no atomics).
-// Like K1 the kernel runs in two phases per block of 1024 primitives: phase 1
-// finds the primitives visible in at least one view (and, when overwriting,
-// zeroes the gradients of the others); phase 2 runs the chain rule on the
-// compacted visible primitives only.
-template <int K, bool COLOUR>
-__device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ table, int scene_index,
-                                                   const uint32_t* __restrict__ tiles,
-                                                   const float* __restrict__ depth,
-                                                   const float* __restrict__ grad2d,
-                                                   const gabsplat_scene_grads& gr, int64_t i) {
+// Two kernels run one after the other over the primitives of scene
+// `scene_index`, 256 per block: the geometry part (mean through the
+// projection, scale, rotation, opacity, frequencies, weights) and the colour
+// part (SH or RGB coefficients, plus the view-direction term of the mean
+// gradient, added to what the geometry part wrote).  A block stages the
+// attribute planes of its primitives that some view sees into LDS rows (loads
+// of consecutive primitives of one plane per instruction), runs the chain rule
+// once per such primitive over its views (deterministic accumulation, no
+// atomics), puts the gradients back into the same row and writes each
+// gradient plane out for all 256 primitives at once (zeros for the primitives
+// no view sees, unless accumulating).
+constexpr int kBwdBlock = 256;
+constexpr int kColPitch = 3 + 48;  // colour row: mean, then up to 48 SH coefficients (odd pitch)
+
+// Geometry row: mean 3, scale 3, quaternion 4, opacity 1, frequencies 3K, weights K
+template <int K>
+struct GeoRow {
+  static constexpr int NP = 11 + 4 * K;  // odd for every K: conflict-free LDS rows
+};
+
+template <int K>
+__device__ __forceinline__ const float* geo_src(const SceneEntry& S, int p) {
+  if (p < 3) return S.means + (int64_t)p * S.n;
+  if (p < 6) return S.scales + (int64_t)(p - 3) * S.n;
+  if (p < 10) return S.quats + (int64_t)(p - 6) * S.n;
+  if (p < 11) return S.opac;
+  if (p < 11 + 3 * K) return S.freqs + (int64_t)(p - 11) * S.n;
+  return S.weights + (int64_t)(p - 11 - 3 * K) * S.n;
+}
+
+template <int K>
+__device__ __forceinline__ float* geo_dst(const gabsplat_scene_grads& gr, int64_t n, int p) {
+  if (p < 3) return gr.means ? gr.means + (int64_t)p * n : nullptr;
+  if (p < 6) return gr.scales ? gr.scales + (int64_t)(p - 3) * n : nullptr;
+  if (p < 10) return gr.quats ? gr.quats + (int64_t)(p - 6) * n : nullptr;
+  if (p < 11) return gr.opacities;
+  if (p < 11 + 3 * K) return gr.freqs ? gr.freqs + (int64_t)(p - 11) * n : nullptr;
+  return gr.weights ? gr.weights + (int64_t)(p - 11 - 3 * K) * n : nullptr;
+}
+
+// Chain rule of the geometry part for primitive i, parameters in row P (LDS);
+// the gradients replace them in the same layout.
+template <int K>
+__device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int scene_index,
+                                            const uint32_t* __restrict__ tiles, const float* __restrict__ depth,
+                                            const float* __restrict__ grad2d, int64_t i, float* P) {
   constexpr int GF = (10 + 3 * K + 3) & ~3;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
   const SceneEntry& S = table_scenes(table, nv)[scene_index];
-  const int64_t n = S.n;
-  const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
-  const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
-  const float s[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
-  const float o = S.opac[i];
-  const int deg = S.sh_degree;
-  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+  const float mx = P[0], my = P[1], mz = P[2];
+  const float s[3] = {P[3], P[4], P[5]};
+  const float q[4] = {P[6], P[7], P[8], P[9]};
+  const float o = P[10];
 
   V3 gmean = v3(0.f, 0.f, 0.f);
   float gs[3] = {0.f, 0.f, 0.f};
   float gq[4] = {0.f, 0.f, 0.f, 0.f};
   float go = 0.f;
-  float gcol[3] = {0.f, 0.f, 0.f};
-  float gsh[48];
-#pragma unroll
-  for (int b = 0; b < 48; ++b) gsh[b] = 0.f;
   V3 gf[K > 0 ? K : 1];
   float gw[K > 0 ? K : 1];
 #pragma unroll
@@ -427,16 +454,12 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
     gf[k] = v3(0.f, 0.f, 0.f);
     gw[k] = 0.f;
   }
-  bool any = false;
-
   for (int v = 0; v < nv; ++v) {
     const ViewEntry& V = views[v];
     if (V.scene != scene_index) continue;
     const int64_t item = V.item_offset + i;
     if (tiles[item] == 0) continue;
-    any = true;
     const float* g2 = grad2d + item * GF;
-    if constexpr (!COLOUR) {
     float G2[GF];
 #pragma unroll
     for (int j = 0; j < GF / 4; ++j) {
@@ -475,14 +498,13 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
     V3 gvx = v3(0.f, 0.f, 0.f), gvy = v3(0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
-                      S.freqs[(int64_t)(3 * k + 2) * n + i]);
+      const V3 f = v3(P[11 + 3 * k], P[12 + 3 * k], P[13 + 3 * k]);
       const float gx = G2[10 + 3 * k], gy = G2[11 + 3 * k], gwr = G2[12 + 3 * k];
       gvx = add3(gvx, scale3(f, gx));
       gvy = add3(gvy, scale3(f, gy));
       gf[k] = add3(gf[k], add3(scale3(g.vx, gx), scale3(g.vy, gy)));
       if (atten) {
-        const float wk = S.weights[(int64_t)k * n + i];
+        const float wk = P[11 + 3 * K + k];
         const float v = ray_variance(g, u, f);
         const float a = __expf(-kTwoPiSq * v);
         gw[k] += gwr * a - G2[9];
@@ -592,7 +614,44 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
     // ---- t = R mu + t0
     gmean = add3(gmean, v3(R[0] * gtx + R[3] * gty + R[6] * gtz, R[1] * gtx + R[4] * gty + R[7] * gtz,
                            R[2] * gtx + R[5] * gty + R[8] * gtz));
-    } else {
+  }
+  P[0] = gmean.x; P[1] = gmean.y; P[2] = gmean.z;
+  P[3] = gs[0]; P[4] = gs[1]; P[5] = gs[2];
+  P[6] = gq[0]; P[7] = gq[1]; P[8] = gq[2]; P[9] = gq[3];
+  P[10] = go;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    P[11 + 3 * k] = gf[k].x;
+    P[12 + 3 * k] = gf[k].y;
+    P[13 + 3 * k] = gf[k].z;
+    P[11 + 3 * K + k] = gw[k];
+  }
+}
+
+// Colour part for primitive i: row P = mean, then the nc colour coefficients
+// (SH [(deg+1)^2][3] or RGB 3).  The coefficient gradients replace the
+// coefficients in P; the view-direction term of the mean gradient is returned.
+__device__ __forceinline__ V3 colour_bwd_one(const void* __restrict__ table, int scene_index,
+                                             const uint32_t* __restrict__ tiles, const float* __restrict__ grad2d,
+                                             int gf_stride, int64_t i, float* P) {
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const int nv = hdr->num_views;
+  const ViewEntry* views = table_views(table);
+  const SceneEntry& S = table_scenes(table, nv)[scene_index];
+  const float mx = P[0], my = P[1], mz = P[2];
+  const int deg = S.sh_degree;
+  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+  V3 gmean = v3(0.f, 0.f, 0.f);
+  float gcol[3] = {0.f, 0.f, 0.f};
+  float gsh[48];
+#pragma unroll
+  for (int b = 0; b < 48; ++b) gsh[b] = 0.f;
+  for (int v = 0; v < nv; ++v) {
+    const ViewEntry& V = views[v];
+    if (V.scene != scene_index) continue;
+    const int64_t item = V.item_offset + i;
+    if (tiles[item] == 0) continue;
+    const float* g2 = grad2d + item * (int64_t)gf_stride;
     // ---- colour
     const float G2c[3] = {g2[6], g2[7], g2[8]};
     if (deg >= 0) {
@@ -607,7 +666,7 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
 #pragma unroll
       for (int b = 0; b < 16; ++b)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) shv[b * 3 + ch] = (b < nd) ? S.sh[(int64_t)(b * 3 + ch) * n + i] : 0.f;
+        for (int ch = 0; ch < 3; ++ch) shv[b * 3 + ch] = (b < nd) ? P[3 + b * 3 + ch] : 0.f;
       float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
       for (int b = 0; b < 16; ++b)
@@ -635,128 +694,115 @@ __device__ __forceinline__ void preprocess_bwd_one(const void* __restrict__ tabl
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) gcol[ch] += G2c[ch];
     }
-    }
   }
-  if (!any && gr.accumulate) return;
-  // accumulate: +=; otherwise overwrite (gradients of culled primitives are 0).
-  // The colour part runs second and adds its view-direction term to the mean
-  // gradient that the geometry part has just written.
-  const bool acc = gr.accumulate != 0;
-  auto put = [acc](float* p, float v) { *p = acc ? *p + v : v; };
-  if constexpr (COLOUR) {
-    if (gr.means) {
-      gr.means[i] += gmean.x;
-      gr.means[n + i] += gmean.y;
-      gr.means[2 * n + i] += gmean.z;
-    }
-    if (deg >= 0) {
-      if (gr.sh) {
+  if (deg >= 0) {
 #pragma unroll
-        for (int b = 0; b < 48; ++b)
-          if (b < nd * 3) put(&gr.sh[(int64_t)b * n + i], gsh[b]);
-      }
-    } else if (gr.colors) {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) put(&gr.colors[ch * n + i], gcol[ch]);
-    }
+    for (int b = 0; b < 48; ++b)
+      if (b < nd * 3) P[3 + b] = gsh[b];
   } else {
-    if (gr.means) {
-      put(&gr.means[i], gmean.x);
-      put(&gr.means[n + i], gmean.y);
-      put(&gr.means[2 * n + i], gmean.z);
-    }
-    if (gr.scales) {
-#pragma unroll
-      for (int b = 0; b < 3; ++b) put(&gr.scales[b * n + i], gs[b]);
-    }
-    if (gr.quats) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) put(&gr.quats[b * n + i], gq[b]);
-    }
-    if (gr.opacities) put(&gr.opacities[i], go);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (gr.freqs) {
-        put(&gr.freqs[(int64_t)(3 * k) * n + i], gf[k].x);
-        put(&gr.freqs[(int64_t)(3 * k + 1) * n + i], gf[k].y);
-        put(&gr.freqs[(int64_t)(3 * k + 2) * n + i], gf[k].z);
-      }
-      if (gr.weights) put(&gr.weights[(int64_t)k * n + i], gw[k]);
-    }
+    P[3] = gcol[0]; P[4] = gcol[1]; P[5] = gcol[2];
   }
+  return gmean;
 }
 
 template <int K, bool COLOUR>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
-                                                        const uint32_t* __restrict__ tiles,
-                                                        const float* __restrict__ depth,
-                                                        const float* __restrict__ grad2d,
-                                                        gabsplat_scene_grads gr,
-                                                        const int32_t* __restrict__ d_overflow) {
-  __shared__ uint16_t s_cand[kPreBlock];
-  __shared__ uint32_t s_wave[4];
+__global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
+                                                              const uint32_t* __restrict__ tiles,
+                                                              const float* __restrict__ depth,
+                                                              const float* __restrict__ grad2d,
+                                                              gabsplat_scene_grads gr,
+                                                              const int32_t* __restrict__ d_overflow) {
+  constexpr int PITCH = COLOUR ? kColPitch : GeoRow<K>::NP;
+  constexpr int GF = (10 + 3 * K + 3) & ~3;
+  __shared__ float s_row[kBwdBlock * PITCH];
+  __shared__ int16_t s_prim[kBwdBlock];
+  __shared__ uint32_t s_wave[kBwdBlock / 64];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
   const SceneEntry& S = table_scenes(table, nv)[scene_index];
   const int64_t n = S.n;
-  const int64_t base = (int64_t)blockIdx.x * kPreBlock;
+  const int64_t base = (int64_t)blockIdx.x * kBwdBlock;
   if (base >= n) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int deg = S.sh_degree;
-  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
-  uint32_t cand = 0;
+  const int64_t i = base + t;
+  const bool in = i < n;
+  bool vis = false;
+  for (int v = 0; v < nv && in && !vis; ++v)
+    vis = views[v].scene == scene_index && tiles[views[v].item_offset + i] != 0;
+  // slot of a visible primitive among the block's visible ones (in order)
+  const uint64_t bal = __ballot(vis);
+  const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
+  if (l == 0) s_wave[w] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  int before = 0, count = 0;
 #pragma unroll
-  for (int j = 0; j < kPreItems; ++j) {
-    const int64_t i = base + j * 256 + t;
-    if (i >= n) continue;
-    bool any = false;
-    for (int v = 0; v < nv && !any; ++v)
-      any = views[v].scene == scene_index && tiles[views[v].item_offset + i] != 0;
-    if (any) {
-      cand |= 1u << j;
-    } else if (!gr.accumulate) {
+  for (int q = 0; q < kBwdBlock / 64; ++q) {
+    before += q < w ? (int)s_wave[q] : 0;
+    count += (int)s_wave[q];
+  }
+  const int slot = vis ? before + __popcll(bal & lt) : -1;
+  const bool acc = gr.accumulate != 0;
+  if (count == 0 && acc) return;
+  const int deg = S.sh_degree;
+  const int nc = deg >= 0 ? (deg + 1) * (deg + 1) * 3 : 3;
+  const int npl = COLOUR ? 3 + nc : GeoRow<K>::NP;
+  if (count > 0) {
+    if (vis) {
+      s_prim[slot] = (int16_t)t;
+      float* row = s_row + slot * PITCH;
       if constexpr (COLOUR) {
-        if (deg >= 0 && gr.sh)
-          for (int b = 0; b < nd * 3; ++b) gr.sh[(int64_t)b * n + i] = 0.f;
-        if (deg < 0 && gr.colors)
-          for (int b = 0; b < 3; ++b) gr.colors[b * n + i] = 0.f;
+        const float* cs = deg >= 0 ? S.sh : S.colors;
+        for (int p = 0; p < npl; ++p) row[p] = p < 3 ? S.means[(int64_t)p * n + i] : cs[(int64_t)(p - 3) * n + i];
       } else {
-        if (gr.means) { gr.means[i] = 0.f; gr.means[n + i] = 0.f; gr.means[2 * n + i] = 0.f; }
-        if (gr.scales) { gr.scales[i] = 0.f; gr.scales[n + i] = 0.f; gr.scales[2 * n + i] = 0.f; }
-        if (gr.quats)
-          for (int b = 0; b < 4; ++b) gr.quats[b * n + i] = 0.f;
-        if (gr.opacities) gr.opacities[i] = 0.f;
-        if (gr.freqs)
-          for (int b = 0; b < 3 * K; ++b) gr.freqs[(int64_t)b * n + i] = 0.f;
-        if (gr.weights)
-          for (int b = 0; b < K; ++b) gr.weights[(int64_t)b * n + i] = 0.f;
+#pragma unroll
+        for (int p = 0; p < GeoRow<K>::NP; ++p) row[p] = geo_src<K>(S, p)[i];
+      }
+    }
+    __syncthreads();
+    if (t < count) {
+      const int64_t ii = base + s_prim[t];
+      float* row = s_row + t * PITCH;
+      if constexpr (COLOUR) {
+        const V3 gm = colour_bwd_one(table, scene_index, tiles, grad2d, GF, ii, row);
+        if (gr.means) {  // after the geometry part has written the mean gradient
+          gr.means[ii] += gm.x;
+          gr.means[n + ii] += gm.y;
+          gr.means[2 * n + ii] += gm.z;
+        }
+      } else {
+        geo_bwd_one<K>(table, scene_index, tiles, depth, grad2d, ii, row);
+      }
+    }
+    __syncthreads();
+  }
+  if (!in) return;
+  // gradient planes, one plane per step over the block's 256 primitives
+  const float* row = s_row + (slot >= 0 ? slot : 0) * PITCH;
+  if constexpr (COLOUR) {
+    float* cd = deg >= 0 ? gr.sh : gr.colors;
+    if (cd == nullptr) return;
+    for (int p = 3; p < npl; ++p) {
+      float* dst = cd + (int64_t)(p - 3) * n + i;
+      if (acc) {
+        if (vis) *dst += row[p];
+      } else {
+        *dst = vis ? row[p] : 0.f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < GeoRow<K>::NP; ++p) {
+      float* d = geo_dst<K>(gr, n, p);
+      if (d == nullptr) continue;
+      if (acc) {
+        if (vis) d[i] += row[p];
+      } else {
+        d[i] = vis ? row[p] : 0.f;
       }
     }
   }
-  const uint32_t nc = (uint32_t)__popc(cand);
-  uint32_t inc = nc;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(inc, d, 64);
-    if (l >= d) inc += o;
-  }
-  if (l == 63) s_wave[w] = inc;
-  __syncthreads();
-  uint32_t off = 0, total = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    off += (q < w) ? s_wave[q] : 0u;
-    total += s_wave[q];
-  }
-  uint32_t pos = off + inc - nc;
-#pragma unroll
-  for (int j = 0; j < kPreItems; ++j)
-    if ((cand >> j) & 1u) s_cand[pos++] = (uint16_t)(j * 256 + t);
-  __syncthreads();
-  for (uint32_t c = t; c < total; c += 256)
-    preprocess_bwd_one<K, COLOUR>(table, scene_index, tiles, depth, grad2d, gr, base + s_cand[c]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -795,7 +841,7 @@ static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat
   if (n == 0) return hipSuccess;
   // geometry / frequency / opacity part, then the colour part (which adds
   // its view-direction term to the mean gradient): two register budgets
-  const dim3 grid((unsigned)((n + kPreBlock - 1) / kPreBlock));
+  const dim3 grid((unsigned)((n + kBwdBlock - 1) / kBwdBlock));
   hipLaunchKernelGGL((k_preprocess_bwd<K, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
                      gr, ov);
   hipLaunchKernelGGL((k_preprocess_bwd<K, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
