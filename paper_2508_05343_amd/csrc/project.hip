@@ -752,12 +752,21 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
     if (vis) {
       s_prim[slot] = (int16_t)t;
       float* row = s_row + slot * PITCH;
+      // every load of the row is issued before the first LDS store
       if constexpr (COLOUR) {
         const float* cs = deg >= 0 ? S.sh : S.colors;
-        for (int p = 0; p < npl; ++p) row[p] = p < 3 ? S.means[(int64_t)p * n + i] : cs[(int64_t)(p - 3) * n + i];
-      } else {
+        float v[kColPitch];
 #pragma unroll
-        for (int p = 0; p < GeoRow<K>::NP; ++p) row[p] = geo_src<K>(S, p)[i];
+        for (int p = 0; p < kColPitch; ++p)
+          v[p] = p < 3 ? S.means[(int64_t)p * n + i] : (p < npl ? cs[(int64_t)(p - 3) * n + i] : 0.f);
+#pragma unroll
+        for (int p = 0; p < kColPitch; ++p) row[p] = v[p];
+      } else {
+        float v[GeoRow<K>::NP];
+#pragma unroll
+        for (int p = 0; p < GeoRow<K>::NP; ++p) v[p] = geo_src<K>(S, p)[i];
+#pragma unroll
+        for (int p = 0; p < GeoRow<K>::NP; ++p) row[p] = v[p];
       }
     }
     __syncthreads();
@@ -783,12 +792,15 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
   if constexpr (COLOUR) {
     float* cd = deg >= 0 ? gr.sh : gr.colors;
     if (cd == nullptr) return;
-    for (int p = 3; p < npl; ++p) {
-      float* dst = cd + (int64_t)(p - 3) * n + i;
-      if (acc) {
-        if (vis) *dst += row[p];
-      } else {
-        *dst = vis ? row[p] : 0.f;
+#pragma unroll
+    for (int p = 3; p < kColPitch; ++p) {
+      if (p < npl) {
+        float* dst = cd + (int64_t)(p - 3) * n + i;
+        if (acc) {
+          if (vis) *dst += row[p];
+        } else {
+          *dst = vis ? row[p] : 0.f;
+        }
       }
     }
   } else {

@@ -3,9 +3,9 @@
 // One 256-lane workgroup per 16x16 tile; wave w covers the 8x8 quadrant
 // (w & 1, w >> 1) of the tile so that a wave's pixels are spatially compact.
 // Batches of 256 render records are staged in LDS (one record per lane) and
-// every lane walks them in order.  Workgroups are mapped to tiles so that each
-// of the 8 XCDs (which receive workgroup ids round-robin) renders one
-// contiguous band of tiles and keeps its records in its own L2.
+// every lane walks them in order.  Workgroups are mapped to tiles so that the
+// 8 XCDs (which receive workgroup ids round-robin) get interleaved groups of
+// adjacent tiles: balanced work, shared records within a group.
 //
 // The forward and the backward evaluate alpha with the same sequence of
 // operations and only explicit fused multiply-adds (the library is built
@@ -18,11 +18,20 @@
 namespace gs {
 
 constexpr int kNumXcd = 8;
+constexpr int kTileGroup = 4;
 
+// Workgroup ids reach the 8 XCDs round-robin (id % 8).  Tiles are dealt to
+// the XCDs in groups of kTileGroup consecutive tiles, round-robin: XCD x
+// renders groups x, x + 8, ...  Adjacent tiles of a group share most of their
+// records in that XCD's L2, and the fine interleave spreads the dense parts
+// of the image evenly over the XCDs (contiguous bands of tile rows per XCD
+// leave the XCD with the densest band working ~1.5x longer than the mean).
+// The blocks past the last full round of groups map to themselves.
 __device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
-  const int per = nb / kNumXcd, extra = nb % kNumXcd;
+  const int full = nb / (kNumXcd * kTileGroup) * (kNumXcd * kTileGroup);
+  if (bid >= full) return bid;
   const int x = bid % kNumXcd, j = bid / kNumXcd;
-  return x * per + (x < extra ? x : extra) + j;
+  return ((j / kTileGroup) * kNumXcd + x) * kTileGroup + j % kTileGroup;
 }
 
 __device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv, int tile) {
@@ -40,12 +49,6 @@ __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf
 // 2^x on the hardware unit.  Every result that is used has x >= log2(1/255);
 // lanes with smaller x (whose results are discarded) get 0 or a denormal.
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
-
-// Record field access (see gabsplat_geom.rec)
-template <int K>
-struct Rec {
-  static constexpr int RF = (10 + 3 * K + 3) & ~3;
-};
 
 // Bit q (q = 0..3, quadrant (q & 1, q >> 1) of 8x8 pixels of the tile whose
 // top-left pixel is (ox, oy)) is set when the record's support o G >= 1/255
@@ -87,23 +90,49 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float ox
   return m;
 }
 
-// Envelope exponent q + log2 o for offset (dx, dy).
-__device__ __forceinline__ float rec_power(const float* r, float dx, float dy) {
-  const float t1 = fmaf(r[2], dx, r[3] * dy);
-  return fmaf(t1, dx, fmaf(r[4] * dy, dy, r[5]));
-}
-
-// Gabor modulation B = w0 + sum_k w_k cos(2 pi (f_k . d)).
+// A record as staged in LDS for one tile, relative to the tile origin (ox, oy):
+// with the pixel's in-tile centre (u, v) = (px - ox + 0.5, py - oy + 0.5) and
+// m = (mu_x - ox, mu_y - oy), the envelope exponent q(d) + log2 o (d = (u, v) - m)
+// is the quadratic A u^2 + B u v + C v^2 + D u + E v + F, and the phase of
+// component k is fx_k u + fy_k v + G_k.  Floats (3 + K float4s):
+//   [A B C F] [D E m_x m_y] [r g b w0] then per component [fx fy G w'].
 template <int K>
-__device__ __forceinline__ float rec_modulation(const float* r, float dx, float dy) {
-  float b = r[9];
+struct Staged {
+  static constexpr int S4 = 3 + K;
+};
+
+template <int K>
+__device__ __forceinline__ void stage_record(const float4* q, float ox, float oy, float4* dst) {
+  // record fields (gabsplat_geom.rec): mu 0-1, conic terms 2-4, log2 o 5,
+  // rgb 6-8, w0 9, component k at 10 + 3k (fx, fy, w')
+  constexpr int R4 = (10 + 3 * K + 3) / 4;
+  float f[4 * R4];
+#pragma unroll
+  for (int j = 0; j < R4; ++j) {
+    f[4 * j] = q[j].x; f[4 * j + 1] = q[j].y; f[4 * j + 2] = q[j].z; f[4 * j + 3] = q[j].w;
+  }
+  const float A = f[2], B = f[3], C = f[4];
+  const float mx = f[0] - ox, my = f[1] - oy;
+  const float D = -fmaf(2.0f * A, mx, B * my);
+  const float E = -fmaf(B, mx, 2.0f * C * my);
+  const float F = fmaf(A * mx, mx, fmaf(B * mx, my, fmaf(C * my, my, f[5])));
+  dst[0] = make_float4(A, B, C, F);
+  dst[1] = make_float4(D, E, mx, my);
+  dst[2] = make_float4(f[6], f[7], f[8], f[9]);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float ph = fmaf(r[10 + 3 * k], dx, r[11 + 3 * k] * dy);
-    b = fmaf(r[12 + 3 * k], cos_rev(ph), b);
+    const float fxk = f[10 + 3 * k], fyk = f[11 + 3 * k];
+    dst[3 + k] = make_float4(fxk, fyk, -fmaf(fxk, mx, fyk * my), f[12 + 3 * k]);
   }
-  return b;
 }
+
+// Envelope exponent of a staged record at in-tile pixel centre (u, v).
+__device__ __forceinline__ float staged_power(float4 s0, float4 s1, float u, float v) {
+  return fmaf(u, fmaf(s0.x, u, fmaf(s0.y, v, s1.x)), fmaf(v, fmaf(s0.z, v, s1.y), s0.w));
+}
+
+// Phase (cycles) of a staged component (fx, fy, G) at (u, v).
+__device__ __forceinline__ float staged_phase(float4 c, float u, float v) { return fmaf(c.x, u, fmaf(c.y, v, c.z)); }
 
 // --------------------------------------------------------------------- K6
 // The ANALYSIS variant (never the timed one) can also report, per pixel, how
@@ -122,9 +151,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
                                                        uint32_t* __restrict__ eval_counts,
                                                        float* __restrict__ freq_map,
                                                        const int32_t* __restrict__ d_overflow) {
-  constexpr int RF = Rec<K>::RF;
+  constexpr int RF = (10 + 3 * K + 3) & ~3;
   constexpr int R4 = RF / 4;
-  __shared__ float4 s_rec[kBlock * R4];
+  constexpr int S4 = Staged<K>::S4;
+  __shared__ float4 s_rec[kBlock * S4];
   __shared__ uint32_t s_mask[kBlock];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -137,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   const int px = tx * kTile + (w & 1) * 8 + (l & 7);
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
 
@@ -154,36 +184,33 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
       float4 q[R4];
 #pragma unroll
       for (int j = 0; j < R4; ++j) q[j] = src[j];
-#pragma unroll
-      for (int j = 0; j < R4; ++j) s_rec[t * R4 + j] = q[j];
+      stage_record<K>(q, ox, oy, &s_rec[t * S4]);
       m = quadrant_mask(q[0], q[1], ox, oy);
     }
     s_mask[t] = m;
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBlock, end - b);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
-      if (__ballot(!done) == 0ull) break;
+      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;
       uint64_t bits = __ballot(c0 + l < cnt && ((s_mask[c0 + l] >> w) & 1u));
       while (bits) {
         const int j = c0 + __builtin_ctzll(bits);
         bits &= bits - 1;
-        const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
-        const float dx = fx - r0.x, dy = fy - r0.y;
-        const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
+        const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
+        const float pw = staged_power(s0, s1, u, v);
         // o G < 1/255 with B <= 1 means alpha < 1/255: no full evaluation
         bool live = !done && !(pw < kLog2AlphaMin);
-        if (__ballot(live) == 0ull) continue;
+        if (__builtin_amdgcn_ballot_w64(live) == 0ull) continue;
         if (ANALYSIS) n_full += live ? 1u : 0u;
-        float r[RF];
-        r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
-#pragma unroll
-        for (int q = 2; q < R4; ++q) {
-          const float4 v = s_rec[j * R4 + q];
-          r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
-        }
+        const float4 col = s_rec[j * S4 + 2];
         // straight-line update: lanes that do not take the record keep their state
         const float E = exp2_hw(pw);
-        const float Bv = rec_modulation<K>(r, dx, dy);
+        float Bv = col.w;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float4 c = s_rec[j * S4 + 3 + k];
+          Bv = fmaf(c.w, cos_rev(staged_phase(c, u, v)), Bv);
+        }
         const float alpha = fminf(kAlphaMax, E * Bv);
         live = live && !(alpha < kAlphaMin);
         const float Tn = T * (1.0f - alpha);
@@ -192,14 +219,16 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         if (ANALYSIS && stop) stop_pos = b - start + (uint32_t)j + 1;
         done = done || stop;
         const float wt = take ? alpha * T : 0.f;
-        C0 = fmaf(r[6], wt, C0);
-        C1 = fmaf(r[7], wt, C1);
-        C2 = fmaf(r[8], wt, C2);
+        C0 = fmaf(col.x, wt, C0);
+        C1 = fmaf(col.y, wt, C1);
+        C2 = fmaf(col.z, wt, C2);
         if (ANALYSIS) {
           float phi = 0.f;
 #pragma unroll
-          for (int k = 0; k < K; ++k)
-            phi = fmaf(r[12 + 3 * k], sqrtf(r[10 + 3 * k] * r[10 + 3 * k] + r[11 + 3 * k] * r[11 + 3 * k]), phi);
+          for (int k = 0; k < K; ++k) {
+            const float4 c = s_rec[j * S4 + 3 + k];
+            phi = fmaf(c.w, sqrtf(c.x * c.x + c.y * c.y), phi);
+          }
           Fm = fmaf(phi, wt, Fm);
         }
         T = take ? Tn : T;
@@ -301,12 +330,13 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
                                                        const float* __restrict__ dl_dimage,
                                                        float* __restrict__ grad2d,
                                                        const int32_t* __restrict__ d_overflow) {
-  constexpr int RF = Rec<K>::RF;
+  constexpr int RF = (10 + 3 * K + 3) & ~3;
   constexpr int R4 = RF / 4;
+  constexpr int S4 = Staged<K>::S4;
   constexpr int GS = 10 + 3 * K;           // gradient components per pair (one per record field)
   constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
   constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
-  __shared__ float4 s_rec[kBlock * R4];
+  __shared__ float4 s_rec[kBlock * S4];
   __shared__ uint32_t s_id[kBlock];
   __shared__ uint32_t s_mask[kBlock];
   __shared__ uint32_t s_max;
@@ -321,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   const int px = tx * kTile + (w & 1) * 8 + (l & 7);
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile];
 
@@ -362,8 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
       float4 q[R4];
 #pragma unroll
       for (int j = 0; j < R4; ++j) q[j] = src[j];
-#pragma unroll
-      for (int j = 0; j < R4; ++j) s_rec[t * R4 + j] = q[j];
+      stage_record<K>(q, ox, oy, &s_rec[t * S4]);
       m = quadrant_mask(q[0], q[1], ox, oy);
     }
     s_mask[t] = m;
@@ -377,35 +406,29 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         bits &= ~(1ull << hb);
         const int j = c0 + hb;
         const uint32_t pos = lo + (uint32_t)j + 1;
-        const float4 r0 = s_rec[j * R4], r1 = s_rec[j * R4 + 1];
-        const float dx = fx - r0.x, dy = fy - r0.y;
-        const float pw = fmaf(fmaf(r0.z, dx, r0.w * dy), dx, fmaf(r1.x * dy, dy, r1.y));
+        const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
+        const float pw = staged_power(s0, s1, u, v);
         bool contrib = pos <= last && !(pw < kLog2AlphaMin);
-        if (__ballot(contrib) == 0ull) continue;
-        float r[RF];
-        r[0] = r0.x; r[1] = r0.y; r[2] = r0.z; r[3] = r0.w;
-        r[4] = r1.x; r[5] = r1.y; r[6] = r1.z; r[7] = r1.w;
+        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
+        const float4 col = s_rec[j * S4 + 2];
+        float4 cc[K > 0 ? K : 1];
 #pragma unroll
-        for (int q = 2; q < R4; ++q) {
-          const float4 v = s_rec[j * R4 + q];
-          r[4 * q] = v.x; r[4 * q + 1] = v.y; r[4 * q + 2] = v.z; r[4 * q + 3] = v.w;
-        }
+        for (int k = 0; k < K; ++k) cc[k] = s_rec[j * S4 + 3 + k];
         // alpha exactly as the forward evaluates it (same operations, same order)
         const float E = exp2_hw(pw);
         float cs[K > 0 ? K : 1], sn[K > 0 ? K : 1];
-        float Bv = r[9];
+        float Bv = col.w;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float ph = fmaf(r[10 + 3 * k], dx, r[11 + 3 * k] * dy);
-          const float fr = __builtin_amdgcn_fractf(ph);
+          const float fr = __builtin_amdgcn_fractf(staged_phase(cc[k], u, v));
           cs[k] = __builtin_amdgcn_cosf(fr);
           sn[k] = __builtin_amdgcn_sinf(fr);
-          Bv = fmaf(r[12 + 3 * k], cs[k], Bv);
+          Bv = fmaf(cc[k].w, cs[k], Bv);
         }
         const float EB = E * Bv;
         const float alpha = fminf(kAlphaMax, EB);
         contrib = contrib && !(alpha < kAlphaMin);
-        if (__ballot(contrib) == 0ull) continue;
+        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
         // lanes without a contribution keep their state and produce zero gradients
         const float om = 1.0f - alpha;
         const float inv = __builtin_amdgcn_rcpf(om);
@@ -416,36 +439,37 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         acc0 = contrib ? na0 : acc0;
         acc1 = contrib ? na1 : acc1;
         acc2 = contrib ? na2 : acc2;
-        lc0 = contrib ? r[6] : lc0;
-        lc1 = contrib ? r[7] : lc1;
-        lc2 = contrib ? r[8] : lc2;
+        lc0 = contrib ? col.x : lc0;
+        lc1 = contrib ? col.y : lc1;
+        lc2 = contrib ? col.z : lc2;
         la = contrib ? alpha : la;
         const float wt = contrib ? alpha * T : 0.f;
-        float da = (r[6] - acc0) * dC0 + (r[7] - acc1) * dC1 + (r[8] - acc2) * dC2;
+        float da = (col.x - acc0) * dC0 + (col.y - acc1) * dC1 + (col.z - acc2) * dC2;
         da = da * T - Tf * bgdot * inv;
         da = (contrib && !(EB > kAlphaMax)) ? da : 0.f;  // a binding clamp has zero derivative
         const float dB = da * E;
         const float dp = da * Bv * E * kLn2;
         float gv[NP];
-        gv[2] = dp * dx * dx;
-        gv[3] = dp * dx * dy;
-        gv[4] = dp * dy * dy;
         gv[5] = dp;
         gv[6] = wt * dC0;
         gv[7] = wt * dC1;
         gv[8] = wt * dC2;
         gv[9] = dB;  // DC weight
-        float ddx = dp * (2.0f * r[2] * dx + r[3] * dy);
-        float ddy = dp * (r[3] * dx + 2.0f * r[4] * dy);
+        const float dx = u - s1.z, dy = v - s1.w;
+        gv[2] = dp * dx * dx;
+        gv[3] = dp * dx * dy;
+        gv[4] = dp * dy * dy;
+        float ddx = dp * (2.0f * s0.x * dx + s0.y * dy);
+        float ddy = dp * (s0.y * dx + 2.0f * s0.z * dy);
         const float dB2pi = -dB * 6.283185307179586f;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float dph = dB2pi * r[12 + 3 * k] * sn[k];
+          const float dph = dB2pi * cc[k].w * sn[k];
           gv[10 + 3 * k] = dph * dx;
           gv[11 + 3 * k] = dph * dy;
           gv[12 + 3 * k] = dB * cs[k];
-          ddx = fmaf(dph, r[10 + 3 * k], ddx);
-          ddy = fmaf(dph, r[11 + 3 * k], ddy);
+          ddx = fmaf(dph, cc[k].x, ddx);
+          ddy = fmaf(dph, cc[k].y, ddy);
         }
         gv[0] = -ddx;
         gv[1] = -ddy;
