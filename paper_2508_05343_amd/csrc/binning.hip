@@ -194,11 +194,17 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint32_t n = *d_count;
+  // Only the first ceil(n / kPart) blocks take tickets (one shared counter:
+  // every ticket is a same-address atomic).  When the grid has a block per
+  // partition each of them takes exactly one; otherwise blocks keep taking
+  // tickets until they run past the key count.  A block only ever waits on
+  // partitions that running blocks hold.
+  const uint32_t nparts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+  if (blockIdx.x >= nparts) return;
+  const bool one_each = gridDim.x >= nparts;
   // exclusive digit offsets of this pass
   uint32_t dummy;
   const uint32_t goff = block_excl_scan(hist[t], s_wave, &dummy);
-  // partitions are taken from the ticket until they run past the key count;
-  // a block only ever waits on partitions that running blocks hold
   for (;;) {
     __syncthreads();
     if (t == 0) s_part = atomicAdd(ticket, 1u);
@@ -309,6 +315,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
       keys_out[dst] = k;
       vals_out[dst] = s_vals[i];
     }
+    if (one_each) return;
   }
 }
 
@@ -332,21 +339,25 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
   __shared__ uint32_t s_misc[2];
   const int t = threadIdx.x;
   const uint32_t V = counters[C_NUM_VISIBLE];
+  if (V == 0) {
+    if (blockIdx.x == 0 && t == 0) {
+      counters[C_NUM_PAIRS] = 0;
+      counters[C_OVERFLOW] = 0;
+      *d_num_pairs = 0;
+      *d_overflow = 0;
+    }
+    return;
+  }
+  // tickets as in k_onesweep: only the blocks needed take them
+  const uint32_t nparts = (V + kPart - 1) / kPart;
+  if (blockIdx.x >= nparts) return;
+  const bool one_each = gridDim.x >= nparts;
   for (;;) {
     __syncthreads();
     if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_EXPAND], 1u);
     __syncthreads();
     const uint32_t part = s_misc[0];
     const uint64_t base = (uint64_t)part * kPart;
-    if (V == 0) {
-      if (part == 0 && t == 0) {
-        counters[C_NUM_PAIRS] = 0;
-        counters[C_OVERFLOW] = 0;
-        *d_num_pairs = 0;
-        *d_overflow = 0;
-      }
-      return;
-    }
     if (base >= V) return;
     const uint64_t first = base + (uint64_t)t * kSortItems;
     uint32_t x[kSortItems];
@@ -385,6 +396,7 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
       }
       pos += x[j];
     }
+    if (one_each) return;
   }
 }
 
@@ -405,12 +417,14 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
 
 // k_emit: globally load-balanced pair emission.  Chunk c holds pairs
 // [c * kPart, (c + 1) * kPart) of the depth-ordered pair sequence; blocks
-// stride over the chunks.  For one chunk a block stages
-// the offsets of the items from chunk_first[b] on in LDS, every thread finds
-// the item of its first pair (one binary search) and walks its 16 consecutive
-// pairs item by item and tile by tile (row-major inside the item's tile
-// rectangle), and the block writes the (tile, item) pairs coalesced from LDS
-// while accumulating the tile-digit histograms of the tile passes.
+// stride over the chunks.  For one chunk a block first stages, for each item
+// from chunk_first[c] on, its pair offset, id, first tile (view tile offset +
+// rect corner) and rect width / tiles per row in LDS (coalesced loads plus
+// one gather of the rects, all in parallel); every thread then finds the
+// item of its first pair (one binary search) and walks its 16 consecutive
+// pairs item by item and tile by tile (row-major inside the rect) in LDS
+// alone.  The block writes the (tile, item) pairs coalesced from LDS while
+// accumulating the tile-digit histograms of the tile passes.
 constexpr int kPad = kPart + kPart / kSortItems;  // LDS index i + i / 16: conflict-free per-thread runs
 
 __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ table,
@@ -422,6 +436,8 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
                                                        uint32_t* __restrict__ thist, uint32_t* __restrict__ tkeys,
                                                        uint32_t* __restrict__ pvals) {
   __shared__ uint32_t s_off[kPart];
+  __shared__ uint32_t s_id[kPart];
+  __shared__ uint2 s_geo[kPart];  // (first tile, width | tiles per row << 16)
   __shared__ uint32_t s_tile[kPad];
   __shared__ uint32_t s_item[kPad];
   __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
@@ -439,7 +455,20 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
     __syncthreads();
     const uint32_t first = chunk_first[chunk];
     const uint32_t nitems = min((uint32_t)kPart, V - first);
-    for (uint32_t i = t; i < nitems; i += kSortThreads) s_off[i] = offsets[first + i];
+    for (uint32_t i = t; i < nitems; i += kSortThreads) {
+      const uint32_t item = ids[first + i];
+      s_off[i] = offsets[first + i];
+      s_id[i] = item;
+      const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
+      int vlo = 0, vhi = nv - 1;
+      while (vlo < vhi) {
+        const int mid = (vlo + vhi + 1) >> 1;
+        if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+      }
+      const uint32_t tx = (uint32_t)views[vlo].tiles_x;
+      const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16;
+      s_geo[i] = make_uint2((uint32_t)views[vlo].tile_offset + y0 * tx + x0, ((r.y & 0xffffu) - x0) | (tx << 16));
+    }
     __syncthreads();
     const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
     const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kSortItems;
@@ -449,39 +478,28 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
         const uint32_t mid = (lo + hi + 1) >> 1;
         if (s_off[mid] <= mb) lo = mid; else hi = mid - 1;
       }
-      uint32_t cur = lo, item = 0, x0 = 0, y0 = 0, wdt = 1, row = 0, col = 0, tiles_x = 0, toff = 0;
-      uint32_t next = 0;
-      bool fresh = true;
+      uint32_t cur = lo;
+      uint2 gg = s_geo[cur];
+      uint32_t wdt = gg.y & 0xffffu, tx = gg.y >> 16;
+      const uint32_t q = mb - s_off[cur];
+      uint32_t row = q / wdt, col = q - row * wdt;
+      uint32_t next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
 #pragma unroll 1
       for (int j = 0; j < kSortItems; ++j) {
         const uint32_t m = mb + (uint32_t)j;
         if (m >= pend) break;
-        if (!fresh && m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
+        if (m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
           ++cur;
-          fresh = true;
-        }
-        if (fresh) {
-          item = ids[first + cur];
+          gg = s_geo[cur];
+          wdt = gg.y & 0xffffu;
+          tx = gg.y >> 16;
+          row = 0;
+          col = 0;
           next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
-          const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
-          x0 = r.x & 0xffffu;
-          y0 = r.x >> 16;
-          wdt = (r.y & 0xffffu) - x0;
-          const uint32_t q = m - s_off[cur];
-          row = q / wdt;
-          col = q - row * wdt;
-          int vlo = 0, vhi = nv - 1;
-          while (vlo < vhi) {
-            const int mid = (vlo + vhi + 1) >> 1;
-            if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
-          }
-          toff = (uint32_t)views[vlo].tile_offset;
-          tiles_x = (uint32_t)views[vlo].tiles_x;
-          fresh = false;
         }
         const uint32_t li = (uint32_t)t * (kSortItems + 1) + (uint32_t)j;
-        s_tile[li] = toff + (y0 + row) * tiles_x + x0 + col;
-        s_item[li] = item;
+        s_tile[li] = gg.x + row * tx + col;
+        s_item[li] = s_id[cur];
         if (++col == wdt) {
           col = 0;
           ++row;
@@ -604,7 +622,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // grids of the ticket / stride loops: bounded, independent of the capacity
   const unsigned grid_i = parts_i < kLoopBlocks ? parts_i : kLoopBlocks;
   const unsigned grid_p = parts_p < kLoopBlocks ? parts_p : kLoopBlocks;
-  const unsigned grid_e = parts_p < 2 * kLoopBlocks ? parts_p : 2 * kLoopBlocks;
+  const unsigned grid_e = parts_p < kLoopBlocks / 2 ? parts_p : kLoopBlocks / 2;  // one 104 KB-LDS block per CU
   uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
   uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 

@@ -19,6 +19,11 @@ namespace gs {
 
 constexpr int kNumXcd = 8;
 constexpr int kTileGroup = 4;
+// records staged in LDS per batch (<= kBlock): the forward's smaller batch
+// lowers its LDS use so that more wavefronts fit on a CU (measured faster);
+// the backward is not LDS-limited in the same way
+constexpr int kBatchFwd = 192;
+constexpr int kBatchBwd = 256;
 
 // Workgroup ids reach the 8 XCDs round-robin (id % 8).  Tiles are dealt to
 // the XCDs in groups of kTileGroup consecutive tiles, round-robin: XCD x
@@ -154,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   constexpr int RF = (10 + 3 * K + 3) & ~3;
   constexpr int R4 = RF / 4;
   constexpr int S4 = Staged<K>::S4;
-  __shared__ float4 s_rec[kBlock * S4];
-  __shared__ uint32_t s_mask[kBlock];
+  __shared__ float4 s_rec[kBatchFwd * S4];
+  __shared__ uint32_t s_mask[kBatchFwd];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
@@ -175,11 +180,11 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   uint32_t last = 0, stop_pos = end - start, n_full = 0;
   float Fm = 0.f;
   bool done = !inside;
-  for (uint32_t b = start; b < end; b += kBlock) {
+  for (uint32_t b = start; b < end; b += kBatchFwd) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = b + t;
     uint32_t m = 0;
-    if (idx < end) {
+    if (t < kBatchFwd && idx < end) {
       const float4* src = reinterpret_cast<const float4*>(rec + (size_t)vals[idx] * RF);
       float4 q[R4];
 #pragma unroll
@@ -187,9 +192,9 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
       stage_record<K>(q, ox, oy, &s_rec[t * S4]);
       m = quadrant_mask(q[0], q[1], ox, oy);
     }
-    s_mask[t] = m;
+    if (t < kBatchFwd) s_mask[t] = m;
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, end - b);
+    const int cnt = (int)min((uint32_t)kBatchFwd, end - b);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
       if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;
       uint64_t bits = __ballot(c0 + l < cnt && ((s_mask[c0 + l] >> w) & 1u));
@@ -336,9 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   constexpr int GS = 10 + 3 * K;           // gradient components per pair (one per record field)
   constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
   constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
-  __shared__ float4 s_rec[kBlock * S4];
-  __shared__ uint32_t s_id[kBlock];
-  __shared__ uint32_t s_mask[kBlock];
+  __shared__ float4 s_rec[kBatchBwd * S4];
+  __shared__ uint32_t s_id[kBatchBwd];
+  __shared__ uint32_t s_mask[kBatchBwd];
   __shared__ uint32_t s_max;
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
 
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, la = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
   for (uint32_t hi = maxlast; hi > 0;) {
-    const uint32_t lo = hi > (uint32_t)kBlock ? hi - kBlock : 0u;
+    const uint32_t lo = hi > (uint32_t)kBatchBwd ? hi - kBatchBwd : 0u;
     const uint32_t cnt = hi - lo;
     __syncthreads();
     uint32_t m = 0;
@@ -395,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
       stage_record<K>(q, ox, oy, &s_rec[t * S4]);
       m = quadrant_mask(q[0], q[1], ox, oy);
     }
-    s_mask[t] = m;
+    if (t < kBatchBwd) s_mask[t] = m;
     __syncthreads();
     // chunks of 64 records, newest first; records past the wave's last contributor are skipped
     for (int c0 = ((int)cnt - 1) & ~63; c0 >= 0; c0 -= 64) {
