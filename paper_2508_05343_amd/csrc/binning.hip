@@ -36,6 +36,8 @@ constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr int kDepthPasses = 4;
 constexpr int kMaxTilePasses = 4;
 constexpr unsigned kLoopBlocks = 512;  // two 256-lane blocks per CU
+constexpr int kEmitChunk = 2048;                  // pairs per emission chunk
+constexpr int kEmitItems = kEmitChunk / kSortThreads;  // consecutive pairs walked per thread
 
 // counters (u32) at the start of the workspace
 enum {
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 // k_expand_scan: over the V depth-sorted visible items, exclusive scan of
 // tiles touched (single pass, wave-parallel decoupled look-back) into
 // offsets[]; the last partition writes P and the overflow flag.  Every
-// visible item touches at least one tile, so pair index c * kPart lies in
+// visible item touches at least one tile, so pair index c * kEmitChunk lies in
 // exactly one item's range: that item's position is stored as chunk_first[c]
 // (c < max_chunks) for the emission kernel.  Blocks take partitions from a
 // ticket until they run past V.
@@ -391,7 +393,8 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
       const uint64_t jj = first + j;
       if (jj < V) {
         offsets[jj] = pos;
-        for (uint32_t c = (pos + kPart - 1) / kPart; c < max_chunks && (uint64_t)c * kPart < (uint64_t)pos + x[j]; ++c)
+        for (uint32_t c = (pos + kEmitChunk - 1) / kEmitChunk;
+             c < max_chunks && (uint64_t)c * kEmitChunk < (uint64_t)pos + x[j]; ++c)
           chunk_first[c] = (uint32_t)jj;
       }
       pos += x[j];
@@ -416,16 +419,16 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
 }
 
 // k_emit: globally load-balanced pair emission.  Chunk c holds pairs
-// [c * kPart, (c + 1) * kPart) of the depth-ordered pair sequence; blocks
+// [c * kEmitChunk, (c + 1) * kEmitChunk) of the depth-ordered pair sequence; blocks
 // stride over the chunks.  For one chunk a block first stages, for each item
 // from chunk_first[c] on, its pair offset, id, first tile (view tile offset +
 // rect corner) and rect width / tiles per row in LDS (coalesced loads plus
 // one gather of the rects, all in parallel); every thread then finds the
-// item of its first pair (one binary search) and walks its 16 consecutive
+// item of its first pair (one binary search) and walks its kEmitItems consecutive
 // pairs item by item and tile by tile (row-major inside the rect) in LDS
 // alone.  The block writes the (tile, item) pairs coalesced from LDS while
 // accumulating the tile-digit histograms of the tile passes.
-constexpr int kPad = kPart + kPart / kSortItems;  // LDS index i + i / 16: conflict-free per-thread runs
+constexpr int kPad = kEmitChunk + kEmitChunk / kEmitItems;  // LDS index i + i / kEmitItems: conflict-free runs
 
 __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ table,
                                                        const uint32_t* __restrict__ rect,
@@ -435,26 +438,26 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
                                                        const uint32_t* __restrict__ counters,
                                                        uint32_t* __restrict__ thist, uint32_t* __restrict__ tkeys,
                                                        uint32_t* __restrict__ pvals) {
-  __shared__ uint32_t s_off[kPart];
-  __shared__ uint32_t s_id[kPart];
-  __shared__ uint2 s_geo[kPart];  // (first tile, width | tiles per row << 16)
+  __shared__ uint32_t s_off[kEmitChunk];
+  __shared__ uint32_t s_id[kEmitChunk];
+  __shared__ uint2 s_geo[kEmitChunk];  // (first tile, width | tiles per row << 16)
   __shared__ uint32_t s_tile[kPad];
   __shared__ uint32_t s_item[kPad];
   __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
   const uint32_t V = counters[C_NUM_VISIBLE];
-  if ((uint64_t)blockIdx.x * kPart >= P) return;
+  if ((uint64_t)blockIdx.x * kEmitChunk >= P) return;
   const int t = threadIdx.x;
   for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
-  for (uint64_t chunk = blockIdx.x; chunk * kPart < P; chunk += gridDim.x) {
-    const uint64_t p0 = chunk * kPart;
+  for (uint64_t chunk = blockIdx.x; chunk * kEmitChunk < P; chunk += gridDim.x) {
+    const uint64_t p0 = chunk * kEmitChunk;
     __syncthreads();
     const uint32_t first = chunk_first[chunk];
-    const uint32_t nitems = min((uint32_t)kPart, V - first);
+    const uint32_t nitems = min((uint32_t)kEmitChunk, V - first);
     for (uint32_t i = t; i < nitems; i += kSortThreads) {
       const uint32_t item = ids[first + i];
       s_off[i] = offsets[first + i];
@@ -470,8 +473,8 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
       s_geo[i] = make_uint2((uint32_t)views[vlo].tile_offset + y0 * tx + x0, ((r.y & 0xffffu) - x0) | (tx << 16));
     }
     __syncthreads();
-    const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kPart);
-    const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kSortItems;
+    const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kEmitChunk);
+    const uint32_t mb = (uint32_t)p0 + (uint32_t)t * kEmitItems;
     if (mb < pend) {
       uint32_t lo = 0, hi = nitems - 1;
       while (lo < hi) {
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
       uint32_t row = q / wdt, col = q - row * wdt;
       uint32_t next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
 #pragma unroll 1
-      for (int j = 0; j < kSortItems; ++j) {
+      for (int j = 0; j < kEmitItems; ++j) {
         const uint32_t m = mb + (uint32_t)j;
         if (m >= pend) break;
         if (m >= next) {  // the next item starts exactly here (every item has >= 1 pair)
@@ -497,7 +500,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
           col = 0;
           next = cur + 1 < nitems ? s_off[cur + 1] : 0xffffffffu;
         }
-        const uint32_t li = (uint32_t)t * (kSortItems + 1) + (uint32_t)j;
+        const uint32_t li = (uint32_t)t * (kEmitItems + 1) + (uint32_t)j;
         s_tile[li] = gg.x + row * tx + col;
         s_item[li] = s_id[cur];
         if (++col == wdt) {
@@ -508,12 +511,12 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
     }
     __syncthreads();
     // uniform trip count so that every lane takes part in the ballots
-    for (uint32_t i = t; i < (uint32_t)kPart; i += kSortThreads) {
+    for (uint32_t i = t; i < (uint32_t)kEmitChunk; i += kSortThreads) {
       const uint32_t m = (uint32_t)p0 + i;
       const bool on = m < pend;
       uint32_t tile = 0;
       if (on) {
-        const uint32_t li = i + i / kSortItems;
+        const uint32_t li = i + i / kEmitItems;
         tile = s_tile[li];
         tkeys[m] = tile;
         pvals[m] = s_item[li];
@@ -578,7 +581,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_dvals_a = off; off = align_up(off + (size_t)items * 4);
   p.off_dvals_b = off; off = align_up(off + (size_t)items * 4);
   p.off_offsets = off; off = align_up(off + (size_t)items * 4);
-  p.off_chunks = off; off = align_up(off + (size_t)(p.parts_pairs + 1) * 4);
+  p.off_chunks = off; off = align_up(off + (size_t)((capacity + kEmitChunk - 1) / kEmitChunk + 1) * 4);
   p.off_tkeys_a = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
@@ -622,7 +625,9 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // grids of the ticket / stride loops: bounded, independent of the capacity
   const unsigned grid_i = parts_i < kLoopBlocks ? parts_i : kLoopBlocks;
   const unsigned grid_p = parts_p < kLoopBlocks ? parts_p : kLoopBlocks;
-  const unsigned grid_e = parts_p < kLoopBlocks / 2 ? parts_p : kLoopBlocks / 2;  // one 104 KB-LDS block per CU
+  const int64_t pe = (p.capacity + kEmitChunk - 1) / kEmitChunk;
+  const unsigned parts_e = (unsigned)(pe > 0 ? pe : 1);
+  const unsigned grid_e = parts_e < kLoopBlocks ? parts_e : kLoopBlocks;  // two 54 KB-LDS blocks per CU
   uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
   uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 
@@ -640,7 +645,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K2b: tiles-touched scan in depth order, P, overflow
   uint32_t* thist = hist + kDepthPasses * kRadix;
   hipLaunchKernelGGL(k_expand_scan, dim3(grid_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
-                     counters, look_expand, offsets, chunk_first, parts_p, d_num_pairs, d_overflow);
+                     counters, look_expand, offsets, chunk_first, parts_e, d_num_pairs, d_overflow);
   // K3: load-balanced pair emission in depth order + tile-digit histograms
   hipLaunchKernelGGL(k_emit, dim3(grid_e), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first, tpass,
                      counters, thist, tk[0], pv[0]);
