@@ -35,8 +35,8 @@ VALU_PEAK_TFLOPS = 78.6
 # 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
 # taken on (hash of the blend's source text); otherwise traffic is null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "415e95020b33a5e42a27185e54a2382d13603fb5741a6e1e0425e774d1c89170",
-    "fetch_kib": 20365.97, "write_kib": 21500.91, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "f753d3849572598b47b8ecbeb1af26340c852ce1b84b3b5f93630a348e892c41",
+    "fetch_kib": 43683.80, "write_kib": 23993.38, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -148,9 +148,10 @@ typedef struct {
  * match the scene's colour mode).  grad2d [items][gabsplat_grad2d_floats(k)]
  * is scratch that receives the image-plane gradients, i.e. the gradient with
  * respect to every field of the render record, in the record's order; the call
- * clears it first, and it may be read afterwards (e.g. the view-space
- * positional gradient used by density control).  All scenes of one call
- * share the same grad2d buffer. */
+ * first zeroes the rows of the items that touch a tile (geom->tiles != 0, the
+ * only rows it writes or reads; other rows are left as they are), and those
+ * rows may be read afterwards (e.g. the view-space positional gradient used
+ * by density control).  All scenes of one call share the same grad2d buffer. */
 typedef struct {
   int32_t accumulate;
   int32_t pad;

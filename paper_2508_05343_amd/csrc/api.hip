@@ -263,7 +263,7 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
                                     const uint32_t* n_contrib, const float* dl_dimage,
                                     const gabsplat_scene_grads* grads, const int32_t* d_overflow, void* stream) {
   try {
-    if (!geom || !geom->views || !geom->rec || !grads || !tile_ranges || !final_T || !n_contrib || !dl_dimage)
+    if (!geom || !geom->views || !geom->rec || !geom->tiles || !grads || !tile_ranges || !final_T || !n_contrib || !dl_dimage)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     TableBuild tb;
     gabsplat_status st = build_table(scenes, num_scenes, scene_of_view, cams, num_views, tb);
@@ -279,8 +279,7 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
     if (tb.hdr.total_tiles > 0 && !vals) return GABSPLAT_ERR_INVALID_ARGUMENT;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HostTable h = tb.host();
-    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(grads[0].grad2d), 0u,
-                            (size_t)tb.hdr.total_items * grad2d_floats(geom->k), s);
+    hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items, grad2d_floats(geom->k), s);
     if (e != hipSuccess) return GABSPLAT_ERR_HIP;
     e = launch_render_bwd(geom->views, h, *geom, geom->k, vals, tile_ranges, final_T, n_contrib,
                                      dl_dimage, grads[0].grad2d, d_overflow, s);

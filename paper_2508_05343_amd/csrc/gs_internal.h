@@ -126,5 +126,6 @@ hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, floa
 
 // generic fill kernel (used instead of memset so that callers may capture)
 hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_clear_grad2d(const uint32_t* tiles, float* grad2d, int64_t items, int gf, hipStream_t s);
 
 }  // namespace gs
