@@ -259,69 +259,101 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
 }
 
 // ------------------------------------------------- wave reduce-scatter-add
-// Sums v[0..NP) over the 64 lanes of a wavefront by recursive halving: at each
-// stage a lane keeps half of its remaining components and adds its partner's
-// partial sums of that half, so after log2 NP stages lane l holds the total of
-// component l >> (6 - log2 NP) (the stages left over when NP < 64 only add) and
-// a single vector atomic writes every component.  Partners, stage by stage:
-// lane l ^ 32 and l ^ 16 through the lane-swap instructions of gfx950 --
-// swapping the upper 32 (odd 16-lane) lanes of x with the lower 32 (even) lanes
-// of y leaves x's pair sums in the lower and y's in the upper lanes of x + y, one
-// add per pair of components -- then the DPP patterns 15 - i within a row of 16,
-// 7 - i within its halves, 3 - i and i ^ 1 within quads.  Each stage pairs lanes
-// that differ in the stage's bit and agree in the bits above it, and the six
-// partner masks 32, 16, 15, 7, 3, 1 together span all six lane bits.  Every
-// lane of the wavefront must be active.
+// Sums v[0..G) over the 64 lanes of a wavefront by recursive halving: at each
+// of six stages a lane holding L partial sums pairs them as (j, j + ceil(L/2))
+// and keeps one of each pair (the first on the lower side of the stage's lane
+// bit, the second on the upper side), adding the partner lane's partial sum
+// of that component; an unpaired last component (L odd) is summed with the
+// partner and kept on both sides.  After the stages every lane holds the
+// wavefront total of one component (which, and whether the lane is the one
+// that writes it, depends only on the lane: halving_slot) and a single vector
+// atomic writes all G components.  Partners, stage by stage: lane l ^ 32 and
+// l ^ 16 through the lane-swap instructions of gfx950 -- swapping the upper
+// 32 (odd 16-lane) lanes of x with the lower 32 (even) lanes of y leaves x's
+// pair sums in the lower and y's in the upper lanes of x + y, one add per
+// pair -- then the DPP patterns 15 - i within a row of 16, 7 - i within its
+// halves, 3 - i and i ^ 1 within quads.  Each stage pairs lanes that differ
+// in the stage's bit and agree in the bits above it, and the six partner
+// masks 32, 16, 15, 7, 3, 1 together span all six lane bits.  Every lane of
+// the wavefront must be active.
+constexpr int halving_len(int g, int stage) {
+  for (int i = 0; i < stage; ++i) g = (g + 1) / 2;
+  return g;
+}
+
+// Component held by `lane` after the six stages; *writer is set for exactly
+// one lane per component.
+template <int G>
+__device__ __forceinline__ int halving_slot(int lane, bool* writer) {
+  int j = 0;
+  bool w = true;
+#pragma unroll
+  for (int st = 5; st >= 0; --st) {
+    const int L = halving_len(G, st), h = (L + 1) / 2;
+    const bool upper = (lane >> (5 - st)) & 1;
+    if (upper) {
+      if (j + h < L) j += h;
+      else w = false;  // duplicate of the lower side's component
+    }
+  }
+  *writer = w;
+  return j;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_get(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-template <int N, int L>
-__device__ __forceinline__ void stage_swap32(float (&v)[N]) {
+template <int G, int ST, bool SWAP32>
+__device__ __forceinline__ void stage_swap(float (&v)[G]) {
+  constexpr int L = halving_len(G, ST), h = (L + 1) / 2;
 #pragma unroll
-  for (int j = 0; j < L / 2; ++j) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + L / 2]), false, false);
+  for (int j = 0; j < h; ++j) {
+    const uint32_t x = __float_as_uint(v[j]);
+    const uint32_t y = (j + h < L) ? __float_as_uint(v[j + h]) : x;
+    const auto r = SWAP32 ? __builtin_amdgcn_permlane32_swap(x, y, false, false)
+                          : __builtin_amdgcn_permlane16_swap(x, y, false, false);
     v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
 }
 
-template <int N, int L>
-__device__ __forceinline__ void stage_swap16(float (&v)[N]) {
-#pragma unroll
-  for (int j = 0; j < L / 2; ++j) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + L / 2]), false, false);
-    v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
+// a where the lane's bit of `upper` is clear, b where it is set.  Written as
+// the instruction itself: as a plain ?: the optimizer merges the selects of a
+// stage into one run-time index into v[] and lowers that as a compare chain
+// over every element.
+__device__ __forceinline__ float lane_select(float a, float b, uint64_t upper) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(upper));
+  return r;
 }
 
-template <int N, int L, int CTRL>
-__device__ __forceinline__ void stage_dpp(float (&v)[N], bool upper) {
-  if constexpr (L >= 2) {
+template <int G, int ST, int CTRL>
+__device__ __forceinline__ void stage_dpp(float (&v)[G], uint64_t upper) {
+  constexpr int L = halving_len(G, ST), h = (L + 1) / 2;
 #pragma unroll
-    for (int j = 0; j < L / 2; ++j) {
-      const float keep = upper ? v[j + L / 2] : v[j];
-      const float send = upper ? v[j] : v[j + L / 2];
+  for (int j = 0; j < h; ++j) {
+    if (j + h < L) {
+      const float keep = lane_select(v[j], v[j + h], upper);
+      const float send = lane_select(v[j + h], v[j], upper);
       v[j] = keep + dpp_get<CTRL>(send);
+    } else {
+      v[j] += dpp_get<CTRL>(v[j]);
     }
-  } else {
-    v[0] += dpp_get<CTRL>(v[0]);
   }
 }
 
-template <int NP>
-__device__ __forceinline__ void wave_reduce_add(float (&v)[NP], float* dst, int ncomp) {
-  static_assert(NP == 16 || NP == 32 || NP == 64, "component count");
-  const int l = __lane_id();
-  stage_swap32<NP, NP>(v);
-  stage_swap16<NP, NP / 2>(v);
-  stage_dpp<NP, NP / 4, 0x140>(v, (l & 8) != 0);   // row mirror
-  stage_dpp<NP, NP / 8, 0x141>(v, (l & 4) != 0);   // half-row mirror
-  stage_dpp<NP, NP / 16, 0x1B>(v, (l & 2) != 0);   // quad (3, 2, 1, 0)
-  stage_dpp<NP, NP / 32, 0xB1>(v, (l & 1) != 0);   // quad (1, 0, 3, 2)
-  constexpr int SH = NP == 64 ? 0 : (NP == 32 ? 1 : 2);
-  const int comp = l >> SH;
-  if ((l & ((1 << SH) - 1)) == 0 && comp < ncomp) atomicAdd(dst + comp, v[0]);
+template <int G>
+__device__ __forceinline__ void wave_reduce_add(float (&v)[G], float* dst, int slot, bool writer) {
+  static_assert(G >= 1 && G <= 64, "component count");
+  stage_swap<G, 0, true>(v);
+  stage_swap<G, 1, false>(v);
+  // lane masks of the stage bits 3, 2, 1, 0
+  stage_dpp<G, 2, 0x140>(v, 0xFF00FF00FF00FF00ull);   // row mirror
+  stage_dpp<G, 3, 0x141>(v, 0xF0F0F0F0F0F0F0F0ull);   // half-row mirror
+  stage_dpp<G, 4, 0x1B>(v, 0xCCCCCCCCCCCCCCCCull);    // quad (3, 2, 1, 0)
+  stage_dpp<G, 5, 0xB1>(v, 0xAAAAAAAAAAAAAAAAull);    // quad (1, 0, 3, 2)
+  if (writer) atomicAdd(dst + slot, v[0]);
 }
 
 // --------------------------------------------------------------------- K7
@@ -340,7 +372,6 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   constexpr int S4 = Staged<K>::S4;
   constexpr int GS = 10 + 3 * K;           // gradient components per pair (one per record field)
   constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
-  constexpr int NP = GS <= 16 ? 16 : (GS <= 32 ? 32 : 64);
   __shared__ float4 s_rec[kBatchBwd * S4];
   __shared__ uint32_t s_id[kBatchBwd];
   __shared__ uint32_t s_mask[kBatchBwd];
@@ -359,6 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile];
+  bool red_writer;
+  const int red_slot = halving_slot<GS>(l, &red_writer);
 
   float T = 1.0f, Tf = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
   uint32_t last = 0;
@@ -454,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         da = (contrib && !(EB > kAlphaMax)) ? da : 0.f;  // a binding clamp has zero derivative
         const float dB = da * E;
         const float dp = da * Bv * E * kLn2;
-        float gv[NP];
+        float gv[GS];
         gv[5] = dp;
         gv[6] = wt * dC0;
         gv[7] = wt * dC1;
@@ -478,9 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         }
         gv[0] = -ddx;
         gv[1] = -ddy;
-#pragma unroll
-        for (int q = GS; q < NP; ++q) gv[q] = 0.f;
-        wave_reduce_add<NP>(gv, grad2d + (size_t)s_id[j] * GF, GS);
+        wave_reduce_add<GS>(gv, grad2d + (size_t)s_id[j] * GF, red_slot, red_writer);
       }
     }
     hi = lo;
