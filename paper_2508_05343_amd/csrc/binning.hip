@@ -552,6 +552,263 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
     keys[i] = ((uint64_t)tkeys[i] << 32) | (uint64_t)depth_bits[vals[i]];
 }
 
+// ---------------------------------------------------------- tile-count path
+// For frames with at most kTcMaxTiles tiles the pairs are binned without a
+// global radix sort: per-tile pair counts (atomics), one scan of the counts
+// into the tile ranges, a scatter of (depth bits, item) into each tile's
+// segment through an atomic cursor (arbitrary order inside the segment), and
+// a sort of every segment by the unique key (depth bits, item).  The result
+// is the same order as the stable (tile, depth) sort of the onesweep path.
+constexpr int kTcMaxTiles = 16384;
+constexpr int kTcBig = 64;        // items with more tiles are walked by a whole wavefront
+constexpr int kSegCap = 4096;     // segment sorted in LDS in one piece (u64 keys, 32 KB)
+
+struct ItemTiles {
+  uint32_t base;  // global tile id of the rect's top-left tile
+  uint32_t w, h;  // rect width and height in tiles
+  uint32_t tx;    // tiles per row of the item's view
+};
+
+__device__ __forceinline__ ItemTiles item_tiles(const ViewEntry* views, int nv, uint32_t item,
+                                               const uint32_t* __restrict__ rect) {
+  int vlo = 0, vhi = nv - 1;
+  while (vlo < vhi) {
+    const int mid = (vlo + vhi + 1) >> 1;
+    if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+  }
+  const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
+  const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+  ItemTiles it;
+  it.tx = (uint32_t)views[vlo].tiles_x;
+  it.base = (uint32_t)views[vlo].tile_offset + y0 * it.tx + x0;
+  it.w = x1 - x0;
+  it.h = y1 - y0;
+  return it;
+}
+
+__device__ __forceinline__ uint32_t tile_of(const ItemTiles& it, uint32_t q) {
+  const uint32_t row = q / it.w;
+  return it.base + row * it.tx + (q - row * it.w);
+}
+
+// Calls f(item, tile, q) for every (visible item, tile) pair of items
+// [i0, i1): small rects by their own lane, large ones by the whole wavefront
+// (so that no lane walks thousands of tiles).  Must be called by full waves.
+template <typename F>
+__device__ __forceinline__ void for_each_pair(const ViewEntry* views, int nv, const uint32_t* __restrict__ tiles,
+                                              const uint32_t* __restrict__ rect, uint32_t item, bool valid, F f) {
+  uint32_t nt = valid ? tiles[item] : 0u;
+  ItemTiles it{};
+  if (nt) {
+    it = item_tiles(views, nv, item, rect);
+    nt = min(nt, it.w * it.h);  // never past the rectangle (and no division by a zero width)
+  }
+  if (nt && nt <= (uint32_t)kTcBig)
+    for (uint32_t q = 0; q < nt; ++q) f(item, tile_of(it, q), q);
+  uint64_t big = __ballot(nt > (uint32_t)kTcBig);
+  const int l = __lane_id();
+  while (big) {
+    const int src = __builtin_ctzll(big);
+    big &= big - 1;
+    const uint32_t bi = (uint32_t)__shfl((int)item, src, 64);
+    const uint32_t bn = (uint32_t)__shfl((int)nt, src, 64);
+    ItemTiles bt;
+    bt.base = (uint32_t)__shfl((int)it.base, src, 64);
+    bt.w = (uint32_t)__shfl((int)it.w, src, 64);
+    bt.h = (uint32_t)__shfl((int)it.h, src, 64);
+    bt.tx = (uint32_t)__shfl((int)it.tx, src, 64);
+    for (uint32_t q = (uint32_t)l; q < bn; q += 64) f(bi, tile_of(bt, q), q);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tc_count(const void* __restrict__ table, int64_t items,
+                                                  const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rect,
+                                                  uint32_t* __restrict__ tcount) {
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry* views = table_views(table);
+  const int nv = hdr->num_views;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // uniform trip count: every lane of a wave runs the same number of steps
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < items; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < items,
+                  [&](uint32_t, uint32_t t, uint32_t) { atomicAdd(&tcount[t], 1u); });
+  }
+}
+
+// One block: exclusive scan of the tile counts -> ranges ((0, 0) for empty
+// tiles), cursors, pair count and overflow flag.
+__global__ __launch_bounds__(kSortThreads) void k_tc_scan(const uint32_t* __restrict__ tcount, int ntiles,
+                                                         uint32_t capacity, uint32_t* __restrict__ tcursor,
+                                                         uint32_t* __restrict__ ranges,
+                                                         uint32_t* __restrict__ counters,
+                                                         int64_t* __restrict__ d_num_pairs,
+                                                         int32_t* __restrict__ d_overflow) {
+  __shared__ uint32_t s_wave[kSortThreads / 64];
+  const int t = threadIdx.x;
+  const int per = (ntiles + kSortThreads - 1) / kSortThreads;
+  const int t0 = t * per, t1 = min(ntiles, t0 + per);
+  uint32_t sum = 0;
+  for (int i = t0; i < t1; ++i) sum += tcount[i];
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, s_wave, &total);
+  for (int i = t0; i < t1; ++i) {
+    const uint32_t c = tcount[i];
+    tcursor[i] = run;
+    ranges[2 * (size_t)i] = c ? run : 0u;
+    ranges[2 * (size_t)i + 1] = c ? run + c : 0u;
+    run += c;
+  }
+  if (t == 0) {
+    const uint32_t ov = total > capacity ? 1u : 0u;
+    counters[C_NUM_PAIRS] = total;
+    counters[C_OVERFLOW] = ov;
+    *d_num_pairs = (int64_t)total;
+    *d_overflow = (int32_t)ov;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ table, int64_t items,
+                                                    const uint32_t* __restrict__ tiles,
+                                                    const uint32_t* __restrict__ rect,
+                                                    const uint32_t* __restrict__ depth_bits,
+                                                    uint32_t* __restrict__ tcursor,
+                                                    const uint32_t* __restrict__ counters,
+                                                    uint32_t* __restrict__ skey, uint32_t* __restrict__ sval) {
+  if (counters[C_OVERFLOW]) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const ViewEntry* views = table_views(table);
+  const int nv = hdr->num_views;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < items; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < items, [&](uint32_t item, uint32_t t, uint32_t) {
+      const uint32_t pos = atomicAdd(&tcursor[t], 1u);
+      skey[pos] = depth_bits[item];
+      sval[pos] = item;
+    });
+  }
+}
+
+__device__ __forceinline__ uint64_t pair_key(const uint32_t* k, const uint32_t* v, uint32_t i) {
+  return ((uint64_t)k[i] << 32) | v[i];
+}
+
+// Bitonic sort of s[0, n2) (n2 a power of two) by the block.
+__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of (key,
+// val) into out at o0, by the whole block (each thread a contiguous slice of
+// the output, split points by merge-path binary search).
+__device__ void block_merge(const uint32_t* __restrict__ k, const uint32_t* __restrict__ v, uint32_t a0, uint32_t na,
+                            uint32_t b0, uint32_t nb, uint32_t* __restrict__ ko, uint32_t* __restrict__ vo,
+                            uint32_t o0) {
+  const uint32_t n = na + nb;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t d0 = min(n, threadIdx.x * per), d1 = min(n, d0 + per);
+  if (d0 >= d1) return;
+  // split of diagonal d: number of elements taken from a
+  auto split = [&](uint32_t d) {
+    uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+    while (lo < hi) {
+      const uint32_t m = (lo + hi) >> 1;
+      // take a[m] before b[d - 1 - m] when a[m] <= b[d - 1 - m] (a first on ties: keys are unique anyway)
+      if (pair_key(k, v, a0 + m) <= pair_key(k, v, b0 + d - 1 - m)) lo = m + 1; else hi = m;
+    }
+    return lo;
+  };
+  uint32_t ia = split(d0), ib = d0 - ia;
+  for (uint32_t o = d0; o < d1; ++o) {
+    bool takea;
+    if (ia >= na) takea = false;
+    else if (ib >= nb) takea = true;
+    else takea = pair_key(k, v, a0 + ia) <= pair_key(k, v, b0 + ib);
+    const uint32_t src = takea ? a0 + ia : b0 + ib;
+    ko[o0 + o] = k[src];
+    vo[o0 + o] = v[src];
+    if (takea) ++ia; else ++ib;
+  }
+}
+
+// One block per tile: sorts the tile's segment by (depth bits, item) and
+// writes the item ids to vals (and the 64-bit keys when asked for).
+// Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
+// runs of kSegCap merged pairwise through the ping-pong buffers (kb, vb),
+// all by the same block.
+__global__ __launch_bounds__(256) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
+                                                 const uint32_t* __restrict__ counters, uint32_t* __restrict__ ka,
+                                                 uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
+                                                 uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+  __shared__ uint64_t s[kSegCap];
+  if (counters[C_OVERFLOW]) return;
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
+  const uint32_t n = end - start;
+  if (n == 0) return;
+  const int t = threadIdx.x;
+  if (n <= (uint32_t)kSegCap) {
+    int n2 = 1;
+    while (n2 < (int)n) n2 <<= 1;
+    for (int i = t; i < n2; i += blockDim.x) s[i] = i < (int)n ? pair_key(ka, va, start + i) : ~0ull;
+    __syncthreads();
+    lds_bitonic(s, n2);
+    for (int i = t; i < (int)n; i += blockDim.x) {
+      const uint64_t x = s[i];
+      vals[start + i] = (uint32_t)x;
+      if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
+    }
+    return;
+  }
+  // long segment: sorted runs, then pairwise merges ka/va <-> kb/vals
+  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap) {
+    const uint32_t m = min((uint32_t)kSegCap, n - r0);
+    __syncthreads();
+    for (int i = t; i < kSegCap; i += blockDim.x) s[i] = i < (int)m ? pair_key(ka, va, start + r0 + i) : ~0ull;
+    __syncthreads();
+    lds_bitonic(s, kSegCap);
+    for (int i = t; i < (int)m; i += blockDim.x) {
+      ka[start + r0 + i] = (uint32_t)(s[i] >> 32);
+      va[start + r0 + i] = (uint32_t)s[i];
+    }
+  }
+  __syncthreads();
+  uint32_t *sk = ka, *sv = va, *dk = kb, *dv = vals;
+  for (uint32_t width = kSegCap; width < n; width <<= 1) {
+    for (uint32_t lo = 0; lo < n; lo += 2 * width) {
+      const uint32_t na = min(width, n - lo);
+      const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
+      block_merge(sk, sv, start + lo, na, start + lo + na, nb, dk, dv, start + lo);
+    }
+    __syncthreads();
+    __threadfence_block();
+    uint32_t* tk = sk; sk = dk; dk = tk;
+    uint32_t* tv = sv; sv = dv; dv = tv;
+  }
+  // the sorted segment is in (sk, sv); the item ids must end in vals
+  for (uint32_t i = t; i < n; i += blockDim.x) {
+    if (sv != vals) vals[start + i] = sv[start + i];
+    if (keys) keys[start + i] = ((uint64_t)tile << 32) | sk[start + i];
+  }
+}
+
 // ------------------------------------------------------------------ plan
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -570,6 +827,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   size_t off = 0;
   // --- head: cleared at the start of every call
   p.off_counters = off; off += C_COUNT * 4;
+  p.off_tcount = off; off += (size_t)total_tiles * 4;
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
   p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
   p.off_look_sort = off;
@@ -585,6 +843,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_tkeys_a = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
+  p.off_tcursor = off; off = align_up(off + (size_t)total_tiles * 4);
   p.bytes = off;
   return p;
 }
@@ -613,6 +872,29 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   }
   const uint32_t* depth_bits = reinterpret_cast<const uint32_t*>(g.depth);
   const uint32_t* ov = counters + C_OVERFLOW;
+
+  if (p.total_tiles <= kTcMaxTiles) {
+    uint32_t* tcount = reinterpret_cast<uint32_t*>(w + p.off_tcount);
+    uint32_t* tcursor = reinterpret_cast<uint32_t*>(w + p.off_tcursor);
+    uint32_t* skey = reinterpret_cast<uint32_t*>(w + p.off_tkeys_a);
+    uint32_t* sval = reinterpret_cast<uint32_t*>(w + p.off_tkeys_b);
+    uint32_t* spare = reinterpret_cast<uint32_t*>(w + p.off_pvals_b);
+    const size_t nclear = (size_t)C_COUNT + (size_t)p.total_tiles;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, counters, 0u, nclear);
+    int64_t gb = (p.items + 255) / 256;
+    const unsigned grid = (unsigned)(gb < 1 ? 1 : (gb > 2048 ? 2048 : gb));
+    if (p.items > 0)
+      hipLaunchKernelGGL(k_tc_count, dim3(grid), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, tcount);
+    hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(kSortThreads), 0, s, tcount, p.total_tiles, (uint32_t)p.capacity,
+                       tcursor, ranges, counters, d_num_pairs, d_overflow);
+    if (p.items > 0)
+      hipLaunchKernelGGL(k_tc_scatter, dim3(grid), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, depth_bits,
+                         tcursor, counters, skey, sval);
+    if (p.total_tiles > 0)
+      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)p.total_tiles), dim3(256), 0, s, ranges, p.total_tiles, counters,
+                         skey, sval, spare, vals, keys);
+    return hipGetLastError();
+  }
 
   {
     const size_t nh = (p.off_dkeys_a - p.off_counters) / 4, nr = (size_t)p.total_tiles * 2;

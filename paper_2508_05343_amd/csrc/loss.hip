@@ -86,8 +86,10 @@ __device__ __forceinline__ void load_run(const float* row, float (&v)[kRunIn]) {
 // pass 1: moments, SSIM map, per-pixel factors for the backward, partial sums
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Window win, float lambda, float inv_n,
-                                                  float* __restrict__ f3, float* __restrict__ partial) {
+                                                  float* __restrict__ f3, float* __restrict__ partial,
+                                                  uint32_t* __restrict__ counter) {
   __shared__ __align__(16) float s_in[2][kSY][kSP];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *counter = 0u;
   __shared__ __align__(16) float s_h[5][kSY][kTX];
   __shared__ float s_red[4];
   const int c = blockIdx.z;
@@ -227,22 +229,54 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
   }
 }
 
+// Sum of the per-tile partials: up to kFinalBlocks blocks reduce contiguous
+// slices; the last block to finish (completion counter, zeroed by k_ssim_fwd
+// and again by that block) adds the block sums in block order, so the result
+// does not depend on which block finishes last.  Block sums are published
+// and read with agent-scope atomics (the XCDs' L2s are not coherent).
+constexpr int kFinalBlocks = 256;
+constexpr int kFinalSlice = 2048;  // partial pairs per block (before the cap)
+
 __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ partial, int nb, float lambda,
-                                                    float inv_n, float* __restrict__ d_loss) {
+                                                    float inv_n, float* __restrict__ part2,
+                                                    uint32_t* __restrict__ counter, float* __restrict__ d_loss) {
   __shared__ float s_red[4];
+  __shared__ int s_last;
+  const int per = (nb + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b0 = (int)blockIdx.x * per, b1 = min(nb, b0 + per);
   float l1 = 0.f, ss = 0.f;
-  for (int i = threadIdx.x; i < nb; i += 256) {
+  for (int i = b0 + (int)threadIdx.x; i < b1; i += 256) {
     l1 += partial[2 * i];
     ss += partial[2 * i + 1];
   }
   l1 = block_sum(l1, s_red);
   ss = block_sum(ss, s_red);
-  if (threadIdx.x == 0) *d_loss = (1.f - lambda) * l1 * inv_n + lambda * (1.f - ss * inv_n);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&part2[2 * blockIdx.x], l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&part2[2 * blockIdx.x + 1], ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  float a = 0.f, b = 0.f;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += 256) {
+    a += __hip_atomic_load(&part2[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b += __hip_atomic_load(&part2[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  a = block_sum(a, s_red);
+  b = block_sum(b, s_red);
+  if (threadIdx.x == 0) {
+    *d_loss = (1.f - lambda) * a * inv_n + lambda * (1.f - b * inv_n);
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t loss_workspace_bytes(int c, int h, int w) {
   const size_t nb = (size_t)((w + kTX - 1) / kTX) * ((h + kTY - 1) / kTY) * c;
-  return (size_t)3 * c * h * w * 4 + nb * 2 * 4 + 256;
+  return align256((size_t)3 * c * h * w * 4 + nb * 2 * 4) + kFinalBlocks * 2 * 4 + 256;
 }
 
 hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, float lambda, float* d_loss,
@@ -252,10 +286,15 @@ hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, floa
   const int nb = grid.x * grid.y * grid.z;
   float* f3 = static_cast<float*>(ws);
   float* partial = f3 + (size_t)3 * c * h * w;
+  char* tail = static_cast<char*>(ws) + align256((size_t)3 * c * h * w * 4 + (size_t)nb * 2 * 4);
+  float* part2 = reinterpret_cast<float*>(tail);
+  uint32_t* counter = reinterpret_cast<uint32_t*>(tail + kFinalBlocks * 2 * 4);
   const float inv_n = (float)(1.0 / ((double)c * h * w));
-  hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, partial);
+  int nfin = (nb + kFinalSlice - 1) / kFinalSlice;
+  nfin = nfin < 1 ? 1 : (nfin > kFinalBlocks ? kFinalBlocks : nfin);
+  hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, partial, counter);
   hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, dl_dx);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partial, nb, lambda, inv_n, d_loss);
+  hipLaunchKernelGGL(k_loss_final, dim3(nfin), dim3(256), 0, s, partial, nb, lambda, inv_n, part2, counter, d_loss);
   return hipGetLastError();
 }
 

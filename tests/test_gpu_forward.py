@@ -58,20 +58,37 @@ def _write_synthetic_geom(plan, rect, depth, vis):
     plan.tiles_touched.copy_(torch.from_numpy(t).cuda())
 
 
-@pytest.mark.parametrize("n,views,seed", [(3000, 1, 1), (20000, 2, 2), (1, 1, 3), (9000, 3, 4)])
-def test_bin_sort_bit_exact_on_synthetic_geometry(gpu_lib, n, views, seed):
-    """Stage-isolated K2-K5: seeded synthetic rects/depths (with ties) go into
-    the GPU bin sort and the oracle's library stable sort; keys, values and
-    ranges must be identical."""
+def _bin_sort_case(n, views, seed, width=200, height=150, hot_share=0.0):
     sc = synth.uniform_scene(seed, n, 1)
-    cams = [synth.pinhole_camera(200 + 37 * v, 150 + 11 * v, 60.0, (0, 0, -3), (0, 0, 0)) for v in range(views)]
-    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * views)
+    cams = [synth.pinhole_camera(width + 37 * v, height + 11 * v, 60.0, (0, 0, -3), (0, 0, 0)) for v in range(views)]
+    # capacity for the largest rectangles (6 x 6 tiles) of every item
+    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * views, capacity=36 * n * views + 1024)
     plan.preprocess()  # writes the view table
     rects, depths, viss = [], [], []
     for v, c in enumerate(cams):
         r, d, vi = synth.random_geom(100 * seed + v, n, c.tiles_x, c.tiles_y)
+        if hot_share > 0:  # pile a share of the rectangles onto the first tiles
+            hot = np.random.Generator(np.random.PCG64(seed + 77)).uniform(size=n) < hot_share
+            r[hot, 0] = 0; r[hot, 1] = 0
+            r[hot, 2] = 1 + (np.arange(n)[hot] % 2); r[hot, 3] = 1 + (np.arange(n)[hot] % 3 == 0)
+            r[hot & ~vi] = 0
         rects.append(r); depths.append(d); viss.append(vi)
     rect, depth, vis = np.concatenate(rects), np.concatenate(depths), np.concatenate(viss)
+    return cams, plan, rect, depth, vis
+
+
+@pytest.mark.parametrize("n,views,seed,width,height,hot",
+                         [(3000, 1, 1, 200, 150, 0.0), (20000, 2, 2, 200, 150, 0.0), (1, 1, 3, 200, 150, 0.0),
+                          (9000, 3, 4, 200, 150, 0.0),
+                          # a tile with ~11,000 pairs: sorted as runs of 4096 merged pairwise
+                          (20000, 1, 5, 200, 150, 0.7),
+                          # 8 views of 1024x1024 = 33,000+ tiles: the radix-sort binning path
+                          (3000, 8, 6, 1024, 1024, 0.0)])
+def test_bin_sort_bit_exact_on_synthetic_geometry(gpu_lib, n, views, seed, width, height, hot):
+    """Stage-isolated K2-K5: seeded synthetic rects/depths (with ties) go into
+    the GPU bin sort and the oracle's library stable sort; keys, values and
+    ranges must be identical."""
+    cams, plan, rect, depth, vis = _bin_sort_case(n, views, seed, width, height, hot)
     _write_synthetic_geom(plan, rect, depth, vis)
     plan.bin_sort()
     torch.cuda.synchronize()
