@@ -48,6 +48,7 @@ enum {
   C_NUM_VISIBLE = 16,
   C_NUM_PAIRS = 17,
   C_OVERFLOW = 18,
+  C_TICKET_TC = 19,
   C_COUNT = 64
 };
 
@@ -559,7 +560,7 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
 // segment through an atomic cursor (arbitrary order inside the segment), and
 // a sort of every segment by the unique key (depth bits, item).  The result
 // is the same order as the stable (tile, depth) sort of the onesweep path.
-constexpr int kTcMaxTiles = 16384;
+constexpr int kTcMaxTiles = 8192;   // per-block tile histograms in LDS (32 KB)
 constexpr int kTcBig = 64;        // items with more tiles are walked by a whole wavefront
 constexpr int kSegCap = 4096;     // segment sorted in LDS in one piece (u64 keys, 32 KB)
 
@@ -621,69 +622,115 @@ __device__ __forceinline__ void for_each_pair(const ViewEntry* views, int nv, co
   }
 }
 
-__global__ __launch_bounds__(256) void k_tc_count(const void* __restrict__ table, int64_t items,
-                                                  const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rect,
-                                                  uint32_t* __restrict__ tcount) {
+// The items are split into kTcBlocks contiguous ranges, one per block of the
+// histogram and scatter kernels (the same ranges in both).
+constexpr int kTcBlocks = 256;
+
+__device__ __forceinline__ void tc_item_range(int64_t items, int64_t* i0, int64_t* i1) {
+  const int64_t per = (items + kTcBlocks - 1) / kTcBlocks;
+  *i0 = min(items, (int64_t)blockIdx.x * per);
+  *i1 = min(items, *i0 + per);
+}
+
+// Per-block tile histograms in LDS, written as row blockIdx.x of cnt[kTcBlocks][T].
+__global__ __launch_bounds__(256) void k_tc_hist(const void* __restrict__ table, int64_t items,
+                                                 const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rect,
+                                                 int ntiles, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_h[kTcMaxTiles];
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // uniform trip count: every lane of a wave runs the same number of steps
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < items; i0 += stride) {
-    const int64_t i = i0 + threadIdx.x;
-    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < items,
-                  [&](uint32_t, uint32_t t, uint32_t) { atomicAdd(&tcount[t], 1u); });
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s_h[i] = 0;
+  __syncthreads();
+  int64_t i0, i1;
+  tc_item_range(items, &i0, &i1);
+  for (int64_t b = i0; b < i1; b += blockDim.x) {  // uniform trip count
+    const int64_t i = b + threadIdx.x;
+    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < i1,
+                  [&](uint32_t, uint32_t t, uint32_t) { atomicAdd(&s_h[t], 1u); });
   }
+  __syncthreads();
+  uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) row[i] = s_h[i];
 }
 
-// One block: exclusive scan of the tile counts -> ranges ((0, 0) for empty
-// tiles), cursors, pair count and overflow flag.
-__global__ __launch_bounds__(kSortThreads) void k_tc_scan(const uint32_t* __restrict__ tcount, int ntiles,
-                                                         uint32_t capacity, uint32_t* __restrict__ tcursor,
-                                                         uint32_t* __restrict__ ranges,
-                                                         uint32_t* __restrict__ counters,
-                                                         int64_t* __restrict__ d_num_pairs,
-                                                         int32_t* __restrict__ d_overflow) {
+// Column scan: for each tile (one per thread) the per-block counts become
+// exclusive offsets in place, then the tile totals are scanned across the
+// blocks of this kernel (ticketed decoupled look-back) into the tile starts:
+// ranges ((0, 0) for empty tiles), starts, pair count and overflow flag.
+__global__ __launch_bounds__(kSortThreads) void k_tc_colscan(uint32_t* __restrict__ cnt, int ntiles,
+                                                            uint32_t capacity, uint32_t* __restrict__ tstart,
+                                                            uint32_t* __restrict__ ranges,
+                                                            uint32_t* __restrict__ counters,
+                                                            uint32_t* __restrict__ look,
+                                                            int64_t* __restrict__ d_num_pairs,
+                                                            int32_t* __restrict__ d_overflow) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
+  __shared__ uint32_t s_misc[2];
   const int t = threadIdx.x;
-  const int per = (ntiles + kSortThreads - 1) / kSortThreads;
-  const int t0 = t * per, t1 = min(ntiles, t0 + per);
-  uint32_t sum = 0;
-  for (int i = t0; i < t1; ++i) sum += tcount[i];
-  uint32_t total;
-  uint32_t run = block_excl_scan(sum, s_wave, &total);
-  for (int i = t0; i < t1; ++i) {
-    const uint32_t c = tcount[i];
-    tcursor[i] = run;
-    ranges[2 * (size_t)i] = c ? run : 0u;
-    ranges[2 * (size_t)i + 1] = c ? run + c : 0u;
-    run += c;
+  if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_TC], 1u);
+  __syncthreads();
+  const uint32_t part = s_misc[0];
+  const int tile = (int)part * kSortThreads + t;
+  uint32_t run = 0;
+  if (tile < ntiles) {
+    for (int b = 0; b < kTcBlocks; ++b) {
+      uint32_t* p = cnt + (size_t)b * ntiles + tile;
+      const uint32_t c = *p;
+      *p = run;
+      run += c;
+    }
   }
-  if (t == 0) {
-    const uint32_t ov = total > capacity ? 1u : 0u;
-    counters[C_NUM_PAIRS] = total;
-    counters[C_OVERFLOW] = ov;
-    *d_num_pairs = (int64_t)total;
-    *d_overflow = (int32_t)ov;
+  uint32_t block_total;
+  const uint32_t pre = block_excl_scan(run, s_wave, &block_total);
+  if (t < 64) {
+    const uint32_t excl = lookback_wave(look, part, block_total);
+    if (t == 0) {
+      s_misc[1] = excl;
+      if ((int)(part + 1) * kSortThreads >= ntiles) {
+        const uint32_t P = excl + block_total;
+        const uint32_t ov = P > capacity ? 1u : 0u;
+        counters[C_NUM_PAIRS] = P;
+        counters[C_OVERFLOW] = ov;
+        *d_num_pairs = (int64_t)P;
+        *d_overflow = (int32_t)ov;
+      }
+    }
+  }
+  __syncthreads();
+  if (tile < ntiles) {
+    const uint32_t st = s_misc[1] + pre;
+    tstart[tile] = st;
+    ranges[2 * (size_t)tile] = run ? st : 0u;
+    ranges[2 * (size_t)tile + 1] = run ? st + run : 0u;
   }
 }
 
+// Scatter of every (item, tile) pair into its tile's segment: block b owns
+// the positions tstart[t] + cnt[b][t] onwards of each tile (LDS cursors, so
+// the order inside a segment is arbitrary; the segment sort fixes it).
 __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ table, int64_t items,
                                                     const uint32_t* __restrict__ tiles,
                                                     const uint32_t* __restrict__ rect,
-                                                    const uint32_t* __restrict__ depth_bits,
-                                                    uint32_t* __restrict__ tcursor,
+                                                    const uint32_t* __restrict__ depth_bits, int ntiles,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ tstart,
                                                     const uint32_t* __restrict__ counters,
                                                     uint32_t* __restrict__ skey, uint32_t* __restrict__ sval) {
+  __shared__ uint32_t s_cur[kTcMaxTiles];
   if (counters[C_OVERFLOW]) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < items; i0 += stride) {
-    const int64_t i = i0 + threadIdx.x;
-    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < items, [&](uint32_t item, uint32_t t, uint32_t) {
-      const uint32_t pos = atomicAdd(&tcursor[t], 1u);
+  const uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s_cur[i] = tstart[i] + row[i];
+  __syncthreads();
+  int64_t i0, i1;
+  tc_item_range(items, &i0, &i1);
+  for (int64_t b = i0; b < i1; b += blockDim.x) {
+    const int64_t i = b + threadIdx.x;
+    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < i1, [&](uint32_t item, uint32_t t, uint32_t) {
+      const uint32_t pos = atomicAdd(&s_cur[t], 1u);
       skey[pos] = depth_bits[item];
       sval[pos] = item;
     });
@@ -749,9 +796,35 @@ __device__ void block_merge(const uint32_t* __restrict__ k, const uint32_t* __re
 
 // One block per tile: sorts the tile's segment by (depth bits, item) and
 // writes the item ids to vals (and the 64-bit keys when asked for).
-// Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
-// runs of kSegCap merged pairwise through the ping-pong buffers (kb, vb),
-// all by the same block.
+// Segments of up to kSegSmall pairs are sorted by one wavefront in a small
+// LDS buffer (k_tc_sort_small); up to kSegCap by a block in LDS; longer ones
+// as sorted runs of kSegCap merged pairwise through the ping-pong buffers
+// (kb, vals), all by the same block.
+constexpr int kSegSmall = 512;  // segments up to this length: one wavefront, 4 KB of LDS
+
+__global__ __launch_bounds__(64) void k_tc_sort_small(const uint32_t* __restrict__ ranges, int ntiles,
+                                                      const uint32_t* __restrict__ counters,
+                                                      const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
+                                                      uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+  __shared__ uint64_t s[kSegSmall];
+  if (counters[C_OVERFLOW]) return;
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
+  const uint32_t n = end - start;
+  if (n == 0 || n > (uint32_t)kSegSmall) return;
+  int n2 = 1;
+  while (n2 < (int)n) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) s[i] = i < (int)n ? pair_key(ka, va, start + i) : ~0ull;
+  __syncthreads();
+  lds_bitonic(s, n2);
+  for (int i = threadIdx.x; i < (int)n; i += blockDim.x) {
+    const uint64_t x = s[i];
+    vals[start + i] = (uint32_t)x;
+    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
                                                  const uint32_t* __restrict__ counters, uint32_t* __restrict__ ka,
                                                  uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
@@ -762,7 +835,7 @@ __global__ __launch_bounds__(256) void k_tc_sort(const uint32_t* __restrict__ ra
   if (tile >= ntiles) return;
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
   const uint32_t n = end - start;
-  if (n == 0) return;
+  if (n <= (uint32_t)kSegSmall) return;  // empty or sorted by k_tc_sort_small
   const int t = threadIdx.x;
   if (n <= (uint32_t)kSegCap) {
     int n2 = 1;
@@ -827,7 +900,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   size_t off = 0;
   // --- head: cleared at the start of every call
   p.off_counters = off; off += C_COUNT * 4;
-  p.off_tcount = off; off += (size_t)total_tiles * 4;
+  p.off_tcount = off; off += (size_t)((total_tiles + kSortThreads - 1) / kSortThreads + 1) * 4;  // look-back words
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
   p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
   p.off_look_sort = off;
@@ -844,6 +917,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tcursor = off; off = align_up(off + (size_t)total_tiles * 4);
+  p.off_tcmat = off; off = align_up(off + (total_tiles <= kTcMaxTiles ? (size_t)kTcBlocks * total_tiles * 4 : 0));
   p.bytes = off;
   return p;
 }
@@ -874,25 +948,30 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const uint32_t* ov = counters + C_OVERFLOW;
 
   if (p.total_tiles <= kTcMaxTiles) {
-    uint32_t* tcount = reinterpret_cast<uint32_t*>(w + p.off_tcount);
-    uint32_t* tcursor = reinterpret_cast<uint32_t*>(w + p.off_tcursor);
+    uint32_t* tlook = reinterpret_cast<uint32_t*>(w + p.off_tcount);
+    uint32_t* tstart = reinterpret_cast<uint32_t*>(w + p.off_tcursor);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(w + p.off_tcmat);
     uint32_t* skey = reinterpret_cast<uint32_t*>(w + p.off_tkeys_a);
     uint32_t* sval = reinterpret_cast<uint32_t*>(w + p.off_tkeys_b);
     uint32_t* spare = reinterpret_cast<uint32_t*>(w + p.off_pvals_b);
-    const size_t nclear = (size_t)C_COUNT + (size_t)p.total_tiles;
+    const int nt = p.total_tiles;
+    const unsigned tparts = (unsigned)((nt + kSortThreads - 1) / kSortThreads);
+    const size_t nclear = (p.off_tcount - p.off_counters) / 4 + tparts + 1;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, counters, 0u, nclear);
-    int64_t gb = (p.items + 255) / 256;
-    const unsigned grid = (unsigned)(gb < 1 ? 1 : (gb > 2048 ? 2048 : gb));
-    if (p.items > 0)
-      hipLaunchKernelGGL(k_tc_count, dim3(grid), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, tcount);
-    hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(kSortThreads), 0, s, tcount, p.total_tiles, (uint32_t)p.capacity,
-                       tcursor, ranges, counters, d_num_pairs, d_overflow);
-    if (p.items > 0)
-      hipLaunchKernelGGL(k_tc_scatter, dim3(grid), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, depth_bits,
-                         tcursor, counters, skey, sval);
-    if (p.total_tiles > 0)
-      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)p.total_tiles), dim3(256), 0, s, ranges, p.total_tiles, counters,
-                         skey, sval, spare, vals, keys);
+    if (nt == 0) {  // nothing to bin: zero pairs
+      hipLaunchKernelGGL(k_tc_colscan, dim3(1), dim3(kSortThreads), 0, s, cnt, 0, (uint32_t)p.capacity, tstart, ranges,
+                         counters, tlook, d_num_pairs, d_overflow);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
+    hipLaunchKernelGGL(k_tc_colscan, dim3(tparts), dim3(kSortThreads), 0, s, cnt, nt, (uint32_t)p.capacity, tstart,
+                       ranges, counters, tlook, d_num_pairs, d_overflow);
+    hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, depth_bits,
+                       nt, cnt, tstart, counters, skey, sval);
+    hipLaunchKernelGGL(k_tc_sort_small, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, skey, sval, vals,
+                       keys);
+    hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(256), 0, s, ranges, nt, counters, skey, sval, spare, vals,
+                       keys);
     return hipGetLastError();
   }
 
