@@ -48,7 +48,6 @@ enum {
   C_NUM_VISIBLE = 16,
   C_NUM_PAIRS = 17,
   C_OVERFLOW = 18,
-  C_TICKET_TC = 19,
   C_COUNT = 64
 };
 
@@ -562,7 +561,7 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
 // is the same order as the stable (tile, depth) sort of the onesweep path.
 constexpr int kTcMaxTiles = 8192;   // per-block tile histograms in LDS (32 KB)
 constexpr int kTcBig = 64;        // items with more tiles are walked by a whole wavefront
-constexpr int kSegCap = 4096;     // segment sorted in LDS in one piece (u64 keys, 32 KB)
+constexpr int kSegCap = 512;      // segment sorted in LDS in one piece (u64 keys, 4 KB): one wavefront per tile
 
 struct ItemTiles {
   uint32_t base;  // global tile id of the rect's top-left tile
@@ -570,14 +569,12 @@ struct ItemTiles {
   uint32_t tx;    // tiles per row of the item's view
 };
 
-__device__ __forceinline__ ItemTiles item_tiles(const ViewEntry* views, int nv, uint32_t item,
-                                               const uint32_t* __restrict__ rect) {
+__device__ __forceinline__ ItemTiles item_tiles(const ViewEntry* views, int nv, uint32_t item, uint2 r) {
   int vlo = 0, vhi = nv - 1;
   while (vlo < vhi) {
     const int mid = (vlo + vhi + 1) >> 1;
     if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
   }
-  const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
   const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
   ItemTiles it;
   it.tx = (uint32_t)views[vlo].tiles_x;
@@ -592,39 +589,55 @@ __device__ __forceinline__ uint32_t tile_of(const ItemTiles& it, uint32_t q) {
   return it.base + row * it.tx + (q - row * it.w);
 }
 
-// Calls f(item, tile, q) for every (visible item, tile) pair of items
-// [i0, i1): small rects by their own lane, large ones by the whole wavefront
-// (so that no lane walks thousands of tiles).  Must be called by full waves.
+// Calls f(item, tile) for every (visible item, tile) pair of the items
+// i0 + k * blockDim + lane (k < kTcItems, below i1) of a wavefront: the tile
+// counts and rectangles of all of them are loaded first; small rectangles are
+// walked by their own lane, large ones by the whole wavefront (so that no
+// lane walks thousands of tiles).  Must be called by full wavefronts.
+constexpr int kTcItems = 4;
+
 template <typename F>
 __device__ __forceinline__ void for_each_pair(const ViewEntry* views, int nv, const uint32_t* __restrict__ tiles,
-                                              const uint32_t* __restrict__ rect, uint32_t item, bool valid, F f) {
-  uint32_t nt = valid ? tiles[item] : 0u;
-  ItemTiles it{};
-  if (nt) {
-    it = item_tiles(views, nv, item, rect);
-    nt = min(nt, it.w * it.h);  // never past the rectangle (and no division by a zero width)
+                                              const uint32_t* __restrict__ rect, int64_t i0, int64_t i1, F f) {
+  uint32_t nt[kTcItems];
+  uint2 rc[kTcItems];
+#pragma unroll
+  for (int k = 0; k < kTcItems; ++k) {
+    const int64_t i = i0 + (int64_t)k * blockDim.x + threadIdx.x;
+    nt[k] = i < i1 ? tiles[i] : 0u;
+    rc[k] = i < i1 ? reinterpret_cast<const uint2*>(rect)[i] : make_uint2(0u, 0u);
   }
-  if (nt && nt <= (uint32_t)kTcBig)
-    for (uint32_t q = 0; q < nt; ++q) f(item, tile_of(it, q), q);
-  uint64_t big = __ballot(nt > (uint32_t)kTcBig);
   const int l = __lane_id();
-  while (big) {
-    const int src = __builtin_ctzll(big);
-    big &= big - 1;
-    const uint32_t bi = (uint32_t)__shfl((int)item, src, 64);
-    const uint32_t bn = (uint32_t)__shfl((int)nt, src, 64);
-    ItemTiles bt;
-    bt.base = (uint32_t)__shfl((int)it.base, src, 64);
-    bt.w = (uint32_t)__shfl((int)it.w, src, 64);
-    bt.h = (uint32_t)__shfl((int)it.h, src, 64);
-    bt.tx = (uint32_t)__shfl((int)it.tx, src, 64);
-    for (uint32_t q = (uint32_t)l; q < bn; q += 64) f(bi, tile_of(bt, q), q);
+#pragma unroll
+  for (int k = 0; k < kTcItems; ++k) {
+    const uint32_t item = (uint32_t)(i0 + (int64_t)k * blockDim.x + threadIdx.x);
+    ItemTiles it{};
+    uint32_t n = nt[k];
+    if (n) {
+      it = item_tiles(views, nv, item, rc[k]);
+      n = min(n, it.w * it.h);  // never past the rectangle (and no division by a zero width)
+    }
+    if (n && n <= (uint32_t)kTcBig)
+      for (uint32_t q = 0; q < n; ++q) f(item, tile_of(it, q));
+    uint64_t big = __ballot(n > (uint32_t)kTcBig);
+    while (big) {
+      const int src = __builtin_ctzll(big);
+      big &= big - 1;
+      const uint32_t bi = (uint32_t)__shfl((int)item, src, 64);
+      const uint32_t bn = (uint32_t)__shfl((int)n, src, 64);
+      ItemTiles bt;
+      bt.base = (uint32_t)__shfl((int)it.base, src, 64);
+      bt.w = (uint32_t)__shfl((int)it.w, src, 64);
+      bt.h = (uint32_t)__shfl((int)it.h, src, 64);
+      bt.tx = (uint32_t)__shfl((int)it.tx, src, 64);
+      for (uint32_t q = (uint32_t)l; q < bn; q += 64) f(bi, tile_of(bt, q));
+    }
   }
 }
 
 // The items are split into kTcBlocks contiguous ranges, one per block of the
 // histogram and scatter kernels (the same ranges in both).
-constexpr int kTcBlocks = 256;
+constexpr int kTcBlocks = 512;
 
 __device__ __forceinline__ void tc_item_range(int64_t items, int64_t* i0, int64_t* i1) {
   const int64_t per = (items + kTcBlocks - 1) / kTcBlocks;
@@ -644,65 +657,81 @@ __global__ __launch_bounds__(256) void k_tc_hist(const void* __restrict__ table,
   __syncthreads();
   int64_t i0, i1;
   tc_item_range(items, &i0, &i1);
-  for (int64_t b = i0; b < i1; b += blockDim.x) {  // uniform trip count
-    const int64_t i = b + threadIdx.x;
-    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < i1,
-                  [&](uint32_t, uint32_t t, uint32_t) { atomicAdd(&s_h[t], 1u); });
-  }
+  for (int64_t b = i0; b < i1; b += (int64_t)kTcItems * blockDim.x)  // uniform trip count
+    for_each_pair(views, nv, tiles, rect, b, i1, [&](uint32_t, uint32_t t) { atomicAdd(&s_h[t], 1u); });
   __syncthreads();
   uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
   for (int i = threadIdx.x; i < ntiles; i += blockDim.x) row[i] = s_h[i];
 }
 
-// Column scan: for each tile (one per thread) the per-block counts become
-// exclusive offsets in place, then the tile totals are scanned across the
-// blocks of this kernel (ticketed decoupled look-back) into the tile starts:
-// ranges ((0, 0) for empty tiles), starts, pair count and overflow flag.
-__global__ __launch_bounds__(kSortThreads) void k_tc_colscan(uint32_t* __restrict__ cnt, int ntiles,
-                                                            uint32_t capacity, uint32_t* __restrict__ tstart,
-                                                            uint32_t* __restrict__ ranges,
-                                                            uint32_t* __restrict__ counters,
-                                                            uint32_t* __restrict__ look,
-                                                            int64_t* __restrict__ d_num_pairs,
-                                                            int32_t* __restrict__ d_overflow) {
+// Column offsets: lane (tile j of the block's 8, group g of 32) sums 16
+// rows; the 32 group sums of a tile are scanned in LDS; the per-block counts
+// become exclusive offsets in place and the tile totals go to tot[].
+constexpr int kColTiles = 8, kColGroups = 32, kColRows = kTcBlocks / kColGroups;
+__global__ __launch_bounds__(256) void k_tc_colscan(uint32_t* __restrict__ cnt, int ntiles,
+                                                    uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_g[kColTiles][kColGroups + 1];
+  const int j = threadIdx.x % kColTiles, g = threadIdx.x / kColTiles;
+  const int tile = blockIdx.x * kColTiles + j;
+  uint32_t c[kColRows];
+  uint32_t sum = 0;
+  if (tile < ntiles) {
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) c[r] = cnt[(size_t)(g * kColRows + r) * ntiles + tile];
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) sum += c[r];
+  }
+  s_g[j][g] = sum;
+  __syncthreads();
+  if (g == 0) {  // exclusive scan of the 32 group sums of tile j
+    uint32_t run = 0;
+    for (int q = 0; q < kColGroups; ++q) {
+      const uint32_t v = s_g[j][q];
+      s_g[j][q] = run;
+      run += v;
+    }
+    if (tile < ntiles) tot[tile] = run;
+  }
+  __syncthreads();
+  if (tile < ntiles) {
+    uint32_t run = s_g[j][g];
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) {
+      cnt[(size_t)(g * kColRows + r) * ntiles + tile] = run;
+      run += c[r];
+    }
+  }
+}
+
+// One block: exclusive scan of the tile totals -> tile starts, ranges ((0, 0)
+// for empty tiles), pair count and overflow flag.
+__global__ __launch_bounds__(kSortThreads) void k_tc_tilescan(const uint32_t* __restrict__ tot, int ntiles,
+                                                             uint32_t capacity, uint32_t* __restrict__ tstart,
+                                                             uint32_t* __restrict__ ranges,
+                                                             uint32_t* __restrict__ counters,
+                                                             int64_t* __restrict__ d_num_pairs,
+                                                             int32_t* __restrict__ d_overflow) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
-  __shared__ uint32_t s_misc[2];
   const int t = threadIdx.x;
-  if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_TC], 1u);
-  __syncthreads();
-  const uint32_t part = s_misc[0];
-  const int tile = (int)part * kSortThreads + t;
-  uint32_t run = 0;
-  if (tile < ntiles) {
-    for (int b = 0; b < kTcBlocks; ++b) {
-      uint32_t* p = cnt + (size_t)b * ntiles + tile;
-      const uint32_t c = *p;
-      *p = run;
-      run += c;
-    }
+  const int per = (ntiles + kSortThreads - 1) / kSortThreads;
+  const int t0 = min(ntiles, t * per), t1 = min(ntiles, t0 + per);
+  uint32_t sum = 0;
+  for (int i = t0; i < t1; ++i) sum += tot[i];
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, s_wave, &total);
+  for (int i = t0; i < t1; ++i) {
+    const uint32_t c = tot[i];
+    tstart[i] = run;
+    ranges[2 * (size_t)i] = c ? run : 0u;
+    ranges[2 * (size_t)i + 1] = c ? run + c : 0u;
+    run += c;
   }
-  uint32_t block_total;
-  const uint32_t pre = block_excl_scan(run, s_wave, &block_total);
-  if (t < 64) {
-    const uint32_t excl = lookback_wave(look, part, block_total);
-    if (t == 0) {
-      s_misc[1] = excl;
-      if ((int)(part + 1) * kSortThreads >= ntiles) {
-        const uint32_t P = excl + block_total;
-        const uint32_t ov = P > capacity ? 1u : 0u;
-        counters[C_NUM_PAIRS] = P;
-        counters[C_OVERFLOW] = ov;
-        *d_num_pairs = (int64_t)P;
-        *d_overflow = (int32_t)ov;
-      }
-    }
-  }
-  __syncthreads();
-  if (tile < ntiles) {
-    const uint32_t st = s_misc[1] + pre;
-    tstart[tile] = st;
-    ranges[2 * (size_t)tile] = run ? st : 0u;
-    ranges[2 * (size_t)tile + 1] = run ? st + run : 0u;
+  if (t == 0) {
+    const uint32_t ov = total > capacity ? 1u : 0u;
+    counters[C_NUM_PAIRS] = total;
+    counters[C_OVERFLOW] = ov;
+    *d_num_pairs = (int64_t)total;
+    *d_overflow = (int32_t)ov;
   }
 }
 
@@ -727,14 +756,12 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
   __syncthreads();
   int64_t i0, i1;
   tc_item_range(items, &i0, &i1);
-  for (int64_t b = i0; b < i1; b += blockDim.x) {
-    const int64_t i = b + threadIdx.x;
-    for_each_pair(views, nv, tiles, rect, (uint32_t)i, i < i1, [&](uint32_t item, uint32_t t, uint32_t) {
+  for (int64_t b = i0; b < i1; b += (int64_t)kTcItems * blockDim.x)
+    for_each_pair(views, nv, tiles, rect, b, i1, [&](uint32_t item, uint32_t t) {
       const uint32_t pos = atomicAdd(&s_cur[t], 1u);
       skey[pos] = depth_bits[item];
       sval[pos] = item;
     });
-  }
 }
 
 __device__ __forceinline__ uint64_t pair_key(const uint32_t* k, const uint32_t* v, uint32_t i) {
@@ -794,48 +821,21 @@ __device__ void block_merge(const uint32_t* __restrict__ k, const uint32_t* __re
   }
 }
 
-// One block per tile: sorts the tile's segment by (depth bits, item) and
+// One wavefront per tile: sorts the tile's segment by (depth bits, item) and
 // writes the item ids to vals (and the 64-bit keys when asked for).
-// Segments of up to kSegSmall pairs are sorted by one wavefront in a small
-// LDS buffer (k_tc_sort_small); up to kSegCap by a block in LDS; longer ones
-// as sorted runs of kSegCap merged pairwise through the ping-pong buffers
-// (kb, vals), all by the same block.
-constexpr int kSegSmall = 512;  // segments up to this length: one wavefront, 4 KB of LDS
-
-__global__ __launch_bounds__(64) void k_tc_sort_small(const uint32_t* __restrict__ ranges, int ntiles,
-                                                      const uint32_t* __restrict__ counters,
-                                                      const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
-                                                      uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
-  __shared__ uint64_t s[kSegSmall];
-  if (counters[C_OVERFLOW]) return;
-  const int tile = blockIdx.x;
-  if (tile >= ntiles) return;
-  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
-  const uint32_t n = end - start;
-  if (n == 0 || n > (uint32_t)kSegSmall) return;
-  int n2 = 1;
-  while (n2 < (int)n) n2 <<= 1;
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) s[i] = i < (int)n ? pair_key(ka, va, start + i) : ~0ull;
-  __syncthreads();
-  lds_bitonic(s, n2);
-  for (int i = threadIdx.x; i < (int)n; i += blockDim.x) {
-    const uint64_t x = s[i];
-    vals[start + i] = (uint32_t)x;
-    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
-                                                 const uint32_t* __restrict__ counters, uint32_t* __restrict__ ka,
-                                                 uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
-                                                 uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+// Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
+// runs of kSegCap merged pairwise through the ping-pong buffers (kb, vals).
+__global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
+                                                const uint32_t* __restrict__ counters, uint32_t* __restrict__ ka,
+                                                uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
+                                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
   __shared__ uint64_t s[kSegCap];
   if (counters[C_OVERFLOW]) return;
   const int tile = blockIdx.x;
   if (tile >= ntiles) return;
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
   const uint32_t n = end - start;
-  if (n <= (uint32_t)kSegSmall) return;  // empty or sorted by k_tc_sort_small
+  if (n == 0) return;
   const int t = threadIdx.x;
   if (n <= (uint32_t)kSegCap) {
     int n2 = 1;
@@ -871,7 +871,6 @@ __global__ __launch_bounds__(256) void k_tc_sort(const uint32_t* __restrict__ ra
       block_merge(sk, sv, start + lo, na, start + lo + na, nb, dk, dv, start + lo);
     }
     __syncthreads();
-    __threadfence_block();
     uint32_t* tk = sk; sk = dk; dk = tk;
     uint32_t* tv = sv; sv = dv; dv = tv;
   }
@@ -900,7 +899,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   size_t off = 0;
   // --- head: cleared at the start of every call
   p.off_counters = off; off += C_COUNT * 4;
-  p.off_tcount = off; off += (size_t)((total_tiles + kSortThreads - 1) / kSortThreads + 1) * 4;  // look-back words
+  p.off_tcount = off; off += (size_t)total_tiles * 4;  // tile totals
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
   p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
   p.off_look_sort = off;
@@ -948,30 +947,27 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const uint32_t* ov = counters + C_OVERFLOW;
 
   if (p.total_tiles <= kTcMaxTiles) {
-    uint32_t* tlook = reinterpret_cast<uint32_t*>(w + p.off_tcount);
+    uint32_t* tot = reinterpret_cast<uint32_t*>(w + p.off_tcount);
     uint32_t* tstart = reinterpret_cast<uint32_t*>(w + p.off_tcursor);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(w + p.off_tcmat);
     uint32_t* skey = reinterpret_cast<uint32_t*>(w + p.off_tkeys_a);
     uint32_t* sval = reinterpret_cast<uint32_t*>(w + p.off_tkeys_b);
     uint32_t* spare = reinterpret_cast<uint32_t*>(w + p.off_pvals_b);
     const int nt = p.total_tiles;
-    const unsigned tparts = (unsigned)((nt + kSortThreads - 1) / kSortThreads);
-    const size_t nclear = (p.off_tcount - p.off_counters) / 4 + tparts + 1;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, counters, 0u, nclear);
-    if (nt == 0) {  // nothing to bin: zero pairs
-      hipLaunchKernelGGL(k_tc_colscan, dim3(1), dim3(kSortThreads), 0, s, cnt, 0, (uint32_t)p.capacity, tstart, ranges,
-                         counters, tlook, d_num_pairs, d_overflow);
-      return hipGetLastError();
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (size_t)C_COUNT);
+    if (nt > 0) {
+      hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
+      hipLaunchKernelGGL(k_tc_colscan, dim3((unsigned)((nt + kColTiles - 1) / kColTiles)), dim3(256), 0, s, cnt, nt,
+                         tot);
     }
-    hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
-    hipLaunchKernelGGL(k_tc_colscan, dim3(tparts), dim3(kSortThreads), 0, s, cnt, nt, (uint32_t)p.capacity, tstart,
-                       ranges, counters, tlook, d_num_pairs, d_overflow);
-    hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, depth_bits,
-                       nt, cnt, tstart, counters, skey, sval);
-    hipLaunchKernelGGL(k_tc_sort_small, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, skey, sval, vals,
-                       keys);
-    hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(256), 0, s, ranges, nt, counters, skey, sval, spare, vals,
-                       keys);
+    hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kSortThreads), 0, s, tot, nt, (uint32_t)p.capacity, tstart,
+                       ranges, counters, d_num_pairs, d_overflow);
+    if (nt > 0) {
+      hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
+                         depth_bits, nt, cnt, tstart, counters, skey, sval);
+      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, skey, sval, spare, vals,
+                         keys);
+    }
     return hipGetLastError();
   }
 
