@@ -768,18 +768,35 @@ __device__ __forceinline__ uint64_t pair_key(const uint32_t* k, const uint32_t* 
   return ((uint64_t)k[i] << 32) | v[i];
 }
 
-// Bitonic sort of s[0, n2) (n2 a power of two) by the block.
+// Bitonic sort of s[0, n2) (n2 a power of two, n2 <= kSegCap) by one
+// wavefront.  A stage's pairs are disjoint: each lane loads all of its pairs
+// first and then compares and stores them, so that a stage costs one LDS
+// round trip (LDS loads cannot be moved above possibly aliasing stores).
 __device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
+  constexpr int kPer = kSegCap / 2 / 64;  // pairs per lane at most
+  const int t = threadIdx.x;
+  const int half = n2 >> 1;
   for (int k = 2; k <= n2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = s[i], b = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[ixj] = a;
+      int lo[kPer];
+      uint64_t a[kPer], b[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int p = t + 64 * q;
+        lo[q] = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // lower index of pair p (its partner is lo + j)
+        if (p < half) {
+          a[q] = s[lo[q]];
+          b[q] = s[lo[q] + j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int p = t + 64 * q;
+        if (p < half) {
+          const bool up = (lo[q] & k) == 0;
+          if ((a[q] > b[q]) == up) {
+            s[lo[q]] = b[q];
+            s[lo[q] + j] = a[q];
           }
         }
       }
