@@ -735,9 +735,10 @@ __global__ __launch_bounds__(kSortThreads) void k_tc_tilescan(const uint32_t* __
   }
 }
 
-// Scatter of every (item, tile) pair into its tile's segment: block b owns
-// the positions tstart[t] + cnt[b][t] onwards of each tile (LDS cursors, so
-// the order inside a segment is arbitrary; the segment sort fixes it).
+// Scatter of every (item, tile) pair into its tile's segment as the 64-bit
+// key (depth bits << 32 | item): block b owns the positions tstart[t] +
+// cnt[b][t] onwards of each tile (LDS cursors, so the order inside a segment
+// is arbitrary; the segment sort fixes it).
 __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ table, int64_t items,
                                                     const uint32_t* __restrict__ tiles,
                                                     const uint32_t* __restrict__ rect,
@@ -745,7 +746,7 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ tstart,
                                                     const uint32_t* __restrict__ counters,
-                                                    uint32_t* __restrict__ skey, uint32_t* __restrict__ sval) {
+                                                    uint64_t* __restrict__ spair) {
   __shared__ uint32_t s_cur[kTcMaxTiles];
   if (counters[C_OVERFLOW]) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -759,13 +760,8 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
   for (int64_t b = i0; b < i1; b += (int64_t)kTcItems * blockDim.x)
     for_each_pair(views, nv, tiles, rect, b, i1, [&](uint32_t item, uint32_t t) {
       const uint32_t pos = atomicAdd(&s_cur[t], 1u);
-      skey[pos] = depth_bits[item];
-      sval[pos] = item;
+      spair[pos] = ((uint64_t)depth_bits[item] << 32) | item;  // the sort key (depth bits, item)
     });
-}
-
-__device__ __forceinline__ uint64_t pair_key(const uint32_t* k, const uint32_t* v, uint32_t i) {
-  return ((uint64_t)k[i] << 32) | v[i];
 }
 
 // Bitonic sort of s[0, n2) (n2 a power of two, n2 <= kSegCap) by one
@@ -805,47 +801,35 @@ __device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
   }
 }
 
-// Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of (key,
-// val) into out at o0, by the whole block (each thread a contiguous slice of
-// the output, split points by merge-path binary search).
-__device__ void block_merge(const uint32_t* __restrict__ k, const uint32_t* __restrict__ v, uint32_t a0, uint32_t na,
-                            uint32_t b0, uint32_t nb, uint32_t* __restrict__ ko, uint32_t* __restrict__ vo,
-                            uint32_t o0) {
+// Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of x
+// into out at o0, by the whole block (each lane a contiguous slice of the
+// output, split points by merge-path binary search; keys are unique).
+__device__ void block_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
+                            uint64_t* __restrict__ out, uint32_t o0) {
   const uint32_t n = na + nb;
   const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
   const uint32_t d0 = min(n, threadIdx.x * per), d1 = min(n, d0 + per);
   if (d0 >= d1) return;
-  // split of diagonal d: number of elements taken from a
-  auto split = [&](uint32_t d) {
-    uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
-    while (lo < hi) {
-      const uint32_t m = (lo + hi) >> 1;
-      // take a[m] before b[d - 1 - m] when a[m] <= b[d - 1 - m] (a first on ties: keys are unique anyway)
-      if (pair_key(k, v, a0 + m) <= pair_key(k, v, b0 + d - 1 - m)) lo = m + 1; else hi = m;
-    }
-    return lo;
-  };
-  uint32_t ia = split(d0), ib = d0 - ia;
+  uint32_t lo = d0 > nb ? d0 - nb : 0u, hi = min(d0, na);
+  while (lo < hi) {  // number of elements of a among the first d0 outputs
+    const uint32_t m = (lo + hi) >> 1;
+    if (x[a0 + m] <= x[b0 + d0 - 1 - m]) lo = m + 1; else hi = m;
+  }
+  uint32_t ia = lo, ib = d0 - lo;
   for (uint32_t o = d0; o < d1; ++o) {
-    bool takea;
-    if (ia >= na) takea = false;
-    else if (ib >= nb) takea = true;
-    else takea = pair_key(k, v, a0 + ia) <= pair_key(k, v, b0 + ib);
-    const uint32_t src = takea ? a0 + ia : b0 + ib;
-    ko[o0 + o] = k[src];
-    vo[o0 + o] = v[src];
-    if (takea) ++ia; else ++ib;
+    const bool takea = ib >= nb || (ia < na && x[a0 + ia] <= x[b0 + ib]);
+    out[o0 + o] = takea ? x[a0 + ia++] : x[b0 + ib++];
   }
 }
 
-// One wavefront per tile: sorts the tile's segment by (depth bits, item) and
-// writes the item ids to vals (and the 64-bit keys when asked for).
+// One wavefront per tile: sorts the tile's segment of (depth bits, item) keys
+// and writes the item ids to vals (and the 64-bit keys when asked for).
 // Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
-// runs of kSegCap merged pairwise through the ping-pong buffers (kb, vals).
+// runs of kSegCap merged pairwise through the ping-pong buffer pb.
 __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
-                                                const uint32_t* __restrict__ counters, uint32_t* __restrict__ ka,
-                                                uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
-                                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+                                                const uint32_t* __restrict__ counters, uint64_t* __restrict__ pa,
+                                                uint64_t* __restrict__ pb, uint32_t* __restrict__ vals,
+                                                uint64_t* __restrict__ keys) {
   __shared__ uint64_t s[kSegCap];
   if (counters[C_OVERFLOW]) return;
   const int tile = blockIdx.x;
@@ -857,7 +841,7 @@ __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ran
   if (n <= (uint32_t)kSegCap) {
     int n2 = 1;
     while (n2 < (int)n) n2 <<= 1;
-    for (int i = t; i < n2; i += blockDim.x) s[i] = i < (int)n ? pair_key(ka, va, start + i) : ~0ull;
+    for (int i = t; i < n2; i += blockDim.x) s[i] = i < (int)n ? pa[start + i] : ~0ull;
     __syncthreads();
     lds_bitonic(s, n2);
     for (int i = t; i < (int)n; i += blockDim.x) {
@@ -867,34 +851,30 @@ __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ran
     }
     return;
   }
-  // long segment: sorted runs, then pairwise merges ka/va <-> kb/vals
+  // long segment: sorted runs in place, then pairwise merges pa <-> pb
   for (uint32_t r0 = 0; r0 < n; r0 += kSegCap) {
     const uint32_t m = min((uint32_t)kSegCap, n - r0);
     __syncthreads();
-    for (int i = t; i < kSegCap; i += blockDim.x) s[i] = i < (int)m ? pair_key(ka, va, start + r0 + i) : ~0ull;
+    for (int i = t; i < kSegCap; i += blockDim.x) s[i] = i < (int)m ? pa[start + r0 + i] : ~0ull;
     __syncthreads();
     lds_bitonic(s, kSegCap);
-    for (int i = t; i < (int)m; i += blockDim.x) {
-      ka[start + r0 + i] = (uint32_t)(s[i] >> 32);
-      va[start + r0 + i] = (uint32_t)s[i];
-    }
+    for (int i = t; i < (int)m; i += blockDim.x) pa[start + r0 + i] = s[i];
   }
   __syncthreads();
-  uint32_t *sk = ka, *sv = va, *dk = kb, *dv = vals;
+  uint64_t *src = pa, *dst = pb;
   for (uint32_t width = kSegCap; width < n; width <<= 1) {
     for (uint32_t lo = 0; lo < n; lo += 2 * width) {
       const uint32_t na = min(width, n - lo);
       const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
-      block_merge(sk, sv, start + lo, na, start + lo + na, nb, dk, dv, start + lo);
+      block_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo);
     }
     __syncthreads();
-    uint32_t* tk = sk; sk = dk; dk = tk;
-    uint32_t* tv = sv; sv = dv; dv = tv;
+    uint64_t* tmp = src; src = dst; dst = tmp;
   }
-  // the sorted segment is in (sk, sv); the item ids must end in vals
   for (uint32_t i = t; i < n; i += blockDim.x) {
-    if (sv != vals) vals[start + i] = sv[start + i];
-    if (keys) keys[start + i] = ((uint64_t)tile << 32) | sk[start + i];
+    const uint64_t x = src[start + i];
+    vals[start + i] = (uint32_t)x;
+    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
   }
 }
 
@@ -933,7 +913,10 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tcursor = off; off = align_up(off + (size_t)total_tiles * 4);
-  p.off_tcmat = off; off = align_up(off + (total_tiles <= kTcMaxTiles ? (size_t)kTcBlocks * total_tiles * 4 : 0));
+  const bool tc = total_tiles <= kTcMaxTiles;
+  p.off_tcmat = off; off = align_up(off + (tc ? (size_t)kTcBlocks * total_tiles * 4 : 0));
+  p.off_tcpair_a = off; off = align_up(off + (tc ? (size_t)capacity * 8 : 0));
+  p.off_tcpair_b = off; off = align_up(off + (tc ? (size_t)capacity * 8 : 0));
   p.bytes = off;
   return p;
 }
@@ -967,9 +950,8 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     uint32_t* tot = reinterpret_cast<uint32_t*>(w + p.off_tcount);
     uint32_t* tstart = reinterpret_cast<uint32_t*>(w + p.off_tcursor);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(w + p.off_tcmat);
-    uint32_t* skey = reinterpret_cast<uint32_t*>(w + p.off_tkeys_a);
-    uint32_t* sval = reinterpret_cast<uint32_t*>(w + p.off_tkeys_b);
-    uint32_t* spare = reinterpret_cast<uint32_t*>(w + p.off_pvals_b);
+    uint64_t* pa = reinterpret_cast<uint64_t*>(w + p.off_tcpair_a);
+    uint64_t* pb = reinterpret_cast<uint64_t*>(w + p.off_tcpair_b);
     const int nt = p.total_tiles;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (size_t)C_COUNT);
     if (nt > 0) {
@@ -981,9 +963,8 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
                        ranges, counters, d_num_pairs, d_overflow);
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
-                         depth_bits, nt, cnt, tstart, counters, skey, sval);
-      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, skey, sval, spare, vals,
-                         keys);
+                         depth_bits, nt, cnt, tstart, counters, pa);
+      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, pa, pb, vals, keys);
     }
     return hipGetLastError();
   }
