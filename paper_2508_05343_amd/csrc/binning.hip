@@ -764,21 +764,13 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
     });
 }
 
-// Orders the LDS and global accesses of one wavefront around this point
-// (the lanes of a wavefront run in lockstep; the fences make the compiler
-// wait for the wavefront's outstanding memory operations).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // Bitonic sort of s[0, n2) (n2 a power of two, n2 <= kSegCap) by one
 // wavefront.  A stage's pairs are disjoint: each lane loads all of its pairs
 // first and then compares and stores them, so that a stage costs one LDS
 // round trip (LDS loads cannot be moved above possibly aliasing stores).
-__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2, int lane) {
+__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
   constexpr int kPer = kSegCap / 2 / 64;  // pairs per lane at most
+  const int t = threadIdx.x;
   const int half = n2 >> 1;
   for (int k = 2; k <= n2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -786,7 +778,7 @@ __device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2, int lane) {
       uint64_t a[kPer], b[kPer];
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
-        const int p = lane + 64 * q;
+        const int p = t + 64 * q;
         lo[q] = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // lower index of pair p (its partner is lo + j)
         if (p < half) {
           a[q] = s[lo[q]];
@@ -795,7 +787,7 @@ __device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2, int lane) {
       }
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
-        const int p = lane + 64 * q;
+        const int p = t + 64 * q;
         if (p < half) {
           const bool up = (lo[q] & k) == 0;
           if ((a[q] > b[q]) == up) {
@@ -804,19 +796,19 @@ __device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2, int lane) {
           }
         }
       }
-      wave_sync();
+      __syncthreads();
     }
   }
 }
 
 // Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of x
-// into out at o0, by one wavefront (each lane a contiguous slice of the
+// into out at o0, by the whole block (each lane a contiguous slice of the
 // output, split points by merge-path binary search; keys are unique).
-__device__ void wave_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
-                           uint64_t* __restrict__ out, uint32_t o0, int lane) {
+__device__ void block_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
+                            uint64_t* __restrict__ out, uint32_t o0) {
   const uint32_t n = na + nb;
-  const uint32_t per = (n + 63) / 64;
-  const uint32_t d0 = min(n, (uint32_t)lane * per), d1 = min(n, d0 + per);
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t d0 = min(n, threadIdx.x * per), d1 = min(n, d0 + per);
   if (d0 >= d1) return;
   uint32_t lo = d0 > nb ? d0 - nb : 0u, hi = min(d0, na);
   while (lo < hi) {  // number of elements of a among the first d0 outputs
@@ -830,66 +822,59 @@ __device__ void wave_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t
   }
 }
 
-// One wavefront per tile (blocks of kSortWaves wavefronts striding over the
-// tiles, so that the short-lived per-tile work does not wait on workgroup
-// dispatch): sorts the tile's segment of (depth bits, item) keys
+// One wavefront per tile: sorts the tile's segment of (depth bits, item) keys
 // and writes the item ids to vals (and the 64-bit keys when asked for).
 // Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
 // runs of kSegCap merged pairwise through the ping-pong buffer pb.
-constexpr int kSortWaves = 4;  // wavefronts per block of the segment sort, each with its own LDS slice
-
-__global__ __launch_bounds__(64 * kSortWaves) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
-                                                             const uint32_t* __restrict__ counters,
-                                                             uint64_t* __restrict__ pa, uint64_t* __restrict__ pb,
-                                                             uint32_t* __restrict__ vals,
-                                                             uint64_t* __restrict__ keys) {
-  __shared__ uint64_t s_all[kSortWaves][kSegCap];
+__global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
+                                                const uint32_t* __restrict__ counters, uint64_t* __restrict__ pa,
+                                                uint64_t* __restrict__ pb, uint32_t* __restrict__ vals,
+                                                uint64_t* __restrict__ keys) {
+  __shared__ uint64_t s[kSegCap];
   if (counters[C_OVERFLOW]) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t* s = s_all[w];
-  for (int tile = blockIdx.x * kSortWaves + w; tile < ntiles; tile += gridDim.x * kSortWaves) {
-    const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
-    const uint32_t n = end - start;
-    if (n == 0) continue;
-    if (n <= (uint32_t)kSegCap) {
-      int n2 = 1;
-      while (n2 < (int)n) n2 <<= 1;
-      for (int i = lane; i < n2; i += 64) s[i] = i < (int)n ? pa[start + i] : ~0ull;
-      wave_sync();
-      lds_bitonic(s, n2, lane);
-      for (int i = lane; i < (int)n; i += 64) {
-        const uint64_t x = s[i];
-        vals[start + i] = (uint32_t)x;
-        if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
-      }
-      wave_sync();
-      continue;
-    }
-    // long segment: sorted runs in place, then pairwise merges pa <-> pb
-    for (uint32_t r0 = 0; r0 < n; r0 += kSegCap) {
-      const uint32_t m = min((uint32_t)kSegCap, n - r0);
-      for (int i = lane; i < kSegCap; i += 64) s[i] = i < (int)m ? pa[start + r0 + i] : ~0ull;
-      wave_sync();
-      lds_bitonic(s, kSegCap, lane);
-      for (int i = lane; i < (int)m; i += 64) pa[start + r0 + i] = s[i];
-      wave_sync();
-    }
-    uint64_t *src = pa, *dst = pb;
-    for (uint32_t width = kSegCap; width < n; width <<= 1) {
-      for (uint32_t lo = 0; lo < n; lo += 2 * width) {
-        const uint32_t na = min(width, n - lo);
-        const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
-        wave_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo, lane);
-      }
-      wave_sync();
-      uint64_t* tmp = src; src = dst; dst = tmp;
-    }
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint64_t x = src[start + i];
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
+  const uint32_t n = end - start;
+  if (n == 0) return;
+  const int t = threadIdx.x;
+  if (n <= (uint32_t)kSegCap) {
+    int n2 = 1;
+    while (n2 < (int)n) n2 <<= 1;
+    for (int i = t; i < n2; i += blockDim.x) s[i] = i < (int)n ? pa[start + i] : ~0ull;
+    __syncthreads();
+    lds_bitonic(s, n2);
+    for (int i = t; i < (int)n; i += blockDim.x) {
+      const uint64_t x = s[i];
       vals[start + i] = (uint32_t)x;
       if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
     }
-    wave_sync();
+    return;
+  }
+  // long segment: sorted runs in place, then pairwise merges pa <-> pb
+  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap) {
+    const uint32_t m = min((uint32_t)kSegCap, n - r0);
+    __syncthreads();
+    for (int i = t; i < kSegCap; i += blockDim.x) s[i] = i < (int)m ? pa[start + r0 + i] : ~0ull;
+    __syncthreads();
+    lds_bitonic(s, kSegCap);
+    for (int i = t; i < (int)m; i += blockDim.x) pa[start + r0 + i] = s[i];
+  }
+  __syncthreads();
+  uint64_t *src = pa, *dst = pb;
+  for (uint32_t width = kSegCap; width < n; width <<= 1) {
+    for (uint32_t lo = 0; lo < n; lo += 2 * width) {
+      const uint32_t na = min(width, n - lo);
+      const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
+      block_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo);
+    }
+    __syncthreads();
+    uint64_t* tmp = src; src = dst; dst = tmp;
+  }
+  for (uint32_t i = t; i < n; i += blockDim.x) {
+    const uint64_t x = src[start + i];
+    vals[start + i] = (uint32_t)x;
+    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
   }
 }
 
@@ -979,9 +964,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
                          depth_bits, nt, cnt, tstart, counters, pa);
-      const int sb = (nt + kSortWaves - 1) / kSortWaves;
-      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)(sb < 1024 ? sb : 1024)), dim3(64 * kSortWaves), 0, s, ranges, nt,
-                         counters, pa, pb, vals, keys);
+      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, pa, pb, vals, keys);
     }
     return hipGetLastError();
   }
