@@ -1,24 +1,30 @@
-// K2-K5: visibility compaction, depth sort, tile-key duplication, tile sort,
-// tile ranges.
+// K2-K5: binning -- the (tile, item) pairs of every visible item ordered by
+// tile, then fp32 depth bits, then item index (the stable sort of the 64-bit
+// key tile << 32 | depth bits), and the per-tile ranges.
 //
-// The pairs must end up ordered by the 64-bit key (global tile << 32 | fp32
-// depth bits), ties by item index.  An LSD radix sort over that key first
-// sorts by the 32 depth bits and then, stably, by the tile bits.  All pairs of
-// one primitive share its depth, so the depth passes are run on the visible
-// primitives before duplication (V items instead of P pairs); duplication
-// then emits pairs in depth order and only ceil(tile_bits / 8) passes run on
-// the P pairs, moving 8 bytes per pair instead of 12.
+// Frames of at most kTcMaxTiles tiles (one view up to 1920x1080, say) take
+// the tile-count path: per-block tile histograms in LDS, per-tile column
+// offsets and one scan of the tile totals (which are the ranges), a scatter
+// of (depth bits << 32 | item) into each tile's segment through per-block
+// LDS cursors, and a sort of every segment by that unique key (bitonic in
+// LDS; runs merged for long segments).  Seven launches, no global radix
+// passes and no global atomics.
 //
-// Every pass is one onesweep kernel: partitions of 4096 keys are taken from an
-// atomic ticket (so a partition only ever waits on partitions whose blocks are
-// already running), ranked in LDS with wave64 ballot matching, and placed
-// with a decoupled look-back over per-(partition, digit) status words.
-//
-// Launch sequence (9 + tile-pass launches): clear the workspace head;
-// compaction of the visible items fused with the depth-digit histograms; 4
-// depth passes; tiles-touched scan; pair emission balanced over fixed chunks
-// of pairs, fused with the tile-digit histograms; the tile passes; per-tile
-// ranges from the boundaries between runs of equal tile keys.
+// Larger batches (many views) take the radix path: an LSD radix sort over
+// the same key that first sorts by the 32 depth bits and then, stably, by
+// the tile bits.  All pairs of one primitive share its depth, so the depth
+// passes run on the visible primitives before duplication (V items instead
+// of P pairs); duplication then emits pairs in depth order and only
+// ceil(tile_bits / 8) passes run on the P pairs.  Every pass is one onesweep
+// kernel: partitions of 4096 keys are taken from an atomic ticket (so a
+// partition only ever waits on partitions whose blocks are already running),
+// ranked in LDS with wave64 ballot matching, and placed with a decoupled
+// look-back over per-(partition, digit) status words.  Launch sequence:
+// clear the workspace head; compaction of the visible items fused with the
+// depth-digit histograms; 4 depth passes; tiles-touched scan; pair emission
+// balanced over fixed chunks of pairs, fused with the tile-digit histograms;
+// the tile passes; per-tile ranges from the boundaries between runs of equal
+// tile keys.
 #include <hip/hip_runtime.h>
 
 #include "gs_block.h"
