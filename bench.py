@@ -35,8 +35,8 @@ VALU_PEAK_TFLOPS = 78.6
 # 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
 # taken on (hash of the blend's source text); otherwise traffic is null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "f753d3849572598b47b8ecbeb1af26340c852ce1b84b3b5f93630a348e892c41",
-    "fetch_kib": 43683.80, "write_kib": 23993.38, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "d842f81d544b0b183aa72a52eb1ce42e4046e7da40af8020fbe632fa6b1fc880",
+    "fetch_kib": 43668.33, "write_kib": 24003.35, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
