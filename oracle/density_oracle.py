@@ -10,6 +10,13 @@ Small values follow the paper's initialisation (f = 0.001, w = 0.01, Sec.
 3.4.1 and Sec. 4 implementation details; supplementary B: reset to 0.001 and
 0.01 after densification, prune threshold 0.01, opacity reset 0.02).
 
+The AbsGS variant (the densification the paper plugs its primitive into in
+Sec. 4.1 / Table 1) adds a second statistic, the homodirectional gradient:
+the per-axis sums over pixels of the absolute per-pixel mean gradients, in
+the same NDC units.  Reading: it widens the split test only -- a large
+primitive splits when either statistic reaches its threshold; cloning keeps
+the ordinary statistic.
+
 Everything here is plain numpy in float64 on float32 inputs; decisions
 (comparisons against thresholds) are taken on the float32 values.
 """
@@ -32,17 +39,25 @@ class DensifyParams:
     weight_reset: float = 0.01       # every frequency weight of a new child
     split_count: int = 2
     split_shrink: float = 1.0 / 1.6  # child scale factor (3DGS: 1 / (0.8 N))
+    abs_grad_threshold: float = 0.0  # AbsGS split threshold on the homodirectional statistic (0: off)
+
+
+def _ndc_norm(g, width, height):
+    g = np.asarray(g, np.float64)
+    return np.sqrt((g[:, 0] * width / 2.0) ** 2 + (g[:, 1] * height / 2.0) ** 2)
 
 
 def accumulate_stats(grad_mu2d: np.ndarray, visible: np.ndarray, width: int, height: int,
-                     accum: np.ndarray, denom: np.ndarray):
+                     accum: np.ndarray, denom: np.ndarray, abs_mu2d=None, accum_abs=None):
     """accum += |dL/d mu2d| measured in normalised device coordinates
-    (pixel gradient times (W/2, H/2)), denom += 1, for the visible primitives."""
-    g = np.asarray(grad_mu2d, np.float64)
-    nrm = np.sqrt((g[:, 0] * width / 2.0) ** 2 + (g[:, 1] * height / 2.0) ** 2)
+    (pixel gradient times (W/2, H/2)), denom += 1, for the visible primitives;
+    with abs_mu2d (per-axis sums of |dL_p/d mu2d| over pixels) also
+    accum_abs += its norm in the same units."""
     v = np.asarray(visible, bool)
-    accum[v] += nrm[v]
+    accum[v] += _ndc_norm(grad_mu2d, width, height)[v]
     denom[v] += 1.0
+    if abs_mu2d is not None:
+        accum_abs[v] += _ndc_norm(abs_mu2d, width, height)[v]
 
 
 def quat_rot(q):
@@ -54,31 +69,38 @@ def quat_rot(q):
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
 
 
-def decide(scene, accum, denom, prm: DensifyParams):
-    """Per primitive: 0 keep, 1 clone, 2 split, 3 prune."""
+def _mean(accum, denom):
     accum = np.asarray(accum, np.float32)
+    return np.where(denom > 0, accum / np.where(denom > 0, denom, 1), 0).astype(np.float32)
+
+
+def decide(scene, accum, denom, prm: DensifyParams, accum_abs=None):
+    """Per primitive: 0 keep, 1 clone, 2 split, 3 prune."""
     denom = np.asarray(denom, np.float32)
-    avg = np.where(denom > 0, accum / np.where(denom > 0, denom, 1), 0).astype(np.float32)
+    avg = _mean(accum, denom)
     smax = np.asarray(scene.scales, np.float32).max(1)
     sel = avg >= np.float32(prm.grad_threshold)
+    sel_split = sel
+    if prm.abs_grad_threshold > 0:
+        sel_split = sel | (_mean(accum_abs, denom) >= np.float32(prm.abs_grad_threshold))
     big = smax > np.float32(prm.percent_dense) * np.float32(prm.scene_extent)
     prune = np.asarray(scene.opacities, np.float32) < np.float32(prm.min_opacity)
     if prm.prune_big:
         prune |= smax > np.float32(prm.max_world_frac) * np.float32(prm.scene_extent)
     kind = np.zeros(scene.n, np.int64)
     kind[sel & ~big] = 1
-    kind[sel & big] = 2
+    kind[sel_split & big] = 2
     kind[prune] = 3
     return kind
 
 
-def densify(scene, accum, denom, normals, prm: DensifyParams):
+def densify(scene, accum, denom, normals, prm: DensifyParams, accum_abs=None):
     """Returns (new attribute dict, source index per output, child kind per
     output (0 original, 1 clone, 2 + c split child c)).  Output order: kept
     originals, then clone copies, then split children, each by ascending source
     index.  normals [n, split_count, 3] are the standard normal draws of the
     split children (passed in so that both implementations use the same)."""
-    kind = decide(scene, accum, denom, prm)
+    kind = decide(scene, accum, denom, prm, accum_abs)
     idx = np.arange(scene.n)
     kept = idx[(kind == 0) | (kind == 1)]
     clones = idx[kind == 1]

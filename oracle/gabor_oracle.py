@@ -51,6 +51,12 @@ ALPHA_MAX = 0.99
 T_MIN = 1e-4
 DILATION = 0.3
 TILE = 16
+# Plug-in anti-aliasing (Mip-Splatting, combined with 3DGabSplat in Sec. 4.1
+# and Table 1): the 2D filter replaces the dilation by a Gaussian of variance
+# 0.1 px^2 (a one-pixel box) and rescales the opacity so that the envelope's
+# integral is kept; the ratio det(S) / det(S + 0.1 I) is floored (a reading).
+MIP2D_VARIANCE = 0.1
+MIP2D_MIN_RATIO = 1e-6
 
 
 # --------------------------------------------------------------------------
@@ -168,6 +174,18 @@ def depth_fp32(means_f32: np.ndarray, R_f32: np.ndarray, t_f32: np.ndarray) -> n
     return ((a + b) + c) + t2
 
 
+def filtered_envelope(scales: torch.Tensor, opacities: torch.Tensor, variances):
+    """Mip-Splatting's 3D smoothing filter applied to the Gaussian envelope:
+    the envelope o exp(-x^T Sigma^-1 x / 2) convolved with the normalised
+    isotropic Gaussian of variance v is o' exp(-x^T Sigma'^-1 x / 2) with
+    Sigma' = Sigma + v I -- for Sigma = R diag(s^2) R^T, the scales
+    sqrt(s^2 + v) -- and o' = o sqrt(det Sigma / det Sigma') = o prod_j s_j /
+    sqrt(s_j^2 + v).  Returns (filtered scales, filtered opacities)."""
+    fv = torch.as_tensor(np.asarray(variances, np.float64), dtype=DT)
+    s_f = torch.sqrt(scales * scales + fv[:, None])
+    return s_f, opacities * torch.prod(scales / s_f, -1)
+
+
 @dataclass
 class Projected:
     visible: torch.Tensor       # [n] bool
@@ -186,7 +204,7 @@ class Projected:
 
 
 def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
-            attenuation: bool = False) -> Projected:
+            attenuation: bool = False, mip2d: bool = False, filter3d=None) -> Projected:
     """Per-primitive projection.  ``p`` holds fp64 tensors (possibly requiring
     grad); ``scene_f32`` supplies the float32 means/opacities for the fp32
     decisions (defaults to rounding p's values, which are exact copies).
@@ -195,7 +213,21 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
     produces for every cosine term and the paper's final 2D primitive drops:
     w_k -> w_k exp(-2 pi^2 v_k), v_k = f_k^T Sigma f_k - (T Sigma f_k)^T
     (T Sigma T^T)^-1 (T Sigma f_k), the variance of f_k . x along the ray
-    given the image-plane point (the DC weight 1 - sum w is unchanged)."""
+    given the image-plane point (the DC weight 1 - sum w is unchanged).
+
+    filter3d (per-primitive variances, see mip_filter3d) convolves the Gaussian
+    envelope with an isotropic 3D Gaussian of that variance: Sigma -> Sigma +
+    v I, i.e. every scale s -> sqrt(s^2 + v), and the opacity is multiplied by
+    sqrt(det Sigma / det(Sigma + v I)) = prod_j s_j / sqrt(s_j^2 + v), which
+    keeps the envelope's integral.  mip2d replaces the 0.3 px^2 dilation by the
+    2D filter (variance 0.1 px^2, opacity times sqrt(det S / det(S + 0.1 I)),
+    S the undilated 2D covariance).  Both act on the envelope only: the 3D
+    frequencies and weights are left as they are (the plug-in reading: the
+    Gaussian of the other method is replaced by the Gabor primitive and nothing
+    else changes), and the frequency projection, like every other use of
+    Sigma, sees the filtered covariance.  The near and opacity culls stay on
+    the input values; a primitive whose filtered opacity is at most 1/255 is
+    invisible."""
     R, t = cam["R"], cam["t"]
     fx, fy, cx, cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
     W, H = cam["W"], cam["H"]
@@ -213,6 +245,9 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
     tc = means @ R.T + t
     tx, ty, tz = tc.unbind(-1)
     depth32 = depth_fp32(m32, R32, t32)
+    scales, opac = p["scales"], p["opacities"]
+    if filter3d is not None:
+        scales, opac = filtered_envelope(scales, opac, filter3d)
     in_front = torch.from_numpy(depth32 > np.float32(cam["near"]))
     opac_ok = torch.from_numpy(o32 * np.float32(255.0) > np.float32(1.0))
 
@@ -231,11 +266,12 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
         torch.stack([zero, fy / tz_safe, -fy * tyc / (tz_safe * tz_safe)], -1),
     ], -2)                                   # [n,2,3]
     T = J2 @ R                               # first two rows of J W
-    Sig = covariance_3d(p["scales"], p["quats"])
+    Sig = covariance_3d(scales, p["quats"])
     cov_raw = T @ Sig @ T.transpose(-1, -2)  # [n,2,2]
-    a = cov_raw[:, 0, 0] + DILATION
+    dil = MIP2D_VARIANCE if mip2d else DILATION
+    a = cov_raw[:, 0, 0] + dil
     b = cov_raw[:, 0, 1]
-    c = cov_raw[:, 1, 1] + DILATION
+    c = cov_raw[:, 1, 1] + dil
     det = a * c - b * b
     det_ok = det > 0
     det_safe = torch.where(det_ok, det, torch.ones_like(det))
@@ -264,6 +300,11 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
         f2d = torch.zeros((n, 0, 2), dtype=DT)
         w_cos = p["weights"]
 
+    if mip2d:
+        det_r = cov_raw[:, 0, 0] * cov_raw[:, 1, 1] - cov_raw[:, 0, 1] ** 2
+        ratio = torch.clamp(det_r / det_safe, min=MIP2D_MIN_RATIO)
+        opac = opac * torch.sqrt(ratio)
+
     # colour
     if "sh" in p:
         rgb = sh_to_rgb(p["sh"], means, cam["eye"])
@@ -272,7 +313,7 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
 
     # support: o * G >= 1/255 inside the ellipse d^T conic d <= 2 ln(255 o)
     with torch.no_grad():
-        o64 = p["opacities"].detach()
+        o64 = opac.detach()
         kk = torch.sqrt(torch.clamp(2.0 * torch.log(255.0 * o64), min=0.0))
         rx = kk * torch.sqrt(torch.clamp(a.detach(), min=0.0))
         ry = kk * torch.sqrt(torch.clamp(c.detach(), min=0.0))
@@ -286,6 +327,9 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
             py1 = np.minimum(np.floor(by1), H - 1)
         ok = (px0 <= px1) & (py0 <= py1) & np.isfinite(bx0) & np.isfinite(by0)
         vis = in_front.numpy() & opac_ok.numpy() & det_ok.numpy() & ok
+        filtered = filter3d is not None or mip2d
+        if filtered:
+            vis &= (255.0 * o64).numpy() > 1.0
         rect = np.zeros((n, 4), np.int64)
         rect[vis, 0] = (px0[vis] // TILE).astype(np.int64)
         rect[vis, 1] = (py0[vis] // TILE).astype(np.int64)
@@ -297,9 +341,11 @@ def project(p: Dict[str, torch.Tensor], cam: Dict[str, object], scene_f32=None,
             with np.errstate(invalid="ignore"):
                 return np.abs(v - np.round(v)) < 2e-3
         fr = vis & (near_int(bx0) | near_int(bx1) | near_int(by0) | near_int(by1))
+        if filtered:  # the filtered-opacity test taken in fp32 may differ near 1/255
+            fr |= in_front.numpy() & opac_ok.numpy() & (np.abs(255.0 * o64.numpy() - 1.0) < 1e-4)
         fp = vis & cond_bad.numpy()
     pr = Projected(visible=torch.from_numpy(vis), depth32=depth32, mu2d=mu2d, cov2d_raw=cov_raw,
-                   conic=conic, opac=p["opacities"], rgb=rgb, f2d=f2d, w=w_cos,
+                   conic=conic, opac=opac, rgb=rgb, f2d=f2d, w=w_cos,
                    rect=rect, tiles=tiles.astype(np.int64), fragile_rect=fr, fragile_prim=fp)
     pr.w_dc = 1.0 - p["weights"].sum(-1)  # DC weight, never attenuated
     return pr
@@ -360,9 +406,12 @@ class PixelResult:
 
 
 def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Tensor,
-                 bg: torch.Tensor, tau_alpha=1e-4, tau_T=1e-3) -> PixelResult:
+                 bg: torch.Tensor, tau_alpha=1e-4, tau_T=1e-3, mu: Optional[torch.Tensor] = None) -> PixelResult:
     """Blend the candidates ``cand`` (already sorted front to back) at the
-    sample points (px, py), vectorised over pixels and candidates."""
+    sample points (px, py), vectorised over pixels and candidates.  ``mu``
+    ([P, m, 2], optional) gives every pixel its own copy of the candidates'
+    image-plane means (same values), so that a backward pass returns each
+    pixel's share of the mean gradient separately."""
     P = px.shape[0]
     m = len(cand)
     if m == 0:
@@ -370,10 +419,11 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
         return PixelResult(col, torch.ones(P, dtype=DT), -np.ones(P, np.int64),
                            np.zeros(P, np.int64), np.zeros(P, bool), torch.zeros(P, dtype=DT))
     ci = torch.from_numpy(np.asarray(cand, np.int64))
-    mu = pr.mu2d[ci]
+    if mu is None:
+        mu = pr.mu2d[ci]
     con = pr.conic[ci]
-    dx = px[:, None] - mu[None, :, 0]
-    dy = py[:, None] - mu[None, :, 1]
+    dx = px[:, None] - mu[..., 0]
+    dy = py[:, None] - mu[..., 1]
     G = torch.exp(-0.5 * (con[None, :, 0] * dx * dx + 2.0 * con[None, :, 1] * dx * dy
                           + con[None, :, 2] * dy * dy))
     w = pr.w[ci]
@@ -474,13 +524,13 @@ def tile_candidates(pr: Projected, order: np.ndarray, tx: int, ty: int) -> np.nd
 
 def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binned",
            tiles: Optional[Sequence[tuple]] = None, scene_f32=None, pr: Optional[Projected] = None,
-           chunk: int = 4096, attenuation: bool = False) -> Image:
+           chunk: int = 4096, attenuation: bool = False, mip2d: bool = False, filter3d=None) -> Image:
     """Render the whole image (or only the listed tiles; other pixels are NaN).
     mode 'brute': every visible primitive at every pixel; 'binned': per-tile
     candidate lists from the tile rects (exact culling: the rect covers every
     pixel where o G >= 1/255)."""
     if pr is None:
-        pr = project(p, cam, scene_f32, attenuation)
+        pr = project(p, cam, scene_f32, attenuation, mip2d, filter3d)
     W, H = cam["W"], cam["H"]
     bg = cam["bg"]
     order = depth_order(pr.depth32, pr.visible.numpy())
@@ -524,11 +574,11 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
                  nbl.reshape(H, W), frag.reshape(H, W), fm.reshape(H, W))
 
 
-def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False) -> Image:
+def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False, mip2d=False, filter3d=None) -> Image:
     """Convenience: numpy scene/camera objects -> fp64 image."""
     with torch.no_grad():
         return render(scene_tensors(scene), camera_tensors(cam), mode, tiles, scene_f32=scene,
-                      attenuation=attenuation)
+                      attenuation=attenuation, mip2d=mip2d, filter3d=filter3d)
 
 
 # --------------------------------------------------------------------------
@@ -537,14 +587,93 @@ def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False) -> Im
 GRAD_NAMES = ("means", "scales", "quats", "opacities", "colors", "sh", "freqs", "weights")
 
 
-def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned", attenuation=False) -> Dict[str, np.ndarray]:
+def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned", attenuation=False, mip2d=False,
+                 filter3d=None) -> Dict[str, np.ndarray]:
     """d(sum dl_dimage * C)/d(params) for every activated attribute (fp64)."""
     p = scene_tensors(scene, requires_grad=True)
     ct = camera_tensors(cam)
-    img = render(p, ct, mode, scene_f32=scene, attenuation=attenuation)
+    img = render(p, ct, mode, scene_f32=scene, attenuation=attenuation, mip2d=mip2d, filter3d=filter3d)
     g = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
     (img.color * g).sum().backward()
     return {k: v.grad.numpy() for k, v in p.items()}
+
+
+def mean2d_grads(scene, cam, dl_dimage: np.ndarray, attenuation=False, mip2d=False, filter3d=None):
+    """Per primitive, the gradient of L = sum(dl_dimage * C) with respect to
+    its image-plane mean (pixels), two ways: summed over pixels (the
+    view-space positional gradient that density control accumulates, Sec.
+    3.4.2), and as per-axis sums over pixels of the absolute per-pixel
+    gradients |dL_p / d mu2d| (the homodirectional gradient of AbsGS, the
+    densification variant that the paper combines with its primitive in Sec.
+    4.1 and Table 1).  Every pixel blends with its own copy of the means, so
+    autograd hands back each pixel's contribution separately.  Binned mode
+    (tile lists from the rects).  Returns (sum [n, 2], abs [n, 2])."""
+    ct = camera_tensors(cam)
+    with torch.no_grad():
+        pr = project(scene_tensors(scene), ct, scene, attenuation, mip2d, filter3d)
+    W, H = ct["W"], ct["H"]
+    order = depth_order(pr.depth32, pr.visible.numpy())
+    g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+    tot = np.zeros((scene.n, 2))
+    ab = np.zeros((scene.n, 2))
+    for ty in range((H + TILE - 1) // TILE):
+        for tx in range((W + TILE - 1) // TILE):
+            cand = tile_candidates(pr, order, tx, ty)
+            if len(cand) == 0:
+                continue
+            gx, gy = _tile_pixels(tx, ty, W, H)
+            mu = pr.mu2d[torch.from_numpy(cand)].detach()[None].expand(len(gx), -1, -1).clone()
+            mu.requires_grad_(True)
+            res = blend_pixels(pr, cand, torch.from_numpy(gx + 0.5).to(DT), torch.from_numpy(gy + 0.5).to(DT),
+                               ct["bg"], mu=mu)
+            gsel = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
+            (res.color * gsel).sum().backward()
+            gp = mu.grad.numpy()
+            np.add.at(tot, cand, gp.sum(0))
+            np.add.at(ab, cand, np.abs(gp).sum(0))
+    return tot, ab
+
+
+def mip_filter3d(means: np.ndarray, cams: Sequence, s: float = 0.2, margin: float = 0.15):
+    """Variance of the 3D smoothing filter of every primitive (Mip-Splatting's
+    3D filter, used with the Gabor primitive in Sec. 4.1 and Table 1).  The
+    sampling rate of a camera at a primitive is its focal length over the
+    primitive's depth, max(fx, fy) / z, counted for the cameras whose frustum
+    holds the mean (z > near plane, image point inside the image grown by
+    ``margin`` of its size on every side); with the largest rate r the filter
+    variance is s / r^2.  A primitive that no camera sees gets the largest
+    variance of the others (0 if none is seen).  Returns (variances [n],
+    fragile [n]: a frustum decision within rounding distance of its bound)."""
+    m = np.asarray(means, np.float64)
+    n = m.shape[0]
+    best = np.zeros(n)
+    seen = np.zeros(n, bool)
+    fragile = np.zeros(n, bool)
+    for cam in cams:
+        R = np.asarray(cam.R, np.float64)
+        t = np.asarray(cam.t, np.float64)
+        pc = m @ R.T + t
+        z = pc[:, 2]
+        front = z > cam.near
+        zs = np.where(front, z, 1.0)
+        x = cam.fx * pc[:, 0] / zs + cam.cx
+        y = cam.fy * pc[:, 1] / zs + cam.cy
+        lo_x, hi_x = -margin * cam.width, (1.0 + margin) * cam.width
+        lo_y, hi_y = -margin * cam.height, (1.0 + margin) * cam.height
+        inside = front & (x >= lo_x) & (x <= hi_x) & (y >= lo_y) & (y <= hi_y)
+        rate = max(cam.fx, cam.fy) / zs
+        best = np.where(inside, np.maximum(best, rate), best)
+        seen |= inside
+        tol = 1e-3 + 1e-5 * np.abs(x)
+        tol_y = 1e-3 + 1e-5 * np.abs(y)
+        fragile |= np.abs(z - cam.near) <= 1e-5 * max(1.0, abs(cam.near))
+        fragile |= front & ((np.abs(x - lo_x) <= tol) | (np.abs(x - hi_x) <= tol)
+                            | (np.abs(y - lo_y) <= tol_y) | (np.abs(y - hi_y) <= tol_y))
+    var = np.zeros(n)
+    var[seen] = s / best[seen] ** 2
+    if seen.any() and not seen.all():
+        var[~seen] = var[seen].max()
+    return var, fragile
 
 
 def _take(pr: Projected, rows: np.ndarray, local_i: int, one: Projected) -> Projected:
