@@ -959,7 +959,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     uint64_t* pa = reinterpret_cast<uint64_t*>(w + p.off_tcpair_a);
     uint64_t* pb = reinterpret_cast<uint64_t*>(w + p.off_tcpair_b);
     const int nt = p.total_tiles;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (size_t)C_COUNT);
+    // no counter clear: the tile scan writes the only counters this path reads
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
       hipLaunchKernelGGL(k_tc_colscan, dim3((unsigned)((nt + kColTiles - 1) / kColTiles)), dim3(256), 0, s, cnt, nt,
