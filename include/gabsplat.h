@@ -40,13 +40,17 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 1
+#define GABSPLAT_ABI_VERSION 2
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
 #define GABSPLAT_MAX_VIEWS 4096
 /* gabsplat_scene.flags */
 #define GABSPLAT_FLAG_ATTENUATION 1
+#define GABSPLAT_FLAG_MIP_2D 2
+#define GABSPLAT_FLAG_MIP_3D 4
+/* gabsplat_scene_grads.flags */
+#define GABSPLAT_GRAD_ABS_MEAN2D 1
 
 typedef enum {
   GABSPLAT_OK = 0,
@@ -74,6 +78,22 @@ typedef enum {
  *             produces (v_j the variance of f_j . x along the ray given the
  *             image point) and the paper's final 2D primitive (Sec. 3.3.2)
  *             drops; 0 reproduces the paper's primitive.
+ *             GABSPLAT_FLAG_MIP_3D and GABSPLAT_FLAG_MIP_2D: the anti-aliasing
+ *             filters of Mip-Splatting, which the paper combines with its
+ *             primitive (Sec. 4.1, Table 1).  They act on the Gaussian envelope
+ *             only.  MIP_3D convolves it with an isotropic 3D Gaussian of
+ *             variance filter3d[i]: every scale s becomes sqrt(s^2 + v) and the
+ *             opacity is multiplied by prod_j s_j / sqrt(s_j^2 + v), which keeps
+ *             the envelope's integral.  MIP_2D replaces the 0.3 px^2 dilation
+ *             with a 0.1 px^2 Gaussian and multiplies the opacity by
+ *             sqrt(max(det S / det(S + 0.1 I), 1e-6)), S the undilated 2D
+ *             covariance.  The near and opacity culls test the input opacity.
+ *             A filtered primitive whose opacity is at most 1/255 is culled.
+ *             The 3D frequencies and weights are not changed.  Gradients are
+ *             taken with respect to the unfiltered scales and opacity.
+ *   filter3d  [n] variance of the 3D filter (world units squared, >= 0), e.g.
+ *             from gabsplat_mip_filter3d; read only with GABSPLAT_FLAG_MIP_3D
+ *             (may be NULL otherwise).
  * Limits: 0 <= k <= GABSPLAT_MAX_K, sh_degree in [0, 3] when sh != NULL,
  * 0 <= n < 2^31.  All scenes of one call share k, the colour mode and flags. */
 typedef struct {
@@ -90,6 +110,7 @@ typedef struct {
   const float* colors;
   const float* freqs;
   const float* weights;
+  const float* filter3d;
 } gabsplat_scene;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point x
@@ -147,14 +168,19 @@ typedef struct {
  * ones get 0).  Entries may be NULL to skip that gradient (sh or colors must
  * match the scene's colour mode).  grad2d [items][gabsplat_grad2d_floats(k)]
  * is scratch that receives the image-plane gradients, i.e. the gradient with
- * respect to every field of the render record, in the record's order; the call
+ * respect to every field of the render record, in the record's order (row
+ * stride gabsplat_grad2d_stride(k, flags)).  With flags GABSPLAT_GRAD_ABS_MEAN2D
+ * the two floats after those fields receive, per item, the sums over pixels
+ * of the absolute per-pixel gradients |dL_p / d mu2d_x| and |dL_p / d mu2d_y|.
+ * This is the homodirectional gradient of AbsGS, the densification variant
+ * the paper combines with its primitive (Sec. 4.1, Table 1).  The call
  * first zeroes the rows of the items that touch a tile (geom->tiles != 0, the
  * only rows it writes or reads; other rows are left as they are), and those
  * rows may be read afterwards (e.g. the view-space positional gradient used
  * by density control).  All scenes of one call share the same grad2d buffer. */
 typedef struct {
   int32_t accumulate;
-  int32_t pad;
+  int32_t flags;
   float* means;
   float* scales;
   float* quats;
@@ -173,6 +199,9 @@ const char* gabsplat_status_string(gabsplat_status s);
 int32_t gabsplat_record_floats(int32_t k);
 /* Floats per item of the image-plane gradient: round_up(10 + 3k, 4). */
 int32_t gabsplat_grad2d_floats(int32_t k);
+/* Row stride of grad2d for gabsplat_scene_grads.flags: round_up(10 + 3k, 4),
+ * or round_up(12 + 3k, 4) with GABSPLAT_GRAD_ABS_MEAN2D; -1 if invalid. */
+int32_t gabsplat_grad2d_stride(int32_t k, int32_t grad_flags);
 /* Bytes for gabsplat_geom.views. */
 size_t gabsplat_views_bytes(int32_t num_views, int32_t num_scenes);
 /* Device workspace for gabsplat_bin_sort: `items` = total items, `pair_capacity`
@@ -294,6 +323,8 @@ typedef struct {
   float weight_reset;    /* every frequency weight of a new child (0.01) */
   float split_shrink;    /* child scale factor (1 / 1.6) */
   int32_t split_count;   /* children per split primitive (2), 1..8 */
+  float abs_grad_threshold; /* AbsGS: split also when the mean homodirectional
+                               statistic reaches it (e.g. 0.0004); <= 0: off */
 } gabsplat_densify_params;
 
 /* Writable scene buffers (same layout and meaning as gabsplat_scene). */
@@ -316,15 +347,20 @@ typedef struct {
 /* accum[i] += |dL/d mu2d| in normalised device coordinates (the pixel
  * gradient from grad2d scaled by (W/2, H/2)) and denom[i] += 1 for every view
  * of `geom` (one scene of n primitives, views as given to the preprocess that
- * wrote geom) in which primitive i is visible. */
+ * wrote geom) in which primitive i is visible.  grad_flags are the flags of
+ * the backward that wrote grad2d (its row stride); with
+ * GABSPLAT_GRAD_ABS_MEAN2D, accum_abs[i] also receives the norm of the
+ * homodirectional gradient in the same units (else accum_abs may be NULL). */
 gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat_camera* cams,
-                                       int32_t num_views, int64_t n, const float* grad2d, float* accum,
-                                       float* denom, void* stream);
+                                       int32_t num_views, int64_t n, const float* grad2d, int32_t grad_flags,
+                                       float* accum, float* accum_abs, float* denom, void* stream);
 
 /* Clone / split / prune.  Decision per primitive, in order: prune if opacity <
  * min_opacity (or too large, with prune_big); else clone if accum/denom >=
  * grad_threshold and max scale <= percent_dense * extent; split if the
- * threshold is met and the primitive is larger; keep otherwise.  Output rows:
+ * primitive is larger and the threshold is met, or, with abs_grad_threshold >
+ * 0, accum_abs/denom >= abs_grad_threshold (accum_abs then required, else it
+ * may be NULL); keep otherwise.  Output rows:
  * kept and cloned primitives unchanged (ascending source index), then one copy
  * of each cloned primitive, then split_count children of each split primitive
  * with mean + R(q)(s * z_c) (z_c = normals[c][.][i], standard normal draws
@@ -337,7 +373,7 @@ gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat
  * written) if n_out > out_capacity.  ws >= gabsplat_densify_workspace_size(n). */
 size_t gabsplat_densify_workspace_size(int64_t n);
 gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, const float* denom,
-                                 const float* normals, const gabsplat_densify_params* params,
+                                 const float* accum_abs, const float* normals, const gabsplat_densify_params* params,
                                  const gabsplat_scene_out* out, int64_t out_capacity, uint32_t* src_index,
                                  uint32_t* tag, int64_t* d_n_out, int32_t* d_overflow, void* ws,
                                  size_t ws_bytes, void* stream);
@@ -346,6 +382,20 @@ gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, c
  * min(opacity, opacity_cap). */
 gabsplat_status gabsplat_reset_frequency_weights(const gabsplat_scene_out* scene, float weight_value,
                                                  float opacity_cap, void* stream);
+
+/* Variance of Mip-Splatting's 3D smoothing filter for every primitive (the
+ * anti-aliasing the paper combines with its primitive, Sec. 4.1, Table 1).
+ * The sampling rate of camera c at primitive i is max(fx, fy) / z, counted for
+ * the cameras with z > near_plane whose image, grown by `margin` of its width
+ * and height on every side, holds the projected mean.  With r the largest rate,
+ * filter3d[i] = s / r^2.  Primitives that no camera sees get the largest
+ * variance of the others (0 if no primitive is seen).
+ *   means [3][n] (device), cams[num_cams] (host), s e.g. 0.2, margin e.g. 0.15,
+ *   filter3d [n] (device, output), ws >= gabsplat_mip_filter3d_workspace_size. */
+size_t gabsplat_mip_filter3d_workspace_size(int64_t n, int32_t num_cams);
+gabsplat_status gabsplat_mip_filter3d(const float* means, int64_t n, const gabsplat_camera* cams,
+                                      int32_t num_cams, float s, float margin, float* filter3d, void* ws,
+                                      size_t ws_bytes, void* stream);
 
 /* Reads *d_overflow synchronously (waits for `stream`); returns
  * GABSPLAT_ERR_CAPACITY_EXCEEDED if it is set, GABSPLAT_OK otherwise. */

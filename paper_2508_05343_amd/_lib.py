@@ -22,11 +22,15 @@ EXPORTS = (
     "gabsplat_preprocess", "gabsplat_bin_sort", "gabsplat_render_fwd", "gabsplat_render_bwd",
     "gabsplat_loss_workspace_size", "gabsplat_loss_l1_dssim", "gabsplat_read_overflow",
     "gabsplat_densify_stats", "gabsplat_densify_workspace_size", "gabsplat_densify",
-    "gabsplat_reset_frequency_weights",
+    "gabsplat_reset_frequency_weights", "gabsplat_grad2d_stride", "gabsplat_mip_filter3d_workspace_size",
+    "gabsplat_mip_filter3d",
 )
 
 OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE = range(6)
 FLAG_ATTENUATION = 1
+FLAG_MIP_2D = 2
+FLAG_MIP_3D = 4
+GRAD_ABS_MEAN2D = 1
 
 
 class GabsplatError(RuntimeError):
@@ -38,7 +42,8 @@ class GabsplatError(RuntimeError):
 class Scene(ctypes.Structure):
     _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32), ("flags", c_int32), ("pad", c_int32),
                 ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
-                ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p)]
+                ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p),
+                ("filter3d", c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -53,7 +58,7 @@ class Geom(ctypes.Structure):
 
 
 class SceneGrads(ctypes.Structure):
-    _fields_ = [("accumulate", c_int32), ("pad", c_int32), ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+    _fields_ = [("accumulate", c_int32), ("flags", c_int32), ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
                 ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p),
                 ("grad2d", c_void_p)]
 
@@ -62,7 +67,7 @@ class DensifyParams(ctypes.Structure):
     _fields_ = [("grad_threshold", c_float), ("percent_dense", c_float), ("scene_extent", c_float),
                 ("min_opacity", c_float), ("max_world_frac", c_float), ("prune_big", c_int32),
                 ("freq_reset", c_float), ("weight_reset", c_float), ("split_shrink", c_float),
-                ("split_count", c_int32)]
+                ("split_count", c_int32), ("abs_grad_threshold", c_float)]
 
 
 class SceneOut(ctypes.Structure):
@@ -89,6 +94,8 @@ def lib() -> ctypes.CDLL:
     L.gabsplat_record_floats.argtypes = [c_int32]
     L.gabsplat_grad2d_floats.restype = c_int32
     L.gabsplat_grad2d_floats.argtypes = [c_int32]
+    L.gabsplat_grad2d_stride.restype = c_int32
+    L.gabsplat_grad2d_stride.argtypes = [c_int32, c_int32]
     L.gabsplat_views_bytes.restype = c_size_t
     L.gabsplat_views_bytes.argtypes = [c_int32, c_int32]
     L.gabsplat_bin_sort_workspace_size.restype = c_size_t
@@ -115,16 +122,21 @@ def lib() -> ctypes.CDLL:
     L.gabsplat_read_overflow.restype = c_int32
     L.gabsplat_read_overflow.argtypes = [c_void_p, c_void_p]
     L.gabsplat_densify_stats.restype = c_int32
-    L.gabsplat_densify_stats.argtypes = [POINTER(Geom), POINTER(Camera), c_int32, c_int64, c_void_p, c_void_p,
-                                         c_void_p, c_void_p]
+    L.gabsplat_densify_stats.argtypes = [POINTER(Geom), POINTER(Camera), c_int32, c_int64, c_void_p, c_int32,
+                                         c_void_p, c_void_p, c_void_p, c_void_p]
     L.gabsplat_densify_workspace_size.restype = c_size_t
     L.gabsplat_densify_workspace_size.argtypes = [c_int64]
     L.gabsplat_densify.restype = c_int32
-    L.gabsplat_densify.argtypes = [POINTER(Scene), c_void_p, c_void_p, c_void_p, POINTER(DensifyParams),
+    L.gabsplat_densify.argtypes = [POINTER(Scene), c_void_p, c_void_p, c_void_p, c_void_p, POINTER(DensifyParams),
                                    POINTER(SceneOut), c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_size_t, c_void_p]
     L.gabsplat_reset_frequency_weights.restype = c_int32
     L.gabsplat_reset_frequency_weights.argtypes = [POINTER(SceneOut), c_float, c_float, c_void_p]
+    L.gabsplat_mip_filter3d_workspace_size.restype = c_size_t
+    L.gabsplat_mip_filter3d_workspace_size.argtypes = [c_int64, c_int32]
+    L.gabsplat_mip_filter3d.restype = c_int32
+    L.gabsplat_mip_filter3d.argtypes = [c_void_p, c_int64, POINTER(Camera), c_int32, c_float, c_float, c_void_p,
+                                        c_void_p, c_size_t, c_void_p]
     _LIB = L
     return L
 
@@ -164,6 +176,10 @@ def gabsplat_record_floats(k: int) -> int:
 
 def gabsplat_grad2d_floats(k: int) -> int:
     return int(lib().gabsplat_grad2d_floats(k))
+
+
+def gabsplat_grad2d_stride(k: int, grad_flags: int) -> int:
+    return int(lib().gabsplat_grad2d_stride(k, grad_flags))
 
 
 def gabsplat_views_bytes(num_views: int, num_scenes: int) -> int:
@@ -227,19 +243,20 @@ def gabsplat_loss_l1_dssim(x, y, lam: float, d_loss, dl_dx, ws, stream=None):
            "gabsplat_loss_l1_dssim")
 
 
-def gabsplat_densify_stats(geom: Geom, cams: Sequence[Camera], n: int, grad2d, accum, denom, stream=None):
+def gabsplat_densify_stats(geom: Geom, cams: Sequence[Camera], n: int, grad2d, grad_flags: int, accum, accum_abs,
+                           denom, stream=None):
     ca = _arr(Camera, cams)
-    _check(lib().gabsplat_densify_stats(ctypes.byref(geom), ca, len(cams), n, ptr(grad2d), ptr(accum), ptr(denom),
-                                        stream_handle(stream)), "gabsplat_densify_stats")
+    _check(lib().gabsplat_densify_stats(ctypes.byref(geom), ca, len(cams), n, ptr(grad2d), grad_flags, ptr(accum),
+                                        ptr(accum_abs), ptr(denom), stream_handle(stream)), "gabsplat_densify_stats")
 
 
 def gabsplat_densify_workspace_size(n: int) -> int:
     return int(lib().gabsplat_densify_workspace_size(n))
 
 
-def gabsplat_densify(scene_in: Scene, accum, denom, normals, params: DensifyParams, out: SceneOut,
+def gabsplat_densify(scene_in: Scene, accum, denom, accum_abs, normals, params: DensifyParams, out: SceneOut,
                      out_capacity: int, src_index, tag, d_n_out, d_overflow, ws, stream=None):
-    _check(lib().gabsplat_densify(ctypes.byref(scene_in), ptr(accum), ptr(denom), ptr(normals),
+    _check(lib().gabsplat_densify(ctypes.byref(scene_in), ptr(accum), ptr(denom), ptr(accum_abs), ptr(normals),
                                   ctypes.byref(params), ctypes.byref(out), out_capacity, ptr(src_index), ptr(tag),
                                   ptr(d_n_out), ptr(d_overflow), ptr(ws), ws.numel() * ws.element_size(),
                                   stream_handle(stream)), "gabsplat_densify")
@@ -248,6 +265,17 @@ def gabsplat_densify(scene_in: Scene, accum, denom, normals, params: DensifyPara
 def gabsplat_reset_frequency_weights(scene: SceneOut, weight_value: float, opacity_cap: float, stream=None):
     _check(lib().gabsplat_reset_frequency_weights(ctypes.byref(scene), float(weight_value), float(opacity_cap),
                                                   stream_handle(stream)), "gabsplat_reset_frequency_weights")
+
+
+def gabsplat_mip_filter3d_workspace_size(n: int, num_cams: int) -> int:
+    return int(lib().gabsplat_mip_filter3d_workspace_size(n, num_cams))
+
+
+def gabsplat_mip_filter3d(means, n: int, cams: Sequence[Camera], s: float, margin: float, filter3d, ws,
+                          stream=None):
+    ca = _arr(Camera, cams)
+    _check(lib().gabsplat_mip_filter3d(ptr(means), n, ca, len(cams), float(s), float(margin), ptr(filter3d), ptr(ws),
+                                       ws.numel() * ws.element_size(), stream_handle(stream)), "gabsplat_mip_filter3d")
 
 
 def gabsplat_read_overflow(d_overflow, stream=None) -> bool:

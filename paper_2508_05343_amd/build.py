@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgabsplat.so")
-SOURCES = ("api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "densify.hip")
+SOURCES = ("api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "densify.hip", "mipfilter.hip")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

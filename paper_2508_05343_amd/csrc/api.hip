@@ -32,11 +32,17 @@ hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s) {
   std::memcpy(p + sizeof(ViewTableHeader), h.views, sizeof(ViewEntry) * h.hdr.num_views);
   std::memcpy(p + sizeof(ViewTableHeader) + sizeof(ViewEntry) * h.hdr.num_views, h.scenes,
               sizeof(SceneEntry) * h.hdr.num_scenes);
-  uint32_t* dst = static_cast<uint32_t*>(d_table);
-  for (size_t off = 0; off < buf.size(); off += kChunkWords) {
+  return upload_words(d_table, buf.data(), buf.size() * 4, s);
+}
+
+hipError_t upload_words(void* d_dst, const void* h_src, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  uint32_t* dst = static_cast<uint32_t*>(d_dst);
+  const uint32_t* src = static_cast<const uint32_t*>(h_src);
+  for (size_t off = 0; off < words; off += kChunkWords) {
     WordChunk c;
-    c.n = (uint32_t)((buf.size() - off) < (size_t)kChunkWords ? (buf.size() - off) : (size_t)kChunkWords);
-    std::memcpy(c.w, buf.data() + off, c.n * 4);
+    c.n = (uint32_t)((words - off) < (size_t)kChunkWords ? (words - off) : (size_t)kChunkWords);
+    std::memcpy(c.w, src + off, c.n * 4);
     hipLaunchKernelGGL(k_store_words, dim3(1), dim3(256), 0, s, dst + off, c);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -71,6 +77,7 @@ bool valid_scene(const gabsplat_scene& s) {
   if ((s.sh == nullptr) == (s.colors == nullptr)) return false;
   if (s.sh && (s.sh_degree < 0 || s.sh_degree > GABSPLAT_MAX_SH_DEGREE)) return false;
   if (s.k > 0 && (!s.freqs || !s.weights)) return false;
+  if ((s.flags & GABSPLAT_FLAG_MIP_3D) && !s.filter3d) return false;
   return true;
 }
 
@@ -95,11 +102,12 @@ gabsplat_status build_table(const gabsplat_scene* scenes, int32_t num_scenes, co
     const gabsplat_scene& s = scenes[i];
     if (!valid_scene(s)) return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (s.k != k || (s.sh != nullptr) != use_sh || (use_sh && s.sh_degree != deg) || s.flags != flags ||
-        (s.flags & ~GABSPLAT_FLAG_ATTENUATION) != 0)
+        (s.flags & ~(GABSPLAT_FLAG_ATTENUATION | GABSPLAT_FLAG_MIP_2D | GABSPLAT_FLAG_MIP_3D)) != 0)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     SceneEntry& e = tb.scenes[i];
     e.means = s.means; e.scales = s.scales; e.quats = s.quats; e.opac = s.opacities;
     e.sh = s.sh; e.colors = s.colors; e.freqs = s.freqs; e.weights = s.weights;
+    e.filter3d = (s.flags & GABSPLAT_FLAG_MIP_3D) ? s.filter3d : nullptr;
     e.n = s.n; e.k = s.k; e.sh_degree = deg; e.flags = s.flags; e.pad = 0;
   }
   tb.views.resize(num_views);
@@ -166,6 +174,10 @@ const char* gabsplat_status_string(gabsplat_status s) {
 
 int32_t gabsplat_record_floats(int32_t k) { return (k < 0 || k > GABSPLAT_MAX_K) ? -1 : record_floats(k); }
 int32_t gabsplat_grad2d_floats(int32_t k) { return (k < 0 || k > GABSPLAT_MAX_K) ? -1 : grad2d_floats(k); }
+int32_t gabsplat_grad2d_stride(int32_t k, int32_t grad_flags) {
+  if (k < 0 || k > GABSPLAT_MAX_K || (grad_flags & ~GABSPLAT_GRAD_ABS_MEAN2D) != 0) return -1;
+  return grad2d_stride(k, grad_flags);
+}
 
 size_t gabsplat_views_bytes(int32_t num_views, int32_t num_scenes) {
   if (num_views < 0 || num_scenes < 0) return 0;
@@ -271,7 +283,8 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
     if (tb.scenes[0].k != geom->k) return GABSPLAT_ERR_INVALID_ARGUMENT;
     for (int i = 0; i < num_scenes; ++i) {
       const gabsplat_scene_grads& g = grads[i];
-      if (!g.grad2d) return GABSPLAT_ERR_INVALID_ARGUMENT;
+      if (!g.grad2d || (g.flags & ~GABSPLAT_GRAD_ABS_MEAN2D) != 0 || g.flags != grads[0].flags)
+        return GABSPLAT_ERR_INVALID_ARGUMENT;
       if (scenes[i].sh && g.colors) return GABSPLAT_ERR_INVALID_ARGUMENT;
       if (scenes[i].colors && g.sh) return GABSPLAT_ERR_INVALID_ARGUMENT;
       if (i > 0 && g.grad2d != grads[0].grad2d) return GABSPLAT_ERR_INVALID_ARGUMENT;
@@ -279,10 +292,12 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
     if (tb.hdr.total_tiles > 0 && !vals) return GABSPLAT_ERR_INVALID_ARGUMENT;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HostTable h = tb.host();
-    hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items, grad2d_floats(geom->k), s);
+    const bool abs_mean2d = (grads[0].flags & GABSPLAT_GRAD_ABS_MEAN2D) != 0;
+    hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items,
+                                       grad2d_stride(geom->k, grads[0].flags), s);
     if (e != hipSuccess) return GABSPLAT_ERR_HIP;
-    e = launch_render_bwd(geom->views, h, *geom, geom->k, vals, tile_ranges, final_T, n_contrib,
-                                     dl_dimage, grads[0].grad2d, d_overflow, s);
+    e = launch_render_bwd(geom->views, h, *geom, geom->k, vals, tile_ranges, final_T, n_contrib, dl_dimage,
+                          grads[0].grad2d, abs_mean2d, d_overflow, s);
     if (e != hipSuccess) return GABSPLAT_ERR_HIP;
     for (int i = 0; i < num_scenes; ++i) {
       e = launch_preprocess_bwd(geom->views, h, *geom, i, grads[i], d_overflow, s);

@@ -1,7 +1,10 @@
 // Frequency-adaptive density control (Sec. 3.4.2): view-space gradient
 // statistics, clone / split / prune with the frequencies and frequency weights
 // of every new child reset to small values, and the periodic reset of all
-// frequency weights together with the opacity reset.
+// frequency weights together with the opacity reset.  With the AbsGS variant
+// (the densification the paper combines with its primitive, Sec. 4.1) a second
+// statistic, the norm of the per-axis sums of absolute per-pixel mean
+// gradients, can also trigger splits.
 //
 // Densification keeps a stable output order (kept primitives, then clone
 // copies, then split children, each by ascending source index) with three
@@ -19,25 +22,35 @@ constexpr int kDenBlock = 256 * kDenItems;
 
 // --------------------------------------------------------------- statistics
 // accum[i] += |dL/d mu2d| in normalised device coordinates (pixel gradient
-// times (W/2, H/2)), denom[i] += 1, for every view in which i is visible.
+// times (W/2, H/2)), denom[i] += 1, for every view in which i is visible; with
+// abs_col >= 0 also accum_abs[i] += the norm of grad2d columns abs_col and
+// abs_col + 1 (the per-axis absolute sums) in the same units.
 __global__ __launch_bounds__(256) void k_densify_stats(const void* __restrict__ table, int64_t n,
                                                        const uint32_t* __restrict__ tiles,
-                                                       const float* __restrict__ grad2d, int gf,
-                                                       float* __restrict__ accum, float* __restrict__ denom) {
+                                                       const float* __restrict__ grad2d, int gf, int abs_col,
+                                                       float* __restrict__ accum, float* __restrict__ accum_abs,
+                                                       float* __restrict__ denom) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
-  float a = 0.f, d = 0.f;
+  float a = 0.f, aa = 0.f, d = 0.f;
   for (int v = 0; v < hdr->num_views; ++v) {
     const int64_t item = views[v].item_offset + i;
     if (tiles[item] == 0) continue;
-    const float gx = grad2d[item * gf] * 0.5f * (float)views[v].width;
-    const float gy = grad2d[item * gf + 1] * 0.5f * (float)views[v].height;
+    const float hw = 0.5f * (float)views[v].width, hh = 0.5f * (float)views[v].height;
+    const float gx = grad2d[item * gf] * hw;
+    const float gy = grad2d[item * gf + 1] * hh;
     a += sqrtf(gx * gx + gy * gy);
+    if (abs_col >= 0) {
+      const float ax = grad2d[item * gf + abs_col] * hw;
+      const float ay = grad2d[item * gf + abs_col + 1] * hh;
+      aa += sqrtf(ax * ax + ay * ay);
+    }
     d += 1.f;
   }
   accum[i] += a;
+  if (abs_col >= 0) accum_abs[i] += aa;
   denom[i] += d;
 }
 
@@ -45,7 +58,7 @@ __global__ __launch_bounds__(256) void k_densify_stats(const void* __restrict__ 
 enum { KIND_KEEP = 0, KIND_CLONE = 1, KIND_SPLIT = 2, KIND_PRUNE = 3 };
 
 __device__ __forceinline__ int densify_kind(const gabsplat_scene& in, const float* accum, const float* denom,
-                                            const gabsplat_densify_params& p, int64_t i) {
+                                            const float* accum_abs, const gabsplat_densify_params& p, int64_t i) {
   const int64_t n = in.n;
   const float dn = denom[i];
   const float avg = dn > 0.f ? accum[i] / dn : 0.f;
@@ -54,13 +67,17 @@ __device__ __forceinline__ int densify_kind(const gabsplat_scene& in, const floa
   bool prune = o < p.min_opacity;
   if (p.prune_big) prune = prune || smax > p.max_world_frac * p.scene_extent;
   if (prune) return KIND_PRUNE;
-  if (avg >= p.grad_threshold) return smax > p.percent_dense * p.scene_extent ? KIND_SPLIT : KIND_CLONE;
+  const bool big = smax > p.percent_dense * p.scene_extent;
+  bool sel = avg >= p.grad_threshold;
+  if (big && !sel && p.abs_grad_threshold > 0.f) sel = (dn > 0.f ? accum_abs[i] / dn : 0.f) >= p.abs_grad_threshold;
+  if (sel) return big ? KIND_SPLIT : KIND_CLONE;
   return KIND_KEEP;
 }
 
 // counts[b][3]: kept (keep + clone), clone, split of block b
 __global__ __launch_bounds__(256) void k_densify_count(gabsplat_scene in, const float* __restrict__ accum,
-                                                       const float* __restrict__ denom, gabsplat_densify_params p,
+                                                       const float* __restrict__ denom,
+                                                       const float* __restrict__ accum_abs, gabsplat_densify_params p,
                                                        uint32_t* __restrict__ counts) {
   __shared__ uint32_t s_c[3];
   if (threadIdx.x < 3) s_c[threadIdx.x] = 0;
@@ -70,7 +87,7 @@ __global__ __launch_bounds__(256) void k_densify_count(gabsplat_scene in, const 
   for (int j = 0; j < kDenItems; ++j) {
     const int64_t i = (int64_t)blockIdx.x * kDenBlock + j * 256 + threadIdx.x;
     if (i >= in.n) continue;
-    const int k = densify_kind(in, accum, denom, p, i);
+    const int k = densify_kind(in, accum, denom, accum_abs, p, i);
     kept += (k == KIND_KEEP || k == KIND_CLONE);
     clone += (k == KIND_CLONE);
     split += (k == KIND_SPLIT);
@@ -131,6 +148,7 @@ __device__ __forceinline__ void copy_attrs(const gabsplat_scene& in, const gabsp
 
 __global__ __launch_bounds__(256) void k_densify_write(gabsplat_scene in, const float* __restrict__ accum,
                                                        const float* __restrict__ denom,
+                                                       const float* __restrict__ accum_abs,
                                                        const float* __restrict__ normals, gabsplat_densify_params p,
                                                        const uint32_t* __restrict__ counts,
                                                        const uint32_t* __restrict__ totals, gabsplat_scene_out out,
@@ -147,7 +165,7 @@ __global__ __launch_bounds__(256) void k_densify_write(gabsplat_scene in, const 
   for (int j = 0; j < kDenItems; ++j) {
     // blocked within the block so that a thread's items are consecutive
     const int64_t i = (int64_t)blockIdx.x * kDenBlock + t * kDenItems + j;
-    kind[j] = i < n ? densify_kind(in, accum, denom, p, i) : KIND_PRUNE;
+    kind[j] = i < n ? densify_kind(in, accum, denom, accum_abs, p, i) : KIND_PRUNE;
     ck += (kind[j] == KIND_KEEP || kind[j] == KIND_CLONE);
     cc += (kind[j] == KIND_CLONE);
     cs += (kind[j] == KIND_SPLIT);
@@ -213,15 +231,19 @@ using namespace gs;
 extern "C" {
 
 gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat_camera* cams, int32_t num_views,
-                                       int64_t n, const float* grad2d, float* accum, float* denom, void* stream) {
+                                       int64_t n, const float* grad2d, int32_t grad_flags, float* accum,
+                                       float* accum_abs, float* denom, void* stream) {
   try {
+    const bool abs_stat = (grad_flags & GABSPLAT_GRAD_ABS_MEAN2D) != 0;
     if (!geom || !geom->views || !geom->tiles || !cams || num_views < 1 || n < 0 || n >= (1ll << 31) ||
-        !grad2d || !accum || !denom || geom->k < 0 || geom->k > GABSPLAT_MAX_K)
+        !grad2d || !accum || !denom || geom->k < 0 || geom->k > GABSPLAT_MAX_K ||
+        (grad_flags & ~GABSPLAT_GRAD_ABS_MEAN2D) != 0 || (abs_stat && !accum_abs))
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (n == 0) return GABSPLAT_OK;
     hipLaunchKernelGGL(k_densify_stats, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), geom->views, n, geom->tiles, grad2d, grad2d_floats(geom->k),
-                       accum, denom);
+                       static_cast<hipStream_t>(stream), geom->views, n, geom->tiles, grad2d,
+                       grad2d_stride(geom->k, grad_flags), abs_stat ? 10 + 3 * geom->k : -1, accum, accum_abs,
+                       denom);
     return hipGetLastError() == hipSuccess ? GABSPLAT_OK : GABSPLAT_ERR_HIP;
   } catch (...) {
     return GABSPLAT_ERR_HIP;
@@ -234,7 +256,7 @@ size_t gabsplat_densify_workspace_size(int64_t n) {
 }
 
 gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, const float* denom,
-                                 const float* normals, const gabsplat_densify_params* prm,
+                                 const float* accum_abs, const float* normals, const gabsplat_densify_params* prm,
                                  const gabsplat_scene_out* out, int64_t out_capacity, uint32_t* src_index,
                                  uint32_t* tag, int64_t* d_n_out, int32_t* d_overflow, void* ws, size_t ws_bytes,
                                  void* stream) {
@@ -248,18 +270,20 @@ gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, c
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (out->k != in->k || (out->sh == nullptr) != (in->sh == nullptr) || !src_index || !tag)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
+    if (in->n > 0 && prm->abs_grad_threshold > 0.f && !accum_abs) return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (!ws || ws_bytes < gabsplat_densify_workspace_size(in->n)) return GABSPLAT_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nblocks = (int)((in->n + kDenBlock - 1) / kDenBlock);
     uint32_t* counts = static_cast<uint32_t*>(ws);
     uint32_t* totals = counts + 3 * (size_t)(nblocks + 1);
     if (nblocks > 0)
-      hipLaunchKernelGGL(k_densify_count, dim3(nblocks), dim3(256), 0, s, *in, accum, denom, *prm, counts);
+      hipLaunchKernelGGL(k_densify_count, dim3(nblocks), dim3(256), 0, s, *in, accum, denom, accum_abs, *prm,
+                         counts);
     hipLaunchKernelGGL(k_densify_scan, dim3(1), dim3(256), 0, s, counts, nblocks, prm->split_count, out_capacity,
                        totals, d_n_out, d_overflow);
     if (nblocks > 0)
-      hipLaunchKernelGGL(k_densify_write, dim3(nblocks), dim3(256), 0, s, *in, accum, denom, normals, *prm, counts,
-                         totals, *out, src_index, tag);
+      hipLaunchKernelGGL(k_densify_write, dim3(nblocks), dim3(256), 0, s, *in, accum, denom, accum_abs, normals,
+                         *prm, counts, totals, *out, src_index, tag);
     return hipGetLastError() == hipSuccess ? GABSPLAT_OK : GABSPLAT_ERR_HIP;
   } catch (...) {
     return GABSPLAT_ERR_HIP;

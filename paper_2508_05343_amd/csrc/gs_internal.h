@@ -14,6 +14,8 @@ constexpr float kAlphaMin = 1.0f / 255.0f;     // skip threshold on alpha
 constexpr float kAlphaMax = 0.99f;             // alpha clamp
 constexpr float kTMin = 1e-4f;                 // transmittance stop
 constexpr float kDilation = 0.3f;              // px^2 added to the 2D covariance
+constexpr float kMip2dVariance = 0.1f;         // px^2 of the 2D anti-aliasing filter
+constexpr float kMip2dMinRatio = 1e-6f;        // floor of det S / det(S + 0.1 I)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 // log2(1/255): o G < 1/255  <=>  q + log2 o < kLog2AlphaMin
@@ -29,6 +31,7 @@ struct SceneEntry {
   const float* colors;
   const float* freqs;
   const float* weights;
+  const float* filter3d;  // [n] 3D filter variance (GABSPLAT_FLAG_MIP_3D)
   int64_t n;
   int32_t k;
   int32_t sh_degree;  // -1 for precomputed colours
@@ -74,7 +77,10 @@ __host__ __device__ inline const SceneEntry* table_scenes(const void* t, int num
 }
 
 inline int record_floats(int k) { return (10 + 3 * k + 3) & ~3; }
-inline int grad2d_floats(int k) { return (10 + 3 * k + 3) & ~3; }
+__host__ __device__ inline int grad2d_floats(int k) { return (10 + 3 * k + 3) & ~3; }
+__host__ __device__ inline int grad2d_stride(int k, int grad_flags) {
+  return (grad_flags & GABSPLAT_GRAD_ABS_MEAN2D) ? (12 + 3 * k + 3) & ~3 : grad2d_floats(k);
+}
 
 // Host-side packed copy of the table (built by the API layer).
 struct HostTable {
@@ -85,6 +91,9 @@ struct HostTable {
 
 // --- launchers (each returns hipSuccess or the first launch error) ---------
 hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s);
+// Copies `bytes` (a multiple of 4) of host memory to device memory with small
+// kernels whose arguments carry the data (no copy engine, no host sync).
+hipError_t upload_words(void* d_dst, const void* h_src, size_t bytes, hipStream_t s);
 
 hipError_t launch_preprocess(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                              hipStream_t s);
@@ -114,7 +123,7 @@ hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabs
 hipError_t launch_render_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                              int k, const uint32_t* vals, const uint32_t* ranges,
                              const float* final_T, const uint32_t* n_contrib, const float* dl_dimage,
-                             float* grad2d, const int32_t* d_overflow, hipStream_t s);
+                             float* grad2d, bool abs_mean2d, const int32_t* d_overflow, hipStream_t s);
 
 hipError_t launch_preprocess_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                                  int scene_index, const gabsplat_scene_grads& gr,

@@ -115,9 +115,10 @@ __device__ __forceinline__ float depth_key(const float* R, const float* t, float
   return __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(R[6], x), __fmul_rn(R[7], y)), __fmul_rn(R[8], z)), t[2]);
 }
 
-// Geometry of one item; `tz` is the fp32 depth key.
+// Geometry of one item; `tz` is the fp32 depth key, `dil` the px^2 added to
+// the 2D covariance (the 0.3 dilation, or the 0.1 anti-aliasing filter).
 __device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my, float mz, float tz,
-                                         const float* q, const float* s, Geo& g) {
+                                         const float* q, const float* s, float dil, Geo& g) {
   const float* R = V.R;
   g.tx = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
   g.ty = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
@@ -170,11 +171,11 @@ __device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my,
   g.rc = dot3(g.r1, g.r1);
   g.c = cross3(g.r0, g.r1);
   g.D = dot3(g.c, g.c);
-  g.det = g.D + kDilation * (g.ra + g.rc) + kDilation * kDilation;
+  g.det = g.D + dil * (g.ra + g.rc) + dil * dil;
   const float idet = 1.0f / g.det;
-  g.conic[0] = (g.rc + kDilation) * idet;
+  g.conic[0] = (g.rc + dil) * idet;
   g.conic[1] = -g.rb * idet;
-  g.conic[2] = (g.ra + kDilation) * idet;
+  g.conic[2] = (g.ra + dil) * idet;
   g.ux_ = cross3(g.r1, g.c);
   g.uy_ = cross3(g.c, g.r0);
   if (g.D > 0.f) {
@@ -243,6 +244,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
   if (base >= n) return;
   const int t = threadIdx.x;
   const float Wf = (float)V.width, Hf = (float)V.height;
+  const bool mip3d = (S.flags & GABSPLAT_FLAG_MIP_3D) != 0;
+  const bool mip2d = (S.flags & GABSPLAT_FLAG_MIP_2D) != 0;
+  const float dil = mip2d ? kMip2dVariance : kDilation;
 
   // ---- phase 1
   uint32_t cand = 0;
@@ -257,7 +261,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     const float o = S.opac[i];
     bool ok = (tz > V.near_plane) && (o * 255.0f > 1.0f);
     if (ok) {
-      const float smax = fmaxf(fmaxf(S.scales[i], S.scales[n + i]), S.scales[2 * n + i]);
+      float smax = fmaxf(fmaxf(S.scales[i], S.scales[n + i]), S.scales[2 * n + i]);
+      if (mip3d) smax = sqrtf(fmaf(smax, smax, S.filter3d[i]));
       const float* R = V.R;
       const float tx = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
       const float ty = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       const float a0 = V.fx * iz, a1 = V.fy * iz;
       const float jf2 = a0 * a0 * (1.0f + ux * ux) + a1 * a1 * (1.0f + uy * uy);
       const float kk = sqrtf(fmaxf(2.0f * kLn2 * log2f(255.0f * o), 0.0f));
-      const float rb = 1.01f * kk * sqrtf(jf2 * smax * smax + kDilation) + 1.0f;
+      const float rb = 1.01f * kk * sqrtf(jf2 * smax * smax + dil) + 1.0f;
       // also keep anything whose numbers are not finite: phase 2 decides
       ok = !(mux + rb < 0.0f || mux - rb > Wf || muy + rb < 0.0f || muy - rb > Hf);
     }
@@ -311,19 +316,31 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     const float tz = depth_out[item];
     const float o = S.opac[i];
     const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
-    const float sc[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+    float sc[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+    // filtered envelope: scales sqrt(s^2 + v), opacity times prod s / sqrt(s^2 + v)
+    float oe = o;
+    if (mip3d) {
+      const float fv = S.filter3d[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float sf = sqrtf(fmaf(sc[j], sc[j], fv));
+        oe *= sc[j] / sf;
+        sc[j] = sf;
+      }
+    }
     Geo g;
-    geometry(V, mx, my, mz, tz, q, sc, g);
+    geometry(V, mx, my, mz, tz, q, sc, dil, g);
+    if (mip2d) oe *= sqrtf(fmaxf(g.D / g.det, kMip2dMinRatio));
     const float mux = fmaf(V.fx * g.tx, g.inv_tz, V.cx);
     const float muy = fmaf(V.fy * g.ty, g.inv_tz, V.cy);
     // exact support of o G >= 1/255: d^T C d <= 2 ln(255 o)
-    const float kk = sqrtf(2.0f * kLn2 * log2f(255.0f * o));
-    const float rx = kk * sqrtf(g.ra + kDilation), ry = kk * sqrtf(g.rc + kDilation);
+    const float kk = sqrtf(fmaxf(2.0f * kLn2 * log2f(255.0f * oe), 0.0f));
+    const float rx = kk * sqrtf(g.ra + dil), ry = kk * sqrtf(g.rc + dil);
     const float px0 = fmaxf(ceilf(mux - rx - 0.5f), 0.0f);
     const float px1 = fminf(floorf(mux + rx - 0.5f), (float)(V.width - 1));
     const float py0 = fmaxf(ceilf(muy - ry - 0.5f), 0.0f);
     const float py1 = fminf(floorf(muy + ry - 0.5f), (float)(V.height - 1));
-    const bool vis = (g.det > 0.f) && (px0 <= px1) && (py0 <= py1);
+    const bool vis = (g.det > 0.f) && (px0 <= px1) && (py0 <= py1) && (oe * 255.0f > 1.0f);
     uint2 rect = make_uint2(0u, 0u);
     uint32_t ntiles = 0;
     if (vis) {
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       r[2] = -0.5f * kLog2e * g.conic[0];
       r[3] = -kLog2e * g.conic[1];
       r[4] = -0.5f * kLog2e * g.conic[2];
-      r[5] = log2f(o);
+      r[5] = log2f(oe);
       if (S.sh_degree >= 0) {
         const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
         const float il = 1.0f / sqrtf(dot3(d, d));
@@ -428,20 +445,30 @@ __device__ __forceinline__ float* geo_dst(const gabsplat_scene_grads& gr, int64_
 }
 
 // Chain rule of the geometry part for primitive i, parameters in row P (LDS);
-// the gradients replace them in the same layout.
+// the gradients replace them in the same layout.  grad2d rows are `gstride`
+// floats apart; the first round_up(10 + 3K, 4) are read.
 template <int K>
 __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int scene_index,
                                             const uint32_t* __restrict__ tiles, const float* __restrict__ depth,
-                                            const float* __restrict__ grad2d, int64_t i, float* P) {
+                                            const float* __restrict__ grad2d, int gstride, int64_t i, float* P) {
   constexpr int GF = (10 + 3 * K + 3) & ~3;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
   const SceneEntry& S = table_scenes(table, nv)[scene_index];
   const float mx = P[0], my = P[1], mz = P[2];
-  const float s[3] = {P[3], P[4], P[5]};
+  const float s_in[3] = {P[3], P[4], P[5]};
   const float q[4] = {P[6], P[7], P[8], P[9]};
   const float o = P[10];
+  const bool mip3d = (S.flags & GABSPLAT_FLAG_MIP_3D) != 0;
+  const bool mip2d = (S.flags & GABSPLAT_FLAG_MIP_2D) != 0;
+  const float dil = mip2d ? kMip2dVariance : kDilation;
+  // scales the projection sees (filtered: sqrt(s^2 + v))
+  const float fv = mip3d ? S.filter3d[i] : 0.f;
+  float s[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) s[j] = mip3d ? sqrtf(fmaf(s_in[j], s_in[j], fv)) : s_in[j];
+  float g5 = 0.f;  // sum over views of dL/d rec[5]
 
   V3 gmean = v3(0.f, 0.f, 0.f);
   float gs[3] = {0.f, 0.f, 0.f};
@@ -459,7 +486,7 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
     if (V.scene != scene_index) continue;
     const int64_t item = V.item_offset + i;
     if (tiles[item] == 0) continue;
-    const float* g2 = grad2d + item * GF;
+    const float* g2 = grad2d + item * (int64_t)gstride;
     float G2[GF];
 #pragma unroll
     for (int j = 0; j < GF / 4; ++j) {
@@ -467,20 +494,30 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
       G2[4 * j] = t4.x; G2[4 * j + 1] = t4.y; G2[4 * j + 2] = t4.z; G2[4 * j + 3] = t4.w;
     }
     Geo g;
-    geometry(V, mx, my, mz, depth[item], q, s, g);
+    geometry(V, mx, my, mz, depth[item], q, s, dil, g);
 
-    // ---- opacity: rec[5] = log2(o)
+    // ---- opacity: rec[5] = log2(o) [+ sum_j log2(s_j / s'_j)] [+ log2 of the 2D factor]
     go += G2[5] / (o * kLn2);
+    g5 += G2[5];
 
     // ---- conic record terms -> dilated covariance (a, b, c)
     const float dQ00 = -0.5f * kLog2e * G2[2];
     const float dQ01 = -kLog2e * G2[3];
     const float dQ11 = -0.5f * kLog2e * G2[4];
-    const float ca = g.ra + kDilation, cb = g.rb, cc = g.rc + kDilation;
+    const float ca = g.ra + dil, cb = g.rb, cc = g.rc + dil;
     const float id2 = 1.0f / (g.det * g.det);
-    const float dra = (-cc * cc * dQ00 + cb * cc * dQ01 - cb * cb * dQ11) * id2;
-    const float drc = (-cb * cb * dQ00 + ca * cb * dQ01 - ca * ca * dQ11) * id2;
-    const float drb = (2.f * cb * cc * dQ00 - (ca * cc + cb * cb) * dQ01 + 2.f * ca * cb * dQ11) * id2;
+    float dra = (-cc * cc * dQ00 + cb * cc * dQ01 - cb * cb * dQ11) * id2;
+    float drc = (-cb * cb * dQ00 + ca * cb * dQ01 - ca * ca * dQ11) * id2;
+    float drb = (2.f * cb * cc * dQ00 - (ca * cc + cb * cb) * dQ01 + 2.f * ca * cb * dQ11) * id2;
+    // 2D filter factor: rec[5] += log2(D / det) / 2 with D = ra rc - rb^2 and
+    // det = ca cc - rb^2 (a floored ratio has zero derivative)
+    if (mip2d && g.D / g.det > kMip2dMinRatio) {
+      const float c5 = 0.5f * G2[5] * kLog2e;
+      const float iD = 1.0f / g.D, idt = 1.0f / g.det;
+      dra += c5 * (g.rc * iD - cc * idt);
+      drc += c5 * (g.ra * iD - ca * idt);
+      drb += c5 * 2.f * g.rb * (idt - iD);
+    }
     V3 gr0 = add3(scale3(g.r0, 2.f * dra), scale3(g.r1, drb));
     V3 gr1 = add3(scale3(g.r1, 2.f * drc), scale3(g.r0, drb));
     float gM[3][3];
@@ -616,7 +653,14 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
                            R[2] * gtx + R[5] * gty + R[8] * gtz));
   }
   P[0] = gmean.x; P[1] = gmean.y; P[2] = gmean.z;
-  P[3] = gs[0]; P[4] = gs[1]; P[5] = gs[2];
+  if (mip3d) {
+    // s' = sqrt(s^2 + v): ds'/ds = s / s'; the opacity factor adds
+    // d/ds log2(s / s') = v / (ln 2 s s'^2) per unit of rec[5]
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[3 + j] = gs[j] * (s_in[j] / s[j]) + g5 * kLog2e * fv / (s_in[j] * s[j] * s[j]);
+  } else {
+    P[3] = gs[0]; P[4] = gs[1]; P[5] = gs[2];
+  }
   P[6] = gq[0]; P[7] = gq[1]; P[8] = gq[2]; P[9] = gq[3];
   P[10] = go;
 #pragma unroll
@@ -713,7 +757,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
                                                               gabsplat_scene_grads gr,
                                                               const int32_t* __restrict__ d_overflow) {
   constexpr int PITCH = COLOUR ? kColPitch : GeoRow<K>::NP;
-  constexpr int GF = (10 + 3 * K + 3) & ~3;
+  const int gstride = grad2d_stride(K, gr.flags);
   __shared__ float s_row[kBwdBlock * PITCH];
   __shared__ int16_t s_prim[kBwdBlock];
   __shared__ uint32_t s_wave[kBwdBlock / 64];
@@ -774,14 +818,14 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
       const int64_t ii = base + s_prim[t];
       float* row = s_row + t * PITCH;
       if constexpr (COLOUR) {
-        const V3 gm = colour_bwd_one(table, scene_index, tiles, grad2d, GF, ii, row);
+        const V3 gm = colour_bwd_one(table, scene_index, tiles, grad2d, gstride, ii, row);
         if (gr.means) {  // after the geometry part has written the mean gradient
           gr.means[ii] += gm.x;
           gr.means[n + ii] += gm.y;
           gr.means[2 * n + ii] += gm.z;
         }
       } else {
-        geo_bwd_one<K>(table, scene_index, tiles, depth, grad2d, ii, row);
+        geo_bwd_one<K>(table, scene_index, tiles, depth, grad2d, gstride, ii, row);
       }
     }
     __syncthreads();

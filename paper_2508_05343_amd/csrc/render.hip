@@ -357,7 +357,9 @@ __device__ __forceinline__ void wave_reduce_add(float (&v)[G], float* dst, int s
 }
 
 // --------------------------------------------------------------------- K7
-template <int K>
+// ABS adds two components per pair: |dL_p/d mu2d_x| and |dL_p/d mu2d_y| of the
+// pixel, whose wave sums build the homodirectional (AbsGS) statistic.
+template <int K, bool ABS>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ table,
                                                        const float* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -370,8 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   constexpr int RF = (10 + 3 * K + 3) & ~3;
   constexpr int R4 = RF / 4;
   constexpr int S4 = Staged<K>::S4;
-  constexpr int GS = 10 + 3 * K;           // gradient components per pair (one per record field)
-  constexpr int GF = (GS + 3) & ~3;        // grad2d row stride
+  constexpr int GS = 10 + 3 * K + (ABS ? 2 : 0);  // gradient components per pair (record fields [+ 2])
+  constexpr int GF = (GS + 3) & ~3;               // grad2d row stride
   __shared__ float4 s_rec[kBatchBwd * S4];
   __shared__ uint32_t s_id[kBatchBwd];
   __shared__ uint32_t s_mask[kBatchBwd];
@@ -511,6 +513,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         }
         gv[0] = -ddx;
         gv[1] = -ddy;
+        if (ABS) {
+          gv[GS - 2] = fabsf(ddx);
+          gv[GS - 1] = fabsf(ddy);
+        }
         wave_reduce_add<GS>(gv, grad2d + (size_t)s_id[j] * GF, red_slot, red_writer);
       }
     }
@@ -575,27 +581,31 @@ hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabs
 template <int K>
 static hipError_t bwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, const uint32_t* vals,
                         const uint32_t* ranges, const float* final_T, const uint32_t* n_contrib,
-                        const float* dl, float* grad2d, const int32_t* ov, hipStream_t s) {
+                        const float* dl, float* grad2d, bool abs_mean2d, const int32_t* ov, hipStream_t s) {
   if (h.hdr.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_render_bwd<K>, dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table, g.rec, vals,
-                     ranges, final_T, n_contrib, dl, grad2d, ov);
+  if (abs_mean2d)
+    hipLaunchKernelGGL((k_render_bwd<K, true>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table,
+                       g.rec, vals, ranges, final_T, n_contrib, dl, grad2d, ov);
+  else
+    hipLaunchKernelGGL((k_render_bwd<K, false>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table,
+                       g.rec, vals, ranges, final_T, n_contrib, dl, grad2d, ov);
   return hipGetLastError();
 }
 
 hipError_t launch_render_bwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int k,
                              const uint32_t* vals, const uint32_t* ranges, const float* final_T,
-                             const uint32_t* n_contrib, const float* dl, float* grad2d, const int32_t* ov,
-                             hipStream_t s) {
+                             const uint32_t* n_contrib, const float* dl, float* grad2d, bool abs_mean2d,
+                             const int32_t* ov, hipStream_t s) {
   switch (k) {
-    case 0: return bwd_k<0>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 1: return bwd_k<1>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 2: return bwd_k<2>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 3: return bwd_k<3>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 4: return bwd_k<4>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 5: return bwd_k<5>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 6: return bwd_k<6>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 7: return bwd_k<7>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
-    case 8: return bwd_k<8>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, ov, s);
+    case 0: return bwd_k<0>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 1: return bwd_k<1>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 2: return bwd_k<2>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 3: return bwd_k<3>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 4: return bwd_k<4>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 5: return bwd_k<5>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 6: return bwd_k<6>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 7: return bwd_k<7>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
+    case 8: return bwd_k<8>(d_table, h, g, vals, ranges, final_T, n_contrib, dl, grad2d, abs_mean2d, ov, s);
   }
   return hipErrorInvalidValue;
 }

@@ -24,11 +24,18 @@ TILE = 16
 class DeviceScene:
     """Activated primitive attributes as planar fp32 device tensors:
     means [3,n], scales [3,n], quats [4,n], opacities [n], sh [D*3,n] or
-    colors [3,n], freqs [3K,n], weights [K,n]."""
+    colors [3,n], freqs [3K,n], weights [K,n].
+
+    Options: attenuation (keep the z-integration factor of every cosine term),
+    mip2d (Mip-Splatting's 2D filter instead of the 0.3 px^2 dilation) and
+    filter3d ([n] variances of Mip-Splatting's 3D filter, e.g. from
+    compute_filter3d; None = no 3D filter)."""
 
     def __init__(self, means, scales, quats, opacities, freqs, weights, sh=None, colors=None, sh_degree=-1,
-                 attenuation=False):
+                 attenuation=False, mip2d=False, filter3d=None):
         self.attenuation = bool(attenuation)
+        self.mip2d = bool(mip2d)
+        self.filter3d = filter3d
         self.means, self.scales, self.quats, self.opacities = means, scales, quats, opacities
         self.freqs, self.weights, self.sh, self.colors = freqs, weights, sh, colors
         self.sh_degree = sh_degree if sh is not None else -1
@@ -36,7 +43,7 @@ class DeviceScene:
         self.k = int(weights.shape[0])
 
     @staticmethod
-    def from_host(scene, device="cuda", attenuation=False) -> "DeviceScene":
+    def from_host(scene, device="cuda", attenuation=False, mip2d=False) -> "DeviceScene":
         """From AoS numpy arrays (synthetic generator layout)."""
         def planar(a):
             a = np.asarray(a, np.float32)
@@ -49,16 +56,36 @@ class DeviceScene:
                            torch.from_numpy(np.ascontiguousarray(scene.opacities, np.float32)).to(device),
                            planar(scene.freqs.reshape(n, -1)), planar(scene.weights), sh=sh,
                            colors=None if scene.colors is None else planar(scene.colors),
-                           sh_degree=scene.sh_degree if scene.sh is not None else -1, attenuation=attenuation)
+                           sh_degree=scene.sh_degree if scene.sh is not None else -1, attenuation=attenuation,
+                           mip2d=mip2d)
 
     def tensors(self):
         return [self.means, self.scales, self.quats, self.opacities, self.sh if self.sh is not None else self.colors,
                 self.freqs, self.weights]
 
+    def flags(self) -> int:
+        f = _lib.FLAG_ATTENUATION if self.attenuation else 0
+        f |= _lib.FLAG_MIP_2D if self.mip2d else 0
+        f |= _lib.FLAG_MIP_3D if self.filter3d is not None else 0
+        return f
+
+    def compute_filter3d(self, cams, s: float = 0.2, margin: float = 0.15, stream=None) -> torch.Tensor:
+        """Variances of Mip-Splatting's 3D filter from the training cameras
+        (gabsplat_mip_filter3d), kept in self.filter3d (the same tensor across
+        calls while n is unchanged, so plans built earlier stay valid)."""
+        if self.filter3d is None or self.filter3d.numel() != self.n:
+            self.filter3d = torch.empty(max(self.n, 1), dtype=torch.float32, device=self.means.device)
+        cc = [camera_struct(c) for c in cams]
+        wsb = _lib.gabsplat_mip_filter3d_workspace_size(self.n, len(cc))
+        ws = torch.empty((wsb + 3) // 4, dtype=torch.int32, device=self.means.device)
+        _lib.gabsplat_mip_filter3d(self.means, self.n, cc, s, margin, self.filter3d, ws, stream)
+        return self.filter3d
+
     def cstruct(self) -> _lib.Scene:
         s = _lib.Scene()
         s.n, s.k, s.sh_degree = self.n, self.k, max(self.sh_degree, 0)
-        s.flags = _lib.FLAG_ATTENUATION if self.attenuation else 0
+        s.flags = self.flags()
+        s.filter3d = _lib.ptr(self.filter3d)
         s.means, s.scales, s.quats = _lib.ptr(self.means), _lib.ptr(self.scales), _lib.ptr(self.quats)
         s.opacities = _lib.ptr(self.opacities)
         s.sh = _lib.ptr(self.sh) if self.sh is not None else None
@@ -103,8 +130,10 @@ class RenderPlan:
     per-step calls."""
 
     def __init__(self, scenes: Sequence[DeviceScene], cams: Sequence, scene_of_view: Optional[Sequence[int]] = None,
-                 pair_capacity: Optional[int] = None, device="cuda", want_keys=False):
+                 pair_capacity: Optional[int] = None, device="cuda", want_keys=False, abs_mean2d=False):
         self.scenes = list(scenes)
+        # backward flags: abs_mean2d adds the AbsGS per-pixel absolute mean gradients to grad2d
+        self.grad_flags = _lib.GRAD_ABS_MEAN2D if abs_mean2d else 0
         self.cams = list(cams)
         self.scene_of_view = None if scene_of_view is None else [int(s) for s in scene_of_view]
         sv = self.scene_of_view or [0] * len(self.cams)
@@ -183,12 +212,13 @@ class RenderPlan:
         -> tensor (same layout as the scene) that receives the gradient, added
         to it (accumulate=True) or overwriting it."""
         if self.grad2d is None:
-            gf = _lib.gabsplat_grad2d_floats(self.k)
+            gf = _lib.gabsplat_grad2d_stride(self.k, self.grad_flags)
             self.grad2d = torch.empty((max(self.items, 1), gf), dtype=torch.float32, device=self.device)
         gs = []
         for g in grads:
             c = _lib.SceneGrads()
             c.accumulate = 1 if accumulate else 0
+            c.flags = self.grad_flags
             for name in ("means", "scales", "quats", "opacities", "sh", "colors", "freqs", "weights"):
                 setattr(c, name, _lib.ptr(g.get(name)))
             c.grad2d = _lib.ptr(self.grad2d)

@@ -35,11 +35,17 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_helpers(L):
-    assert L.gabsplat_abi_version() == 1
+    assert L.gabsplat_abi_version() == 2
     assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 16
     assert L.gabsplat_record_floats(4) == 24 and L.gabsplat_record_floats(8) == 36
     assert L.gabsplat_record_floats(9) == -1
     assert L.gabsplat_grad2d_floats(4) == 24 and L.gabsplat_grad2d_floats(2) == 16
+    # the AbsGS columns follow the record's fields
+    assert L.gabsplat_grad2d_stride(4, 0) == 24 and L.gabsplat_grad2d_stride(4, L.GRAD_ABS_MEAN2D) == 24
+    assert L.gabsplat_grad2d_stride(2, L.GRAD_ABS_MEAN2D) == 20 and L.gabsplat_grad2d_stride(0, 1) == 12
+    assert L.gabsplat_grad2d_stride(2, 2) == -1 and L.gabsplat_grad2d_stride(9, 0) == -1
+    assert L.gabsplat_mip_filter3d_workspace_size(1000, 3) >= 3 * 80 + 4 * 4
+    assert L.gabsplat_mip_filter3d_workspace_size(10, 0) == 0
     assert L.gabsplat_views_bytes(1, 1) > 0
     small = L.gabsplat_bin_sort_workspace_size(1000, 10000, 64)
     big = L.gabsplat_bin_sort_workspace_size(10 ** 6, 2 * 10 ** 7, 4346)
@@ -74,6 +80,16 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     st = lib.gabsplat_loss_l1_dssim(None, None, 3, 4, 4, 0.2, None, None, None, 0, None)
     assert st == L.INVALID_ARGUMENT
     assert lib.gabsplat_read_overflow(None, None) == L.INVALID_ARGUMENT
+    # 3D filter flag without variances
+    sc.flags = L.FLAG_MIP_3D
+    st = lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    st = lib.gabsplat_mip_filter3d(None, 10, ctypes.byref(cam), 1, 0.2, 0.15, None, None, 0, None)
+    assert st == L.INVALID_ARGUMENT
+    # AbsGS statistic requested without its output
+    g.views = g.tiles = 1
+    st = lib.gabsplat_densify_stats(ctypes.byref(g), ctypes.byref(cam), 1, 10, 1, L.GRAD_ABS_MEAN2D, 1, None, 1, None)
+    assert st == L.INVALID_ARGUMENT
 
 
 def test_missing_library_fails_loudly(L, monkeypatch):
