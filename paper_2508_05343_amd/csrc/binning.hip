@@ -6,9 +6,9 @@
 // the tile-count path: per-block tile histograms in LDS, per-tile column
 // offsets and one scan of the tile totals (which are the ranges), a scatter
 // of (depth bits << 32 | item) into each tile's segment through per-block
-// LDS cursors, and a sort of every segment by that unique key (bitonic in
-// LDS; runs merged for long segments).  Seven launches, no global radix
-// passes and no global atomics.
+// LDS cursors, and a sort of every segment by that unique key (one wavefront
+// per tile, bitonic in registers; runs of 1024 merged for longer segments).
+// Five launches, no global radix passes and no global atomics.
 //
 // Larger batches (many views) take the radix path: an LSD radix sort over
 // the same key that first sorts by the 32 depth bits and then, stably, by
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
 // is the same order as the stable (tile, depth) sort of the onesweep path.
 constexpr int kTcMaxTiles = 8192;   // per-block tile histograms in LDS (32 KB)
 constexpr int kTcBig = 64;        // items with more tiles are walked by a whole wavefront
-constexpr int kSegCap = 512;      // segment sorted in LDS in one piece (u64 keys, 4 KB): one wavefront per tile
+constexpr int kSegCap = 1024;     // segment sorted in registers in one piece (16 u64 keys per lane): one wavefront per tile
 
 struct ItemTiles {
   uint32_t base;  // global tile id of the rect's top-left tile
@@ -770,42 +770,6 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
     });
 }
 
-// Bitonic sort of s[0, n2) (n2 a power of two, n2 <= kSegCap) by one
-// wavefront.  A stage's pairs are disjoint: each lane loads all of its pairs
-// first and then compares and stores them, so that a stage costs one LDS
-// round trip (LDS loads cannot be moved above possibly aliasing stores).
-__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
-  constexpr int kPer = kSegCap / 2 / 64;  // pairs per lane at most
-  const int t = threadIdx.x;
-  const int half = n2 >> 1;
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      int lo[kPer];
-      uint64_t a[kPer], b[kPer];
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int p = t + 64 * q;
-        lo[q] = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // lower index of pair p (its partner is lo + j)
-        if (p < half) {
-          a[q] = s[lo[q]];
-          b[q] = s[lo[q] + j];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int p = t + 64 * q;
-        if (p < half) {
-          const bool up = (lo[q] & k) == 0;
-          if ((a[q] > b[q]) == up) {
-            s[lo[q]] = b[q];
-            s[lo[q] + j] = a[q];
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
 
 // Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of x
 // into out at o0, by the whole block (each lane a contiguous slice of the
@@ -828,15 +792,86 @@ __device__ void block_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_
   }
 }
 
+// Bitonic sort of 64 E keys held in registers, E consecutive keys per lane
+// (key i = lane E + r).  Steps whose partner distance j is below E pair keys of
+// one lane; the others pair key r of lanes l and l ^ (j / E) through a lane
+// shuffle, each side keeping the minimum or the maximum.  No LDS, no barrier.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+  const int lo = __shfl_xor((int)(uint32_t)x, m, 64), hi = __shfl_xor((int)(uint32_t)(x >> 32), m, 64);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
+  const int lane = threadIdx.x;
+  constexpr int N = 64 * E;
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if ((r & j) == 0) {
+            const bool up = (((lane * E + r) & k) == 0);
+            const uint64_t a = x[r], b = x[r | j];
+            const bool sw = (a > b) == up;
+            x[r] = sw ? b : a;
+            x[r | j] = sw ? a : b;
+          }
+        }
+      } else {
+        const int m = j / E;
+        const bool lower = (lane & m) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool up = (((lane * E + r) & k) == 0);
+          const uint64_t y = shfl_xor_u64(x[r], m);
+          const bool take_min = lower == up;
+          x[r] = take_min ? (x[r] < y ? x[r] : y) : (x[r] > y ? x[r] : y);
+        }
+      }
+    }
+  }
+}
+
+// Sorts the n <= 64 E keys at pa[start ..) and writes them either as item ids
+// (+ 64-bit tile keys) to vals / keys, or (TO_VALS = false) back to pa.
+template <int E, bool TO_VALS>
+__device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ pa, uint32_t start, uint32_t n,
+                                               uint32_t tile, uint32_t* __restrict__ vals,
+                                               uint64_t* __restrict__ keys) {
+  const int lane = threadIdx.x;
+  uint64_t x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = (uint32_t)(lane * E + r);
+    x[r] = i < n ? pa[start + i] : ~0ull;
+  }
+  wave_bitonic<E>(x);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = (uint32_t)(lane * E + r);
+    if (i < n) {
+      if (TO_VALS) {
+        vals[start + i] = (uint32_t)x[r];
+        if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x[r] >> 32);
+      } else {
+        pa[start + i] = x[r];
+      }
+    }
+  }
+}
+
 // One wavefront per tile: sorts the tile's segment of (depth bits, item) keys
 // and writes the item ids to vals (and the 64-bit keys when asked for).
-// Segments of up to kSegCap pairs are sorted in LDS; longer ones as sorted
-// runs of kSegCap merged pairwise through the ping-pong buffer pb.
+// Segments of up to kSegCap pairs are sorted in registers; longer ones as
+// register-sorted runs of kSegCap merged pairwise through the ping-pong
+// buffer pb.
 __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
                                                 const uint32_t* __restrict__ counters, uint64_t* __restrict__ pa,
                                                 uint64_t* __restrict__ pb, uint32_t* __restrict__ vals,
                                                 uint64_t* __restrict__ keys) {
-  __shared__ uint64_t s[kSegCap];
   if (counters[C_OVERFLOW]) return;
   const int tile = blockIdx.x;
   if (tile >= ntiles) return;
@@ -844,28 +879,15 @@ __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ran
   const uint32_t n = end - start;
   if (n == 0) return;
   const int t = threadIdx.x;
-  if (n <= (uint32_t)kSegCap) {
-    int n2 = 1;
-    while (n2 < (int)n) n2 <<= 1;
-    for (int i = t; i < n2; i += blockDim.x) s[i] = i < (int)n ? pa[start + i] : ~0ull;
-    __syncthreads();
-    lds_bitonic(s, n2);
-    for (int i = t; i < (int)n; i += blockDim.x) {
-      const uint64_t x = s[i];
-      vals[start + i] = (uint32_t)x;
-      if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
-    }
-    return;
-  }
+  static_assert(kSegCap == 1024, "register sort sizes");
+  if (n <= 64) return tile_sort_regs<1, true>(pa, start, n, tile, vals, keys);
+  if (n <= 128) return tile_sort_regs<2, true>(pa, start, n, tile, vals, keys);
+  if (n <= 256) return tile_sort_regs<4, true>(pa, start, n, tile, vals, keys);
+  if (n <= 512) return tile_sort_regs<8, true>(pa, start, n, tile, vals, keys);
+  if (n <= 1024) return tile_sort_regs<16, true>(pa, start, n, tile, vals, keys);
   // long segment: sorted runs in place, then pairwise merges pa <-> pb
-  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap) {
-    const uint32_t m = min((uint32_t)kSegCap, n - r0);
-    __syncthreads();
-    for (int i = t; i < kSegCap; i += blockDim.x) s[i] = i < (int)m ? pa[start + r0 + i] : ~0ull;
-    __syncthreads();
-    lds_bitonic(s, kSegCap);
-    for (int i = t; i < (int)m; i += blockDim.x) pa[start + r0 + i] = s[i];
-  }
+  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap)
+    tile_sort_regs<16, false>(pa, start + r0, min((uint32_t)kSegCap, n - r0), tile, vals, keys);
   __syncthreads();
   uint64_t *src = pa, *dst = pb;
   for (uint32_t width = kSegCap; width < n; width <<= 1) {
