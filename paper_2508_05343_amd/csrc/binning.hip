@@ -427,7 +427,7 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
 // k_emit: globally load-balanced pair emission.  Chunk c holds pairs
 // [c * kEmitChunk, (c + 1) * kEmitChunk) of the depth-ordered pair sequence; blocks
 // stride over the chunks.  For one chunk a block first stages, for each item
-// from chunk_first[c] on, its pair offset, id, first tile (view tile offset +
+// from chunk_first[c] to chunk_first[c + 1], its pair offset, id, first tile (view tile offset +
 // rect corner) and rect width / tiles per row in LDS (coalesced loads plus
 // one gather of the rects, all in parallel); every thread then finds the
 // item of its first pair (one binary search) and walks its kEmitItems consecutive
@@ -462,8 +462,12 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
   for (uint64_t chunk = blockIdx.x; chunk * kEmitChunk < P; chunk += gridDim.x) {
     const uint64_t p0 = chunk * kEmitChunk;
     __syncthreads();
+    // the chunk's pairs belong to items first .. chunk_first[chunk + 1] (the
+    // item holding the next chunk's first pair; V - 1 for the last chunk)
     const uint32_t first = chunk_first[chunk];
-    const uint32_t nitems = min((uint32_t)kEmitChunk, V - first);
+    const uint64_t nchunks = ((uint64_t)P + kEmitChunk - 1) / kEmitChunk;
+    const uint32_t last = chunk + 1 < nchunks ? chunk_first[chunk + 1] : V - 1;
+    const uint32_t nitems = min((uint32_t)kEmitChunk, last - first + 1);
     for (uint32_t i = t; i < nitems; i += kSortThreads) {
       const uint32_t item = ids[first + i];
       s_off[i] = offsets[first + i];
