@@ -435,30 +435,38 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on
 // alone.  The block writes the (tile, item) pairs coalesced from LDS while
 // accumulating the tile-digit histograms of the tile passes.
 constexpr int kPad = kEmitChunk + kEmitChunk / kEmitItems;  // LDS index i + i / kEmitItems: conflict-free runs
+constexpr int kEmitViews = 1024;  // views whose table columns are cached in LDS (more: searched in memory)
 
 __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ table,
                                                        const uint32_t* __restrict__ rect,
                                                        const uint32_t* __restrict__ ids,
                                                        const uint32_t* __restrict__ offsets,
-                                                       const uint32_t* __restrict__ chunk_first, int tpass,
-                                                       const uint32_t* __restrict__ counters,
-                                                       uint32_t* __restrict__ thist, uint32_t* __restrict__ tkeys,
+                                                       const uint32_t* __restrict__ chunk_first,
+                                                       const uint32_t* __restrict__ counters, uint32_t* __restrict__ tkeys,
                                                        uint32_t* __restrict__ pvals) {
   __shared__ uint32_t s_off[kEmitChunk];
   __shared__ uint32_t s_id[kEmitChunk];
   __shared__ uint2 s_geo[kEmitChunk];  // (first tile, width | tiles per row << 16)
   __shared__ uint32_t s_tile[kPad];
   __shared__ uint32_t s_item[kPad];
-  __shared__ uint32_t s_h[kMaxTilePasses * kRadix];
+  // view table columns (first item, first tile, tiles per row) for the item -> view search
+  __shared__ uint32_t s_vitem[kEmitViews], s_vtile[kEmitViews], s_vtx[kEmitViews];
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
   const uint32_t V = counters[C_NUM_VISIBLE];
   if ((uint64_t)blockIdx.x * kEmitChunk >= P) return;
   const int t = threadIdx.x;
-  for (int i = t; i < kMaxTilePasses * kRadix; i += kSortThreads) s_h[i] = 0;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
   const int nv = hdr->num_views;
+  const bool cached = nv <= kEmitViews;
+  if (cached) {
+    for (int v = t; v < nv; v += kSortThreads) {
+      s_vitem[v] = (uint32_t)views[v].item_offset;  // items < 2^32
+      s_vtile[v] = (uint32_t)views[v].tile_offset;
+      s_vtx[v] = (uint32_t)views[v].tiles_x;
+    }
+  }
   for (uint64_t chunk = blockIdx.x; chunk * kEmitChunk < P; chunk += gridDim.x) {
     const uint64_t p0 = chunk * kEmitChunk;
     __syncthreads();
@@ -474,13 +482,24 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
       s_id[i] = item;
       const uint2 r = reinterpret_cast<const uint2*>(rect)[item];
       int vlo = 0, vhi = nv - 1;
-      while (vlo < vhi) {
-        const int mid = (vlo + vhi + 1) >> 1;
-        if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+      uint32_t tx, toff;
+      if (cached) {
+        while (vlo < vhi) {
+          const int mid = (vlo + vhi + 1) >> 1;
+          if (s_vitem[mid] <= item) vlo = mid; else vhi = mid - 1;
+        }
+        tx = s_vtx[vlo];
+        toff = s_vtile[vlo];
+      } else {
+        while (vlo < vhi) {
+          const int mid = (vlo + vhi + 1) >> 1;
+          if (views[mid].item_offset <= (int64_t)item) vlo = mid; else vhi = mid - 1;
+        }
+        tx = (uint32_t)views[vlo].tiles_x;
+        toff = (uint32_t)views[vlo].tile_offset;
       }
-      const uint32_t tx = (uint32_t)views[vlo].tiles_x;
       const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16;
-      s_geo[i] = make_uint2((uint32_t)views[vlo].tile_offset + y0 * tx + x0, ((r.y & 0xffffu) - x0) | (tx << 16));
+      s_geo[i] = make_uint2(toff + y0 * tx + x0, ((r.y & 0xffffu) - x0) | (tx << 16));
     }
     __syncthreads();
     const uint32_t pend = (uint32_t)min((uint64_t)P, p0 + kEmitChunk);
@@ -520,24 +539,196 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
       }
     }
     __syncthreads();
-    // uniform trip count so that every lane takes part in the ballots
-    for (uint32_t i = t; i < (uint32_t)kEmitChunk; i += kSortThreads) {
-      const uint32_t m = (uint32_t)p0 + i;
-      const bool on = m < pend;
-      uint32_t tile = 0;
-      if (on) {
-        const uint32_t li = i + i / kEmitItems;
-        tile = s_tile[li];
-        tkeys[m] = tile;
-        pvals[m] = s_item[li];
-      }
-      for (int ps = 0; ps < tpass; ++ps) wave_hist_add(s_h + ps * kRadix, (tile >> (8 * ps)) & 255u, on);
+    for (uint32_t i = t; i < pend - (uint32_t)p0; i += kSortThreads) {
+      const uint32_t li = i + i / kEmitItems;
+      tkeys[(uint32_t)p0 + i] = s_tile[li];
+      pvals[(uint32_t)p0 + i] = s_item[li];
     }
   }
+}
+
+// ------------------------------------------------ reduce-then-scan passes
+// The tile passes over the P pairs are reduce-then-scan LSD passes.  With
+// hundreds of partitions in flight, a single-pass look-back makes every
+// partition read the 256 digit words of each of them, and those loads bound
+// the pass; here nothing waits on another block.  Block b owns a contiguous
+// range of partitions of kPart keys: (1) k_rs_upsweep counts its digits (and
+// adds them into the pass's global histogram), (2) k_rs_scan turns the counts
+// into the output base of every (digit, block), (3) k_rs_downsweep re-reads the
+// range and places each partition stably (the ranking of k_onesweep),
+// advancing the block's digit bases partition by partition.
+constexpr int kRsBlocks = 768;  // three 256-lane downsweep blocks per CU (141 VGPRs, 39 KB LDS)
+static_assert(kRadix == kSortThreads, "one lane per digit");
+
+__device__ __forceinline__ void rs_range(uint32_t n, uint32_t* p0, uint32_t* p1) {
+  const uint32_t nparts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+  const uint32_t per = (nparts + gridDim.x - 1) / gridDim.x;
+  *p0 = min(nparts, blockIdx.x * per);
+  *p1 = min(nparts, *p0 + per);
+}
+
+// bhist[d * gridDim.x + b] = keys of block b's range with digit d; ghist[d] += the same.
+constexpr int kRsUpThreads = 512;
+__global__ __launch_bounds__(kRsUpThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ d_count, int shift,
+                                                             uint32_t* __restrict__ bhist,
+                                                             uint32_t* __restrict__ ghist,
+                                                             const uint32_t* __restrict__ d_overflow) {
+  __shared__ uint32_t s_h[kRadix];
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const uint32_t n = *d_count;
+  const int t = threadIdx.x;
+  if (t < kRadix) s_h[t] = 0;
   __syncthreads();
-  for (int i = t; i < tpass * kRadix; i += kSortThreads) {
-    const uint32_t v = s_h[i];
-    if (v) atomicAdd(&thist[i], v);
+  uint32_t p0, p1;
+  rs_range(n, &p0, &p1);
+  const uint64_t b0 = (uint64_t)p0 * kPart, b1 = min((uint64_t)n, (uint64_t)p1 * kPart);
+  constexpr int kU = 8;  // loads in flight per lane
+  for (uint64_t i0 = b0; i0 < b1; i0 += (uint64_t)kU * kRsUpThreads) {  // uniform trip count
+    uint32_t k[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const uint64_t i = i0 + (uint64_t)j * kRsUpThreads + t;
+      k[j] = i < b1 ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kU; ++j)
+      wave_hist_add(s_h, (k[j] >> shift) & 255u, i0 + (uint64_t)j * kRsUpThreads + t < b1);
+  }
+  __syncthreads();
+  if (t < kRadix) {
+    const uint32_t c = s_h[t];
+    bhist[(size_t)t * gridDim.x + blockIdx.x] = c;
+    if (c) atomicAdd(&ghist[t], c);
+  }
+}
+
+// Block d: bhist[d][b] := (keys with a digit below d) + (keys with digit d in
+// the ranges of blocks before b).  nblocks <= 4 * kSortThreads.
+static_assert(kRsBlocks <= 4 * kSortThreads, "k_rs_scan covers four blocks per lane");
+__global__ __launch_bounds__(kSortThreads) void k_rs_scan(uint32_t* __restrict__ bhist, int nblocks,
+                                                          const uint32_t* __restrict__ ghist,
+                                                          const uint32_t* __restrict__ d_overflow) {
+  __shared__ uint32_t s_wave[kSortThreads / 64];
+  __shared__ uint32_t s_base;
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const int t = threadIdx.x, d = blockIdx.x;
+  uint32_t dummy;
+  const uint32_t below = block_excl_scan(ghist[t], s_wave, &dummy);
+  if (t == d) s_base = below;
+  uint32_t* row = bhist + (size_t)d * nblocks;
+  uint32_t c[4], sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int b = 4 * t + j;
+    c[j] = b < nblocks ? row[b] : 0u;
+    sum += c[j];
+  }
+  uint32_t run = block_excl_scan(sum, s_wave, &dummy);  // its barriers also publish s_base
+  run += s_base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int b = 4 * t + j;
+    if (b < nblocks) row[b] = run;
+    run += c[j];
+  }
+}
+
+// keys per lane in the downsweep: 4096-key steps (about 16 keys per digit, so
+// the scattered writes fill whole 64-byte sectors); 2048-key steps, with more
+// blocks resident, measured slower
+constexpr int kDsItems = 16;
+constexpr int kDsPart = kSortThreads * kDsItems;
+static_assert(kPart % kDsPart == 0, "block ranges split into whole sub-partitions");
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+                                                               const uint32_t* __restrict__ vals_in,
+                                                               uint32_t* __restrict__ keys_out,
+                                                               uint32_t* __restrict__ vals_out,
+                                                               const uint32_t* __restrict__ d_count, int shift,
+                                                               const uint32_t* __restrict__ bbase,
+                                                               const uint32_t* __restrict__ d_overflow) {
+  __shared__ uint32_t s_keys[kDsPart];
+  __shared__ uint32_t s_vals[kDsPart];
+  __shared__ uint32_t s_wh[kSortThreads / 64][kRadix];
+  __shared__ uint32_t s_local[kRadix];
+  __shared__ uint32_t s_run[kRadix];
+  __shared__ uint32_t s_wave[kSortThreads / 64];
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const uint32_t n = *d_count;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  uint32_t p0, p1;
+  rs_range(n, &p0, &p1);
+  const uint64_t b0 = (uint64_t)p0 * kPart, b1 = min((uint64_t)n, (uint64_t)p1 * kPart);
+  s_run[t] = bbase[(size_t)t * gridDim.x + blockIdx.x];
+  const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+  for (uint64_t base = b0; base < b1; base += kDsPart) {
+    __syncthreads();
+    for (int i = t; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&s_wh[0][0])[i] = 0;
+    __syncthreads();
+    // wave-striped load: wave w owns [w*64*kDsItems, (w+1)*64*kDsItems), item j of lane l at j*64 + l
+    uint32_t key[kDsItems], val[kDsItems];
+    uint16_t rank[kDsItems];
+    const uint64_t wbase = base + (uint64_t)w * (64 * kDsItems);
+#pragma unroll
+    for (int j = 0; j < kDsItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      key[j] = i < b1 ? keys_in[i] : 0xffffffffu;
+      val[j] = i < b1 ? vals_in[i] : 0u;
+    }
+    // stable rank within the wave's digit (ballot matching), in index order
+#pragma unroll
+    for (int j = 0; j < kDsItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      const bool ok = i < b1;
+      const uint32_t d = (key[j] >> shift) & 255u;
+      uint64_t peers = __ballot(ok);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t lower = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t cur = s_wh[w][d];
+      rank[j] = (uint16_t)(cur + lower);
+      const bool leader = ok && ((peers >> l) == 1ull);
+      if (leader) s_wh[w][d] = cur + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit (lane t = digit): wave prefixes, sub-partition count, local start
+    uint32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < kSortThreads / 64; ++i) {
+      const uint32_t c = s_wh[i][t];
+      s_wh[i][t] = tot;
+      tot += c;
+    }
+    uint32_t dummy;
+    s_local[t] = block_excl_scan(tot, s_wave, &dummy);
+    __syncthreads();
+    // scatter into LDS in digit order
+#pragma unroll
+    for (int j = 0; j < kDsItems; ++j) {
+      const uint64_t i = wbase + (uint64_t)j * 64 + l;
+      if (i < b1) {
+        const uint32_t dd = (key[j] >> shift) & 255u;
+        const uint32_t lp = s_local[dd] + s_wh[w][dd] + rank[j];
+        s_keys[lp] = key[j];
+        s_vals[lp] = val[j];
+      }
+    }
+    __syncthreads();
+    const uint32_t nvalid = (uint32_t)((b1 - base) < (uint64_t)kDsPart ? (b1 - base) : (uint64_t)kDsPart);
+    for (uint32_t i = t; i < nvalid; i += kSortThreads) {
+      const uint32_t k = s_keys[i];
+      const uint32_t dd = (k >> shift) & 255u;
+      const uint32_t dst = s_run[dd] + (i - s_local[dd]);
+      keys_out[dst] = k;
+      vals_out[dst] = s_vals[i];
+    }
+    __syncthreads();
+    s_run[t] += tot;
   }
 }
 
@@ -924,15 +1115,14 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.parts_items = (items + kPart - 1) / kPart;
   p.parts_pairs = (capacity + kPart - 1) / kPart;
   const int64_t parts_exp = (items + kPart - 1) / kPart;
-  const int tpass = (bits + 7) / 8;
   size_t off = 0;
   // --- head: cleared at the start of every call
   p.off_counters = off; off += C_COUNT * 4;
   p.off_tcount = off; off += (size_t)total_tiles * 4;  // tile totals
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
   p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
-  p.off_look_sort = off;
-  off += ((size_t)p.parts_items * kDepthPasses + (size_t)p.parts_pairs * tpass) * kRadix * 4;
+  p.off_look_sort = off;  // look-back words of the depth passes
+  off += (size_t)p.parts_items * kDepthPasses * kRadix * 4;
   off = align_up(off);
   p.off_dkeys_a = off; off = align_up(off + (size_t)items * 4);
   // --- body
@@ -945,6 +1135,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_tkeys_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_pvals_b = off; off = align_up(off + (size_t)capacity * 4);
   p.off_tcursor = off; off = align_up(off + (size_t)total_tiles * 4);
+  p.off_rs_hist = off; off = align_up(off + (size_t)kRadix * kRsBlocks * 4);
   const bool tc = total_tiles <= kTcMaxTiles;
   p.off_tcmat = off; off = align_up(off + (tc ? (size_t)kTcBlocks * total_tiles * 4 : 0));
   p.off_tcpair_a = off; off = align_up(off + (tc ? (size_t)capacity * 8 : 0));
@@ -961,7 +1152,6 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   uint32_t* look_compact = reinterpret_cast<uint32_t*>(w + p.off_look_scan);
   uint32_t* look_expand = look_compact + (p.parts_items + 1);
   uint32_t* look_depth = reinterpret_cast<uint32_t*>(w + p.off_look_sort);
-  uint32_t* look_tile = look_depth + (size_t)p.parts_items * kDepthPasses * kRadix;
   uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(w + p.off_dkeys_a), reinterpret_cast<uint32_t*>(w + p.off_dkeys_b)};
   uint32_t* dv[2] = {reinterpret_cast<uint32_t*>(w + p.off_dvals_a), reinterpret_cast<uint32_t*>(w + p.off_dvals_b)};
   uint32_t* tk[2] = {reinterpret_cast<uint32_t*>(w + p.off_tkeys_a), reinterpret_cast<uint32_t*>(w + p.off_tkeys_b)};
@@ -1011,7 +1201,6 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const unsigned parts_p = (unsigned)(p.parts_pairs > 0 ? p.parts_pairs : 1);
   // grids of the ticket / stride loops: bounded, independent of the capacity
   const unsigned grid_i = parts_i < kLoopBlocks ? parts_i : kLoopBlocks;
-  const unsigned grid_p = parts_p < kLoopBlocks ? parts_p : kLoopBlocks;
   const int64_t pe = (p.capacity + kEmitChunk - 1) / kEmitChunk;
   const unsigned parts_e = (unsigned)(pe > 0 ? pe : 1);
   const unsigned grid_e = parts_e < kLoopBlocks ? parts_e : kLoopBlocks;  // two 54 KB-LDS blocks per CU
@@ -1033,15 +1222,20 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   uint32_t* thist = hist + kDepthPasses * kRadix;
   hipLaunchKernelGGL(k_expand_scan, dim3(grid_i), dim3(kSortThreads), 0, s, g.tiles, dv[0], (uint32_t)p.capacity,
                      counters, look_expand, offsets, chunk_first, parts_e, d_num_pairs, d_overflow);
-  // K3: load-balanced pair emission in depth order + tile-digit histograms
-  hipLaunchKernelGGL(k_emit, dim3(grid_e), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first, tpass,
-                     counters, thist, tk[0], pv[0]);
-  // K4b: tile passes over the P pairs
+  // K3: load-balanced pair emission in depth order
+  hipLaunchKernelGGL(k_emit, dim3(grid_e), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first,
+                     counters, tk[0], pv[0]);
+  // K4b: tile passes over the P pairs (reduce-then-scan)
+  uint32_t* bhist = reinterpret_cast<uint32_t*>(w + p.off_rs_hist);
+  const unsigned grid_rs = parts_p < (unsigned)kRsBlocks ? parts_p : (unsigned)kRsBlocks;
   for (int ps = 0; ps < tpass; ++ps) {
     const int a = ps & 1;
-    hipLaunchKernelGGL(k_onesweep, dim3(grid_p), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1], pv[a ^ 1],
-                       counters + C_NUM_PAIRS, 8 * ps, ps, tpass, thist + ps * kRadix, look_tile,
-                       counters + C_TICKET_TILE + ps, ov);
+    hipLaunchKernelGGL(k_rs_upsweep, dim3(grid_rs), dim3(kRsUpThreads), 0, s, tk[a], counters + C_NUM_PAIRS, 8 * ps,
+                       bhist, thist + ps * kRadix, ov);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kSortThreads), 0, s, bhist, (int)grid_rs, thist + ps * kRadix,
+                       ov);
+    hipLaunchKernelGGL(k_rs_downsweep, dim3(grid_rs), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1], pv[a ^ 1],
+                       counters + C_NUM_PAIRS, 8 * ps, bhist, ov);
   }
   uint32_t* tk_final = tk[tpass & 1];
   // K5: ranges
