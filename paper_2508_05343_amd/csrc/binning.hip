@@ -412,10 +412,11 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
 // Adds 1 to s_h[d] for every active lane with `on`, one LDS atomic per group of
 // lanes sharing the digit (ballot matching), so that the common case of a
 // whole wave on one digit costs one atomic instead of 64 serialised ones.
+template <int RB = 8>
 __device__ __forceinline__ void wave_hist_add(uint32_t* s_h, uint32_t d, bool on) {
   uint64_t peers = __ballot(on);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < RB; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t m = __ballot(bit);
     peers &= bit ? m : ~m;
@@ -569,16 +570,18 @@ __device__ __forceinline__ void rs_range(uint32_t n, uint32_t* p0, uint32_t* p1)
 
 // bhist[d * gridDim.x + b] = keys of block b's range with digit d; ghist[d] += the same.
 constexpr int kRsUpThreads = 512;
+template <int RB>
 __global__ __launch_bounds__(kRsUpThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ d_count, int shift,
                                                              uint32_t* __restrict__ bhist,
                                                              uint32_t* __restrict__ ghist,
                                                              const uint32_t* __restrict__ d_overflow) {
-  __shared__ uint32_t s_h[kRadix];
+  constexpr int D = 1 << RB;
+  __shared__ uint32_t s_h[D];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const uint32_t n = *d_count;
   const int t = threadIdx.x;
-  if (t < kRadix) s_h[t] = 0;
+  if (t < D) s_h[t] = 0;
   __syncthreads();
   uint32_t p0, p1;
   rs_range(n, &p0, &p1);
@@ -593,10 +596,10 @@ __global__ __launch_bounds__(kRsUpThreads) void k_rs_upsweep(const uint32_t* __r
     }
 #pragma unroll
     for (int j = 0; j < kU; ++j)
-      wave_hist_add(s_h, (k[j] >> shift) & 255u, i0 + (uint64_t)j * kRsUpThreads + t < b1);
+      wave_hist_add<RB>(s_h, (k[j] >> shift) & (uint32_t)(D - 1), i0 + (uint64_t)j * kRsUpThreads + t < b1);
   }
   __syncthreads();
-  if (t < kRadix) {
+  if (t < D) {
     const uint32_t c = s_h[t];
     bhist[(size_t)t * gridDim.x + blockIdx.x] = c;
     if (c) atomicAdd(&ghist[t], c);
@@ -606,6 +609,7 @@ __global__ __launch_bounds__(kRsUpThreads) void k_rs_upsweep(const uint32_t* __r
 // Block d: bhist[d][b] := (keys with a digit below d) + (keys with digit d in
 // the ranges of blocks before b).  nblocks <= 4 * kSortThreads.
 static_assert(kRsBlocks <= 4 * kSortThreads, "k_rs_scan covers four blocks per lane");
+template <int RB>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scan(uint32_t* __restrict__ bhist, int nblocks,
                                                           const uint32_t* __restrict__ ghist,
                                                           const uint32_t* __restrict__ d_overflow) {
@@ -614,7 +618,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scan(uint32_t* __restrict__
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const int t = threadIdx.x, d = blockIdx.x;
   uint32_t dummy;
-  const uint32_t below = block_excl_scan(ghist[t], s_wave, &dummy);
+  const uint32_t below = block_excl_scan(t < (1 << RB) ? ghist[t] : 0u, s_wave, &dummy);
   if (t == d) s_base = below;
   uint32_t* row = bhist + (size_t)d * nblocks;
   uint32_t c[4], sum = 0;
@@ -641,6 +645,7 @@ constexpr int kDsItems = 16;
 constexpr int kDsPart = kSortThreads * kDsItems;
 static_assert(kPart % kDsPart == 0, "block ranges split into whole sub-partitions");
 
+template <int RB>
 __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                                const uint32_t* __restrict__ vals_in,
                                                                uint32_t* __restrict__ keys_out,
@@ -650,9 +655,11 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
                                                                const uint32_t* __restrict__ d_overflow) {
   __shared__ uint32_t s_keys[kDsPart];
   __shared__ uint32_t s_vals[kDsPart];
-  __shared__ uint32_t s_wh[kSortThreads / 64][kRadix];
-  __shared__ uint32_t s_local[kRadix];
-  __shared__ uint32_t s_run[kRadix];
+  constexpr int D = 1 << RB;
+  constexpr uint32_t kMask = (uint32_t)(D - 1);
+  __shared__ uint32_t s_wh[kSortThreads / 64][D];
+  __shared__ uint32_t s_local[D];
+  __shared__ uint32_t s_run[D];
   __shared__ uint32_t s_wave[kSortThreads / 64];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const uint32_t n = *d_count;
@@ -660,11 +667,11 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
   uint32_t p0, p1;
   rs_range(n, &p0, &p1);
   const uint64_t b0 = (uint64_t)p0 * kPart, b1 = min((uint64_t)n, (uint64_t)p1 * kPart);
-  s_run[t] = bbase[(size_t)t * gridDim.x + blockIdx.x];
+  if (t < D) s_run[t] = bbase[(size_t)t * gridDim.x + blockIdx.x];
   const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
   for (uint64_t base = b0; base < b1; base += kDsPart) {
     __syncthreads();
-    for (int i = t; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&s_wh[0][0])[i] = 0;
+    for (int i = t; i < (kSortThreads / 64) * D; i += kSortThreads) (&s_wh[0][0])[i] = 0;
     __syncthreads();
     // wave-striped load: wave w owns [w*64*kDsItems, (w+1)*64*kDsItems), item j of lane l at j*64 + l
     uint32_t key[kDsItems], val[kDsItems];
@@ -681,10 +688,10 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
     for (int j = 0; j < kDsItems; ++j) {
       const uint64_t i = wbase + (uint64_t)j * 64 + l;
       const bool ok = i < b1;
-      const uint32_t d = (key[j] >> shift) & 255u;
+      const uint32_t d = (key[j] >> shift) & kMask;
       uint64_t peers = __ballot(ok);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < RB; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t m = __ballot(bit);
         peers &= bit ? m : ~m;
@@ -698,21 +705,24 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
     __syncthreads();
     // per digit (lane t = digit): wave prefixes, sub-partition count, local start
     uint32_t tot = 0;
+    if (t < D) {
 #pragma unroll
-    for (int i = 0; i < kSortThreads / 64; ++i) {
-      const uint32_t c = s_wh[i][t];
-      s_wh[i][t] = tot;
-      tot += c;
+      for (int i = 0; i < kSortThreads / 64; ++i) {
+        const uint32_t c = s_wh[i][t];
+        s_wh[i][t] = tot;
+        tot += c;
+      }
     }
     uint32_t dummy;
-    s_local[t] = block_excl_scan(tot, s_wave, &dummy);
+    const uint32_t lstart = block_excl_scan(tot, s_wave, &dummy);
+    if (t < D) s_local[t] = lstart;
     __syncthreads();
     // scatter into LDS in digit order
 #pragma unroll
     for (int j = 0; j < kDsItems; ++j) {
       const uint64_t i = wbase + (uint64_t)j * 64 + l;
       if (i < b1) {
-        const uint32_t dd = (key[j] >> shift) & 255u;
+        const uint32_t dd = (key[j] >> shift) & kMask;
         const uint32_t lp = s_local[dd] + s_wh[w][dd] + rank[j];
         s_keys[lp] = key[j];
         s_vals[lp] = val[j];
@@ -722,13 +732,13 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
     const uint32_t nvalid = (uint32_t)((b1 - base) < (uint64_t)kDsPart ? (b1 - base) : (uint64_t)kDsPart);
     for (uint32_t i = t; i < nvalid; i += kSortThreads) {
       const uint32_t k = s_keys[i];
-      const uint32_t dd = (k >> shift) & 255u;
+      const uint32_t dd = (k >> shift) & kMask;
       const uint32_t dst = s_run[dd] + (i - s_local[dd]);
       keys_out[dst] = k;
       vals_out[dst] = s_vals[i];
     }
     __syncthreads();
-    s_run[t] += tot;
+    if (t < D) s_run[t] += tot;
   }
 }
 
@@ -1144,6 +1154,20 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   return p;
 }
 
+// One reduce-then-scan pass over the P pairs: digit ps of RB bits.
+template <int RB>
+static hipError_t rs_pass(uint32_t* const* tk, uint32_t* const* pv, int a, int ps, uint32_t* counters,
+                          uint32_t* bhist, uint32_t* thist, unsigned grid_rs, const uint32_t* ov, hipStream_t s) {
+  const int shift = RB * ps;
+  hipLaunchKernelGGL((k_rs_upsweep<RB>), dim3(grid_rs), dim3(kRsUpThreads), 0, s, tk[a], counters + C_NUM_PAIRS, shift,
+                     bhist, thist + ps * kRadix, ov);
+  hipLaunchKernelGGL((k_rs_scan<RB>), dim3(1u << RB), dim3(kSortThreads), 0, s, bhist, (int)grid_rs,
+                     thist + ps * kRadix, ov);
+  hipLaunchKernelGGL((k_rs_downsweep<RB>), dim3(grid_rs), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1],
+                     pv[a ^ 1], counters + C_NUM_PAIRS, shift, bhist, ov);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* ws, uint64_t* keys, uint32_t* vals,
                            uint32_t* ranges, int64_t* d_num_pairs, int32_t* d_overflow, hipStream_t s) {
   char* w = static_cast<char*>(ws);
@@ -1225,17 +1249,24 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K3: load-balanced pair emission in depth order
   hipLaunchKernelGGL(k_emit, dim3(grid_e), dim3(kSortThreads), 0, s, g.views, g.rect, dv[0], offsets, chunk_first,
                      counters, tk[0], pv[0]);
-  // K4b: tile passes over the P pairs (reduce-then-scan)
+  // K4b: tile passes over the P pairs (reduce-then-scan), tpass passes of rb
+  // bits each: the fewest passes, then the narrowest digits (fewer, longer
+  // output runs per digit)
   uint32_t* bhist = reinterpret_cast<uint32_t*>(w + p.off_rs_hist);
   const unsigned grid_rs = parts_p < (unsigned)kRsBlocks ? parts_p : (unsigned)kRsBlocks;
+  int rb = (p.tile_bits + tpass - 1) / tpass;
+  if (rb < 4) rb = 4;
   for (int ps = 0; ps < tpass; ++ps) {
     const int a = ps & 1;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3(grid_rs), dim3(kRsUpThreads), 0, s, tk[a], counters + C_NUM_PAIRS, 8 * ps,
-                       bhist, thist + ps * kRadix, ov);
-    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kSortThreads), 0, s, bhist, (int)grid_rs, thist + ps * kRadix,
-                       ov);
-    hipLaunchKernelGGL(k_rs_downsweep, dim3(grid_rs), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1], pv[a ^ 1],
-                       counters + C_NUM_PAIRS, 8 * ps, bhist, ov);
+    hipError_t e;
+    switch (rb) {
+      case 4: e = rs_pass<4>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+      case 5: e = rs_pass<5>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+      case 6: e = rs_pass<6>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+      case 7: e = rs_pass<7>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+      default: e = rs_pass<8>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+    }
+    if (e != hipSuccess) return e;
   }
   uint32_t* tk_final = tk[tpass & 1];
   // K5: ranges
