@@ -742,15 +742,37 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(const uint32_t* _
   }
 }
 
+// Tile ranges from the sorted tile keys: every lane takes 8 consecutive keys
+// (two 16-byte loads) and their two neighbours, and writes the start / end of
+// every tile that begins / ends among them.
+constexpr int kRangeKeys = 8;
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkeys,
                                                 const uint32_t* __restrict__ counters,
                                                 uint32_t* __restrict__ ranges) {
   if (counters[C_OVERFLOW]) return;
   const uint32_t P = counters[C_NUM_PAIRS];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-    const uint32_t tk = tkeys[i];
-    if (i == 0 || tkeys[i - 1] != tk) ranges[2 * (size_t)tk] = i;
-    if (i == P - 1 || tkeys[i + 1] != tk) ranges[2 * (size_t)tk + 1] = i + 1;
+  constexpr uint32_t kNone = 0xffffffffu;  // no tile (ids are below 2^31)
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kRangeKeys;
+  for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeKeys; i0 < P; i0 += stride) {
+    uint32_t k[kRangeKeys + 2];
+    k[0] = i0 > 0 ? tkeys[i0 - 1] : kNone;
+    if (i0 + kRangeKeys <= P) {
+      const uint4 a = *reinterpret_cast<const uint4*>(tkeys + i0);
+      const uint4 b = *reinterpret_cast<const uint4*>(tkeys + i0 + 4);
+      k[1] = a.x; k[2] = a.y; k[3] = a.z; k[4] = a.w;
+      k[5] = b.x; k[6] = b.y; k[7] = b.z; k[8] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRangeKeys; ++j) k[1 + j] = i0 + j < P ? tkeys[i0 + j] : kNone;
+    }
+    k[kRangeKeys + 1] = i0 + kRangeKeys < P ? tkeys[i0 + kRangeKeys] : kNone;
+#pragma unroll
+    for (int j = 0; j < kRangeKeys; ++j) {
+      const uint32_t i = (uint32_t)(i0 + j), tk = k[1 + j];
+      if (tk == kNone) break;
+      if (k[j] != tk) ranges[2 * (size_t)tk] = i;
+      if (k[j + 2] != tk) ranges[2 * (size_t)tk + 1] = i + 1;
+    }
   }
 }
 
@@ -765,11 +787,12 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
 
 // ---------------------------------------------------------- tile-count path
 // For frames with at most kTcMaxTiles tiles the pairs are binned without a
-// global radix sort: per-tile pair counts (atomics), one scan of the counts
-// into the tile ranges, a scatter of (depth bits, item) into each tile's
-// segment through an atomic cursor (arbitrary order inside the segment), and
-// a sort of every segment by the unique key (depth bits, item).  The result
-// is the same order as the stable (tile, depth) sort of the onesweep path.
+// global radix sort: per-block tile histograms (LDS), per-tile column offsets
+// and one scan of the tile totals into the tile ranges, a scatter of (depth
+// bits, item) into each tile's segment through per-block LDS cursors
+// (arbitrary order inside the segment), and a sort of every segment by the
+// unique key (depth bits, item).  The result is the same order as the stable
+// (tile, depth) sort of the radix path.
 constexpr int kTcMaxTiles = 8192;   // per-block tile histograms in LDS (32 KB)
 constexpr int kTcBig = 64;        // items with more tiles are walked by a whole wavefront
 constexpr int kSegCap = 1024;     // segment sorted in registers in one piece (16 u64 keys per lane): one wavefront per tile
@@ -1272,7 +1295,9 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K5: ranges
   const int64_t pb = (p.capacity + 255) / 256;
   const unsigned pblocks = (unsigned)(pb < 1 ? 1 : (pb > 2048 ? 2048 : pb));
-  hipLaunchKernelGGL(k_ranges, dim3(pblocks), dim3(256), 0, s, tk_final, counters, ranges);
+  const int64_t rbk = (p.capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys);
+  const unsigned rblocks = (unsigned)(rbk < 1 ? 1 : (rbk > 65536 ? 65536 : rbk));
+  hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tk_final, counters, ranges);
   if (keys)
     hipLaunchKernelGGL(k_keys64, dim3(pblocks), dim3(256), 0, s, tk_final, vals, depth_bits, counters, keys);
   return hipGetLastError();

@@ -527,20 +527,18 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
 // ------------------------------------------------------ grad2d row clear
 // Zeroes the grad2d rows of the items that touch a tile: the only rows the
 // backward adds into and the only rows read afterwards.
+// One item per lane (a capped grid-stride loop was latency bound).
 __global__ void k_clear_visible_rows(const uint32_t* __restrict__ tiles, float* __restrict__ grad2d, int64_t items,
                                      int gf4) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += stride) {
-    if (tiles[i] == 0) continue;
-    float4* row = reinterpret_cast<float4*>(grad2d + i * 4 * gf4);
-    for (int j = 0; j < gf4; ++j) row[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= items || tiles[i] == 0) return;
+  float4* row = reinterpret_cast<float4*>(grad2d + i * 4 * gf4);
+  for (int j = 0; j < gf4; ++j) row[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 hipError_t launch_clear_grad2d(const uint32_t* tiles, float* grad2d, int64_t items, int gf, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  int64_t blocks = (items + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  const int64_t blocks = (items + 255) / 256;  // items < 2^32: fewer than 2^24 blocks
   hipLaunchKernelGGL(k_clear_visible_rows, dim3((unsigned)blocks), dim3(256), 0, s, tiles, grad2d, items, gf / 4);
   return hipGetLastError();
 }
