@@ -35,8 +35,8 @@ VALU_PEAK_TFLOPS = 78.6
 # 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
 # taken on (hash of the blend's source text); otherwise traffic is null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "d842f81d544b0b183aa72a52eb1ce42e4046e7da40af8020fbe632fa6b1fc880",
-    "fetch_kib": 43668.33, "write_kib": 24003.35, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "cedf7c6243e69386f71faaf201e0ad477e757b5535c52ea2abc803e1cd3e17aa",
+    "fetch_kib": 43668.12, "write_kib": 24000.09, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles of the frame blended by the CPU oracle")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU baseline (for rocprofv3)")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 64-view training step")
+    ap.add_argument("--profile-multiview", action="store_true",
+                    help="only the 64-view training step, a few steps (for rocprofv3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-qps", type=float, default=200.0)
@@ -118,6 +120,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.profile_multiview:
+        args.steps = min(args.steps, 5)
+        print(json.dumps({"multiview": multiview_step(args, torch, synth, DeviceScene, RenderPlan, LossBuffers)}),
+              flush=True)
+        return
 
     scene = synth.config2_scene()
     cam = synth.config2_camera()

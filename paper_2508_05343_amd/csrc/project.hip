@@ -446,8 +446,10 @@ __device__ __forceinline__ float* geo_dst(const gabsplat_scene_grads& gr, int64_
 
 // Chain rule of the geometry part for primitive i, parameters in row P (LDS);
 // the gradients replace them in the same layout.  grad2d rows are `gstride`
-// floats apart; the first round_up(10 + 3K, 4) are read.
-template <int K>
+// floats apart; the first round_up(10 + 3K, 4) are read.  FILT compiles in
+// the anti-aliasing filters (flags GABSPLAT_FLAG_MIP_*), so that the plain
+// variant keeps its register budget.
+template <int K, bool FILT>
 __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int scene_index,
                                             const uint32_t* __restrict__ tiles, const float* __restrict__ depth,
                                             const float* __restrict__ grad2d, int gstride, int64_t i, float* P) {
@@ -460,8 +462,8 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
   const float s_in[3] = {P[3], P[4], P[5]};
   const float q[4] = {P[6], P[7], P[8], P[9]};
   const float o = P[10];
-  const bool mip3d = (S.flags & GABSPLAT_FLAG_MIP_3D) != 0;
-  const bool mip2d = (S.flags & GABSPLAT_FLAG_MIP_2D) != 0;
+  const bool mip3d = FILT && (S.flags & GABSPLAT_FLAG_MIP_3D) != 0;
+  const bool mip2d = FILT && (S.flags & GABSPLAT_FLAG_MIP_2D) != 0;
   const float dil = mip2d ? kMip2dVariance : kDilation;
   // scales the projection sees (filtered: sqrt(s^2 + v))
   const float fv = mip3d ? S.filter3d[i] : 0.f;
@@ -749,7 +751,7 @@ __device__ __forceinline__ V3 colour_bwd_one(const void* __restrict__ table, int
   return gmean;
 }
 
-template <int K, bool COLOUR>
+template <int K, bool COLOUR, bool FILT>
 __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
                                                               const uint32_t* __restrict__ tiles,
                                                               const float* __restrict__ depth,
@@ -825,7 +827,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
           gr.means[2 * n + ii] += gm.z;
         }
       } else {
-        geo_bwd_one<K>(table, scene_index, tiles, depth, grad2d, gstride, ii, row);
+        geo_bwd_one<K, FILT>(table, scene_index, tiles, depth, grad2d, gstride, ii, row);
       }
     }
     __syncthreads();
@@ -898,10 +900,14 @@ static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat
   // geometry / frequency / opacity part, then the colour part (which adds
   // its view-direction term to the mean gradient): two register budgets
   const dim3 grid((unsigned)((n + kBwdBlock - 1) / kBwdBlock));
-  hipLaunchKernelGGL((k_preprocess_bwd<K, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
-                     gr, ov);
-  hipLaunchKernelGGL((k_preprocess_bwd<K, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth, gr.grad2d,
-                     gr, ov);
+  if (h.scenes[sc].flags & (GABSPLAT_FLAG_MIP_2D | GABSPLAT_FLAG_MIP_3D))
+    hipLaunchKernelGGL((k_preprocess_bwd<K, false, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
+                       gr.grad2d, gr, ov);
+  else
+    hipLaunchKernelGGL((k_preprocess_bwd<K, false, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
+                       gr.grad2d, gr, ov);
+  hipLaunchKernelGGL((k_preprocess_bwd<K, true, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
+                     gr.grad2d, gr, ov);
   return hipGetLastError();
 }
 
