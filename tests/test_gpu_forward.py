@@ -80,10 +80,13 @@ def _bin_sort_case(n, views, seed, width=200, height=150, hot_share=0.0):
 @pytest.mark.parametrize("n,views,seed,width,height,hot",
                          [(3000, 1, 1, 200, 150, 0.0), (20000, 2, 2, 200, 150, 0.0), (1, 1, 3, 200, 150, 0.0),
                           (9000, 3, 4, 200, 150, 0.0),
-                          # a tile with ~11,000 pairs: sorted as runs of 4096 merged pairwise
+                          # a tile with ~11,000 pairs: sorted as runs of 1024 merged pairwise
                           (20000, 1, 5, 200, 150, 0.7),
-                          # 8 views of 1024x1024 = 33,000+ tiles: the radix-sort binning path
-                          (3000, 8, 6, 1024, 1024, 0.0)])
+                          # more than 8192 tiles take the radix-sort binning path; its tile passes
+                          # use digits of 8 (38,859 tiles: 16 bits), 7 (13,005: 14 bits) and
+                          # 6 bits (123,751: 17 bits)
+                          (3000, 8, 6, 1024, 1024, 0.0), (2000, 3, 7, 1024, 1024, 0.0),
+                          (800, 20, 8, 1024, 1024, 0.0)])
 def test_bin_sort_bit_exact_on_synthetic_geometry(gpu_lib, n, views, seed, width, height, hot):
     """Stage-isolated K2-K5: seeded synthetic rects/depths (with ties) go into
     the GPU bin sort and the oracle's library stable sort; keys, values and

@@ -41,6 +41,29 @@ def test_config2_depth_keys_and_visibility(gpu_lib, big):
     print(f"visible {vis_o.sum()} pairs {P} fragile rects {pr.fragile_rect.sum()}")
 
 
+def test_config2_heaviest_tiles_binned_order(gpu_lib, big):
+    """The tiles with the most pairs (chosen from the oracle's rects) come out
+    of the GPU binning in the oracle's (depth, index) order, item for item
+    (items with a fragile rect are left out of both lists)."""
+    sc, cam, ds, plan, pr = big
+    vis = pr.visible.numpy()
+    cnt = np.zeros((cam.tiles_y, cam.tiles_x), np.int64)
+    for x0, y0, x1, y1 in pr.rect[vis]:
+        cnt[y0:y1, x0:x1] += 1
+    heavy = np.argsort(cnt.ravel())[::-1][:6]
+    assert cnt.ravel()[heavy[0]] > 512  # the longest segments take the 1024-key register sort
+    order = O.depth_order(pr.depth32, vis)
+    ranges = plan.ranges.cpu().numpy().view(np.uint32)
+    vals = plan.vals.cpu().numpy().view(np.uint32)
+    frag = pr.fragile_rect
+    for t in heavy:
+        tx, ty = int(t % cam.tiles_x), int(t // cam.tiles_x)
+        ref = O.tile_candidates(pr, order, tx, ty)
+        got = vals[ranges[t, 0]:ranges[t, 1]].astype(np.int64)
+        ref, got = ref[~frag[ref]], got[~frag[got]]
+        assert np.array_equal(got, ref), (tx, ty, len(got), len(ref))
+
+
 def test_config2_sampled_tiles_forward(gpu_lib, big):
     sc, cam, ds, plan, pr = big
     rng = np.random.Generator(np.random.PCG64(2024))
