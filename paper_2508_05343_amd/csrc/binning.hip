@@ -15,16 +15,14 @@
 // the tile bits.  All pairs of one primitive share its depth, so the depth
 // passes run on the visible primitives before duplication (V items instead
 // of P pairs); duplication then emits pairs in depth order and only
-// ceil(tile_bits / 8) passes run on the P pairs.  Every pass is one onesweep
-// kernel: partitions of 4096 keys are taken from an atomic ticket (so a
-// partition only ever waits on partitions whose blocks are already running),
-// ranked in LDS with wave64 ballot matching, and placed with a decoupled
-// look-back over per-(partition, digit) status words.  Launch sequence:
-// clear the workspace head; compaction of the visible items fused with the
-// depth-digit histograms; 4 depth passes; tiles-touched scan; pair emission
-// balanced over fixed chunks of pairs, fused with the tile-digit histograms;
-// the tile passes; per-tile ranges from the boundaries between runs of equal
-// tile keys.
+// ceil(tile_bits / 8) passes of equal digit width run on the P pairs.  Every
+// pass is reduce-then-scan: per-block digit counts over contiguous ranges of
+// partitions of 4096 keys, one scan into (digit, block) output bases, and a
+// downsweep that ranks each partition in LDS with wave64 ballot matching and
+// places it stably.  Launch sequence: clear the workspace head; compaction of
+// the visible items; 4 depth passes; tiles-touched scan; pair emission
+// balanced over fixed chunks of pairs; the tile passes; per-tile ranges from
+// the boundaries between runs of equal tile keys.
 #include <hip/hip_runtime.h>
 
 #include "gs_block.h"
@@ -49,8 +47,6 @@ constexpr int kEmitItems = kEmitChunk / kSortThreads;  // consecutive pairs walk
 enum {
   C_TICKET_COMPACT = 0,
   C_TICKET_EXPAND = 1,
-  C_TICKET_DEPTH = 2,  // 4 entries
-  C_TICKET_TILE = 6,   // 4 entries
   C_NUM_VISIBLE = 16,
   C_NUM_PAIRS = 17,
   C_OVERFLOW = 18,
@@ -124,18 +120,15 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 
 // ------------------------------------------------------------- compaction
 // x_i = (tiles[i] > 0) over all items; emits the compacted depth keys and item
-// ids, accumulates the 4 depth-digit histograms and writes V.
+// ids in item order and writes V.
 __global__ __launch_bounds__(kSortThreads) void k_compact(uint32_t n, const uint32_t* __restrict__ tiles,
                                                           const uint32_t* __restrict__ depth_bits,
                                                           uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
-                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ look,
-                                                          uint32_t* __restrict__ hist) {
+                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ look) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
   __shared__ uint32_t s_misc[2];
-  __shared__ uint32_t s_h[kDepthPasses * kRadix];
   const int t = threadIdx.x;
   if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_COMPACT], 1u);
-  for (int i = t; i < kDepthPasses * kRadix; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
   const uint32_t part = s_misc[0];
   const uint64_t base = (uint64_t)part * kPart;
@@ -164,166 +157,10 @@ __global__ __launch_bounds__(kSortThreads) void k_compact(uint32_t n, const uint
   for (int j = 0; j < kSortItems; ++j) {
     if ((flags >> j) & 1u) {
       const uint64_t i = first + j;
-      const uint32_t k = depth_bits[i];
-      dkeys[pos] = k;
+      dkeys[pos] = depth_bits[i];
       dvals[pos] = (uint32_t)i;
-#pragma unroll
-      for (int p = 0; p < kDepthPasses; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (8 * p)) & 255u)], 1u);
       ++pos;
     }
-  }
-  __syncthreads();
-  for (int i = t; i < kDepthPasses * kRadix; i += kSortThreads) {
-    const uint32_t v = s_h[i];
-    if (v) atomicAdd(&hist[i], v);
-  }
-}
-
-// --------------------------------------------------------------- onesweep
-// One LSD pass over digit (key >> shift) & 255.  `look` is laid out
-// [partition][npass][256]; `hist` holds this pass's 256 digit counts (the
-// exclusive digit offsets are scanned inside every block).
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __restrict__ keys_in,
-                                                           const uint32_t* __restrict__ vals_in,
-                                                           uint32_t* __restrict__ keys_out,
-                                                           uint32_t* __restrict__ vals_out,
-                                                           const uint32_t* __restrict__ d_count, int shift,
-                                                           int pass, int npass, const uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ look, uint32_t* __restrict__ ticket,
-                                                           const uint32_t* __restrict__ d_overflow) {
-  __shared__ uint32_t s_keys[kPart];
-  __shared__ uint32_t s_vals[kPart];
-  __shared__ uint32_t s_wh[kSortThreads / 64][kRadix];
-  __shared__ uint32_t s_local[kRadix];
-  __shared__ uint32_t s_gbase[kRadix];
-  __shared__ uint32_t s_wave[kSortThreads / 64];
-  __shared__ uint32_t s_part;
-
-  if (d_overflow != nullptr && *d_overflow != 0) return;
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const uint32_t n = *d_count;
-  // Only the first ceil(n / kPart) blocks take tickets (one shared counter:
-  // every ticket is a same-address atomic).  When the grid has a block per
-  // partition each of them takes exactly one; otherwise blocks keep taking
-  // tickets until they run past the key count.  A block only ever waits on
-  // partitions that running blocks hold.
-  const uint32_t nparts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
-  if (blockIdx.x >= nparts) return;
-  const bool one_each = gridDim.x >= nparts;
-  // exclusive digit offsets of this pass
-  uint32_t dummy;
-  const uint32_t goff = block_excl_scan(hist[t], s_wave, &dummy);
-  for (;;) {
-    __syncthreads();
-    if (t == 0) s_part = atomicAdd(ticket, 1u);
-    for (int i = t; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&s_wh[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t part = s_part;
-    const uint64_t base = (uint64_t)part * kPart;
-    if (base >= n) return;
-
-    // warp-striped load: wave w owns [w*1024, (w+1)*1024), item j of lane l at j*64 + l
-    uint32_t key[kSortItems], val[kSortItems];
-    uint16_t rank[kSortItems];
-    const uint64_t wbase = base + (uint64_t)w * (64 * kSortItems);
-#pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint64_t i = wbase + (uint64_t)j * 64 + l;
-      const bool ok = i < n;
-      key[j] = ok ? keys_in[i] : 0xffffffffu;
-      val[j] = ok ? vals_in[i] : 0u;
-    }
-    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-#pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint64_t i = wbase + (uint64_t)j * 64 + l;
-      const bool ok = i < n;
-      const uint32_t d = (key[j] >> shift) & 255u;
-      uint64_t peers = __ballot(ok);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      const uint32_t lower = (uint32_t)__popcll(peers & lt_mask);
-      const uint32_t cur = s_wh[w][d];
-      rank[j] = (uint16_t)(cur + lower);
-      const bool leader = ok && ((peers >> l) == 1ull);
-      if (leader) s_wh[w][d] = cur + (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-
-    // per digit: wave prefix, block count, publish, look back
-    const int d = t;
-    uint32_t tot = 0;
-#pragma unroll
-    for (int i = 0; i < kSortThreads / 64; ++i) {
-      const uint32_t c = s_wh[i][d];
-      s_wh[i][d] = tot;
-      tot += c;
-    }
-    uint32_t* my_look = look + ((size_t)part * npass + pass) * kRadix + d;
-    uint32_t excl = 0;
-    if (part == 0) {
-      st_flag(my_look, kFlagInc | tot);
-    } else {
-      st_flag(my_look, kFlagAgg | tot);
-      // walk back 64 predecessors per round trip (independent loads in flight):
-      // a walk over p predecessors costs ceil(p / 64) memory latencies
-      constexpr int kAhead = 64;
-      int64_t hi = (int64_t)part - 1;
-      bool found = false;
-      while (!found) {
-        uint32_t v[kAhead];
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-          const int64_t p = hi - q;
-          v[q] = (p >= 0) ? ld_flag(look + ((size_t)p * npass + pass) * kRadix + d) : kFlagInc;
-        }
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-          if (!found) {
-            const int64_t p = hi - q;
-            uint32_t x = v[q];
-            while ((x & (kFlagAgg | kFlagInc)) == 0) {
-              __builtin_amdgcn_s_sleep(1);
-              x = ld_flag(look + ((size_t)p * npass + pass) * kRadix + d);
-            }
-            excl += x & kCountMask;
-            found = (x & kFlagInc) != 0;
-          }
-        }
-        hi -= kAhead;
-      }
-      st_flag(my_look, kFlagInc | (excl + tot));
-    }
-    s_gbase[d] = goff + excl;
-    const uint32_t lstart = block_excl_scan(tot, s_wave, &dummy);
-    s_local[d] = lstart;
-    __syncthreads();
-
-    // scatter into LDS in digit order
-#pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint64_t i = wbase + (uint64_t)j * 64 + l;
-      if (i < n) {
-        const uint32_t dd = (key[j] >> shift) & 255u;
-        const uint32_t lp = s_local[dd] + s_wh[w][dd] + rank[j];
-        s_keys[lp] = key[j];
-        s_vals[lp] = val[j];
-      }
-    }
-    __syncthreads();
-    const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)kPart ? (n - base) : (uint64_t)kPart);
-    for (uint32_t i = t; i < nvalid; i += kSortThreads) {
-      const uint32_t k = s_keys[i];
-      const uint32_t dd = (k >> shift) & 255u;
-      const uint32_t dst = s_gbase[dd] + (i - s_local[dd]);
-      keys_out[dst] = k;
-      vals_out[dst] = s_vals[i];
-    }
-    if (one_each) return;
   }
 }
 
@@ -356,7 +193,11 @@ __global__ __launch_bounds__(kSortThreads) void k_expand_scan(const uint32_t* __
     }
     return;
   }
-  // tickets as in k_onesweep: only the blocks needed take them
+  // Only the first ceil(V / kPart) blocks take tickets (one shared counter:
+  // every ticket is a same-address atomic).  When the grid has a block per
+  // partition each of them takes exactly one; otherwise blocks keep taking
+  // tickets until they run past V.  A block only ever waits on partitions
+  // that running blocks hold.
   const uint32_t nparts = (V + kPart - 1) / kPart;
   if (blockIdx.x >= nparts) return;
   const bool one_each = gridDim.x >= nparts;
@@ -549,14 +390,15 @@ __global__ __launch_bounds__(kSortThreads) void k_emit(const void* __restrict__ 
 }
 
 // ------------------------------------------------ reduce-then-scan passes
-// The tile passes over the P pairs are reduce-then-scan LSD passes.  With
-// hundreds of partitions in flight, a single-pass look-back makes every
-// partition read the 256 digit words of each of them, and those loads bound
-// the pass; here nothing waits on another block.  Block b owns a contiguous
+// Every pass of the radix path (depth passes over the V visible items, tile
+// passes over the P pairs) is a reduce-then-scan LSD pass.  With hundreds of
+// partitions in flight, a single-pass look-back makes every partition read
+// the digit words of each of them, and those loads bound the pass; here
+// nothing waits on another block.  Block b owns a contiguous
 // range of partitions of kPart keys: (1) k_rs_upsweep counts its digits (and
 // adds them into the pass's global histogram), (2) k_rs_scan turns the counts
 // into the output base of every (digit, block), (3) k_rs_downsweep re-reads the
-// range and places each partition stably (the ranking of k_onesweep),
+// range and places each partition stably (ranks from wave64 ballot matching),
 // advancing the block's digit bases partition by partition.
 constexpr int kRsBlocks = 768;  // three 256-lane downsweep blocks per CU (141 VGPRs, 39 KB LDS)
 static_assert(kRadix == kSortThreads, "one lane per digit");
@@ -1154,8 +996,6 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_tcount = off; off += (size_t)total_tiles * 4;  // tile totals
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
   p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
-  p.off_look_sort = off;  // look-back words of the depth passes
-  off += (size_t)p.parts_items * kDepthPasses * kRadix * 4;
   off = align_up(off);
   p.off_dkeys_a = off; off = align_up(off + (size_t)items * 4);
   // --- body
@@ -1177,17 +1017,17 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   return p;
 }
 
-// One reduce-then-scan pass over the P pairs: digit ps of RB bits.
+// One reduce-then-scan pass: the RB-bit digit at `shift` of the *d_count
+// keys (with their values) from kin / vin to kout / vout; ghist (zeroed)
+// receives the pass's digit histogram.
 template <int RB>
-static hipError_t rs_pass(uint32_t* const* tk, uint32_t* const* pv, int a, int ps, uint32_t* counters,
-                          uint32_t* bhist, uint32_t* thist, unsigned grid_rs, const uint32_t* ov, hipStream_t s) {
-  const int shift = RB * ps;
-  hipLaunchKernelGGL((k_rs_upsweep<RB>), dim3(grid_rs), dim3(kRsUpThreads), 0, s, tk[a], counters + C_NUM_PAIRS, shift,
-                     bhist, thist + ps * kRadix, ov);
-  hipLaunchKernelGGL((k_rs_scan<RB>), dim3(1u << RB), dim3(kSortThreads), 0, s, bhist, (int)grid_rs,
-                     thist + ps * kRadix, ov);
-  hipLaunchKernelGGL((k_rs_downsweep<RB>), dim3(grid_rs), dim3(kSortThreads), 0, s, tk[a], pv[a], tk[a ^ 1],
-                     pv[a ^ 1], counters + C_NUM_PAIRS, shift, bhist, ov);
+static hipError_t rs_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                          const uint32_t* d_count, int shift, uint32_t* bhist, uint32_t* ghist, unsigned grid,
+                          const uint32_t* ov, hipStream_t s) {
+  hipLaunchKernelGGL((k_rs_upsweep<RB>), dim3(grid), dim3(kRsUpThreads), 0, s, kin, d_count, shift, bhist, ghist, ov);
+  hipLaunchKernelGGL((k_rs_scan<RB>), dim3(1u << RB), dim3(kSortThreads), 0, s, bhist, (int)grid, ghist, ov);
+  hipLaunchKernelGGL((k_rs_downsweep<RB>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin, kout, vout, d_count, shift,
+                     bhist, ov);
   return hipGetLastError();
 }
 
@@ -1198,7 +1038,6 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   uint32_t* hist = reinterpret_cast<uint32_t*>(w + p.off_hist);
   uint32_t* look_compact = reinterpret_cast<uint32_t*>(w + p.off_look_scan);
   uint32_t* look_expand = look_compact + (p.parts_items + 1);
-  uint32_t* look_depth = reinterpret_cast<uint32_t*>(w + p.off_look_sort);
   uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(w + p.off_dkeys_a), reinterpret_cast<uint32_t*>(w + p.off_dkeys_b)};
   uint32_t* dv[2] = {reinterpret_cast<uint32_t*>(w + p.off_dvals_a), reinterpret_cast<uint32_t*>(w + p.off_dvals_b)};
   uint32_t* tk[2] = {reinterpret_cast<uint32_t*>(w + p.off_tkeys_a), reinterpret_cast<uint32_t*>(w + p.off_tkeys_b)};
@@ -1254,16 +1093,18 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   uint32_t* offsets = reinterpret_cast<uint32_t*>(w + p.off_offsets);
   uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 
-  // K2a: compaction + depth histograms
+  uint32_t* bhist = reinterpret_cast<uint32_t*>(w + p.off_rs_hist);
+  // K2a: compaction of the visible items (depth keys, item ids, V)
   if (p.items > 0)
     hipLaunchKernelGGL(k_compact, dim3(parts_i), dim3(kSortThreads), 0, s, (uint32_t)p.items, g.tiles, depth_bits,
-                       dk[0], dv[0], counters, look_compact, hist);
+                       dk[0], dv[0], counters, look_compact);
   // K4a: depth passes over the V visible items (even count: result in dk[0], dv[0])
+  const unsigned grid_d = parts_i < (unsigned)kRsBlocks ? parts_i : (unsigned)kRsBlocks;
   for (int ps = 0; ps < kDepthPasses; ++ps) {
     const int a = ps & 1;
-    hipLaunchKernelGGL(k_onesweep, dim3(grid_i), dim3(kSortThreads), 0, s, dk[a], dv[a], dk[a ^ 1], dv[a ^ 1],
-                       counters + C_NUM_VISIBLE, 8 * ps, ps, kDepthPasses, hist + ps * kRadix, look_depth,
-                       counters + C_TICKET_DEPTH + ps, nullptr);
+    const hipError_t e = rs_pass<8>(dk[a], dv[a], dk[a ^ 1], dv[a ^ 1], counters + C_NUM_VISIBLE, 8 * ps, bhist,
+                                    hist + ps * kRadix, grid_d, nullptr, s);
+    if (e != hipSuccess) return e;
   }
   // K2b: tiles-touched scan in depth order, P, overflow
   uint32_t* thist = hist + kDepthPasses * kRadix;
@@ -1275,7 +1116,6 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   // K4b: tile passes over the P pairs (reduce-then-scan), tpass passes of rb
   // bits each: the fewest passes, then the narrowest digits (fewer, longer
   // output runs per digit)
-  uint32_t* bhist = reinterpret_cast<uint32_t*>(w + p.off_rs_hist);
   const unsigned grid_rs = parts_p < (unsigned)kRsBlocks ? parts_p : (unsigned)kRsBlocks;
   int rb = (p.tile_bits + tpass - 1) / tpass;
   if (rb < 4) rb = 4;
@@ -1283,11 +1123,16 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     const int a = ps & 1;
     hipError_t e;
     switch (rb) {
-      case 4: e = rs_pass<4>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
-      case 5: e = rs_pass<5>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
-      case 6: e = rs_pass<6>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
-      case 7: e = rs_pass<7>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
-      default: e = rs_pass<8>(tk, pv, a, ps, counters, bhist, thist, grid_rs, ov, s); break;
+      case 4: e = rs_pass<4>(tk[a], pv[a], tk[a ^ 1], pv[a ^ 1], counters + C_NUM_PAIRS, 4 * ps, bhist,
+                                  thist + ps * kRadix, grid_rs, ov, s); break;
+      case 5: e = rs_pass<5>(tk[a], pv[a], tk[a ^ 1], pv[a ^ 1], counters + C_NUM_PAIRS, 5 * ps, bhist,
+                                  thist + ps * kRadix, grid_rs, ov, s); break;
+      case 6: e = rs_pass<6>(tk[a], pv[a], tk[a ^ 1], pv[a ^ 1], counters + C_NUM_PAIRS, 6 * ps, bhist,
+                                  thist + ps * kRadix, grid_rs, ov, s); break;
+      case 7: e = rs_pass<7>(tk[a], pv[a], tk[a ^ 1], pv[a ^ 1], counters + C_NUM_PAIRS, 7 * ps, bhist,
+                                  thist + ps * kRadix, grid_rs, ov, s); break;
+      default: e = rs_pass<8>(tk[a], pv[a], tk[a ^ 1], pv[a ^ 1], counters + C_NUM_PAIRS, 8 * ps, bhist,
+                              thist + ps * kRadix, grid_rs, ov, s); break;
     }
     if (e != hipSuccess) return e;
   }

@@ -106,7 +106,7 @@ struct BinSortPlan {
   size_t bytes;
   // offsets of each workspace region
   size_t off_counters, off_dkeys_a, off_dkeys_b, off_dvals_a, off_dvals_b, off_offsets, off_chunks;
-  size_t off_tkeys_a, off_tkeys_b, off_pvals_b, off_hist, off_look_sort, off_look_scan, off_tcount, off_tcursor, off_rs_hist, off_tcmat, off_tcpair_a, off_tcpair_b;
+  size_t off_tkeys_a, off_tkeys_b, off_pvals_b, off_hist, off_look_scan, off_tcount, off_tcursor, off_rs_hist, off_tcmat, off_tcpair_a, off_tcpair_b;
   int64_t parts_items, parts_pairs;
 };
 BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles);
