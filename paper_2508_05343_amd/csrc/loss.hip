@@ -155,13 +155,19 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
       const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
       const float A1 = 2.f * mx * my + C1, A2 = 2.f * sxy + C2;
       const float B1 = mx * mx + my * my + C1, B2 = sxx + syy + C2;
-      const float s = (A1 * A2) / (B1 * B2);
+      // four hardware reciprocals (about 1 ulp) instead of seven IEEE
+      // divisions; A1, B1 >= C1 and B2 >= C2 (up to rounding of the moments),
+      // A2 takes the sign of the covariance
+      const float rA1 = __builtin_amdgcn_rcpf(A1), rA2 = __builtin_amdgcn_rcpf(A2);
+      const float rB1 = __builtin_amdgcn_rcpf(B1), rB2 = __builtin_amdgcn_rcpf(B2);
+      const float s = (A1 * A2) * (rB1 * rB2);
       ssim += s;
       l1 += fabsf(s_in[0][r0 + o + kHalo][q + kHalo] - s_in[1][r0 + o + kHalo][q + kHalo]);
       const size_t off = c * plane + (size_t)gy * W + gx;
-      f3[off] = g * s * (2.f * my / A1 - 2.f * my / A2 - 2.f * mx / B1 + 2.f * mx / B2);
-      f3[nn + off] = g * (-s / B2);
-      f3[2 * nn + off] = g * (2.f * s / A2);
+      const float gs = g * s;
+      f3[off] = 2.f * gs * (my * (rA1 - rA2) + mx * (rB2 - rB1));
+      f3[nn + off] = -gs * rB2;
+      f3[2 * nn + off] = 2.f * gs * rA2;
     }
   }
   const float ts = block_sum(ssim, s_red);
