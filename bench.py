@@ -35,8 +35,8 @@ VALU_PEAK_TFLOPS = 78.6
 # 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
 # taken on (hash of the blend's source text); otherwise traffic is null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "cedf7c6243e69386f71faaf201e0ad477e757b5535c52ea2abc803e1cd3e17aa",
-    "fetch_kib": 43668.12, "write_kib": 24000.09, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "2f1d830f667311ef68027f5839ab22d32bb4a5e203ba298d01336564c0769a13",
+    "fetch_kib": 43671.11, "write_kib": 24002.92, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
