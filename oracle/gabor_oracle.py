@@ -595,7 +595,8 @@ def render_grads(scene, cam, dl_dimage: np.ndarray, mode="binned", attenuation=F
     img = render(p, ct, mode, scene_f32=scene, attenuation=attenuation, mip2d=mip2d, filter3d=filter3d)
     g = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
     (img.color * g).sum().backward()
-    return {k: v.grad.numpy() for k, v in p.items()}
+    # attributes outside the graph (the empty frequency arrays of K = 0) get zeros
+    return {k: (v.grad.numpy() if v.grad is not None else np.zeros(tuple(v.shape))) for k, v in p.items()}
 
 
 def mean2d_grads(scene, cam, dl_dimage: np.ndarray, attenuation=False, mip2d=False, filter3d=None):

@@ -66,6 +66,23 @@ def test_backward_k4_sh3_rotated_camera(gpu_lib):
     _check_grads(sc, cam, 7, scene_name="sh3 k4")
 
 
+@pytest.mark.parametrize("k", [0, 1, 5, 8])
+def test_forward_and_backward_every_component_count(gpu_lib, k):
+    """K = 0 (the Gaussian special case: 10 reduced components), 1, 5 and 8
+    (34 components, 11 staged float4s per record): image and gradients
+    against the oracle."""
+    sc = synth.uniform_scene(60 + k, 400, k, sh_degree=1, log_scale_mu=-2.9)
+    cam = synth.pinhole_camera(56, 40, 60.0, eye=(0.3, -0.2, -3.0), target=(0.0, 0.0, 0.0), bg=(0.2, 0.1, 0.3))
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    torch.cuda.synchronize()
+    ref = O.render_scene(sc, cam, "binned")
+    ok = ~ref.fragile
+    err = np.abs(plan.view_image(0).cpu().numpy() - ref.color.numpy())[:, ok].max()
+    assert err <= 1e-4, err
+    _check_grads(sc, cam, 70 + k, scene_name=f"k{k}")
+
+
 def test_loss_matches_oracle(gpu_lib):
     from paper_2508_05343_amd.rasterize import LossBuffers
     for (c, h, w, seed) in [(3, 40, 56, 1), (3, 17, 33, 2), (1, 5, 7, 3)]:
