@@ -45,7 +45,6 @@ constexpr int kEmitItems = kEmitChunk / kSortThreads;  // consecutive pairs walk
 
 // counters (u32) at the start of the workspace
 enum {
-  C_TICKET_COMPACT = 0,
   C_TICKET_EXPAND = 1,
   C_NUM_VISIBLE = 16,
   C_NUM_PAIRS = 17,
@@ -119,48 +118,119 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- compaction
-// x_i = (tiles[i] > 0) over all items; emits the compacted depth keys and item
-// ids in item order and writes V.
-__global__ __launch_bounds__(kSortThreads) void k_compact(uint32_t n, const uint32_t* __restrict__ tiles,
-                                                          const uint32_t* __restrict__ depth_bits,
-                                                          uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
-                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ look) {
+// The visible items (tiles[i] > 0) with their depth keys, in item order, and
+// V, without a single-pass chain: block b owns a contiguous range of items
+// (whole steps of kPart); k_cs_count counts its visible items, k_cs_scan turns
+// the counts into block offsets and writes V, k_cs_write re-reads the range
+// step by step and writes every step in item order.
+__device__ __forceinline__ void cs_range(uint64_t n, uint64_t* b0, uint64_t* b1) {
+  const uint64_t nparts = (n + kPart - 1) / kPart;
+  const uint64_t per = (nparts + gridDim.x - 1) / gridDim.x;
+  *b0 = min(n, (uint64_t)blockIdx.x * per * kPart);
+  *b1 = min(n, *b0 + per * kPart);
+}
+
+__device__ __forceinline__ uint32_t block_total_256(uint32_t v, uint32_t* s_wave) {
+  uint32_t total;
+  (void)block_excl_scan(v, s_wave, &total);
+  return total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_cs_count(uint64_t n, const uint32_t* __restrict__ tiles,
+                                                           uint32_t* __restrict__ bcount) {
   __shared__ uint32_t s_wave[kSortThreads / 64];
-  __shared__ uint32_t s_misc[2];
+  uint64_t b0, b1;
+  cs_range(n, &b0, &b1);
+  uint32_t c = 0;
+  constexpr int kU = 8;  // loads in flight per lane
+  for (uint64_t i0 = b0 + threadIdx.x; i0 < b1; i0 += (uint64_t)kU * kSortThreads) {
+    uint32_t x[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const uint64_t i = i0 + (uint64_t)j * kSortThreads;
+      x[j] = i < b1 ? tiles[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kU; ++j) c += x[j] > 0u ? 1u : 0u;
+  }
+  const uint32_t total = block_total_256(c, s_wave);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = total;
+}
+
+// One block: bcount[b] := visible items of the blocks before b; V.  nblocks <= 4 * kSortThreads.
+__global__ __launch_bounds__(kSortThreads) void k_cs_scan(uint32_t* __restrict__ bcount, int nblocks,
+                                                          uint32_t* __restrict__ counters) {
+  __shared__ uint32_t s_wave[kSortThreads / 64];
   const int t = threadIdx.x;
-  if (t == 0) s_misc[0] = atomicAdd(&counters[C_TICKET_COMPACT], 1u);
-  __syncthreads();
-  const uint32_t part = s_misc[0];
-  const uint64_t base = (uint64_t)part * kPart;
-  if (base >= n) return;
-  const uint64_t first = base + (uint64_t)t * kSortItems;
-  uint32_t flags = 0, sum = 0;
+  uint32_t c[4], sum = 0;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t i = first + j;
-    const uint32_t v = (i < n && tiles[i] > 0) ? 1u : 0u;
-    flags |= v << j;
-    sum += v;
+  for (int j = 0; j < 4; ++j) {
+    const int b = 4 * t + j;
+    c[j] = b < nblocks ? bcount[b] : 0u;
+    sum += c[j];
   }
-  uint32_t block_total;
-  const uint32_t tpre = block_excl_scan(sum, s_wave, &block_total);
-  if (t < 64) {
-    const uint32_t excl = lookback_wave(look, part, block_total);
-    if (t == 0) {
-      s_misc[1] = excl;
-      if (base + kPart >= n) counters[C_NUM_VISIBLE] = excl + block_total;
-    }
-  }
-  __syncthreads();
-  uint32_t pos = s_misc[1] + tpre;
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, s_wave, &total);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    if ((flags >> j) & 1u) {
-      const uint64_t i = first + j;
-      dkeys[pos] = depth_bits[i];
-      dvals[pos] = (uint32_t)i;
-      ++pos;
+  for (int j = 0; j < 4; ++j) {
+    const int b = 4 * t + j;
+    if (b < nblocks) bcount[b] = run;
+    run += c[j];
+  }
+  if (t == 0) counters[C_NUM_VISIBLE] = total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_cs_write(uint64_t n, const uint32_t* __restrict__ tiles,
+                                                           const uint32_t* __restrict__ depth_bits,
+                                                           const uint32_t* __restrict__ bcount,
+                                                           uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
+  // A step of kPart items is loaded striped (item base + j * 256 + t:
+  // coalesced).  Item order is (j, wave, lane), so an item's output position
+  // is the number of visible items in the earlier (j, wave) slots plus its
+  // rank in its wave's ballot.
+  constexpr int kWaves = kSortThreads / 64;
+  constexpr int kSlots = kSortItems * kWaves;
+  static_assert(kSlots == 64, "one lane of wave 0 per (j, wave) slot");
+  __shared__ uint32_t s_cnt[kSlots];
+  __shared__ uint32_t s_total;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+  uint64_t b0, b1;
+  cs_range(n, &b0, &b1);
+  uint32_t run = bcount[blockIdx.x];
+  for (uint64_t base = b0; base < b1; base += kPart) {
+    bool vis[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint64_t i = base + (uint64_t)j * kSortThreads + t;
+      vis[j] = i < b1 && tiles[i] > 0u;
     }
+    uint64_t bal[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) bal[j] = __ballot(vis[j]);
+    __syncthreads();  // the previous step's readers of s_cnt and s_total are done
+    if (l == 0) {
+#pragma unroll
+      for (int j = 0; j < kSortItems; ++j) s_cnt[j * kWaves + w] = (uint32_t)__popcll(bal[j]);
+    }
+    __syncthreads();
+    if (t < 64) {  // exclusive scan over the slots, in item order
+      const uint32_t c = s_cnt[t];
+      const uint32_t inc = wave_incl_scan(c);
+      s_cnt[t] = inc - c;
+      if (t == 63) s_total = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (vis[j]) {
+        const uint64_t i = base + (uint64_t)j * kSortThreads + t;
+        const uint32_t pos = run + s_cnt[j * kWaves + w] + (uint32_t)__popcll(bal[j] & lt_mask);
+        dkeys[pos] = depth_bits[i];
+        dvals[pos] = (uint32_t)i;
+      }
+    }
+    run += s_total;
   }
 }
 
@@ -995,7 +1065,7 @@ BinSortPlan plan_bin_sort(int64_t items, int64_t capacity, int32_t total_tiles) 
   p.off_counters = off; off += C_COUNT * 4;
   p.off_tcount = off; off += (size_t)total_tiles * 4;  // tile totals
   p.off_hist = off; off += (size_t)(kDepthPasses + kMaxTilePasses) * kRadix * 4;
-  p.off_look_scan = off; off += (size_t)(p.parts_items + 1 + parts_exp + 1) * 4;
+  p.off_look_scan = off; off += (size_t)(parts_exp + 1) * 4;
   off = align_up(off);
   p.off_dkeys_a = off; off = align_up(off + (size_t)items * 4);
   // --- body
@@ -1036,8 +1106,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   char* w = static_cast<char*>(ws);
   uint32_t* counters = reinterpret_cast<uint32_t*>(w + p.off_counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(w + p.off_hist);
-  uint32_t* look_compact = reinterpret_cast<uint32_t*>(w + p.off_look_scan);
-  uint32_t* look_expand = look_compact + (p.parts_items + 1);
+  uint32_t* look_expand = reinterpret_cast<uint32_t*>(w + p.off_look_scan);
   uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(w + p.off_dkeys_a), reinterpret_cast<uint32_t*>(w + p.off_dkeys_b)};
   uint32_t* dv[2] = {reinterpret_cast<uint32_t*>(w + p.off_dvals_a), reinterpret_cast<uint32_t*>(w + p.off_dvals_b)};
   uint32_t* tk[2] = {reinterpret_cast<uint32_t*>(w + p.off_tkeys_a), reinterpret_cast<uint32_t*>(w + p.off_tkeys_b)};
@@ -1094,10 +1163,15 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   uint32_t* chunk_first = reinterpret_cast<uint32_t*>(w + p.off_chunks);
 
   uint32_t* bhist = reinterpret_cast<uint32_t*>(w + p.off_rs_hist);
-  // K2a: compaction of the visible items (depth keys, item ids, V)
-  if (p.items > 0)
-    hipLaunchKernelGGL(k_compact, dim3(parts_i), dim3(kSortThreads), 0, s, (uint32_t)p.items, g.tiles, depth_bits,
-                       dk[0], dv[0], counters, look_compact);
+  // K2a: compaction of the visible items (depth keys, item ids, V); the block
+  // counts live in bhist until the depth passes take it over
+  const unsigned grid_c = parts_i < (unsigned)kRsBlocks ? parts_i : (unsigned)kRsBlocks;
+  if (p.items > 0) {
+    hipLaunchKernelGGL(k_cs_count, dim3(grid_c), dim3(kSortThreads), 0, s, (uint64_t)p.items, g.tiles, bhist);
+    hipLaunchKernelGGL(k_cs_scan, dim3(1), dim3(kSortThreads), 0, s, bhist, (int)grid_c, counters);
+    hipLaunchKernelGGL(k_cs_write, dim3(grid_c), dim3(kSortThreads), 0, s, (uint64_t)p.items, g.tiles, depth_bits,
+                       bhist, dk[0], dv[0]);
+  }
   // K4a: depth passes over the V visible items (even count: result in dk[0], dv[0])
   const unsigned grid_d = parts_i < (unsigned)kRsBlocks ? parts_i : (unsigned)kRsBlocks;
   for (int ps = 0; ps < kDepthPasses; ++ps) {
