@@ -22,8 +22,14 @@
  *    >= 0 (the paper applies exp / sigmoid before rasterizing, Sec. 3.4.1).
  *    Quaternions are normalised inside and gradients are taken w.r.t. the
  *    unnormalised input.
- *  - Layouts are planar structure-of-arrays, fp32, attribute-major: element
- *    (attribute a, primitive i) of an array with A attributes is at a*n + i.
+ *  - Layouts are fp32.  Attributes that every call reads for every primitive
+ *    (means, scales, quaternions, opacities, frequencies, weights) are planar
+ *    structure-of-arrays, attribute-major: element (attribute a, primitive i)
+ *    of an array with A attributes is at a*n + i.  Colour coefficients (sh or
+ *    colors), which only the visible primitives need, are stored per
+ *    primitive: element (a, i) of a colour array with A values per primitive
+ *    is at i*A + a, so that reading a visible primitive's colour touches only
+ *    its own row.
  *  - An "item" is a (view, primitive) pair; item = view_item_offset + i where
  *    views are laid out back to back in the order given.
  *  - Pixel (px, py) samples the image point (px + 0.5, py + 0.5).  Tiles are
@@ -40,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 2
+#define GABSPLAT_ABI_VERSION 3
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
@@ -67,9 +73,11 @@ typedef enum {
  *   scales    [3][n]   > 0; Sigma = R S S^T R^T with S = diag(scales)
  *   quats     [4][n]   (w, x, y, z), any non-zero norm
  *   opacities [n]      in (0, 1)
- *   sh        [(deg+1)^2][3][n]  real SH coefficients, coefficient-major then
- *                      channel (element (d, c, i) at (d*3 + c)*n + i); or NULL
- *   colors    [3][n]   precomputed RGB; or NULL (exactly one of sh/colors)
+ *   sh        [n][(deg+1)^2][3]  real SH coefficients per primitive,
+ *                      coefficient-major then channel (element (i, d, c) at
+ *                      (i*(deg+1)^2 + d)*3 + c); or NULL
+ *   colors    [n][3]   precomputed RGB per primitive (element (i, c) at
+ *                      i*3 + c); or NULL (exactly one of sh/colors)
  *   freqs     [k][3][n] cycles per world unit (element (j, axis, i) at
  *                      (j*3 + axis)*n + i)
  *   weights   [k][n]   >= 0 (the DC weight is 1 - sum_j w_j)
@@ -366,8 +374,9 @@ gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat
  * with mean + R(q)(s * z_c) (z_c = normals[c][.][i], standard normal draws
  * supplied by the caller) and scale s * split_shrink.  Every new row (clone
  * copy or split child) gets frequencies freq_reset and weights weight_reset.
- * out: arrays of out_capacity rows; they are written with the planar stride
- * n_out (the output count, written to *d_n_out).  src_index / tag [n_out]:
+ * out: arrays of out_capacity rows; the planar arrays are written with the
+ * stride n_out (the output count, written to *d_n_out), the colour arrays row
+ * by row.  src_index / tag [n_out]:
  * source primitive and 0 kept, 1 clone copy, 2 + c split child c (use them to
  * carry per-primitive optimizer state).  *d_overflow = 1 (and nothing
  * written) if n_out > out_capacity.  ws >= gabsplat_densify_workspace_size(n). */

@@ -15,6 +15,8 @@ from typing import Optional, Sequence
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgabsplat.so")
+# the argument layouts this binding marshals (GABSPLAT_ABI_VERSION)
+ABI_VERSION = 3
 
 EXPORTS = (
     "gabsplat_abi_version", "gabsplat_status_string", "gabsplat_record_floats", "gabsplat_grad2d_floats",
@@ -88,6 +90,9 @@ def lib() -> ctypes.CDLL:
         raise GabsplatError(HIP_ERROR, f"{LIB_PATH} not found: build it with `python -m paper_2508_05343_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     L.gabsplat_abi_version.restype = c_int32
+    if L.gabsplat_abi_version() != ABI_VERSION:
+        raise GabsplatError(INVALID_ARGUMENT, f"{LIB_PATH} has ABI version {L.gabsplat_abi_version()}, the binding "
+                            f"expects {ABI_VERSION}: rebuild it with `python -m paper_2508_05343_amd.build`")
     L.gabsplat_status_string.restype = ctypes.c_char_p
     L.gabsplat_status_string.argtypes = [c_int32]
     L.gabsplat_record_floats.restype = c_int32

@@ -136,11 +136,12 @@ __device__ __forceinline__ void copy_attrs(const gabsplat_scene& in, const gabsp
   for (int a = 0; a < 3; ++a) out.scales[a * no + o] = in.scales[a * n + i];
   for (int a = 0; a < 4; ++a) out.quats[a * no + o] = in.quats[a * n + i];
   out.opacities[o] = in.opacities[i];
+  // colour arrays are stored row by row
   if (in.sh) {
     const int nd = (in.sh_degree + 1) * (in.sh_degree + 1) * 3;
-    for (int a = 0; a < nd; ++a) out.sh[(int64_t)a * no + o] = in.sh[(int64_t)a * n + i];
+    for (int a = 0; a < nd; ++a) out.sh[o * nd + a] = in.sh[i * nd + a];
   } else {
-    for (int a = 0; a < 3; ++a) out.colors[a * no + o] = in.colors[a * n + i];
+    for (int a = 0; a < 3; ++a) out.colors[o * 3 + a] = in.colors[i * 3 + a];
   }
   for (int a = 0; a < 3 * in.k; ++a) out.freqs[(int64_t)a * no + o] = child ? p.freq_reset : in.freqs[(int64_t)a * n + i];
   for (int a = 0; a < in.k; ++a) out.weights[(int64_t)a * no + o] = child ? p.weight_reset : in.weights[(int64_t)a * n + i];

@@ -227,6 +227,27 @@ __device__ __forceinline__ float ray_variance(const Geo& g, V3 u, V3 f) {
 constexpr int kPreItems = 4;
 constexpr int kPreBlock = 256 * kPreItems;
 
+// The nv (<= 48) colour values of primitive i, stored row by row, into
+// v[0..nv) (zeros after): 16-byte loads when every row starts on a 16-byte
+// boundary, else one float at a time.
+__device__ __forceinline__ void load_colour_row(const float* __restrict__ base, int64_t i, int nv, float (&v)[48]) {
+  const float* row = base + i * nv;
+  if ((nv & 3) == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0) {
+    const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      const float4 x = 4 * j < nv ? r4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[4 * j] = x.x;
+      v[4 * j + 1] = x.y;
+      v[4 * j + 2] = x.z;
+      v[4 * j + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 48; ++j) v[j] = j < nv ? row[j] : 0.f;
+  }
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ table,
                                                     float* __restrict__ rec,
@@ -362,21 +383,23 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         const int deg = S.sh_degree;
         sh_basis(d.x * il, d.y * il, d.z * il, deg, Y);
         const int nd = (deg + 1) * (deg + 1);
+        float shv[48];
+        load_colour_row(S.sh, i, 3 * nd, shv);
         float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
         for (int b = 0; b < 16; ++b) {  // compile-time bound keeps Y in registers
           if (b < nd) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], S.sh[(int64_t)(b * 3 + ch) * n + i], col[ch]);
+            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], shv[b * 3 + ch], col[ch]);
           }
         }
         r[6] = fmaxf(col[0], 0.f);
         r[7] = fmaxf(col[1], 0.f);
         r[8] = fmaxf(col[2], 0.f);
       } else {
-        r[6] = S.colors[i];
-        r[7] = S.colors[n + i];
-        r[8] = S.colors[2 * n + i];
+        r[6] = S.colors[3 * i];
+        r[7] = S.colors[3 * i + 1];
+        r[8] = S.colors[3 * i + 2];
       }
       float wsum = 0.f;
       const bool atten = (S.flags & GABSPLAT_FLAG_ATTENUATION) != 0;
@@ -409,12 +432,14 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
 // projection, scale, rotation, opacity, frequencies, weights) and the colour
 // part (SH or RGB coefficients, plus the view-direction term of the mean
 // gradient, added to what the geometry part wrote).  A block stages the
-// attribute planes of its primitives that some view sees into LDS rows (loads
-// of consecutive primitives of one plane per instruction), runs the chain rule
-// once per such primitive over its views (deterministic accumulation, no
-// atomics), puts the gradients back into the same row and writes each
-// gradient plane out for all 256 primitives at once (zeros for the primitives
-// no view sees, unless accumulating).
+// attributes of its primitives that some view sees into LDS rows (from the
+// planar arrays, loads of consecutive primitives of one plane per
+// instruction; from the colour arrays, each primitive's own row), runs the
+// chain rule once per such primitive over its views (deterministic
+// accumulation, no atomics), puts the gradients back into the same row and
+// writes the gradients of all 256 primitives out at once -- plane by plane,
+// or as the one contiguous run of colour rows -- with zeros for the
+// primitives no view sees, unless accumulating.
 constexpr int kBwdBlock = 256;
 constexpr int kColPitch = 3 + 48;  // colour row: mean, then up to 48 SH coefficients (odd pitch)
 
@@ -762,6 +787,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
   const int gstride = grad2d_stride(K, gr.flags);
   __shared__ float s_row[kBwdBlock * PITCH];
   __shared__ int16_t s_prim[kBwdBlock];
+  __shared__ int16_t s_slot[COLOUR ? kBwdBlock : 1];
   __shared__ uint32_t s_wave[kBwdBlock / 64];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -789,24 +815,25 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
     count += (int)s_wave[q];
   }
   const int slot = vis ? before + __popcll(bal & lt) : -1;
+  if constexpr (COLOUR) s_slot[t] = (int16_t)slot;  // read after the syncs below
   const bool acc = gr.accumulate != 0;
   if (count == 0 && acc) return;
   const int deg = S.sh_degree;
-  const int nc = deg >= 0 ? (deg + 1) * (deg + 1) * 3 : 3;
-  const int npl = COLOUR ? 3 + nc : GeoRow<K>::NP;
+  const int nc = deg >= 0 ? (deg + 1) * (deg + 1) * 3 : 3;  // colour values per primitive
   if (count > 0) {
     if (vis) {
       s_prim[slot] = (int16_t)t;
       float* row = s_row + slot * PITCH;
       // every load of the row is issued before the first LDS store
       if constexpr (COLOUR) {
-        const float* cs = deg >= 0 ? S.sh : S.colors;
-        float v[kColPitch];
+        float v[48];
+        load_colour_row(deg >= 0 ? S.sh : S.colors, i, nc, v);
+        const float m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
+        row[0] = m0;
+        row[1] = m1;
+        row[2] = m2;
 #pragma unroll
-        for (int p = 0; p < kColPitch; ++p)
-          v[p] = p < 3 ? S.means[(int64_t)p * n + i] : (p < npl ? cs[(int64_t)(p - 3) * n + i] : 0.f);
-#pragma unroll
-        for (int p = 0; p < kColPitch; ++p) row[p] = v[p];
+        for (int p = 0; p < 48; ++p) row[3 + p] = v[p];
       } else {
         float v[GeoRow<K>::NP];
 #pragma unroll
@@ -832,33 +859,38 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
     }
     __syncthreads();
   }
+  if constexpr (COLOUR) {
+    // the block's colour rows are one contiguous run of cnt * nc floats:
+    // consecutive threads write consecutive floats of it
+    float* cd = deg >= 0 ? gr.sh : gr.colors;
+    if (cd == nullptr) return;
+    const int cnt = (int)(n - base < kBwdBlock ? n - base : kBwdBlock);
+    float* dst = cd + base * nc;
+    // row p = floor(e / nc) through a float reciprocal: e < 2^14 and e + 0.5
+    // sits at least 0.5 / nc from a multiple of nc, far beyond the rounding
+    const float inv_nc = 1.0f / (float)nc;
+    for (int e = t; e < cnt * nc; e += kBwdBlock) {
+      const int p = (int)(((float)e + 0.5f) * inv_nc), a = e - p * nc;
+      const int sl = count > 0 ? s_slot[p] : -1;
+      if (acc) {
+        if (sl >= 0) dst[e] += s_row[sl * PITCH + 3 + a];
+      } else {
+        dst[e] = sl >= 0 ? s_row[sl * PITCH + 3 + a] : 0.f;
+      }
+    }
+    return;
+  }
   if (!in) return;
   // gradient planes, one plane per step over the block's 256 primitives
   const float* row = s_row + (slot >= 0 ? slot : 0) * PITCH;
-  if constexpr (COLOUR) {
-    float* cd = deg >= 0 ? gr.sh : gr.colors;
-    if (cd == nullptr) return;
 #pragma unroll
-    for (int p = 3; p < kColPitch; ++p) {
-      if (p < npl) {
-        float* dst = cd + (int64_t)(p - 3) * n + i;
-        if (acc) {
-          if (vis) *dst += row[p];
-        } else {
-          *dst = vis ? row[p] : 0.f;
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int p = 0; p < GeoRow<K>::NP; ++p) {
-      float* d = geo_dst<K>(gr, n, p);
-      if (d == nullptr) continue;
-      if (acc) {
-        if (vis) d[i] += row[p];
-      } else {
-        d[i] = vis ? row[p] : 0.f;
-      }
+  for (int p = 0; p < GeoRow<K>::NP; ++p) {
+    float* d = geo_dst<K>(gr, n, p);
+    if (d == nullptr) continue;
+    if (acc) {
+      if (vis) d[i] += row[p];
+    } else {
+      d[i] = vis ? row[p] : 0.f;
     }
   }
 }

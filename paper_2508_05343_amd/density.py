@@ -9,6 +9,9 @@ import torch
 from . import _lib
 from .rasterize import DeviceScene, RenderPlan
 
+# attributes stored one row per primitive ([n][A]); the others are planar [A][n]
+ROWS = ("sh", "colors")
+
 
 def default_params(scene_extent: float = 1.0, **kw) -> _lib.DensifyParams:
     p = _lib.DensifyParams()
@@ -65,8 +68,8 @@ def densify(ds: DeviceScene, stats: DensityStats, normals: torch.Tensor, params:
         if t is None:
             bufs[name] = None
             continue
-        rows = t.shape[0] if t.dim() == 2 else 1
-        bufs[name] = torch.empty(rows * max(cap, 1), dtype=torch.float32, device=dev)
+        per_prim = t.shape[1] if name in ROWS else (t.shape[0] if t.dim() == 2 else 1)
+        bufs[name] = torch.empty(per_prim * max(cap, 1), dtype=torch.float32, device=dev)
     out = _lib.SceneOut()
     out.n, out.k, out.sh_degree = cap, ds.k, max(ds.sh_degree, 0)
     for name, b in bufs.items():
@@ -89,6 +92,8 @@ def densify(ds: DeviceScene, stats: DensityStats, normals: torch.Tensor, params:
         t = getattr(ds, name)
         if t.dim() == 1:
             return b[:m].clone()
+        if name in ROWS:
+            return b[:m * t.shape[1]].view(m, t.shape[1]).clone()
         return b[:t.shape[0] * m].view(t.shape[0], m).clone()
     new = DeviceScene(view("means"), view("scales"), view("quats"), view("opacities"), view("freqs"),
                       view("weights"), sh=view("sh"), colors=view("colors"), sh_degree=ds.sh_degree,

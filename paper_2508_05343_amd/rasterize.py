@@ -3,8 +3,9 @@ forward/backward/loss calls and a torch.autograd.Function.
 
 Torch provides device memory and the stream; every step of the rasterizer
 runs in the HIP kernels of libgabsplat.so.  Scene attributes are kept in the
-library's planar layout (attribute-major, [A][n]) so no per-call transposes
-are needed.
+library's layouts (planar [A][n] for the geometry, frequencies and weights,
+one row per primitive [n][A] for the colour coefficients) so no per-call
+transposes are needed.
 """
 from __future__ import annotations
 
@@ -22,9 +23,10 @@ TILE = 16
 
 # ----------------------------------------------------------------- scenes
 class DeviceScene:
-    """Activated primitive attributes as planar fp32 device tensors:
-    means [3,n], scales [3,n], quats [4,n], opacities [n], sh [D*3,n] or
-    colors [3,n], freqs [3K,n], weights [K,n].
+    """Activated primitive attributes as fp32 device tensors: planar means
+    [3,n], scales [3,n], quats [4,n], opacities [n], freqs [3K,n], weights
+    [K,n], and per-primitive colour rows sh [n,D*3] ((d*3 + c) within a row)
+    or colors [n,3]. 
 
     Options: attenuation (keep the z-integration factor of every cosine term),
     mip2d (Mip-Splatting's 2D filter instead of the 0.3 px^2 dilation) and
@@ -48,14 +50,16 @@ class DeviceScene:
         def planar(a):
             a = np.asarray(a, np.float32)
             return torch.from_numpy(np.ascontiguousarray(a.reshape(a.shape[0], -1).T)).to(device)
+
+        def rows(a):
+            a = np.asarray(a, np.float32)
+            return torch.from_numpy(np.ascontiguousarray(a.reshape(a.shape[0], -1))).to(device)
         n = scene.means.shape[0]
-        sh = None
-        if scene.sh is not None:
-            sh = planar(scene.sh.reshape(n, -1))  # [D*3, n], (d*3 + c) major
         return DeviceScene(planar(scene.means), planar(scene.scales), planar(scene.quats),
                            torch.from_numpy(np.ascontiguousarray(scene.opacities, np.float32)).to(device),
-                           planar(scene.freqs.reshape(n, -1)), planar(scene.weights), sh=sh,
-                           colors=None if scene.colors is None else planar(scene.colors),
+                           planar(scene.freqs.reshape(n, -1)), planar(scene.weights),
+                           sh=None if scene.sh is None else rows(scene.sh),
+                           colors=None if scene.colors is None else rows(scene.colors),
                            sh_degree=scene.sh_degree if scene.sh is not None else -1, attenuation=attenuation,
                            mip2d=mip2d)
 
@@ -276,8 +280,8 @@ class LossBuffers:
 # --------------------------------------------------------------- autograd
 class GaborRasterize(torch.autograd.Function):
     """image = rasterize(means, scales, quats, opacities, color, freqs, weights)
-    for one scene and a list of cameras; `color` is the SH tensor [D*3, n]
-    (sh_degree >= 0) or RGB [3, n].  Returns the flat image buffer of the plan
+    for one scene and a list of cameras; `color` is the SH tensor [n, D*3]
+    (sh_degree >= 0) or RGB [n, 3].  Returns the flat image buffer of the plan
     (views back to back, [3][H][W] each)."""
 
     @staticmethod

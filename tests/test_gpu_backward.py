@@ -26,8 +26,10 @@ def _to_aos(name, t, n, k):
     a = t.detach().cpu().numpy()
     if name == "opacities":
         return a
-    if name == "sh":
-        return a.reshape(-1, 3, n).transpose(2, 0, 1)
+    if name == "sh":  # colour arrays are stored one row per primitive
+        return a.reshape(n, -1, 3)
+    if name == "colors":
+        return a
     if name == "freqs":
         return a.reshape(k, 3, n).transpose(2, 0, 1)
     return a.T

@@ -38,7 +38,7 @@ def test_multiview_backward_sums_views(gpu_lib):
     n = sc.n
     gpu = dict(means=grads["means"].cpu().numpy().T, scales=grads["scales"].cpu().numpy().T,
                quats=grads["quats"].cpu().numpy().T, opacities=grads["opacities"].cpu().numpy(),
-               sh=grads["sh"].cpu().numpy().reshape(4, 3, n).transpose(2, 0, 1),
+               sh=grads["sh"].cpu().numpy().reshape(n, 4, 3),
                freqs=grads["freqs"].cpu().numpy().reshape(2, 3, n).transpose(2, 0, 1),
                weights=grads["weights"].cpu().numpy().T)
     for k in NAMES:

@@ -37,7 +37,7 @@ def test_densify_matches_oracle(gpu_lib):
     np.testing.assert_array_equal(new.freqs.cpu().numpy().reshape(2, 3, m).transpose(2, 0, 1),
                                   ref["freqs"].astype(np.float32))
     np.testing.assert_array_equal(new.weights.cpu().numpy().T, ref["weights"].astype(np.float32))
-    np.testing.assert_array_equal(new.sh.cpu().numpy().reshape(9, 3, m).transpose(2, 0, 1),
+    np.testing.assert_array_equal(new.sh.cpu().numpy().reshape(m, 9, 3),
                                   ref["sh"].astype(np.float32))
     np.testing.assert_array_equal(new.opacities.cpu().numpy(), ref["opacities"].astype(np.float32))
 

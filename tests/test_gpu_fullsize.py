@@ -101,7 +101,7 @@ def test_config3_sampled_primitive_gradients(gpu_lib, big):
     gpu["scales"] = grads["scales"].cpu().numpy()[:, prims].T
     gpu["quats"] = grads["quats"].cpu().numpy()[:, prims].T
     gpu["opacities"] = grads["opacities"].cpu().numpy()[prims]
-    gpu["sh"] = grads["sh"].cpu().numpy().reshape(16, 3, n)[:, :, prims].transpose(2, 0, 1)
+    gpu["sh"] = grads["sh"].cpu().numpy().reshape(n, 16, 3)[prims]
     gpu["freqs"] = grads["freqs"].cpu().numpy().reshape(4, 3, n)[:, :, prims].transpose(2, 0, 1)
     gpu["weights"] = grads["weights"].cpu().numpy()[:, prims].T
     rep = {}

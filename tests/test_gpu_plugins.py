@@ -105,8 +105,12 @@ def test_filtered_backward_matches_oracle(gpu_lib, mip2d, mip3d):
     ref = O.render_grads(sc, cam, g_img, "binned", mip2d=mip2d, filter3d=fv)
     for name, t in grads.items():
         a = t.detach().cpu().numpy()
-        a = a if name == "opacities" else (a.reshape(-1, 3, sc.n).transpose(2, 0, 1) if name in ("sh", "freqs")
-                                          else a.T)
+        if name == "sh":  # one row per primitive
+            a = a.reshape(sc.n, -1, 3)
+        elif name == "freqs":
+            a = a.reshape(-1, 3, sc.n).transpose(2, 0, 1)
+        elif name not in ("opacities", "colors"):
+            a = a.T
         r = ref[name]
         rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
         print(name, f"{rel:.2e}")
