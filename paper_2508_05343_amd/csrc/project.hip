@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
 // or as the one contiguous run of colour rows -- with zeros for the
 // primitives no view sees, unless accumulating.
 constexpr int kBwdBlock = 256;
-constexpr int kColPitch = 3 + 48;  // colour row: mean, then up to 48 SH coefficients (odd pitch)
+constexpr int kColPitch = 3 + 48;  // colour part per primitive: mean, then up to 48 colour coefficients
 
 // Geometry row: mean 3, scale 3, quaternion 4, opacity 1, frequencies 3K, weights K
 template <int K>
@@ -699,19 +699,20 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
   }
 }
 
-// Colour part for primitive i: row P = mean, then the nc colour coefficients
-// (SH [(deg+1)^2][3] or RGB 3).  The coefficient gradients replace the
-// coefficients in P; the view-direction term of the mean gradient is returned.
+// Colour part for primitive i of a scene with SH degree DEG (-1: RGB): row
+// P = mean, then the colour coefficients (SH [(DEG+1)^2][3] or RGB 3).  The
+// coefficient gradients replace the coefficients in P; the view-direction
+// term of the mean gradient is returned.
+template <int DEG>
 __device__ __forceinline__ V3 colour_bwd_one(const void* __restrict__ table, int scene_index,
                                              const uint32_t* __restrict__ tiles, const float* __restrict__ grad2d,
                                              int gf_stride, int64_t i, float* P) {
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
-  const SceneEntry& S = table_scenes(table, nv)[scene_index];
   const float mx = P[0], my = P[1], mz = P[2];
-  const int deg = S.sh_degree;
-  const int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+  constexpr int deg = DEG;
+  constexpr int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
   V3 gmean = v3(0.f, 0.f, 0.f);
   float gcol[3] = {0.f, 0.f, 0.f};
   float gsh[48];
@@ -776,18 +777,17 @@ __device__ __forceinline__ V3 colour_bwd_one(const void* __restrict__ table, int
   return gmean;
 }
 
-template <int K, bool COLOUR, bool FILT>
+template <int K, bool FILT>
 __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __restrict__ table, int scene_index,
                                                               const uint32_t* __restrict__ tiles,
                                                               const float* __restrict__ depth,
                                                               const float* __restrict__ grad2d,
                                                               gabsplat_scene_grads gr,
                                                               const int32_t* __restrict__ d_overflow) {
-  constexpr int PITCH = COLOUR ? kColPitch : GeoRow<K>::NP;
+  constexpr int PITCH = GeoRow<K>::NP;
   const int gstride = grad2d_stride(K, gr.flags);
   __shared__ float s_row[kBwdBlock * PITCH];
   __shared__ int16_t s_prim[kBwdBlock];
-  __shared__ int16_t s_slot[COLOUR ? kBwdBlock : 1];
   __shared__ uint32_t s_wave[kBwdBlock / 64];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -815,70 +815,23 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
     count += (int)s_wave[q];
   }
   const int slot = vis ? before + __popcll(bal & lt) : -1;
-  if constexpr (COLOUR) s_slot[t] = (int16_t)slot;  // read after the syncs below
   const bool acc = gr.accumulate != 0;
   if (count == 0 && acc) return;
-  const int deg = S.sh_degree;
-  const int nc = deg >= 0 ? (deg + 1) * (deg + 1) * 3 : 3;  // colour values per primitive
   if (count > 0) {
     if (vis) {
       s_prim[slot] = (int16_t)t;
       float* row = s_row + slot * PITCH;
       // every load of the row is issued before the first LDS store
-      if constexpr (COLOUR) {
-        float v[48];
-        load_colour_row(deg >= 0 ? S.sh : S.colors, i, nc, v);
-        const float m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
-        row[0] = m0;
-        row[1] = m1;
-        row[2] = m2;
+      float v[GeoRow<K>::NP];
 #pragma unroll
-        for (int p = 0; p < 48; ++p) row[3 + p] = v[p];
-      } else {
-        float v[GeoRow<K>::NP];
+      for (int p = 0; p < GeoRow<K>::NP; ++p) v[p] = geo_src<K>(S, p)[i];
 #pragma unroll
-        for (int p = 0; p < GeoRow<K>::NP; ++p) v[p] = geo_src<K>(S, p)[i];
-#pragma unroll
-        for (int p = 0; p < GeoRow<K>::NP; ++p) row[p] = v[p];
-      }
+      for (int p = 0; p < GeoRow<K>::NP; ++p) row[p] = v[p];
     }
     __syncthreads();
-    if (t < count) {
-      const int64_t ii = base + s_prim[t];
-      float* row = s_row + t * PITCH;
-      if constexpr (COLOUR) {
-        const V3 gm = colour_bwd_one(table, scene_index, tiles, grad2d, gstride, ii, row);
-        if (gr.means) {  // after the geometry part has written the mean gradient
-          gr.means[ii] += gm.x;
-          gr.means[n + ii] += gm.y;
-          gr.means[2 * n + ii] += gm.z;
-        }
-      } else {
-        geo_bwd_one<K, FILT>(table, scene_index, tiles, depth, grad2d, gstride, ii, row);
-      }
-    }
+    if (t < count) geo_bwd_one<K, FILT>(table, scene_index, tiles, depth, grad2d, gstride, base + s_prim[t],
+                                        s_row + t * PITCH);
     __syncthreads();
-  }
-  if constexpr (COLOUR) {
-    // the block's colour rows are one contiguous run of cnt * nc floats:
-    // consecutive threads write consecutive floats of it
-    float* cd = deg >= 0 ? gr.sh : gr.colors;
-    if (cd == nullptr) return;
-    const int cnt = (int)(n - base < kBwdBlock ? n - base : kBwdBlock);
-    float* dst = cd + base * nc;
-    // row p = floor(e / nc) through a float reciprocal: e < 2^14 and e + 0.5
-    // sits at least 0.5 / nc from a multiple of nc, far beyond the rounding
-    const float inv_nc = 1.0f / (float)nc;
-    for (int e = t; e < cnt * nc; e += kBwdBlock) {
-      const int p = (int)(((float)e + 0.5f) * inv_nc), a = e - p * nc;
-      const int sl = count > 0 ? s_slot[p] : -1;
-      if (acc) {
-        if (sl >= 0) dst[e] += s_row[sl * PITCH + 3 + a];
-      } else {
-        dst[e] = sl >= 0 ? s_row[sl * PITCH + 3 + a] : 0.f;
-      }
-    }
-    return;
   }
   if (!in) return;
   // gradient planes, one plane per step over the block's 256 primitives
@@ -891,6 +844,74 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
       if (vis) d[i] += row[p];
     } else {
       d[i] = vis ? row[p] : 0.f;
+    }
+  }
+}
+
+// The colour part: one wavefront per 64 consecutive primitives, one lane per
+// primitive.  Visible lanes read their own colour row (the colour arrays hold
+// one row per primitive), run the chain rule and leave the gradient row in
+// LDS; the wavefront then writes its 64 rows -- one contiguous run -- with
+// consecutive lanes on consecutive floats (zeros for the primitives no view
+// sees, unless accumulating).
+constexpr int kColBlock = 64;
+
+template <int DEG>
+__global__ __launch_bounds__(kColBlock) void k_colour_bwd(const void* __restrict__ table, int scene_index,
+                                                          const uint32_t* __restrict__ tiles,
+                                                          const float* __restrict__ grad2d, gabsplat_scene_grads gr,
+                                                          int gstride, const int32_t* __restrict__ d_overflow) {
+  constexpr int NC = DEG >= 0 ? (DEG + 1) * (DEG + 1) * 3 : 3;  // colour values per primitive
+  __shared__ float s_g[kColBlock * NC];
+  if (d_overflow != nullptr && *d_overflow != 0) return;
+  const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
+  const int nv = hdr->num_views;
+  const ViewEntry* views = table_views(table);
+  const SceneEntry& S = table_scenes(table, nv)[scene_index];
+  const int64_t n = S.n;
+  const int64_t base = (int64_t)blockIdx.x * kColBlock;
+  const int l = threadIdx.x;
+  const int64_t i = base + l;
+  bool vis = false;
+  for (int v = 0; v < nv && i < n && !vis; ++v)
+    vis = views[v].scene == scene_index && tiles[views[v].item_offset + i] != 0;
+  const uint64_t vmask = __ballot(vis);
+  const bool acc = gr.accumulate != 0;
+  if (vmask == 0 && acc) return;
+  float* cd = DEG >= 0 ? gr.sh : gr.colors;
+  if (vis) {
+    float v[48];
+    load_colour_row(DEG >= 0 ? S.sh : S.colors, i, NC, v);
+    float P[kColPitch];
+    P[0] = S.means[i];
+    P[1] = S.means[n + i];
+    P[2] = S.means[2 * n + i];
+#pragma unroll
+    for (int p = 0; p < 48; ++p) P[3 + p] = v[p];
+    const V3 gm = colour_bwd_one<DEG>(table, scene_index, tiles, grad2d, gstride, i, P);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) s_g[l * NC + a] = P[3 + a];
+    if (gr.means) {  // after the geometry part has written the mean gradient
+      gr.means[i] += gm.x;
+      gr.means[n + i] += gm.y;
+      gr.means[2 * n + i] += gm.z;
+    }
+  }
+  __syncthreads();
+  if (cd == nullptr) return;
+  const int cnt = (int)(n - base < kColBlock ? n - base : kColBlock);
+  float* dst = cd + base * NC;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int e = j * kColBlock + l;  // float e of the run: primitive e / NC, value e % NC
+    const int p = e / NC;
+    if (p < cnt) {
+      const bool pv = (vmask >> p) & 1ull;
+      if (acc) {
+        if (pv) dst[e] += s_g[e];
+      } else {
+        dst[e] = pv ? s_g[e] : 0.f;
+      }
     }
   }
 }
@@ -933,13 +954,22 @@ static hipError_t pbwd_k(const void* d_table, const HostTable& h, const gabsplat
   // its view-direction term to the mean gradient): two register budgets
   const dim3 grid((unsigned)((n + kBwdBlock - 1) / kBwdBlock));
   if (h.scenes[sc].flags & (GABSPLAT_FLAG_MIP_2D | GABSPLAT_FLAG_MIP_3D))
-    hipLaunchKernelGGL((k_preprocess_bwd<K, false, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
+    hipLaunchKernelGGL((k_preprocess_bwd<K, true>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
                        gr.grad2d, gr, ov);
   else
-    hipLaunchKernelGGL((k_preprocess_bwd<K, false, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
+    hipLaunchKernelGGL((k_preprocess_bwd<K, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
                        gr.grad2d, gr, ov);
-  hipLaunchKernelGGL((k_preprocess_bwd<K, true, false>), grid, dim3(256), 0, s, d_table, sc, g.tiles, g.depth,
-                     gr.grad2d, gr, ov);
+  const int gs = grad2d_stride(K, gr.flags);
+  const dim3 cgr((unsigned)((n + kColBlock - 1) / kColBlock));
+  const void* t = d_table;
+  const uint32_t* tl = g.tiles;
+  switch (h.scenes[sc].sh_degree) {  // -1: RGB colours
+    case -1: hipLaunchKernelGGL(k_colour_bwd<-1>, cgr, dim3(kColBlock), 0, s, t, sc, tl, gr.grad2d, gr, gs, ov); break;
+    case 0: hipLaunchKernelGGL(k_colour_bwd<0>, cgr, dim3(kColBlock), 0, s, t, sc, tl, gr.grad2d, gr, gs, ov); break;
+    case 1: hipLaunchKernelGGL(k_colour_bwd<1>, cgr, dim3(kColBlock), 0, s, t, sc, tl, gr.grad2d, gr, gs, ov); break;
+    case 2: hipLaunchKernelGGL(k_colour_bwd<2>, cgr, dim3(kColBlock), 0, s, t, sc, tl, gr.grad2d, gr, gs, ov); break;
+    default: hipLaunchKernelGGL(k_colour_bwd<3>, cgr, dim3(kColBlock), 0, s, t, sc, tl, gr.grad2d, gr, gs, ov);
+  }
   return hipGetLastError();
 }
 
