@@ -441,7 +441,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
 // or as the one contiguous run of colour rows -- with zeros for the
 // primitives no view sees, unless accumulating.
 constexpr int kBwdBlock = 256;
-constexpr int kColPitch = 3 + 48;  // colour part per primitive: mean, then up to 48 colour coefficients
 
 // Geometry row: mean 3, scale 3, quaternion 4, opacity 1, frequencies 3K, weights K
 template <int K>
@@ -699,80 +698,60 @@ __device__ __forceinline__ void geo_bwd_one(const void* __restrict__ table, int 
   }
 }
 
-// Colour part for primitive i of a scene with SH degree DEG (-1: RGB): row
-// P = mean, then the colour coefficients (SH [(DEG+1)^2][3] or RGB 3).  The
-// coefficient gradients replace the coefficients in P; the view-direction
-// term of the mean gradient is returned.
+// Colour part for primitive i of a scene with SH degree DEG (-1: RGB), mean
+// m and colour coefficients shv (SH [(DEG+1)^2][3] or RGB 3, zeros after):
+// adds the coefficient gradients of every view that sees it to g[0..) (an
+// LDS row, which keeps them out of the register budget) and returns the
+// view-direction term of the mean gradient.
 template <int DEG>
 __device__ __forceinline__ V3 colour_bwd_one(const void* __restrict__ table, int scene_index,
                                              const uint32_t* __restrict__ tiles, const float* __restrict__ grad2d,
-                                             int gf_stride, int64_t i, float* P) {
+                                             int gf_stride, int64_t i, V3 m, const float (&shv)[48], float* g) {
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const int nv = hdr->num_views;
   const ViewEntry* views = table_views(table);
-  const float mx = P[0], my = P[1], mz = P[2];
-  constexpr int deg = DEG;
-  constexpr int nd = deg >= 0 ? (deg + 1) * (deg + 1) : 0;
+  constexpr int nd = DEG >= 0 ? (DEG + 1) * (DEG + 1) : 0;
   V3 gmean = v3(0.f, 0.f, 0.f);
-  float gcol[3] = {0.f, 0.f, 0.f};
-  float gsh[48];
-#pragma unroll
-  for (int b = 0; b < 48; ++b) gsh[b] = 0.f;
   for (int v = 0; v < nv; ++v) {
     const ViewEntry& V = views[v];
     if (V.scene != scene_index) continue;
     const int64_t item = V.item_offset + i;
     if (tiles[item] == 0) continue;
     const float* g2 = grad2d + item * (int64_t)gf_stride;
-    // ---- colour
     const float G2c[3] = {g2[6], g2[7], g2[8]};
-    if (deg >= 0) {
-      const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
+    if constexpr (DEG >= 0) {
+      const V3 d = v3(m.x - V.campos[0], m.y - V.campos[1], m.z - V.campos[2]);
       const float il = 1.0f / sqrtf(dot3(d, d));
       const V3 dir = scale3(d, il);
       float Y[16];
       V3 dY[16];
-      sh_basis(dir.x, dir.y, dir.z, deg, Y);
-      sh_basis_grad(dir.x, dir.y, dir.z, deg, dY);
-      float shv[48];
-#pragma unroll
-      for (int b = 0; b < 16; ++b)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) shv[b * 3 + ch] = (b < nd) ? P[3 + b * 3 + ch] : 0.f;
+      sh_basis(dir.x, dir.y, dir.z, DEG, Y);
+      sh_basis_grad(dir.x, dir.y, dir.z, DEG, dY);
       float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
-      for (int b = 0; b < 16; ++b)
+      for (int b = 0; b < nd; ++b)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = (b < nd) ? fmaf(Y[b], shv[b * 3 + ch], col[ch]) : col[ch];
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(Y[b], shv[b * 3 + ch], col[ch]);
       float drgb[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) drgb[ch] = col[ch] < 0.f ? 0.f : G2c[ch];
       V3 gdir = v3(0.f, 0.f, 0.f);
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        if (b < nd) {
-          float acc = 0.f;
+      for (int b = 0; b < nd; ++b) {
+        float acc = 0.f;
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            gsh[b * 3 + ch] += Y[b] * drgb[ch];
-            acc += shv[b * 3 + ch] * drgb[ch];
-          }
-          gdir = add3(gdir, scale3(dY[b], acc));
+        for (int ch = 0; ch < 3; ++ch) {
+          g[b * 3 + ch] += Y[b] * drgb[ch];
+          acc += shv[b * 3 + ch] * drgb[ch];
         }
+        gdir = add3(gdir, scale3(dY[b], acc));
       }
       const float pr = dot3(dir, gdir);
       gmean = add3(gmean, scale3(add3(gdir, scale3(dir, -pr)), il));
     } else {
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gcol[ch] += G2c[ch];
+      for (int ch = 0; ch < 3; ++ch) g[ch] += G2c[ch];
     }
-  }
-  if (deg >= 0) {
-#pragma unroll
-    for (int b = 0; b < 48; ++b)
-      if (b < nd * 3) P[3 + b] = gsh[b];
-  } else {
-    P[3] = gcol[0]; P[4] = gcol[1]; P[5] = gcol[2];
   }
   return gmean;
 }
@@ -882,15 +861,11 @@ __global__ __launch_bounds__(kColBlock) void k_colour_bwd(const void* __restrict
   if (vis) {
     float v[48];
     load_colour_row(DEG >= 0 ? S.sh : S.colors, i, NC, v);
-    float P[kColPitch];
-    P[0] = S.means[i];
-    P[1] = S.means[n + i];
-    P[2] = S.means[2 * n + i];
+    const V3 m = v3(S.means[i], S.means[n + i], S.means[2 * n + i]);
+    float* g = s_g + l * NC;
 #pragma unroll
-    for (int p = 0; p < 48; ++p) P[3 + p] = v[p];
-    const V3 gm = colour_bwd_one<DEG>(table, scene_index, tiles, grad2d, gstride, i, P);
-#pragma unroll
-    for (int a = 0; a < NC; ++a) s_g[l * NC + a] = P[3 + a];
+    for (int a = 0; a < NC; ++a) g[a] = 0.f;
+    const V3 gm = colour_bwd_one<DEG>(table, scene_index, tiles, grad2d, gstride, i, m, v, g);
     if (gr.means) {  // after the geometry part has written the mean gradient
       gr.means[i] += gm.x;
       gr.means[n + i] += gm.y;
