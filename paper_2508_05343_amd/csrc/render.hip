@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
     dC2 = g[2 * hw + pix];
   }
   T = Tf;
-  const float bgdot = V.bg[0] * dC0 + V.bg[1] * dC1 + V.bg[2] * dC2;
+  const float Tbg = Tf * (V.bg[0] * dC0 + V.bg[1] * dC1 + V.bg[2] * dC2);
   if (t == 0) s_max = 0;
   __syncthreads();
   if (last) atomicMax(&s_max, last);
@@ -419,7 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, d, 64));
 
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, la = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
+  // colour blended from the contributors behind the current record (back to front)
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
   for (uint32_t hi = maxlast; hi > 0;) {
     const uint32_t lo = hi > (uint32_t)kBatchBwd ? hi - kBatchBwd : 0u;
     const uint32_t cnt = hi - lo;
@@ -470,23 +471,18 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         contrib = contrib && !(alpha < kAlphaMin);
         if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
         // lanes without a contribution keep their state and produce zero gradients
-        const float om = 1.0f - alpha;
-        const float inv = __builtin_amdgcn_rcpf(om);
-        T = contrib ? T * inv : T;
-        const float na0 = fmaf(la, lc0, (1.0f - la) * acc0);
-        const float na1 = fmaf(la, lc1, (1.0f - la) * acc1);
-        const float na2 = fmaf(la, lc2, (1.0f - la) * acc2);
-        acc0 = contrib ? na0 : acc0;
-        acc1 = contrib ? na1 : acc1;
-        acc2 = contrib ? na2 : acc2;
-        lc0 = contrib ? col.x : lc0;
-        lc1 = contrib ? col.y : lc1;
-        lc2 = contrib ? col.z : lc2;
-        la = contrib ? alpha : la;
-        const float wt = contrib ? alpha * T : 0.f;
-        float da = (col.x - acc0) * dC0 + (col.y - acc1) * dC1 + (col.z - acc2) * dC2;
-        da = da * T - Tf * bgdot * inv;
+        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+        T = contrib ? T * inv : T;  // T_i = T_(i+1) / (1 - alpha_i)
+        const float ac = contrib ? alpha : 0.f;
+        const float wt = ac * T;
+        const float e0 = col.x - acc0, e1 = col.y - acc1, e2 = col.z - acc2;
+        float da = fmaf(e2, dC2, fmaf(e1, dC1, e0 * dC0));
+        da = da * T - Tbg * inv;
         da = (contrib && !(EB > kAlphaMax)) ? da : 0.f;  // a binding clamp has zero derivative
+        // this record joins the colour behind the next (nearer) one
+        acc0 = fmaf(ac, e0, acc0);
+        acc1 = fmaf(ac, e1, acc1);
+        acc2 = fmaf(ac, e2, acc2);
         const float dB = da * E;
         const float dp = da * Bv * E * kLn2;
         float gv[GS];
@@ -495,27 +491,31 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         gv[7] = wt * dC1;
         gv[8] = wt * dC2;
         gv[9] = dB;  // DC weight
-        const float dx = u - s1.z, dy = v - s1.w;
-        gv[2] = dp * dx * dx;
-        gv[3] = dp * dx * dy;
-        gv[4] = dp * dy * dy;
-        float ddx = dp * (2.0f * s0.x * dx + s0.y * dy);
-        float ddy = dp * (s0.y * dx + 2.0f * s0.z * dy);
-        const float dB2pi = -dB * 6.283185307179586f;
+        // with (ex, ey) = mean - pixel centre the mean gradient -(dL/d pixel
+        // offset) is dp (2A ex + B ey, B ex + 2C ey) - sum_k dph_k f_k, where
+        // dph_k = dL/d phase_k; nph = -dph_k
+        const float ex = s1.z - u, ey = s1.w - v;
+        const float px_ = dp * ex, py_ = dp * ey;
+        gv[2] = px_ * ex;
+        gv[3] = px_ * ey;
+        gv[4] = py_ * ey;
+        float g0 = fmaf(s0.x, px_ + px_, s0.y * py_);
+        float g1 = fmaf(s0.z, py_ + py_, s0.y * px_);
+        const float dB2pi = dB * 6.283185307179586f;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float dph = dB2pi * cc[k].w * sn[k];
-          gv[10 + 3 * k] = dph * dx;
-          gv[11 + 3 * k] = dph * dy;
+          const float nph = dB2pi * cc[k].w * sn[k];
+          gv[10 + 3 * k] = nph * ex;  // = dph_k (u - mean_x)
+          gv[11 + 3 * k] = nph * ey;
           gv[12 + 3 * k] = dB * cs[k];
-          ddx = fmaf(dph, cc[k].x, ddx);
-          ddy = fmaf(dph, cc[k].y, ddy);
+          g0 = fmaf(nph, cc[k].x, g0);
+          g1 = fmaf(nph, cc[k].y, g1);
         }
-        gv[0] = -ddx;
-        gv[1] = -ddy;
+        gv[0] = g0;
+        gv[1] = g1;
         if (ABS) {
-          gv[GS - 2] = fabsf(ddx);
-          gv[GS - 1] = fabsf(ddy);
+          gv[GS - 2] = fabsf(g0);
+          gv[GS - 1] = fabsf(g1);
         }
         wave_reduce_add<GS>(gv, grad2d + (size_t)s_id[j] * GF, red_slot, red_writer);
       }
