@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
       while (bits) {
         const int hb = 63 - __builtin_clzll(bits);
         bits &= ~(1ull << hb);
-        const int j = c0 + hb;
+        const int j = __builtin_amdgcn_readfirstlane(c0 + hb);  // wave-uniform: scalar addressing
         const uint32_t pos = lo + (uint32_t)j + 1;
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
         const float pw = staged_power(s0, s1, u, v);
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         acc1 = fmaf(ac, e1, acc1);
         acc2 = fmaf(ac, e2, acc2);
         const float dB = da * E;
-        const float dp = da * Bv * E * kLn2;
+        const float dp = dB * Bv * kLn2;
         float gv[GS];
         gv[5] = dp;
         gv[6] = wt * dC0;
