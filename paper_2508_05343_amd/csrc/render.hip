@@ -526,14 +526,25 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
 
 // ------------------------------------------------------ grad2d row clear
 // Zeroes the grad2d rows of the items that touch a tile: the only rows the
-// backward adds into and the only rows read afterwards.
-// One item per lane (a capped grid-stride loop was latency bound).
+// backward adds into and the only rows read afterwards.  A wavefront takes 64
+// consecutive items, whose rows are one contiguous run of 64 * gf4 float4s,
+// and writes the run with consecutive lanes on consecutive float4s, skipping
+// the rows of items that touch no tile.
 __global__ void k_clear_visible_rows(const uint32_t* __restrict__ tiles, float* __restrict__ grad2d, int64_t items,
                                      int gf4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= items || tiles[i] == 0) return;
-  float4* row = reinterpret_cast<float4*>(grad2d + i * 4 * gf4);
-  for (int j = 0; j < gf4; ++j) row[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const uint64_t vmask = __ballot(i < items ? tiles[i] != 0 : false);
+  if (vmask == 0) return;
+  const int l = threadIdx.x & 63;
+  float4* run = reinterpret_cast<float4*>(grad2d) + (i - l) * gf4;
+  // row p = floor(q / gf4) through a float reciprocal: q < 64 * 9 and q + 0.5
+  // sits at least 0.5 / gf4 from a multiple of gf4, far beyond the rounding
+  const float inv = 1.0f / (float)gf4;
+  for (int j = 0; j < gf4; ++j) {
+    const int q = j * 64 + l;
+    const int p = (int)(((float)q + 0.5f) * inv);
+    if ((vmask >> p) & 1ull) run[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
 }
 
 hipError_t launch_clear_grad2d(const uint32_t* tiles, float* grad2d, int64_t items, int gf, hipStream_t s) {
