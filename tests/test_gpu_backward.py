@@ -52,10 +52,12 @@ def _check_grads(sc, cam, seed, tol=1e-3, scene_name=""):
         assert rel <= tol, (name, rel)
 
 
-def test_backward_small_sh_scene(gpu_lib):
-    sc = synth.uniform_scene(41, 300, 2, sh_degree=2, log_scale_mu=-2.6)
+@pytest.mark.parametrize("deg", [0, 2])
+def test_backward_small_sh_scene(gpu_lib, deg):
+    """Colour rows of 3 and 27 floats: the one-float-at-a-time row paths."""
+    sc = synth.uniform_scene(41, 300, 2, sh_degree=deg, log_scale_mu=-2.6)
     cam = synth.pinhole_camera(64, 48, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0), bg=(0.1, 0.2, 0.3))
-    _check_grads(sc, cam, 5, scene_name="sh2 k2")
+    _check_grads(sc, cam, 5, scene_name=f"sh{deg} k2")
 
 
 def test_backward_config1(gpu_lib):
@@ -144,3 +146,36 @@ def test_attenuated_forward_and_backward(gpu_lib, high_freq):
         a = _to_aos(name, t, sc.n, sc.k)
         rel = np.linalg.norm(a - rg[name]) / max(np.linalg.norm(rg[name]), 1e-30)
         assert rel <= 1e-3, (name, rel)
+
+
+def test_unaligned_colour_rows(gpu_lib):
+    """SH rows that do not start on a 16-byte boundary (a view one float into
+    a buffer) take the float-at-a-time row loads: the same image, bit for bit,
+    and the same gradients up to the order of the backward's atomic adds."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    sc = synth.uniform_scene(45, 400, 2, sh_degree=3, log_scale_mu=-2.8)
+    cam = synth.pinhole_camera(64, 48, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0), bg=(0.1, 0.2, 0.3))
+    ds = DeviceScene.from_host(sc)
+
+    def shifted(t):
+        buf = torch.zeros(t.numel() + 1, dtype=t.dtype, device=t.device)
+        buf[1:].copy_(t.reshape(-1))
+        return buf[1:].view(t.shape)
+    ds2 = DeviceScene(ds.means, ds.scales, ds.quats, ds.opacities, ds.freqs, ds.weights, sh=shifted(ds.sh),
+                      sh_degree=ds.sh_degree)
+    assert ds2.sh.data_ptr() % 16 != 0
+    g = torch.from_numpy(synth.random_dl_dimage(46, (3 * cam.height * cam.width,))).cuda()
+    out = []
+    for d in (ds, ds2):
+        plan = RenderPlan([d], [cam])
+        img = plan.forward().clone()
+        grads = {n: torch.zeros_like(getattr(d, n)) for n in NAMES if getattr(d, n, None) is not None}
+        grads["sh"] = shifted(grads["sh"])
+        plan.backward(g, [grads], accumulate=False)
+        torch.cuda.synchronize()
+        out.append((img, grads))
+    assert torch.equal(out[0][0], out[1][0])
+    for n, a in out[0][1].items():
+        b = out[1][1][n]
+        scale = float(a.abs().max())
+        assert float((a - b).abs().max()) <= 1e-5 * scale + 1e-7, n
