@@ -196,7 +196,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBatchFwd, end - b);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
-      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;
+      // lanes still blending when the chunk starts (a lane that stops inside
+      // the chunk only makes the skip test below less strict)
+      const uint64_t act = __builtin_amdgcn_ballot_w64(!done);
+      if (act == 0ull) break;
       uint64_t bits = __ballot(c0 + l < cnt && ((s_mask[c0 + l] >> w) & 1u));
       while (bits) {
         const int j = c0 + __builtin_ctzll(bits);
@@ -204,8 +207,9 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
         const float pw = staged_power(s0, s1, u, v);
         // o G < 1/255 with B <= 1 means alpha < 1/255: no full evaluation
-        bool live = !done && !(pw < kLog2AlphaMin);
-        if (__builtin_amdgcn_ballot_w64(live) == 0ull) continue;
+        const bool env = !(pw < kLog2AlphaMin);
+        if ((__builtin_amdgcn_ballot_w64(env) & act) == 0ull) continue;
+        bool live = !done && env;
         if (ANALYSIS) n_full += live ? 1u : 0u;
         const float4 col = s_rec[j * S4 + 2];
         // straight-line update: lanes that do not take the record keep their state
@@ -450,7 +454,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
         const float pw = staged_power(s0, s1, u, v);
         bool contrib = pos <= last && !(pw < kLog2AlphaMin);
-        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
+        const uint64_t cb = __builtin_amdgcn_ballot_w64(contrib);
+        if (cb == 0ull) continue;
         const float4 col = s_rec[j * S4 + 2];
         float4 cc[K > 0 ? K : 1];
 #pragma unroll
@@ -468,8 +473,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         }
         const float EB = E * Bv;
         const float alpha = fminf(kAlphaMax, EB);
-        contrib = contrib && !(alpha < kAlphaMin);
-        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
+        // the ballot of the alpha compare alone, masked in scalar registers
+        const bool a_ok = !(alpha < kAlphaMin);
+        if ((__builtin_amdgcn_ballot_w64(a_ok) & cb) == 0ull) continue;
+        contrib = contrib && a_ok;
         // lanes without a contribution keep their state and produce zero gradients
         const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
         T = contrib ? T * inv : T;  // T_i = T_(i+1) / (1 - alpha_i)
