@@ -35,8 +35,8 @@ VALU_PEAK_TFLOPS = 78.6
 # 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
 # taken on (hash of the blend's source text); otherwise traffic is null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "2f1d830f667311ef68027f5839ab22d32bb4a5e203ba298d01336564c0769a13",
-    "fetch_kib": 43671.11, "write_kib": 24002.92, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "b56fc39df842dc3654e89ecae82461f7b80cdfb0bb53605143543575fc7eab52",
+    "fetch_kib": 43673.4, "write_kib": 23990.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
