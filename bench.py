@@ -23,8 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# fp32 VALU peak without packed-FP32 instructions (which this build does not
-# use): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+# fp32 VALU peak without packed-FP32 instructions (the library is compiled
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 78.6
 
 # HBM traffic of one k_render_fwd<4, false> launch on the default workload,
