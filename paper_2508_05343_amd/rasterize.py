@@ -43,6 +43,12 @@ class DeviceScene:
         self.sh_degree = sh_degree if sh is not None else -1
         self.n = int(means.shape[1])
         self.k = int(weights.shape[0])
+        # colour coefficients are one row per primitive
+        if sh is not None and tuple(sh.shape) != (self.n, 3 * (self.sh_degree + 1) ** 2):
+            raise ValueError(f"sh must be [n, {3 * (self.sh_degree + 1) ** 2}] (one row per primitive), "
+                             f"got {tuple(sh.shape)}")
+        if colors is not None and tuple(colors.shape) != (self.n, 3):
+            raise ValueError(f"colors must be [n, 3] (one row per primitive), got {tuple(colors.shape)}")
 
     @staticmethod
     def from_host(scene, device="cuda", attenuation=False, mip2d=False) -> "DeviceScene":

@@ -97,3 +97,18 @@ def test_missing_library_fails_loudly(L, monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libgabsplat.so")
     with pytest.raises(L.GabsplatError):
         L.lib()
+
+
+def test_device_scene_requires_colour_rows():
+    """Colour coefficients are one row per primitive: a planar [D*3, n] SH
+    tensor (or [3, n] colours) is refused instead of being misread."""
+    import torch
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    n, k = 10, 2
+    z = lambda *s: torch.zeros(*s)
+    DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), sh=z(n, 48), sh_degree=3)
+    DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), colors=z(n, 3))
+    with pytest.raises(ValueError):
+        DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), sh=z(48, n), sh_degree=3)
+    with pytest.raises(ValueError):
+        DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), colors=z(3, n))
