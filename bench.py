@@ -68,7 +68,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles of the frame blended by the CPU oracle")
+    ap.add_argument("--cpu-tiles", type=int, default=4346,
+                    help="tiles of the frame blended by the CPU oracle (default: all 4346 of the forward "
+                         "workload's frame, 10-30 s on 16 host threads)")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU baseline (for rocprofv3)")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 64-view training step")
     ap.add_argument("--profile-multiview", action="store_true",
