@@ -737,9 +737,13 @@ __device__ __forceinline__ uint32_t tile_of(const ItemTiles& it, uint32_t q) {
 
 // Calls f(item, tile) for every (visible item, tile) pair of the items
 // i0 + k * blockDim + lane (k < kTcItems, below i1) of a wavefront: the tile
-// counts and rectangles of all of them are loaded first; small rectangles are
-// walked by their own lane, large ones by the whole wavefront (so that no
-// lane walks thousands of tiles).  Must be called by full wavefronts.
+// counts and rectangles of all of them are loaded first.  The pairs of small
+// rectangles are dealt out evenly: a wave prefix sum of the 64 items' pair
+// counts numbers them, and lane l takes pairs l, l + 64, ..., finding the
+// owning item by a binary search over the prefix sums (most items touch no
+// tile or a few, so walking each item in its own lane would leave most
+// lanes idle for as long as the largest item of the wave).  Large rectangles
+// are walked by the whole wavefront.  Must be called by full wavefronts.
 constexpr int kTcItems = 4;
 
 template <typename F>
@@ -763,8 +767,29 @@ __device__ __forceinline__ void for_each_pair(const ViewEntry* views, int nv, co
       it = item_tiles(views, nv, item, rc[k]);
       n = min(n, it.w * it.h);  // never past the rectangle (and no division by a zero width)
     }
-    if (n && n <= (uint32_t)kTcBig)
-      for (uint32_t q = 0; q < n; ++q) f(item, tile_of(it, q));
+    // small rectangles: pairs numbered by a wave prefix sum, dealt to lanes
+    const uint32_t ns = n <= (uint32_t)kTcBig ? n : 0u;
+    uint32_t inc = ns;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)inc, d, 64);
+      if (l >= d) inc += o;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)inc, 63, 64);
+    for (uint32_t p0 = 0; p0 < total; p0 += 64) {  // uniform trip count, every lane active
+      const uint32_t p = min(p0 + (uint32_t)l, total - 1u);
+      int src = 0;  // the first lane whose inclusive count exceeds p
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if ((uint32_t)__shfl((int)inc, src + step - 1, 64) <= p) src += step;
+      const uint32_t s_inc = (uint32_t)__shfl((int)inc, src, 64), s_n = (uint32_t)__shfl((int)ns, src, 64);
+      ItemTiles st;
+      st.base = (uint32_t)__shfl((int)it.base, src, 64);
+      st.w = (uint32_t)__shfl((int)it.w, src, 64);
+      st.tx = (uint32_t)__shfl((int)it.tx, src, 64);
+      const uint32_t s_item = (uint32_t)__shfl((int)item, src, 64);
+      if (p0 + (uint32_t)l < total) f(s_item, tile_of(st, p - (s_inc - s_n)));
+    }
     uint64_t big = __ballot(n > (uint32_t)kTcBig);
     while (big) {
       const int src = __builtin_ctzll(big);
