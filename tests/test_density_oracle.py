@@ -91,3 +91,48 @@ def test_periodic_reset():
     w, o = D.periodic_reset(sc)
     assert (w == 0.01).all() and (o <= 0.02).all()
     assert (o == np.minimum(sc.opacities.astype(np.float64), 0.02)).all()
+
+
+def test_decision_boundaries_from_the_text():
+    """The three thresholds at their exact boundary values, with the expected
+    decision written from the rule the paper adopts (Sec. 3.4.2 densifies as
+    3DGS does; supplementary B gives the prune threshold): a primitive is
+    selected when its mean view-space gradient is AT LEAST the threshold,
+    cloned when its largest scale is AT MOST percent_dense * extent (split when
+    larger), and pruned when its opacity is BELOW min_opacity.  Values one
+    float32 step to either side flip the decision.  A '>' for '>=', a '<' for
+    '<=' or a '<=' for '<' fails one of the rows."""
+    f32 = np.float32
+    thr, pd, ext, mo = f32(2e-4), f32(0.01), f32(1.0), f32(0.01)
+    below = lambda x: np.nextafter(f32(x), f32(0))  # noqa: E731
+    above = lambda x: np.nextafter(f32(x), f32(1))  # noqa: E731
+    small, big = f32(0.005), f32(0.02)
+    # (mean gradient, max scale, opacity) -> expected kind (0 keep, 1 clone, 2 split, 3 prune)
+    rows = [
+        (thr, small, f32(0.5), 1),           # gradient exactly at the threshold: selected
+        (below(thr), small, f32(0.5), 0),    # just below: kept
+        (thr, pd * ext, f32(0.5), 1),        # max scale exactly percent_dense * extent: clone
+        (thr, above(pd * ext), f32(0.5), 2),  # just above: split
+        (thr, big, f32(0.5), 2),
+        (below(thr), big, f32(0.5), 0),
+        (f32(0.0), small, mo, 0),            # opacity exactly min_opacity: not pruned
+        (f32(0.0), small, below(mo), 3),     # just below: pruned
+        (thr, small, below(mo), 3),          # pruning wins over cloning
+        (thr, big, below(mo), 3),            # and over splitting
+    ]
+    n = len(rows)
+    sc = synth.uniform_scene(11, n, 2, sh_degree=-1)
+    sc.scales[:] = f32(0.001)
+    for i, (g, s, o, _) in enumerate(rows):
+        sc.scales[i, i % 3] = s          # the largest scale on a varying axis
+        sc.opacities[i] = o
+    denom = np.ones(n, np.float32)
+    accum = np.array([r[0] for r in rows], np.float32)
+    prm = D.DensifyParams(grad_threshold=2e-4, percent_dense=0.01, scene_extent=1.0, min_opacity=0.01)
+    kind = D.decide(sc, accum, denom, prm)
+    assert kind.tolist() == [r[3] for r in rows]
+    # a mean over several views: accum / denom at the threshold is still selected
+    sc2 = sc.subset(np.array([0]))
+    assert D.decide(sc2, np.array([f32(thr) * f32(4.0)], np.float32), np.array([4.0], np.float32), prm).tolist() == [1]
+    # never seen (denom 0): mean gradient 0, kept
+    assert D.decide(sc2, np.array([f32(1.0)], np.float32), np.array([0.0], np.float32), prm).tolist() == [0]

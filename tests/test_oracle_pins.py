@@ -249,6 +249,60 @@ def test_real_spherical_harmonics_match_scipy():
             col += 1
 
 
+def _rgb(sh, mean, eye):
+    return O.sh_to_rgb(torch.tensor(np.asarray(sh, np.float64))[None], torch.tensor(np.asarray(mean, np.float64))[None],
+                       torch.tensor(np.asarray(eye, np.float64))).numpy()[0]
+
+
+# real SH constants of degrees 0-2 (textbook closed forms, no Condon-Shortley phase)
+_Y00 = 0.28209479177387814            # 1 / (2 sqrt(pi))
+_Y1 = 0.4886025119029199              # sqrt(3 / (4 pi)): y, z, x for m = -1, 0, 1
+_Y2A = 1.0925484305920792             # sqrt(15 / pi) / 2: xy, yz, xz
+_Y20 = 0.31539156525252005            # sqrt(5 / pi) / 4: 3 z^2 - 1
+_Y22 = 0.5462742152960396             # sqrt(15 / pi) / 4: x^2 - y^2
+
+
+def test_sh_colour_closed_forms():
+    """Colour of a primitive from its SH coefficients (Sec. 3.2 keeps the 3DGS
+    view-dependent colour): max(0, 0.5 + sum_d c_d Y_d(dir)) with dir the unit
+    vector from the camera centre to the mean, coefficients in (l, m) order
+    m = -l..l, one coefficient triple (r, g, b) per basis function.  Every
+    expected value below is written out by hand from the degree-0..2 closed
+    forms: a dropped +0.5, a direction taken from the mean to the camera, a
+    permuted basis order or a missing clamp each fails one of them."""
+    eye = np.array([0.5, -1.0, 2.0])
+    d = np.array([1.0, -2.0, 2.0]) / 3.0           # x = 1/3, y = -2/3, z = 2/3
+    mean = eye + 1.5 * 3.0 * d
+    # degree 0: a constant plus the offset
+    np.testing.assert_allclose(_rgb([[0.4, -0.2, 1.0]], mean, eye),
+                               [0.5 + 0.4 * _Y00, 0.5 - 0.2 * _Y00, 0.5 + 1.0 * _Y00], rtol=1e-14)
+    # degree 1: Y_1,-1 = c y, Y_1,0 = c z, Y_1,1 = c x; one basis function per channel
+    sh1 = [[0.1, 0.1, 0.1], [0.3, 0.0, 0.0], [0.0, 0.3, 0.0], [0.0, 0.0, 0.3]]
+    want = [0.5 + 0.1 * _Y00 + 0.3 * _Y1 * (-2.0 / 3.0),
+            0.5 + 0.1 * _Y00 + 0.3 * _Y1 * (2.0 / 3.0),
+            0.5 + 0.1 * _Y00 + 0.3 * _Y1 * (1.0 / 3.0)]
+    np.testing.assert_allclose(_rgb(sh1, mean, eye), want, rtol=1e-14)
+    # the reversed direction (camera minus mean) gives a different colour
+    flipped = [0.5 + 0.1 * _Y00 - 0.3 * _Y1 * (-2.0 / 3.0), 0.5 + 0.1 * _Y00 - 0.3 * _Y1 * (2.0 / 3.0),
+               0.5 + 0.1 * _Y00 - 0.3 * _Y1 * (1.0 / 3.0)]
+    assert np.abs(np.asarray(want) - flipped).min() > 0.03
+    # the colour depends on the direction only, not on the distance
+    np.testing.assert_allclose(_rgb(sh1, eye + 0.01 * d, eye), want, rtol=1e-13)
+    # degree 2, one basis function at a time on the red channel
+    y2 = [_Y2A * (1 / 3) * (-2 / 3), _Y2A * (-2 / 3) * (2 / 3), _Y20 * (3 * (2 / 3) ** 2 - 1),
+          _Y2A * (1 / 3) * (2 / 3), _Y22 * ((1 / 3) ** 2 - (2 / 3) ** 2)]
+    for j, yv in enumerate(y2):
+        sh2 = np.zeros((9, 3))
+        sh2[4 + j, 0] = 1.0
+        np.testing.assert_allclose(_rgb(sh2, mean, eye), [0.5 + yv, 0.5, 0.5], rtol=1e-14, err_msg=str(j))
+    # clamp at zero, with zero gradient on the clamped channels
+    sh0 = torch.tensor([[[-3.0, 0.2, -1.8]]], dtype=torch.float64, requires_grad=True)
+    rgb = O.sh_to_rgb(sh0, torch.tensor(mean[None]), torch.tensor(eye))
+    np.testing.assert_allclose(rgb.detach().numpy()[0], [0.0, 0.5 + 0.2 * _Y00, 0.0], rtol=1e-14)
+    rgb.sum().backward()
+    np.testing.assert_allclose(sh0.grad.numpy()[0, 0], [0.0, _Y00, 0.0], rtol=1e-14)
+
+
 def test_rotation_matrix_is_orthonormal_and_matches_rotation_of_vectors():
     """R(q) v equals the quaternion sandwich q v q* (Hamilton product)."""
     rng = np.random.Generator(np.random.PCG64(3))
