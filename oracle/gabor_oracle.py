@@ -403,6 +403,8 @@ class PixelResult:
     n_blended: np.ndarray    # [P] number of blended primitives
     fragile: np.ndarray      # [P] bool
     freq_map: Optional[torch.Tensor] = None  # [P] blended sum_k w_k |f2d_k| (cycles/px)
+    n_fragile: Optional[np.ndarray] = None   # [P] number of fragile decisions up to the stop
+    fragile_bound: Optional[np.ndarray] = None  # [P] their largest effect, in units of the colour span
 
 
 def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Tensor,
@@ -417,7 +419,8 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
     if m == 0:
         col = bg[None, :].expand(P, 3).clone()
         return PixelResult(col, torch.ones(P, dtype=DT), -np.ones(P, np.int64),
-                           np.zeros(P, np.int64), np.zeros(P, bool), torch.zeros(P, dtype=DT))
+                           np.zeros(P, np.int64), np.zeros(P, bool), torch.zeros(P, dtype=DT), np.zeros(P, np.int64),
+                           np.zeros(P))
     ci = torch.from_numpy(np.asarray(cand, np.int64))
     if mu is None:
         mu = pr.mu2d[ci]
@@ -463,8 +466,21 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
         fa = np.abs(ar - ALPHA_MIN) <= tau_alpha * ALPHA_MIN
         ft = vn & (np.abs(Ta - T_MIN) <= tau_T * T_MIN)
         fprim = (pr.fragile_prim[np.asarray(cand)][None, :]) & (ar >= ALPHA_MIN * (1 - tau_alpha))
-        fragile = ((fa | ft | fprim) & upto).any(1)
-    return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile, fmap)
+        n_frag = ((fa | ft | fprim) & upto).sum(1)
+        fragile = n_frag > 0
+        # how far each fragile decision can move the pixel, in units of the
+        # colour span max|c - bg|: with T_j the transmittance before record j
+        # on the walk, blending or skipping j changes the colour by
+        # alpha_j T_j (c_j - C_behind) (at most 2 alpha_j T_j span), and
+        # stopping at j instead of walking on by T_j (bg - C_behind) (at most
+        # T_j span); an ill-conditioned frequency solve can move alpha_j
+        # anywhere in [0, 0.99] (at most 2 T_j span)
+        Tb = np.concatenate([np.ones((P, 1)), Ta[:, :-1]], 1)
+        al = alpha.detach().numpy()
+        fb = (fa * 2.0 * np.clip(al, 0.0, None) * Tb + ft * Tb + fprim * 2.0 * Tb) * upto
+        frag_bound = fb.sum(1)
+    return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile, fmap,
+                       n_frag.astype(np.int64), frag_bound)
 
 
 def blend_pixel_loop(pr: Projected, cand: Sequence[int], x: float, y: float, bg) -> tuple:
@@ -506,6 +522,12 @@ class Image:
     n_blended: np.ndarray  # [H,W]
     fragile: np.ndarray    # [H,W]
     freq_map: Optional[torch.Tensor] = None  # [H,W]
+    n_fragile: Optional[np.ndarray] = None   # [H,W] fragile decisions per pixel
+    # max over visible primitives and channels of |colour - background|
+    colour_span: float = 0.0
+    # [H,W] largest change of the pixel that its fragile decisions can cause,
+    # in units of colour_span (PixelResult.fragile_bound)
+    fragile_bound: Optional[np.ndarray] = None
 
 
 def _tile_pixels(tx, ty, W, H):
@@ -540,6 +562,8 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
     last = np.full(H * W, -2, np.int64)
     nbl = np.zeros(H * W, np.int64)
     frag = np.zeros(H * W, bool)
+    nfrag = np.zeros(H * W, np.int64)
+    fbound = np.zeros(H * W)
     if tiles is None:
         tiles = [(tx, ty) for ty in range(ty_n) for tx in range(tx_n)]
     parts = []
@@ -564,14 +588,19 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
         last[idx] = res.last_id
         nbl[idx] = res.n_blended
         frag[idx] = res.fragile
+        nfrag[idx] = res.n_fragile
+        fbound[idx] = res.fragile_bound
     fm = torch.full((H * W,), float("nan"), dtype=DT)
     if idxs:
         ii = torch.cat(idxs)
         color = color.index_put((ii,), torch.cat(cols))
         fT = fT.index_put((ii,), torch.cat(fts))
         fm = fm.index_put((ii,), torch.cat(fms))
+    vis_t = pr.visible
+    span = float((pr.rgb.detach()[vis_t] - bg[None, :]).abs().max()) if bool(vis_t.any()) else 0.0
     return Image(color.T.reshape(3, H, W), fT.reshape(H, W), last.reshape(H, W),
-                 nbl.reshape(H, W), frag.reshape(H, W), fm.reshape(H, W))
+                 nbl.reshape(H, W), frag.reshape(H, W), fm.reshape(H, W), nfrag.reshape(H, W), span,
+                 fbound.reshape(H, W))
 
 
 def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False, mip2d=False, filter3d=None) -> Image:
@@ -695,6 +724,42 @@ def _take(pr: Projected, rows: np.ndarray, local_i: int, one: Projected) -> Proj
     return out
 
 
+def window_setup(pr_all: Projected, order: np.ndarray, i: int):
+    """The window of primitive i: the tiles of its rect, each tile's
+    candidates (depth order), the rows of the projection they use and the
+    position of i among them.  None when i is not visible."""
+    if not bool(pr_all.visible[i]):
+        return None
+    x0, y0, x1, y1 = (int(v) for v in pr_all.rect[i])
+    tiles = [(tx, ty) for ty in range(y0, y1) for tx in range(x0, x1)]
+    cands = [tile_candidates(pr_all, order, tx, ty) for (tx, ty) in tiles]
+    rows = np.unique(np.concatenate(cands + [np.array([i])]))
+    return tiles, cands, rows, int(np.searchsorted(rows, i))
+
+
+def _window_total(scene, ct, g_img: torch.Tensor, pr_all: Projected, win, i: int, pi) -> torch.Tensor:
+    """sum(dl_dimage * C) over the pixels of the tiles in primitive i's rect
+    (``win`` from window_setup), with primitive i projected from the
+    attribute tensors ``pi`` (a one-row scene) and every other primitive as in
+    ``pr_all``.  Outside those tiles primitive i is not a candidate (its alpha
+    there is below 1/255), so this window holds every pixel that depends on it."""
+    W, H = ct["W"], ct["H"]
+    sub = scene.subset(np.array([i]))
+    pri = project(pi, ct, sub)
+    total = torch.zeros((), dtype=DT)
+    if win is None:
+        return total
+    tiles, cands, rows, local_i = win
+    pr = _take(pr_all, rows, local_i, pri)
+    for (tx, ty), cand in zip(tiles, cands):
+        gx, gy = _tile_pixels(tx, ty, W, H)
+        loc = np.searchsorted(rows, cand)
+        res = blend_pixels(pr, loc, torch.from_numpy(gx + 0.5).to(DT), torch.from_numpy(gy + 0.5).to(DT), ct["bg"])
+        gsel = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
+        total = total + (res.color * gsel).sum()
+    return total
+
+
 def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[int],
                              pr_all: Optional[Projected] = None) -> List[Dict[str, np.ndarray]]:
     """Gradients of sum(dl_dimage * C) w.r.t. the attributes of each listed
@@ -702,7 +767,6 @@ def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[
     primitive's rect (outside them its alpha is below 1/255 and it is skipped,
     so no other pixel depends on it)."""
     ct = camera_tensors(cam)
-    W, H = ct["W"], ct["H"]
     with torch.no_grad():
         if pr_all is None:
             pr_all = project(scene_tensors(scene), ct, scene)
@@ -710,24 +774,8 @@ def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[
     g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
     out = []
     for i in prims:
-        sub = scene.subset(np.array([i]))
-        pi = scene_tensors(sub, requires_grad=True)
-        pri = project(pi, ct, sub)
-        total = torch.zeros((), dtype=DT)
-        if bool(pr_all.visible[i]):
-            x0, y0, x1, y1 = (int(v) for v in pr_all.rect[i])
-            tiles = [(tx, ty) for ty in range(y0, y1) for tx in range(x0, x1)]
-            cands = [tile_candidates(pr_all, order, tx, ty) for (tx, ty) in tiles]
-            rows = np.unique(np.concatenate(cands + [np.array([i])]))
-            local_i = int(np.searchsorted(rows, i))
-            pr = _take(pr_all, rows, local_i, pri)
-            for (tx, ty), cand in zip(tiles, cands):
-                gx, gy = _tile_pixels(tx, ty, W, H)
-                loc = np.searchsorted(rows, cand)
-                res = blend_pixels(pr, loc, torch.from_numpy(gx + 0.5).to(DT),
-                                   torch.from_numpy(gy + 0.5).to(DT), ct["bg"])
-                gsel = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
-                total = total + (res.color * gsel).sum()
+        pi = scene_tensors(scene.subset(np.array([i])), requires_grad=True)
+        total = _window_total(scene, ct, g_img, pr_all, window_setup(pr_all, order, i), i, pi)
         if total.requires_grad:
             total.backward()
         grads = {}
@@ -735,6 +783,24 @@ def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[
             grads[k] = (v.grad.numpy()[0] if v.grad is not None else np.zeros(v.shape[1:]))
         out.append(grads)
     return out
+
+
+def primitive_loss_windowed(scene, cam, dl_dimage: np.ndarray, i: int, attrs: Dict[str, np.ndarray],
+                            pr_all: Optional[Projected] = None, win=None) -> float:
+    """sum(dl_dimage * C) over primitive i's window (see _window_total) with
+    primitive i's attributes set to ``attrs`` (fp64 arrays of one primitive,
+    e.g. perturbed for finite differences); the decisions taken on float32
+    values (depth key, culls) stay those of the unperturbed primitive.  ``win``
+    (from window_setup) may be passed to reuse the candidate lists."""
+    ct = camera_tensors(cam)
+    with torch.no_grad():
+        if pr_all is None:
+            pr_all = project(scene_tensors(scene), ct, scene)
+        if win is None:
+            win = window_setup(pr_all, depth_order(pr_all.depth32, pr_all.visible.numpy()), i)
+        g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+        pi = {k: torch.tensor(np.asarray(v, np.float64)[None], dtype=DT) for k, v in attrs.items()}
+        return float(_window_total(scene, ct, g_img, pr_all, win, i, pi))
 
 
 # --------------------------------------------------------------------------
