@@ -22,6 +22,29 @@ TILE = 16
 
 
 # ----------------------------------------------------------------- scenes
+def check_device_tensor(name: str, t, shape, device=None, check_device: bool = True):
+    """Raises ValueError unless ``t`` is a contiguous float32 device tensor of
+    exactly ``shape`` (on ``device`` when given); returns its device.  The
+    kernels read these buffers through raw pointers with the layouts of the C
+    ABI, so a transposed view, a short array or a host tensor would be misread
+    or read out of bounds.  Checked in the order dtype, shape, layout, device."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (the library reads it through a raw pointer)")
+    if not check_device:
+        return t.device
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor, got device {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the other attributes on {device}")
+    return t.device
+
+
 class DeviceScene:
     """Activated primitive attributes as fp32 device tensors: planar means
     [3,n], scales [3,n], quats [4,n], opacities [n], freqs [3K,n], weights
@@ -37,18 +60,39 @@ class DeviceScene:
                  attenuation=False, mip2d=False, filter3d=None):
         self.attenuation = bool(attenuation)
         self.mip2d = bool(mip2d)
-        self.filter3d = filter3d
-        self.means, self.scales, self.quats, self.opacities = means, scales, quats, opacities
-        self.freqs, self.weights, self.sh, self.colors = freqs, weights, sh, colors
-        self.sh_degree = sh_degree if sh is not None else -1
+        if (sh is None) == (colors is None):
+            raise ValueError("exactly one of sh and colors must be given")
+        if sh is not None and not 0 <= int(sh_degree) <= 3:
+            raise ValueError(f"sh_degree must be in [0, 3] with sh, got {sh_degree}")
+        if not isinstance(weights, torch.Tensor) or weights.dim() != 2:
+            raise ValueError("weights must be a [K, n] tensor")
+        if not isinstance(means, torch.Tensor) or means.dim() != 2:
+            raise ValueError("means must be a [3, n] tensor")
         self.n = int(means.shape[1])
         self.k = int(weights.shape[0])
+        if not 0 <= self.k <= 8:
+            raise ValueError(f"K = {self.k} frequency components: at most 8 are supported")
+        self.sh_degree = int(sh_degree) if sh is not None else -1
+        n, k = self.n, self.k
+        shapes = dict(means=(3, n), scales=(3, n), quats=(4, n), opacities=(n,), freqs=(3 * k, n), weights=(k, n))
         # colour coefficients are one row per primitive
-        if sh is not None and tuple(sh.shape) != (self.n, 3 * (self.sh_degree + 1) ** 2):
-            raise ValueError(f"sh must be [n, {3 * (self.sh_degree + 1) ** 2}] (one row per primitive), "
-                             f"got {tuple(sh.shape)}")
-        if colors is not None and tuple(colors.shape) != (self.n, 3):
-            raise ValueError(f"colors must be [n, 3] (one row per primitive), got {tuple(colors.shape)}")
+        if sh is not None:
+            shapes["sh"] = (n, 3 * (self.sh_degree + 1) ** 2)
+        else:
+            shapes["colors"] = (n, 3)
+        if filter3d is not None:
+            shapes["filter3d"] = (n,)
+        given = dict(means=means, scales=scales, quats=quats, opacities=opacities, freqs=freqs, weights=weights,
+                     sh=sh, colors=colors, filter3d=filter3d)
+        # layouts of every attribute first, then where they live
+        for name, shape in shapes.items():
+            check_device_tensor(name, given[name], shape, check_device=False)
+        dev = None
+        for name, shape in shapes.items():
+            dev = check_device_tensor(name, given[name], shape, dev)
+        self.means, self.scales, self.quats, self.opacities = means, scales, quats, opacities
+        self.freqs, self.weights, self.sh, self.colors = freqs, weights, sh, colors
+        self.filter3d = filter3d
 
     @staticmethod
     def from_host(scene, device="cuda", attenuation=False, mip2d=False) -> "DeviceScene":
@@ -181,6 +225,24 @@ class RenderPlan:
         self.capacity = 0
         self._alloc_pairs(pair_capacity if pair_capacity is not None else max(1 << 16, 8 * items))
         self.grad2d = None
+        # bumped by every stage that rewrites the buffers a backward reads
+        # (records, pair lists, final_T, n_contrib); an autograd graph keeps
+        # the value of its forward and refuses a backward after a newer run
+        self.generation = 0
+
+    def bind_scene(self, index: int, scene: DeviceScene):
+        """Renders ``scene`` in place of scene ``index`` from now on.  It must
+        have the same primitive count, component count, colour mode and
+        options (the plan's buffers are sized and laid out for them)."""
+        old = self.scenes[index]
+        if (scene.n, scene.k, scene.sh_degree, scene.flags()) != (old.n, old.k, old.sh_degree, old.flags()) or \
+                (scene.sh is None) != (old.sh is None):
+            raise ValueError(f"scene {index}: (n, k, sh_degree, flags) = {(scene.n, scene.k, scene.sh_degree, scene.flags())}"
+                             f" does not match the plan's {(old.n, old.k, old.sh_degree, old.flags())}")
+        if scene.means.device != torch.device(self.device) and str(self.device) != "cuda":
+            raise ValueError(f"scene on {scene.means.device}, plan on {self.device}")
+        self.scenes[index] = scene
+        self.c_scenes[index] = scene.cstruct()
 
     def _alloc_pairs(self, cap: int):
         cap = int(cap)
@@ -192,13 +254,16 @@ class RenderPlan:
 
     # ----- stages
     def preprocess(self, stream=None):
+        self.generation += 1
         _lib.gabsplat_preprocess(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, stream)
 
     def bin_sort(self, stream=None):
+        self.generation += 1
         _lib.gabsplat_bin_sort(self.geom, self.c_cams, self.items, self.ws, self.keys, self.vals, self.capacity,
                                self.ranges, self.num_pairs, self.overflow, stream)
 
     def render_fwd(self, stream=None, eval_counts=None, freq_map=None):
+        self.generation += 1
         _lib.gabsplat_render_fwd(self.geom, self.vals, self.ranges, self.c_cams, self.image, self.final_T,
                                  self.n_contrib, self.overflow, stream, eval_counts=eval_counts, freq_map=freq_map)
 
@@ -221,16 +286,27 @@ class RenderPlan:
         """dl_dimage has the layout of self.image; grads[s] maps attribute name
         -> tensor (same layout as the scene) that receives the gradient, added
         to it (accumulate=True) or overwriting it."""
+        if not isinstance(dl_dimage, torch.Tensor) or dl_dimage.numel() != 3 * self.pixels:
+            raise ValueError(f"dl_dimage must hold the plan's {3 * self.pixels} image values")
+        check_device_tensor("dl_dimage", dl_dimage, tuple(dl_dimage.shape), self.image.device)
+        if len(grads) != len(self.scenes):
+            raise ValueError(f"{len(grads)} gradient sets for {len(self.scenes)} scenes")
         if self.grad2d is None:
             gf = _lib.gabsplat_grad2d_stride(self.k, self.grad_flags)
             self.grad2d = torch.empty((max(self.items, 1), gf), dtype=torch.float32, device=self.device)
         gs = []
-        for g in grads:
+        for sc, g in zip(self.scenes, grads):
             c = _lib.SceneGrads()
             c.accumulate = 1 if accumulate else 0
             c.flags = self.grad_flags
             for name in ("means", "scales", "quats", "opacities", "sh", "colors", "freqs", "weights"):
-                setattr(c, name, _lib.ptr(g.get(name)))
+                t = g.get(name)
+                if t is not None:
+                    ref = getattr(sc, name)
+                    if ref is None:
+                        raise ValueError(f"gradient for {name}, which the scene does not have")
+                    check_device_tensor(f"grads[{name}]", t, tuple(ref.shape), ref.device)
+                setattr(c, name, _lib.ptr(t))
             c.grad2d = _lib.ptr(self.grad2d)
             gs.append(c)
         _lib.gabsplat_render_bwd(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals, self.ranges,
@@ -285,34 +361,90 @@ class LossBuffers:
 
 # --------------------------------------------------------------- autograd
 class GaborRasterize(torch.autograd.Function):
-    """image = rasterize(means, scales, quats, opacities, color, freqs, weights)
-    for one scene and a list of cameras; `color` is the SH tensor [n, D*3]
-    (sh_degree >= 0) or RGB [n, 3].  Returns the flat image buffer of the plan
-    (views back to back, [3][H][W] each)."""
+    """image = GaborRasterize.apply(means, scales, quats, opacities, color,
+    freqs, weights, plan): the activated attributes of one scene (the layouts
+    of DeviceScene; ``color`` is the SH rows [n, 3 (deg+1)^2] or the RGB rows
+    [n, 3], as the plan's scene) rendered through every camera of ``plan``.
+    Returns the flat image (views back to back, [3][H][W] each).
+
+    The tensors given are the ones rendered: they are validated and bound to
+    the plan as its scene for this call, so they may be the outputs of torch
+    ops (exp of log-scales, sigmoid of logits, Sec. 3.4.1).  The backward
+    reads the plan's per-call buffers, so a plan carries one live graph at a
+    time: a backward after the plan has run again raises."""
 
     @staticmethod
     def forward(ctx, means, scales, quats, opacities, color, freqs, weights, plan: RenderPlan):
+        if len(plan.scenes) != 1:
+            raise ValueError("GaborRasterize renders one scene; the plan has several")
+        tmpl = plan.scenes[0]
+        has_sh = tmpl.sh is not None
+        ds = DeviceScene(means, scales, quats, opacities, freqs, weights, sh=color if has_sh else None,
+                         colors=None if has_sh else color, sh_degree=tmpl.sh_degree, attenuation=tmpl.attenuation,
+                         mip2d=tmpl.mip2d, filter3d=tmpl.filter3d)
+        plan.bind_scene(0, ds)
         img = plan.forward(check_overflow=True)
-        ctx.plan = plan
+        ctx.plan, ctx.scene, ctx.generation = plan, ds, plan.generation
         return img.clone()
 
     @staticmethod
     def backward(ctx, dl_dimage):
         plan: RenderPlan = ctx.plan
-        sc = plan.scenes[0]
-        g = {name: torch.zeros_like(getattr(sc, name)) for name in
-             ("means", "scales", "quats", "opacities", "freqs", "weights")}
-        if sc.sh is not None:
-            g["sh"] = torch.zeros_like(sc.sh)
-        else:
-            g["colors"] = torch.zeros_like(sc.colors)
-        plan.backward(dl_dimage.contiguous(), [g])
+        if plan.generation != ctx.generation or plan.scenes[0] is not ctx.scene:
+            raise RuntimeError("GaborRasterize: the plan has run again since this forward; its buffers no longer "
+                               "hold this graph's state (use one plan per live graph)")
+        sc = ctx.scene
+        names = ("means", "scales", "quats", "opacities", "color", "freqs", "weights")
+        g = {}
+        for i, name in enumerate(names):
+            if not ctx.needs_input_grad[i]:
+                continue
+            attr = ("sh" if sc.sh is not None else "colors") if name == "color" else name
+            g[attr] = torch.empty_like(getattr(sc, attr))
+        if g:
+            plan.backward(dl_dimage.contiguous().view(-1), [g], accumulate=False)
         col = g.get("sh", g.get("colors"))
-        return g["means"], g["scales"], g["quats"], g["opacities"], col, g["freqs"], g["weights"], None
+        return (g.get("means"), g.get("scales"), g.get("quats"), g.get("opacities"), col, g.get("freqs"),
+                g.get("weights"), None)
 
 
-def rasterize(scene: DeviceScene, plan: RenderPlan):
-    """Differentiable render of `plan`'s views of `scene` (flat image buffer)."""
+def rasterize(plan: RenderPlan, means, scales, quats, opacities, color, freqs, weights):
+    """Differentiable render of the given activated attributes through the
+    plan's cameras (flat image buffer); see GaborRasterize."""
+    return GaborRasterize.apply(means, scales, quats, opacities, color, freqs, weights, plan)
+
+
+def rasterize_scene(scene: DeviceScene, plan: RenderPlan):
+    """rasterize() of a DeviceScene's tensors."""
     col = scene.sh if scene.sh is not None else scene.colors
-    return GaborRasterize.apply(scene.means, scene.scales, scene.quats, scene.opacities, col, scene.freqs,
-                                scene.weights, plan)
+    return rasterize(plan, scene.means, scene.scales, scene.quats, scene.opacities, col, scene.freqs, scene.weights)
+
+
+class PhotometricLoss(torch.autograd.Function):
+    """L = (1 - lam) mean|x - y| + lam (1 - mean SSIM(x, y)) of Sec. 3.4.1
+    through the library's loss kernels; x, y [C, H, W] float32 device tensors.
+    The gradient with respect to x is computed by the forward call (one kernel
+    pass yields both) and scaled by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, x, y, lam, buffers):
+        c, h, w = x.shape
+        check_device_tensor("x", x, (c, h, w))
+        check_device_tensor("y", y, (c, h, w), x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty_like(x)
+        if buffers is None:
+            buffers = LossBuffers(c, h, w, device=x.device)
+        _lib.gabsplat_loss_l1_dssim(x, y, float(lam), loss, grad, buffers.ws, None)
+        ctx.save_for_backward(grad)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, go):
+        (grad,) = ctx.saved_tensors
+        return grad * go, None, None, None
+
+
+def photometric_loss(x, y, lam: float = 0.2, buffers: Optional["LossBuffers"] = None):
+    """Differentiable L1 + lam D-SSIM loss (the training objective of Sec. 3.4.1)."""
+    return PhotometricLoss.apply(x, y, lam, buffers)

@@ -43,11 +43,61 @@ def last_ids_from_gpu(plan, v, n_items_offset=0):
     return np.where(ids >= 0, ids - off, -1)
 
 
+# Largest fraction of fragile pixels a forward comparison accepts (pixels
+# where some decision of the oracle lies within its tolerance of a threshold).
+MAX_FRAGILE_FRACTION = 0.01
+
+
 def compare_image(gpu_img, ref, atol=1e-4):
-    """Max abs error on non-fragile pixels, fragile fraction, and the count of
-    non-fragile pixels above atol."""
-    d = np.abs(gpu_img - ref.color.numpy())
-    valid = ~np.isnan(ref.color.numpy()[0])
+    """Compares a rendered [3,H,W] image with the oracle's over the pixels the
+    oracle rendered.  Non-fragile pixels must be within ``atol``; a fragile
+    pixel within atol + fragile_bound * colour_span, the largest change its
+    fragile decisions can cause (each alpha near 1/255 at most 2 alpha T span,
+    each stop-rule decision near 1e-4 at most T span, T the transmittance
+    before it).  Returns (max error on non-fragile pixels, fragile fraction,
+    number of pixels outside their bound)."""
+    c = ref.color.numpy()
+    d = np.abs(gpu_img - c).max(0)
+    valid = ~np.isnan(c[0])
+    bound = atol + ref.fragile_bound * ref.colour_span
+    bad = valid & ~(d <= bound)
     ok = valid & ~ref.fragile
-    bad = (d.max(0) > atol) & ok
-    return float(d[:, ok].max()) if ok.any() else 0.0, float(ref.fragile[valid].mean()), int(bad.sum())
+    err = float(d[ok].max()) if ok.any() else 0.0
+    frac = float(ref.fragile[valid].mean()) if valid.any() else 0.0
+    return err, frac, int(bad.sum())
+
+
+def assert_image(gpu_img, ref, label="", atol=1e-4, max_fragile=MAX_FRAGILE_FRACTION):
+    """compare_image, asserted: every pixel inside its bound and at most
+    ``max_fragile`` of the pixels fragile."""
+    err, frac, nbad = compare_image(gpu_img, ref, atol)
+    print(f"{label}: max err {err:.3e} (non-fragile), fragile {frac:.4%}, outside bound {nbad}")
+    assert nbad == 0, (label, nbad, err)
+    assert err <= atol, (label, err)
+    assert frac <= max_fragile, (label, frac)
+    return err, frac
+
+
+def check_grads_elementwise(name, gpu, ref, rel=1e-3, floor=1e-3, max_outlier_frac=1e-3, norm_tol=1e-3):
+    """Gradient parity per element: |g - g_ref| <= rel (|g_ref| + floor max|g_ref|)
+    for all but at most max_outlier_frac of the elements (rounded down), and
+    the pooled relative L2 error below norm_tol.  Returns (outliers, worst
+    ratio of error to bound, relative L2 error)."""
+    g = np.asarray(gpu, np.float64).reshape(-1)
+    r = np.asarray(ref, np.float64).reshape(-1)
+    assert g.shape == r.shape, (name, g.shape, r.shape)
+    scale = np.abs(r).max() if r.size else 0.0
+    bound = rel * (np.abs(r) + floor * scale)
+    err = np.abs(g - r)
+    out = ~(err <= bound) if scale > 0 else ~(err <= 0.0)
+    nout = int(out.sum())
+    allowed = int(max_outlier_frac * r.size)
+    worst = float((err / np.maximum(bound, 1e-300)).max()) if r.size else 0.0
+    l2 = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30))
+    if nout:
+        j = int(np.argmax(err / np.maximum(bound, 1e-300)))
+        print(f"  {name}: {nout}/{r.size} outside the bound (allowed {allowed}); worst at {j}: "
+              f"gpu {g[j]:.6e} ref {r[j]:.6e}")
+    assert nout <= allowed, (name, nout, allowed, worst)
+    assert l2 <= norm_tol, (name, l2)
+    return nout, worst, l2

@@ -101,14 +101,54 @@ def test_missing_library_fails_loudly(L, monkeypatch):
 
 def test_device_scene_requires_colour_rows():
     """Colour coefficients are one row per primitive: a planar [D*3, n] SH
-    tensor (or [3, n] colours) is refused instead of being misread."""
+    tensor (or [3, n] colours) is refused instead of being misread.  Correctly
+    shaped host tensors pass every check but the last one (device memory)."""
     import torch
     from paper_2508_05343_amd.rasterize import DeviceScene
     n, k = 10, 2
     z = lambda *s: torch.zeros(*s)
-    DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), sh=z(n, 48), sh_degree=3)
-    DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), colors=z(n, 3))
-    with pytest.raises(ValueError):
+    for kw in (dict(sh=z(n, 48), sh_degree=3), dict(colors=z(n, 3))):
+        with pytest.raises(ValueError, match="device tensor"):
+            DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), **kw)
+    with pytest.raises(ValueError, match="shape"):
         DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), sh=z(48, n), sh_degree=3)
-    with pytest.raises(ValueError):
+    with pytest.raises(ValueError, match="shape"):
         DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n), colors=z(3, n))
+
+
+def test_device_scene_rejects_bad_layouts():
+    """Every attribute is checked for dtype, exact shape and contiguity before
+    a raw pointer is taken: a transposed view, a short array, a float64 array
+    or a mismatched filter array is refused with a ValueError (the kernels
+    would otherwise misread it or read past its end)."""
+    import torch
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    n, k = 12, 3
+    z = lambda *s: torch.zeros(*s)  # noqa: E731
+    good = dict(means=z(3, n), scales=z(3, n), quats=z(4, n), opacities=z(n), freqs=z(3 * k, n), weights=z(k, n))
+
+    def make(**over):
+        a = dict(good, **over)
+        col = a.pop("colors", z(n, 3))
+        return DeviceScene(a["means"], a["scales"], a["quats"], a["opacities"], a["freqs"], a["weights"], colors=col,
+                           filter3d=a.get("filter3d"))
+    with pytest.raises(ValueError, match="device tensor"):
+        make()
+    bad = {
+        "means": z(n, 3).t(),                    # transposed view: right shape, wrong layout
+        "scales": z(3, n - 1),                   # short
+        "quats": z(3, n),                        # a missing component
+        "opacities": torch.zeros(n, dtype=torch.float64),  # wrong dtype
+        "freqs": z(3 * k - 1, n),                # fewer than 3K rows
+        "weights": z(k, n + 1)[:, :n],           # strided view
+        "colors": z(3, n),                       # planar colours
+        "filter3d": z(n + 1),                    # wrong length
+    }
+    for name, t in bad.items():
+        with pytest.raises(ValueError, match="float32|shape|contiguous|weights|means") as ei:
+            make(**{name: t})
+        assert "device tensor" not in str(ei.value), name
+    with pytest.raises(ValueError, match="at most 8"):
+        DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(27, n), z(9, n), colors=z(n, 3))
+    with pytest.raises(ValueError, match="exactly one"):
+        DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n))

@@ -1,0 +1,167 @@
+"""The training step of Sec. 3.4.1 through torch autograd: raw parameters ->
+torch activations (exp of log-scales, sigmoid of opacity and frequency-weight
+logits) -> GaborRasterize -> L1 + 0.2 D-SSIM loss -> backward.  Every raw
+gradient is compared element by element with the oracle's exact fp64
+gradient composed with the activations' derivatives."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gabor_oracle as O
+
+from gpu_helpers import assert_image, check_grads_elementwise
+
+pytestmark = pytest.mark.gpu
+
+
+def _raw(sc):
+    """Raw (pre-activation) float32 parameters of a seeded scene."""
+    o = sc.opacities.astype(np.float64)
+    w = np.clip(sc.weights.astype(np.float64), 1e-3, 1 - 1e-3)
+    return dict(means=sc.means.astype(np.float32), log_scales=np.log(sc.scales.astype(np.float64)).astype(np.float32),
+                quats=sc.quats.astype(np.float32), logit_o=np.log(o / (1 - o)).astype(np.float32),
+                sh=sc.sh.astype(np.float32), freqs=sc.freqs.astype(np.float32),
+                logit_w=np.log(w / (1 - w)).astype(np.float32))
+
+
+def _activated_scene(raw):
+    """The activated scene the oracle renders, activations taken in float32 on
+    the host (the device's results may differ in the last bit; the tolerances
+    cover that)."""
+    t = {k: torch.from_numpy(v) for k, v in raw.items()}
+    return synth.Scene(means=raw["means"], scales=torch.exp(t["log_scales"]).numpy(), quats=raw["quats"],
+                       opacities=torch.sigmoid(t["logit_o"]).numpy(), freqs=raw["freqs"],
+                       weights=torch.sigmoid(t["logit_w"]).numpy(), sh=raw["sh"])
+
+
+def _planar(a):
+    return torch.from_numpy(np.ascontiguousarray(a.reshape(a.shape[0], -1).T)).cuda()
+
+
+def _leaves(raw):
+    n = raw["means"].shape[0]
+    L = dict(means=_planar(raw["means"]), log_scales=_planar(raw["log_scales"]), quats=_planar(raw["quats"]),
+             logit_o=torch.from_numpy(raw["logit_o"].copy()).cuda(),
+             sh=torch.from_numpy(np.ascontiguousarray(raw["sh"].reshape(n, -1))).cuda(),
+             freqs=_planar(raw["freqs"].reshape(n, -1)), logit_w=_planar(raw["logit_w"]))
+    for v in L.values():
+        v.requires_grad_(True)
+    return L
+
+
+def _forward(plan, L):
+    from paper_2508_05343_amd.rasterize import rasterize
+    return rasterize(plan, L["means"], torch.exp(L["log_scales"]), L["quats"], torch.sigmoid(L["logit_o"]), L["sh"],
+                     L["freqs"], torch.sigmoid(L["logit_w"]))
+
+
+def _template_plan(sc, cams):
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    return RenderPlan([DeviceScene.from_host(sc)], cams, [0] * len(cams))
+
+
+def _chain(act, ref):
+    """Oracle gradients w.r.t. the activated attributes -> raw parameters."""
+    s = act.scales.astype(np.float64)
+    o = act.opacities.astype(np.float64)
+    w = act.weights.astype(np.float64)
+    return dict(means=ref["means"], log_scales=ref["scales"] * s, quats=ref["quats"],
+                logit_o=ref["opacities"] * o * (1 - o), sh=ref["sh"], freqs=ref["freqs"],
+                logit_w=ref["weights"] * w * (1 - w))
+
+
+def _gpu_raw_grads(L, n, k):
+    g = {name: t.grad.detach().cpu().numpy() for name, t in L.items()}
+    return dict(means=g["means"].T, log_scales=g["log_scales"].T, quats=g["quats"].T, logit_o=g["logit_o"],
+                sh=g["sh"].reshape(n, -1, 3), freqs=g["freqs"].reshape(k, 3, n).transpose(2, 0, 1),
+                logit_w=g["logit_w"].T)
+
+
+@pytest.mark.parametrize("k,deg", [(3, 2), (4, 3)])
+def test_training_step_through_autograd(gpu_lib, k, deg):
+    from paper_2508_05343_amd.rasterize import photometric_loss
+    sc = synth.uniform_scene(200 + k, 500, k, sh_degree=deg, log_scale_mu=-2.9)
+    cam = synth.pinhole_camera(72, 56, 55.0, eye=(0.4, -0.3, -2.8), target=(0.0, 0.0, 0.0), bg=(0.1, 0.2, 0.3))
+    raw = _raw(sc)
+    act = _activated_scene(raw)
+    target = synth.random_target(210 + k, (3, cam.height, cam.width))
+    plan = _template_plan(act, [cam])
+    L = _leaves(raw)
+    img = _forward(plan, L)
+    loss = photometric_loss(img.view(3, cam.height, cam.width), torch.from_numpy(target).cuda())
+    loss.backward()
+    torch.cuda.synchronize()
+    # oracle: image, loss and its image gradient, then the exact parameter gradients
+    ref_img = O.render_scene(act, cam, "binned")
+    assert_image(img.detach().view(3, cam.height, cam.width).cpu().numpy(), ref_img, f"autograd k{k}")
+    Lr, dl = O.loss_and_grad(ref_img.color.numpy(), target)
+    assert abs(float(loss) - Lr) <= 1e-5 * abs(Lr)
+    ref = _chain(act, O.render_grads(act, cam, dl, "binned"))
+    got = _gpu_raw_grads(L, sc.n, k)
+    for name in ref:
+        print(name, check_grads_elementwise(name, got[name], ref[name]))
+
+
+def test_multiview_autograd_sums_views(gpu_lib):
+    """Two cameras in one plan: the raw gradients of sum(w * image) are the
+    sum over views of the oracle's."""
+    sc = synth.uniform_scene(220, 400, 2, sh_degree=1, log_scale_mu=-2.8)
+    cams = [synth.pinhole_camera(48, 40, 60.0, (0.0, 0.0, -3.0), (0, 0, 0), bg=(0.2, 0.2, 0.2)),
+            synth.pinhole_camera(40, 52, 55.0, (1.5, -0.5, -2.5), (0, 0, 0))]
+    raw = _raw(sc)
+    act = _activated_scene(raw)
+    plan = _template_plan(act, cams)
+    L = _leaves(raw)
+    img = _forward(plan, L)
+    gs = [synth.random_dl_dimage(230 + v, (3, c.height, c.width)) for v, c in enumerate(cams)]
+    w = torch.from_numpy(np.concatenate([g.reshape(-1) for g in gs]).astype(np.float32)).cuda()
+    (img * w).sum().backward()
+    torch.cuda.synchronize()
+    ref = None
+    for c, g in zip(cams, gs):
+        r = O.render_grads(act, c, g, "binned")
+        ref = r if ref is None else {a: ref[a] + r[a] for a in ref}
+    ref = _chain(act, ref)
+    got = _gpu_raw_grads(L, sc.n, sc.k)
+    for name in ref:
+        check_grads_elementwise(name, got[name], ref[name])
+
+
+def test_rasterize_renders_the_tensors_it_is_given(gpu_lib):
+    """A plan built for scene A, called with the tensors of scene B (same
+    size), renders B: the same image, bit for bit, as a plan built for B."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan, rasterize_scene
+    cam = synth.pinhole_camera(64, 48, 60.0, (0.0, 0.0, -3.0), (0, 0, 0))
+    a = DeviceScene.from_host(synth.uniform_scene(240, 300, 2, sh_degree=1))
+    b = DeviceScene.from_host(synth.uniform_scene(241, 300, 2, sh_degree=1))
+    plan = RenderPlan([a], [cam])
+    img_b = rasterize_scene(b, plan).detach().clone()
+    alone = RenderPlan([b], [cam]).forward().clone()
+    assert torch.equal(img_b, alone)
+    img_a = rasterize_scene(a, plan).detach()
+    assert not torch.equal(img_a, img_b)
+    # a wrongly laid out tensor (a transposed copy viewed back as [3, n]) is
+    # refused before any kernel runs, and so is a scene of another size
+    from paper_2508_05343_amd.rasterize import rasterize
+    strided = b.means.t().contiguous().t()
+    with pytest.raises(ValueError, match="contiguous"):
+        rasterize(plan, strided, b.scales, b.quats, b.opacities, b.sh, b.freqs, b.weights)
+    c = DeviceScene.from_host(synth.uniform_scene(242, 299, 2, sh_degree=1))
+    with pytest.raises(ValueError, match="does not match"):
+        rasterize_scene(c, plan)
+
+
+def test_backward_after_a_newer_forward_raises(gpu_lib):
+    """A plan holds one live graph: backward of an older forward raises
+    instead of returning the newer forward's gradients."""
+    sc = synth.uniform_scene(250, 300, 2, sh_degree=1, log_scale_mu=-2.8)
+    cam = synth.pinhole_camera(40, 40, 60.0, (0.0, 0.0, -3.0), (0, 0, 0))
+    raw = _raw(sc)
+    plan = _template_plan(_activated_scene(raw), [cam])
+    L = _leaves(raw)
+    img1 = _forward(plan, L)
+    img2 = _forward(plan, L)
+    img2.sum().backward()  # the newest graph is fine
+    with pytest.raises(RuntimeError, match="run again"):
+        img1.sum().backward()

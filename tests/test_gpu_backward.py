@@ -7,7 +7,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import gpu_plan
+from gpu_helpers import assert_image, check_grads_elementwise, gpu_plan
 
 pytestmark = pytest.mark.gpu
 
@@ -43,13 +43,8 @@ def _check_grads(sc, cam, seed, tol=1e-3, scene_name=""):
     ref = O.render_grads(sc, cam, g_img, "binned")
     report = {}
     for name, t in gg.items():
-        a = _to_aos(name, t, sc.n, sc.k)
-        r = ref[name]
-        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
-        report[name] = rel
-    print(scene_name, {k: f"{v:.2e}" for k, v in report.items()})
-    for name, rel in report.items():
-        assert rel <= tol, (name, rel)
+        report[name] = check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), ref[name], norm_tol=tol)
+    print(scene_name, {k: f"out {v[0]} worst {v[1]:.2f} l2 {v[2]:.2e}" for k, v in report.items()})
 
 
 @pytest.mark.parametrize("deg", [0, 2])
@@ -81,9 +76,7 @@ def test_forward_and_backward_every_component_count(gpu_lib, k):
     plan.forward()
     torch.cuda.synchronize()
     ref = O.render_scene(sc, cam, "binned")
-    ok = ~ref.fragile
-    err = np.abs(plan.view_image(0).cpu().numpy() - ref.color.numpy())[:, ok].max()
-    assert err <= 1e-4, err
+    assert_image(plan.view_image(0).cpu().numpy(), ref, f"k{k}")
     _check_grads(sc, cam, 70 + k, scene_name=f"k{k}")
 
 
@@ -103,26 +96,6 @@ def test_loss_matches_oracle(gpu_lib):
         assert np.abs(ga - gr).max() <= 1e-4 * np.abs(gr).max()
 
 
-def test_autograd_function(gpu_lib):
-    """GaborRasterize inside a torch graph: gradients of a scalar through the
-    image equal the plan's backward with that scalar's image gradient."""
-    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan, rasterize
-    sc = synth.uniform_scene(43, 400, 2, sh_degree=1, log_scale_mu=-2.8)
-    cam = synth.pinhole_camera(48, 40, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0))
-    ds = DeviceScene.from_host(sc)
-    for t in ds.tensors():
-        t.requires_grad_(True)
-    plan = RenderPlan([ds], [cam])
-    img = rasterize(ds, plan)
-    w = torch.from_numpy(synth.random_dl_dimage(9, (img.numel(),))).cuda()
-    (img * w).sum().backward()
-    ref = O.render_grads(sc, cam, w.cpu().numpy().reshape(3, 40, 48), "binned")
-    a = ds.means.grad.cpu().numpy().T
-    assert np.linalg.norm(a - ref["means"]) / np.linalg.norm(ref["means"]) <= 1e-3
-    b = ds.freqs.grad.cpu().numpy().reshape(2, 3, -1).transpose(2, 0, 1)
-    assert np.linalg.norm(b - ref["freqs"]) / np.linalg.norm(ref["freqs"]) <= 1e-3
-
-
 @pytest.mark.parametrize("high_freq", [False, True])
 def test_attenuated_forward_and_backward(gpu_lib, high_freq):
     """GABSPLAT_FLAG_ATTENUATION: forward and every gradient against the
@@ -136,16 +109,12 @@ def test_attenuated_forward_and_backward(gpu_lib, high_freq):
     plan = RenderPlan([ds], [cam])
     plan.forward()
     ref = O.render_scene(sc, cam, "binned", attenuation=True)
-    img = plan.view_image(0).cpu().numpy()
-    ok = ~ref.fragile
-    assert np.abs(img - ref.color.numpy())[:, ok].max() <= 1e-4
+    assert_image(plan.view_image(0).cpu().numpy(), ref, f"attenuated, high_freq={high_freq}")
     g_img = synth.random_dl_dimage(45, (3, cam.height, cam.width))
     gg = _gpu_grads([ds], plan, g_img)
     rg = O.render_grads(sc, cam, g_img, "binned", attenuation=True)
     for name, t in gg.items():
-        a = _to_aos(name, t, sc.n, sc.k)
-        rel = np.linalg.norm(a - rg[name]) / max(np.linalg.norm(rg[name]), 1e-30)
-        assert rel <= 1e-3, (name, rel)
+        check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), rg[name])
 
 
 def test_unaligned_colour_rows(gpu_lib):
@@ -179,3 +148,44 @@ def test_unaligned_colour_rows(gpu_lib):
         b = out[1][1][n]
         scale = float(a.abs().max())
         assert float((a - b).abs().max()) <= 1e-5 * scale + 1e-7, n
+
+
+@pytest.mark.parametrize("lo,hi,seed,log_s,wmax,n", [(0.995, 0.9999, 300, 0.6, 0.01, 150),
+                                                    (0.3, 0.6, 301, -0.6, 0.1, 120)])
+def test_backward_stacked_opaque_primitives(gpu_lib, lo, hi, seed, log_s, wmax, n):
+    """Large primitives stacked in front of the camera.  With opacities in
+    [0.995, 0.9999] alpha reaches its 0.99 clamp near the centres and a
+    quarter of the pixels stop after two or three blends with T near 1e-4;
+    with [0.3, 0.6] the chains run over up to ~120 primitives.  The backward
+    recovers every T_i by division from the final transmittance: the image,
+    final T and every gradient element against the oracle.  Two clamped
+    records leave T (1 - alpha) exactly at the 1e-4 threshold in the oracle's
+    arithmetic (just under it in float32), so the first stack has more fragile
+    pixels than a natural scene (each is bounded, not dropped)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = 2
+    means = np.stack([rng.uniform(-0.25, 0.25, n), rng.uniform(-0.2, 0.2, n), rng.uniform(-0.5, 1.5, n)], 1)
+    sc = synth.Scene(means=means.astype(np.float32),
+                     scales=np.exp(rng.normal(log_s, 0.2, (n, 3))).astype(np.float32),
+                     quats=rng.normal(size=(n, 4)).astype(np.float32),
+                     opacities=rng.uniform(lo, hi, n).astype(np.float32),
+                     freqs=rng.normal(0.0, 1.0, (n, k, 3)).astype(np.float32),
+                     weights=rng.uniform(0.0, wmax, (n, k)).astype(np.float32),
+                     sh=rng.normal(0.0, 0.3, (n, 4, 3)).astype(np.float32))
+    cam = synth.pinhole_camera(64, 48, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0), bg=(0.1, 0.2, 0.3))
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    torch.cuda.synchronize()
+    ref = O.render_scene(sc, cam, "binned")
+    assert_image(plan.view_image(0).cpu().numpy(), ref, f"stack [{lo}, {hi}]", max_fragile=0.03)
+    ok = ~ref.fragile
+    T = plan.view_final_T(0).cpu().numpy()
+    Tr = ref.final_T.numpy()
+    assert (np.abs(T - Tr)[ok] <= 1e-4 * Tr[ok] + 1e-9).all()
+    nb = ref.n_blended
+    print("blended per pixel: min", nb.min(), "max", nb.max(), "final T min", float(Tr.min()))
+    if lo >= 0.99:
+        assert ((nb <= 3) & (Tr < 1e-3)).mean() > 0.2
+    else:
+        assert nb.max() >= 100
+    _check_grads(sc, cam, seed + 1, scene_name=f"stack [{lo}, {hi}]")

@@ -76,3 +76,38 @@ def test_stats_and_reset(gpu_lib):
     w, o = D.periodic_reset(sc)
     np.testing.assert_allclose(ds.weights.cpu().numpy().T, w, rtol=1e-7)
     np.testing.assert_allclose(ds.opacities.cpu().numpy(), o, rtol=1e-7)
+
+
+def test_densify_decisions_at_the_exact_thresholds(gpu_lib):
+    """The GPU decisions at the boundary values of the three thresholds
+    (mean gradient = threshold, max scale = percent_dense * extent, opacity =
+    min_opacity, and one float32 step to either side) equal the oracle's,
+    whose boundary behaviour is pinned on the CPU."""
+    from paper_2508_05343_amd.density import DensityStats, default_params, densify
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    f32 = np.float32
+    thr, pd, mo = f32(2e-4), f32(0.01), f32(0.01)
+    lo = lambda x: np.nextafter(f32(x), f32(0))  # noqa: E731
+    hi = lambda x: np.nextafter(f32(x), f32(1))  # noqa: E731
+    rows = [(thr, f32(0.005), f32(0.5)), (lo(thr), f32(0.005), f32(0.5)), (thr, pd, f32(0.5)),
+            (thr, hi(pd), f32(0.5)), (f32(0.0), f32(0.005), mo), (f32(0.0), f32(0.005), lo(mo)),
+            (thr, f32(0.005), lo(mo)), (thr, f32(0.02), lo(mo)), (hi(thr), f32(0.02), f32(0.3))]
+    n = len(rows)
+    sc = synth.uniform_scene(74, n, 2, sh_degree=1)
+    sc.scales[:] = f32(0.001)
+    for i, (_, s, o) in enumerate(rows):
+        sc.scales[i, i % 3] = s
+        sc.opacities[i] = o
+    accum = np.array([r[0] for r in rows], np.float32)
+    denom = np.ones(n, np.float32)
+    normals = np.random.Generator(np.random.PCG64(75)).normal(size=(n, 2, 3)).astype(np.float32)
+    ds = DeviceScene.from_host(sc)
+    st = DensityStats(n)
+    st.accum.copy_(torch.from_numpy(accum))
+    st.denom.copy_(torch.from_numpy(denom))
+    nrm = torch.from_numpy(np.ascontiguousarray(normals.transpose(1, 2, 0).reshape(-1))).cuda()
+    new, src, tag = densify(ds, st, nrm, default_params())
+    ref, rsrc, rtag = D.densify(sc, accum, denom, normals, D.DensifyParams())
+    assert D.decide(sc, accum, denom, D.DensifyParams()).tolist() == [1, 0, 1, 2, 0, 3, 3, 3, 2]
+    np.testing.assert_array_equal(src.cpu().numpy(), rsrc)
+    np.testing.assert_array_equal(tag.cpu().numpy(), rtag)

@@ -7,7 +7,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import compare_image, gpu_plan, last_ids_from_gpu, oracle_project, record_fields_np
+from gpu_helpers import assert_image, gpu_plan, last_ids_from_gpu, oracle_project, record_fields_np
 
 pytestmark = pytest.mark.gpu
 
@@ -151,9 +151,7 @@ def test_render_forward_config1(gpu_lib):
     torch.cuda.synchronize()
     ref = O.render_scene(sc, cam, "binned")
     img = plan.view_image(0).cpu().numpy()
-    err, frag, nbad = compare_image(img, ref)
-    print(f"config1: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
-    assert nbad == 0 and err <= 1e-4
+    assert_image(img, ref, "config1")
     T = plan.view_final_T(0).cpu().numpy()
     ok = ~ref.fragile
     assert np.abs(T - ref.final_T.numpy())[ok].max() <= 1e-4
@@ -168,9 +166,7 @@ def test_render_forward_sh_and_background(gpu_lib, bg):
     ds, plan = gpu_plan(sc, [cam])
     plan.forward()
     ref = O.render_scene(sc, cam, "binned")
-    err, frag, nbad = compare_image(plan.view_image(0).cpu().numpy(), ref)
-    print(f"sh3 K4: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
-    assert nbad == 0 and err <= 1e-4
+    assert_image(plan.view_image(0).cpu().numpy(), ref, f"sh3 K4 bg {bg}")
 
 
 def test_render_forward_high_frequency(gpu_lib):
@@ -183,9 +179,7 @@ def test_render_forward_high_frequency(gpu_lib):
     pr = oracle_project(sc, cam)
     print("max |f2d|", float(pr.f2d.norm(dim=-1).max()))
     ref = O.render_scene(sc, cam, "binned")
-    err, frag, nbad = compare_image(plan.view_image(0).cpu().numpy(), ref)
-    print(f"high-f: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
-    assert nbad == 0 and err <= 1e-4
+    assert_image(plan.view_image(0).cpu().numpy(), ref, "high frequency")
 
 
 def test_render_forward_multiview_ragged(gpu_lib):
@@ -200,8 +194,7 @@ def test_render_forward_multiview_ragged(gpu_lib):
     plan.forward()
     for v, c in enumerate(cams):
         ref = O.render_scene(sc, c, "binned")
-        err, frag, nbad = compare_image(plan.view_image(v).cpu().numpy(), ref)
-        assert nbad == 0 and err <= 1e-4, (v, err, nbad)
+        assert_image(plan.view_image(v).cpu().numpy(), ref, f"view {v}")
 
 
 def test_render_forward_empty_and_culled(gpu_lib):

@@ -9,7 +9,8 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import compare_image, last_ids_from_gpu
+from gpu_helpers import assert_image, check_grads_elementwise, last_ids_from_gpu, record_fields_np
+from sampling import stratified_primitives
 
 pytestmark = pytest.mark.gpu
 
@@ -64,54 +65,83 @@ def test_config2_heaviest_tiles_binned_order(gpu_lib, big):
         assert np.array_equal(got, ref), (tx, ty, len(got), len(ref))
 
 
-def test_config2_sampled_tiles_forward(gpu_lib, big):
+def test_config2_records_of_every_visible_primitive(gpu_lib, big):
+    """K1 at full size: the render record of every visible primitive (mean,
+    conic, opacity, colour, 2D frequencies and weights) against the oracle's
+    projection, within 1e-5 relative (conic and frequencies relative to the
+    largest entry of the primitive)."""
     sc, cam, ds, plan, pr = big
-    rng = np.random.Generator(np.random.PCG64(2024))
-    sel = rng.choice(cam.num_tiles, size=48, replace=False)
-    tiles = [(int(s % cam.tiles_x), int(s // cam.tiles_x)) for s in sel]
-    tiles += [(cam.tiles_x - 1, cam.tiles_y - 1), (cam.tiles_x - 1, 0), (0, cam.tiles_y - 1)]  # ragged edges
+    f = record_fields_np(plan)
+    vis_g = plan.tiles_touched.cpu().numpy()[:sc.n] > 0
+    m = pr.visible.numpy() & vis_g & ~pr.fragile_prim
+    assert m.sum() > 150000
+    mu = pr.mu2d.numpy()[m]
+    assert (np.abs(f["mu2d"][:sc.n][m] - mu) <= 1e-5 * np.abs(mu) + 1e-4).all()
+    con = pr.conic.numpy()[m]
+    assert (np.abs(f["conic"][:sc.n][m] - con) <= 1e-5 * np.abs(con).max(1, keepdims=True) + 1e-12).all()
+    op = pr.opac.numpy()[m]
+    assert (np.abs(f["opacity"][:sc.n][m] - op) <= 1e-5 * op).all()
+    rgb = pr.rgb.numpy()[m]
+    assert (np.abs(f["rgb"][:sc.n][m] - rgb) <= 1e-5 * np.abs(rgb) + 1e-6).all()
+    f2 = pr.f2d.numpy()[m]
+    fs = np.abs(f2).max(axis=(1, 2), keepdims=True) + 1e-6
+    assert (np.abs(f["f2d"][:sc.n][m] - f2) <= 1e-5 * fs).all()
+    w = pr.w.numpy()[m]
+    assert (np.abs(f["w"][:sc.n][m] - w) <= 1e-6).all()
+    w0 = pr.w_dc.detach().numpy()[m]
+    assert (np.abs(f["w0"][:sc.n][m] - w0) <= 1e-6).all()
+
+
+def test_config2_whole_frame_forward(gpu_lib, big):
+    """Every pixel of the 1297x840 frame (all 4346 tiles, ragged edge tiles
+    included) against the oracle's binned fp64 blend, and the last blended
+    primitive of every non-fragile pixel."""
+    sc, cam, ds, plan, pr = big
     with torch.no_grad():
-        ref = O.render(None, O.camera_tensors(cam), "binned", tiles=tiles, scene_f32=sc, pr=pr)
+        ref = O.render(None, O.camera_tensors(cam), "binned", scene_f32=sc, pr=pr)
     img = plan.view_image(0).cpu().numpy()
-    err, frag, nbad = compare_image(img, ref)
-    print(f"config2 sampled: max err {err:.3e} fragile {frag:.4f} bad {nbad}")
-    assert nbad == 0 and err <= 1e-4
-    valid = ~np.isnan(ref.color.numpy()[0]) & ~ref.fragile
+    assert_image(img, ref, "config2 whole frame")
+    ok = ~ref.fragile
+    T = plan.view_final_T(0).cpu().numpy()
+    assert np.abs(T - ref.final_T.numpy())[ok].max() <= 1e-4
     ids = last_ids_from_gpu(plan, 0)
-    assert (ids[valid] == ref.last_id[valid]).all()
+    assert (ids[ok] == ref.last_id[ok]).all()
+
+
+def _gpu_prim_grads(grads, prims, n):
+    return {"means": grads["means"].cpu().numpy()[:, prims].T,
+            "scales": grads["scales"].cpu().numpy()[:, prims].T,
+            "quats": grads["quats"].cpu().numpy()[:, prims].T,
+            "opacities": grads["opacities"].cpu().numpy()[prims],
+            "sh": grads["sh"].cpu().numpy().reshape(n, 16, 3)[prims],
+            "freqs": grads["freqs"].cpu().numpy().reshape(4, 3, n)[:, :, prims].transpose(2, 0, 1),
+            "weights": grads["weights"].cpu().numpy()[:, prims].T}
 
 
 def test_config3_sampled_primitive_gradients(gpu_lib, big):
-    """render_bwd at full size with a seeded image gradient: the gradients of
-    200 seeded visible primitives (every attribute) against the oracle's
-    exact windowed fp64 gradients."""
+    """render_bwd at full size with a seeded image gradient: every attribute
+    gradient of 200 seeded visible primitives, drawn from every tile-count
+    class (30 with one tile ... 24 with 50 to 400 tiles, whose gradients sum
+    the most wavefront atomics over the longest transmittance chains), against
+    the oracle's exact windowed fp64 gradients, element by element."""
     sc, cam, ds, plan, pr = big
     g_img = synth.random_dl_dimage(1003, (3, cam.height, cam.width))
     names = ("means", "scales", "quats", "opacities", "sh", "freqs", "weights")
     grads = {n: torch.zeros_like(getattr(ds, n)) for n in names}
     plan.backward(torch.from_numpy(g_img.reshape(-1)).cuda(), [grads], accumulate=False)
     torch.cuda.synchronize()
-    vis = np.nonzero(pr.visible.numpy() & (pr.tiles <= 9) & ~pr.fragile_prim)[0]
-    rng = np.random.Generator(np.random.PCG64(3003))
-    prims = rng.choice(vis, size=200, replace=False)
+    prims = stratified_primitives(pr, 3003)
+    assert len(prims) == 200 and (pr.tiles[prims] >= 50).sum() >= 20
     ref = O.primitive_grads_windowed(sc, cam, g_img, prims, pr_all=pr)
-    n = sc.n
-    gpu = {}
-    gpu["means"] = grads["means"].cpu().numpy()[:, prims].T
-    gpu["scales"] = grads["scales"].cpu().numpy()[:, prims].T
-    gpu["quats"] = grads["quats"].cpu().numpy()[:, prims].T
-    gpu["opacities"] = grads["opacities"].cpu().numpy()[prims]
-    gpu["sh"] = grads["sh"].cpu().numpy().reshape(n, 16, 3)[prims]
-    gpu["freqs"] = grads["freqs"].cpu().numpy().reshape(4, 3, n)[:, :, prims].transpose(2, 0, 1)
-    gpu["weights"] = grads["weights"].cpu().numpy()[:, prims].T
-    rep = {}
+    gpu = _gpu_prim_grads(grads, prims, sc.n)
     for name in names:
         r = np.stack([ref[j][name] for j in range(len(prims))])
-        a = gpu[name].reshape(r.shape)
-        rep[name] = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
-    print({k: f"{v:.2e}" for k, v in rep.items()})
-    for name, rel in rep.items():
-        assert rel <= 1e-3, (name, rel)
+        print(name, check_grads_elementwise(name, gpu[name].reshape(r.shape), r))
+    # the large primitives on their own
+    big_ = np.nonzero(pr.tiles[prims] >= 50)[0]
+    for name in names:
+        r = np.stack([ref[j][name] for j in big_])
+        check_grads_elementwise(f"{name} (>= 50 tiles)", gpu[name][big_].reshape(r.shape), r)
 
 
 def test_config3_loss_full_frame(gpu_lib, big):
