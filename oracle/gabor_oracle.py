@@ -405,49 +405,85 @@ class PixelResult:
     freq_map: Optional[torch.Tensor] = None  # [P] blended sum_k w_k |f2d_k| (cycles/px)
     n_fragile: Optional[np.ndarray] = None   # [P] number of fragile decisions up to the stop
     fragile_bound: Optional[np.ndarray] = None  # [P] their largest effect, in units of the colour span
+    # [P, m] the fragile skip decisions (alpha within tolerance of 1/255) and
+    # stop decisions (T (1 - alpha) within tolerance of 1e-4) up to the stop
+    frag_alpha: Optional[np.ndarray] = None
+    frag_stop: Optional[np.ndarray] = None
 
+
+# the per-primitive 2D record the blend reads (Projected attributes)
+RECORD_FIELDS = ("mu2d", "conic", "opac", "rgb", "f2d", "w", "w_dc")
 
 def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Tensor,
-                 bg: torch.Tensor, tau_alpha=1e-4, tau_T=1e-3, mu: Optional[torch.Tensor] = None) -> PixelResult:
+                 bg: torch.Tensor, tau_alpha=1e-4, tau_T=1e-3, mu: Optional[torch.Tensor] = None,
+                 rec: Optional[Dict[str, torch.Tensor]] = None, flip_alpha: Optional[np.ndarray] = None,
+                 flip_stop: Optional[np.ndarray] = None) -> PixelResult:
     """Blend the candidates ``cand`` (already sorted front to back) at the
-    sample points (px, py), vectorised over pixels and candidates.  ``mu``
-    ([P, m, 2], optional) gives every pixel its own copy of the candidates'
-    image-plane means (same values), so that a backward pass returns each
-    pixel's share of the mean gradient separately."""
+    sample points (px, py), vectorised over pixels and candidates.
+
+    ``rec`` (optional) gives every pixel its own copy of some of the
+    candidates' 2D record fields (RECORD_FIELDS; each [P, m, ...], same
+    values), so that a backward pass returns each pixel's share of their
+    gradient separately; ``mu`` ([P, m, 2]) is the same for the means alone.
+    ``flip_alpha`` / ``flip_stop`` ([P, m] bool, optional) take the marked
+    decisions the other way: a marked candidate is skipped where the rule
+    blends it and blended where the rule skips it (flip_alpha), or the walk
+    stops at a marked candidate where the rule walks on, and walks on (blending
+    it) where the rule stops (flip_stop).  They describe the other outcome of a
+    decision taken within rounding of its threshold."""
     P = px.shape[0]
     m = len(cand)
     if m == 0:
         col = bg[None, :].expand(P, 3).clone()
         return PixelResult(col, torch.ones(P, dtype=DT), -np.ones(P, np.int64),
                            np.zeros(P, np.int64), np.zeros(P, bool), torch.zeros(P, dtype=DT), np.zeros(P, np.int64),
-                           np.zeros(P))
+                           np.zeros(P), np.zeros((P, 0), bool), np.zeros((P, 0), bool))
     ci = torch.from_numpy(np.asarray(cand, np.int64))
-    if mu is None:
-        mu = pr.mu2d[ci]
-    con = pr.conic[ci]
-    dx = px[:, None] - mu[..., 0]
-    dy = py[:, None] - mu[..., 1]
-    G = torch.exp(-0.5 * (con[None, :, 0] * dx * dx + 2.0 * con[None, :, 1] * dx * dy
-                          + con[None, :, 2] * dy * dy))
-    w = pr.w[ci]
-    if w.shape[1] > 0:
-        f = pr.f2d[ci]
-        phase = f[None, :, :, 0] * dx[..., None] + f[None, :, :, 1] * dy[..., None]
-        Bk = pr.w_dc[ci][None, :] + (w[None] * torch.cos(2.0 * math.pi * phase)).sum(-1)
+    rec = dict(rec or {})
+    if mu is not None:
+        rec["mu2d"] = mu
+
+    def field(name):
+        # [P or 1, m, ...]
+        return rec[name] if name in rec else getattr(pr, name)[ci][None]
+    mu_ = field("mu2d")
+    con = field("conic")
+    dx = px[:, None] - mu_[..., 0]
+    dy = py[:, None] - mu_[..., 1]
+    G = torch.exp(-0.5 * (con[..., 0] * dx * dx + 2.0 * con[..., 1] * dx * dy
+                          + con[..., 2] * dy * dy))
+    w = field("w")
+    if w.shape[-1] > 0:
+        f = field("f2d")
+        phase = f[..., 0] * dx[..., None] + f[..., 1] * dy[..., None]
+        Bk = field("w_dc") + (w * torch.cos(2.0 * math.pi * phase)).sum(-1)
     else:
         Bk = torch.ones_like(G)
-    a_raw = pr.opac[ci][None, :] * G * Bk
+    a_raw = field("opac") * G * Bk
     alpha = torch.clamp(a_raw, max=ALPHA_MAX)
     with torch.no_grad():
         valid = alpha >= ALPHA_MIN
+        if flip_alpha is not None:
+            valid = valid ^ torch.from_numpy(np.asarray(flip_alpha, bool))
         one_m = torch.where(valid, 1.0 - alpha, torch.ones_like(alpha))
         T_after = torch.cumprod(one_m, dim=1)
-        keep = valid & (T_after >= T_MIN)
+        if flip_stop is None:
+            keep = valid & (T_after >= T_MIN)
+        else:
+            # a stop event ends the walk; no record at or after it is blended
+            stop_ev = valid & ((T_after < T_MIN) ^ torch.from_numpy(np.asarray(flip_stop, bool)))
+            before = (torch.cumsum(stop_ev.to(torch.int64), 1) - stop_ev.to(torch.int64)) == 0
+            keep = valid & ~stop_ev & before
     factor = torch.where(keep, 1.0 - alpha, torch.ones_like(alpha))
     T_incl = torch.cumprod(factor, dim=1)
     T_before = torch.cat([torch.ones((P, 1), dtype=DT), T_incl[:, :-1]], 1)
     wgt = torch.where(keep, alpha * T_before, torch.zeros_like(alpha))
-    color = wgt @ pr.rgb[ci] + T_incl[:, -1:] * bg[None, :]
+    rgb = field("rgb")
+    if rgb.shape[0] == 1:
+        blended = wgt @ rgb[0]
+    else:
+        blended = (wgt[..., None] * rgb).sum(1)
+    color = blended + T_incl[:, -1:] * bg[None, :]
     # frequency map (supplementary C): per primitive sum_k w_k |f2d_k|, blended like a colour
     phi = (pr.w[ci] * torch.linalg.norm(pr.f2d[ci], dim=-1)).sum(-1) if pr.w.shape[1] else torch.zeros(m, dtype=DT)
     fmap = wgt @ phi
@@ -480,7 +516,7 @@ def blend_pixels(pr: Projected, cand: np.ndarray, px: torch.Tensor, py: torch.Te
         fb = (fa * 2.0 * np.clip(al, 0.0, None) * Tb + ft * Tb + fprim * 2.0 * Tb) * upto
         frag_bound = fb.sum(1)
     return PixelResult(color, T_incl[:, -1], last_id.astype(np.int64), n_bl.astype(np.int64), fragile, fmap,
-                       n_frag.astype(np.int64), frag_bound)
+                       n_frag.astype(np.int64), frag_bound, fa & upto, ft & upto)
 
 
 def blend_pixel_loop(pr: Projected, cand: Sequence[int], x: float, y: float, bg) -> tuple:
@@ -737,12 +773,41 @@ def window_setup(pr_all: Projected, order: np.ndarray, i: int):
     return tiles, cands, rows, int(np.searchsorted(rows, i))
 
 
-def _window_total(scene, ct, g_img: torch.Tensor, pr_all: Projected, win, i: int, pi) -> torch.Tensor:
+def _row(pr: Projected, i: int) -> Projected:
+    """Primitive i's record fields of a projection as a one-row projection
+    (only the fields _support_pixels reads)."""
+    return Projected(visible=pr.visible[i:i + 1], depth32=pr.depth32[i:i + 1], mu2d=pr.mu2d[i:i + 1],
+                     cov2d_raw=pr.cov2d_raw[i:i + 1], conic=pr.conic[i:i + 1], opac=pr.opac[i:i + 1],
+                     rgb=pr.rgb[i:i + 1], f2d=pr.f2d[i:i + 1], w=pr.w[i:i + 1], rect=pr.rect[i:i + 1],
+                     tiles=pr.tiles[i:i + 1], fragile_rect=pr.fragile_rect[i:i + 1],
+                     fragile_prim=pr.fragile_prim[i:i + 1])
+
+
+def _support_pixels(rec_i: Projected, gx: np.ndarray, gy: np.ndarray, margin: float = 2e-4) -> np.ndarray:
+    """Pixels of (gx, gy) where primitive i (its one-row projection) may
+    reach alpha >= 1/255: o G >= (1/255)(1 - margin).  Since the Gabor factor
+    B is at most 1, alpha <= o G; elsewhere i is skipped (zero derivative) and
+    none of its skip decisions is fragile."""
+    with torch.no_grad():
+        mx, my = float(rec_i.mu2d[0, 0]), float(rec_i.mu2d[0, 1])
+        a, b, c = (float(v) for v in rec_i.conic[0])
+        o = float(rec_i.opac[0])
+    dx, dy = gx + 0.5 - mx, gy + 0.5 - my
+    q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+    with np.errstate(over="ignore"):
+        return o * np.exp(-0.5 * q) >= ALPHA_MIN * (1.0 - margin)
+
+
+def _window_total(scene, ct, g_img: torch.Tensor, pr_all: Projected, win, i: int, pi,
+                  support_only: bool = False) -> torch.Tensor:
     """sum(dl_dimage * C) over the pixels of the tiles in primitive i's rect
     (``win`` from window_setup), with primitive i projected from the
     attribute tensors ``pi`` (a one-row scene) and every other primitive as in
     ``pr_all``.  Outside those tiles primitive i is not a candidate (its alpha
-    there is below 1/255), so this window holds every pixel that depends on it."""
+    there is below 1/255), so this window holds every pixel that depends on it.
+    support_only keeps only the pixels of _support_pixels: the sum then
+    differs by terms that do not depend on i (the same gradient), so it is
+    only for differentiation at the given attributes."""
     W, H = ct["W"], ct["H"]
     sub = scene.subset(np.array([i]))
     pri = project(pi, ct, sub)
@@ -753,6 +818,11 @@ def _window_total(scene, ct, g_img: torch.Tensor, pr_all: Projected, win, i: int
     pr = _take(pr_all, rows, local_i, pri)
     for (tx, ty), cand in zip(tiles, cands):
         gx, gy = _tile_pixels(tx, ty, W, H)
+        if support_only:
+            keep = _support_pixels(pri, gx, gy)
+            if not keep.any():
+                continue
+            gx, gy = gx[keep], gy[keep]
         loc = np.searchsorted(rows, cand)
         res = blend_pixels(pr, loc, torch.from_numpy(gx + 0.5).to(DT), torch.from_numpy(gy + 0.5).to(DT), ct["bg"])
         gsel = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
@@ -765,7 +835,8 @@ def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[
     """Gradients of sum(dl_dimage * C) w.r.t. the attributes of each listed
     primitive, evaluated exactly by re-rendering only the tiles in that
     primitive's rect (outside them its alpha is below 1/255 and it is skipped,
-    so no other pixel depends on it)."""
+    so no other pixel depends on it), and in them only the pixels its
+    envelope reaches (elsewhere its derivative is zero)."""
     ct = camera_tensors(cam)
     with torch.no_grad():
         if pr_all is None:
@@ -775,7 +846,7 @@ def primitive_grads_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[
     out = []
     for i in prims:
         pi = scene_tensors(scene.subset(np.array([i])), requires_grad=True)
-        total = _window_total(scene, ct, g_img, pr_all, window_setup(pr_all, order, i), i, pi)
+        total = _window_total(scene, ct, g_img, pr_all, window_setup(pr_all, order, i), i, pi, support_only=True)
         if total.requires_grad:
             total.backward()
         grads = {}
@@ -801,6 +872,182 @@ def primitive_loss_windowed(scene, cam, dl_dimage: np.ndarray, i: int, attrs: Di
         g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
         pi = {k: torch.tensor(np.asarray(v, np.float64)[None], dtype=DT) for k, v in attrs.items()}
         return float(_window_total(scene, ct, g_img, pr_all, win, i, pi))
+
+
+# --------------------------------------------------------------------------
+# gradient slack of fragile decisions
+# --------------------------------------------------------------------------
+# A skip decision (alpha against 1/255) or a stop decision (T (1 - alpha)
+# against 1e-4) taken within rounding of its threshold may go either way in
+# float32.  Either outcome is a correct evaluation of the definition, and the
+# gradient is piecewise smooth across them, so a float32 rasterizer's gradient
+# can differ from the float64 one by the jump between the two branches.  For
+# every fragile decision of a pixel, the oracle evaluates that jump exactly:
+# the gradient of dl_p . (C_p(other outcome) - C_p) with respect to every
+# attribute of every candidate of the pixel.  The slack of a gradient element
+# is the sum of the jumps' magnitudes over all fragile decisions (several may
+# flip together; their effects add up to first order).
+def record_jacobian(scene, cam, prims: Sequence[int], attenuation=False, mip2d=False,
+                    filter3d=None) -> Dict[str, Dict[str, np.ndarray]]:
+    """Jacobian of the listed primitives' 2D records with respect to their
+    activated attributes: J[field][attr] has shape [len(prims), dim(field),
+    *attr_shape] (fields RECORD_FIELDS flattened per primitive).  The
+    projection is independent per primitive, so one backward per record
+    component over the sum across primitives gives every row."""
+    prims = np.asarray(prims, np.int64)
+    ct = camera_tensors(cam) if not isinstance(cam, dict) else cam
+    sub = scene.subset(prims)
+    p = scene_tensors(sub, requires_grad=True)
+    fv = None if filter3d is None else np.asarray(filter3d)[prims]
+    pr = project(p, ct, sub, attenuation, mip2d, fv)
+    names = list(p.keys())
+    n = len(prims)
+    out: Dict[str, Dict[str, np.ndarray]] = {}
+    for f in RECORD_FIELDS:
+        val = getattr(pr, f).reshape(n, -1)
+        d = val.shape[1]
+        out[f] = {a: np.zeros((n, d) + tuple(p[a].shape[1:])) for a in names}
+        for c in range(d):
+            gr = torch.autograd.grad(val[:, c].sum(), [p[a] for a in names], retain_graph=True, allow_unused=True)
+            for a, g in zip(names, gr):
+                if g is not None:
+                    out[f][a][:, c] = g.numpy()
+    return out
+
+
+def _decision_jumps(pr: Projected, cand: np.ndarray, gx: np.ndarray, gy: np.ndarray, bg: torch.Tensor,
+                    g_pix: torch.Tensor, res: PixelResult) -> Optional[Dict[str, np.ndarray]]:
+    """For the fragile decisions of ``res`` (a blend of ``cand`` at the pixel
+    centres of (gx, gy); g_pix [P, 3] the loss gradient of those pixels), the
+    gradient of dl_p . (C_p(flipped) - C_p) with respect to each candidate's
+    2D record, one row per decision: field -> [R, m, dim].  None if there is
+    no fragile decision."""
+    fa, ft = res.frag_alpha, res.frag_stop
+    dec = [(pix, j, 0) for pix, j in zip(*np.nonzero(fa))] + [(pix, j, 1) for pix, j in zip(*np.nonzero(ft))]
+    if not dec:
+        return None
+    R, m = len(dec), len(cand)
+    rows = np.array([d[0] for d in dec])
+    FA = np.zeros((R, m), bool)
+    FS = np.zeros((R, m), bool)
+    for r, (_, j, kind) in enumerate(dec):
+        (FA if kind == 0 else FS)[r, j] = True
+    ci = torch.from_numpy(np.asarray(cand, np.int64))
+    rec = {}
+    for f in RECORD_FIELDS:
+        base = getattr(pr, f).detach()[ci]
+        rec[f] = base[None].expand((R,) + tuple(base.shape)).clone().requires_grad_(True)
+    X = torch.from_numpy(gx[rows] + 0.5).to(DT)
+    Y = torch.from_numpy(gy[rows] + 0.5).to(DT)
+    flipped = blend_pixels(pr, cand, X, Y, bg, rec=rec, flip_alpha=FA, flip_stop=FS)
+    plain = blend_pixels(pr, cand, X, Y, bg, rec=rec)
+    ((flipped.color - plain.color) * g_pix[torch.from_numpy(rows)]).sum().backward()
+    # fields outside the graph (the empty frequency arrays of K = 0) get zeros
+    return {f: (rec[f].grad if rec[f].grad is not None else torch.zeros_like(rec[f])).reshape(R, m, -1).numpy()
+            for f in RECORD_FIELDS}
+
+
+def _jumps_to_attrs(jumps: Dict[str, np.ndarray], J: Dict[str, Dict[str, np.ndarray]],
+                    jrows: np.ndarray) -> Dict[str, np.ndarray]:
+    """Per decision row and candidate, the jump in attribute space
+    |sum_field jump_2d . J|, summed over the rows: attr -> [m, *attr_shape]
+    (candidate c uses Jacobian row jrows[c])."""
+    out = {}
+    for a in J[RECORD_FIELDS[0]]:
+        acc = None
+        for f in RECORD_FIELDS:
+            Jf = J[f][a][jrows]                                   # [m, d, *attr]
+            t = np.einsum("rmd,md...->rm...", jumps[f], Jf)
+            acc = t if acc is None else acc + t
+        out[a] = np.abs(acc).sum(0)
+    return out
+
+
+def render_grad_slack(scene, cam, dl_dimage: np.ndarray, attenuation=False, mip2d=False,
+                      filter3d=None, with_mean2d=False) -> Dict[str, np.ndarray]:
+    """Slack of every gradient element of render_grads (binned mode): the
+    summed magnitudes of the gradient jumps of every fragile decision in the
+    image (zero for a primitive no such decision reaches).  with_mean2d adds
+    "mean2d" [n, 2]: the same for the image-plane mean gradient of
+    mean2d_grads (it also bounds the change of its per-pixel absolute sums)."""
+    ct = camera_tensors(cam)
+    with torch.no_grad():
+        pr = project(scene_tensors(scene), ct, scene, attenuation, mip2d, filter3d)
+    W, H = ct["W"], ct["H"]
+    order = depth_order(pr.depth32, pr.visible.numpy())
+    g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+    vis = np.nonzero(pr.visible.numpy())[0]
+    J = None
+    row_of = np.full(scene.n, -1, np.int64)
+    row_of[vis] = np.arange(len(vis))
+    slack = {a: np.zeros(tuple(v.shape)) for a, v in scene_tensors(scene).items()}
+    if with_mean2d:
+        slack["mean2d"] = np.zeros((scene.n, 2))
+    for ty in range((H + TILE - 1) // TILE):
+        for tx in range((W + TILE - 1) // TILE):
+            cand = tile_candidates(pr, order, tx, ty)
+            if len(cand) == 0:
+                continue
+            gx, gy = _tile_pixels(tx, ty, W, H)
+            X, Y = torch.from_numpy(gx + 0.5).to(DT), torch.from_numpy(gy + 0.5).to(DT)
+            with torch.no_grad():
+                res = blend_pixels(pr, cand, X, Y, ct["bg"])
+            g_pix = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
+            jumps = _decision_jumps(pr, cand, gx, gy, ct["bg"], g_pix, res)
+            if jumps is None:
+                continue
+            if J is None:
+                J = record_jacobian(scene, ct, vis, attenuation, mip2d, filter3d)
+            per = _jumps_to_attrs(jumps, J, row_of[cand])
+            for a, v in per.items():
+                np.add.at(slack[a], cand, v)
+            if with_mean2d:
+                np.add.at(slack["mean2d"], cand, np.abs(jumps["mu2d"]).sum(0))
+    return slack
+
+
+def primitive_grad_slack_windowed(scene, cam, dl_dimage: np.ndarray, prims: Sequence[int],
+                                  pr_all: Optional[Projected] = None) -> List[Dict[str, np.ndarray]]:
+    """The slack of primitive_grads_windowed: for each listed primitive, the
+    summed jump magnitudes of every fragile decision in the tiles of its rect
+    (the only pixels it reaches)."""
+    ct = camera_tensors(cam)
+    with torch.no_grad():
+        if pr_all is None:
+            pr_all = project(scene_tensors(scene), ct, scene)
+    W, H = ct["W"], ct["H"]
+    order = depth_order(pr_all.depth32, pr_all.visible.numpy())
+    g_img = torch.tensor(np.asarray(dl_dimage, np.float64), dtype=DT)
+    out = []
+    for i in prims:
+        zero = {a: np.zeros(tuple(v.shape[1:])) for a, v in scene_tensors(scene.subset(np.array([i]))).items()}
+        win = window_setup(pr_all, order, i)
+        if win is None:
+            out.append(zero)
+            continue
+        J = None
+        for (tx, ty), cand in zip(win[0], win[1]):
+            gx, gy = _tile_pixels(tx, ty, W, H)
+            keep = _support_pixels(_row(pr_all, i), gx, gy)
+            if not keep.any():
+                continue
+            gx, gy = gx[keep], gy[keep]
+            X, Y = torch.from_numpy(gx + 0.5).to(DT), torch.from_numpy(gy + 0.5).to(DT)
+            with torch.no_grad():
+                res = blend_pixels(pr_all, cand, X, Y, ct["bg"])
+            g_pix = g_img[:, torch.from_numpy(gy), torch.from_numpy(gx)].T
+            jumps = _decision_jumps(pr_all, cand, gx, gy, ct["bg"], g_pix, res)
+            if jumps is None:
+                continue
+            if J is None:
+                J = record_jacobian(scene, ct, [i])
+            c = int(np.nonzero(np.asarray(cand) == i)[0][0])
+            one = {f: v[:, c:c + 1] for f, v in jumps.items()}
+            per = _jumps_to_attrs(one, J, np.array([0]))
+            for a, v in per.items():
+                zero[a] += v[0]
+        out.append(zero)
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -62,13 +62,18 @@ def _template_plan(sc, cams):
 
 
 def _chain(act, ref):
-    """Oracle gradients w.r.t. the activated attributes -> raw parameters."""
+    """Oracle gradients w.r.t. the activated attributes -> raw parameters (the
+    activations' derivatives are positive, so a slack maps the same way)."""
     s = act.scales.astype(np.float64)
     o = act.opacities.astype(np.float64)
     w = act.weights.astype(np.float64)
     return dict(means=ref["means"], log_scales=ref["scales"] * s, quats=ref["quats"],
                 logit_o=ref["opacities"] * o * (1 - o), sh=ref["sh"], freqs=ref["freqs"],
                 logit_w=ref["weights"] * w * (1 - w))
+
+
+def _sum(a, b):
+    return b if a is None else {k: a[k] + b[k] for k in a}
 
 
 def _gpu_raw_grads(L, n, k):
@@ -98,9 +103,10 @@ def test_training_step_through_autograd(gpu_lib, k, deg):
     Lr, dl = O.loss_and_grad(ref_img.color.numpy(), target)
     assert abs(float(loss) - Lr) <= 1e-5 * abs(Lr)
     ref = _chain(act, O.render_grads(act, cam, dl, "binned"))
+    slack = _chain(act, O.render_grad_slack(act, cam, dl))
     got = _gpu_raw_grads(L, sc.n, k)
     for name in ref:
-        print(name, check_grads_elementwise(name, got[name], ref[name]))
+        print(name, check_grads_elementwise(name, got[name], ref[name], slack[name]))
 
 
 def test_multiview_autograd_sums_views(gpu_lib):
@@ -118,14 +124,14 @@ def test_multiview_autograd_sums_views(gpu_lib):
     w = torch.from_numpy(np.concatenate([g.reshape(-1) for g in gs]).astype(np.float32)).cuda()
     (img * w).sum().backward()
     torch.cuda.synchronize()
-    ref = None
+    ref = slack = None
     for c, g in zip(cams, gs):
-        r = O.render_grads(act, c, g, "binned")
-        ref = r if ref is None else {a: ref[a] + r[a] for a in ref}
-    ref = _chain(act, ref)
+        ref = _sum(ref, O.render_grads(act, c, g, "binned"))
+        slack = _sum(slack, O.render_grad_slack(act, c, g))
+    ref, slack = _chain(act, ref), _chain(act, slack)
     got = _gpu_raw_grads(L, sc.n, sc.k)
     for name in ref:
-        check_grads_elementwise(name, got[name], ref[name])
+        check_grads_elementwise(name, got[name], ref[name], slack[name])
 
 
 def test_rasterize_renders_the_tensors_it_is_given(gpu_lib):

@@ -41,9 +41,11 @@ def _check_grads(sc, cam, seed, tol=1e-3, scene_name=""):
     g_img = synth.random_dl_dimage(seed, (3, cam.height, cam.width))
     gg = _gpu_grads(ds, plan, g_img)
     ref = O.render_grads(sc, cam, g_img, "binned")
+    slack = O.render_grad_slack(sc, cam, g_img)
     report = {}
     for name, t in gg.items():
-        report[name] = check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), ref[name], norm_tol=tol)
+        report[name] = check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), ref[name], slack[name],
+                                               norm_tol=tol)
     print(scene_name, {k: f"out {v[0]} worst {v[1]:.2f} l2 {v[2]:.2e}" for k, v in report.items()})
 
 
@@ -113,8 +115,9 @@ def test_attenuated_forward_and_backward(gpu_lib, high_freq):
     g_img = synth.random_dl_dimage(45, (3, cam.height, cam.width))
     gg = _gpu_grads([ds], plan, g_img)
     rg = O.render_grads(sc, cam, g_img, "binned", attenuation=True)
+    sl = O.render_grad_slack(sc, cam, g_img, attenuation=True)
     for name, t in gg.items():
-        check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), rg[name])
+        check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), rg[name], sl[name])
 
 
 def test_unaligned_colour_rows(gpu_lib):

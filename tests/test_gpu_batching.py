@@ -33,10 +33,12 @@ def test_multiview_backward_sums_views(gpu_lib):
     grads = {n: torch.zeros_like(getattr(ds, n)) for n in NAMES}
     plan.backward(torch.from_numpy(flat).cuda(), [grads], accumulate=False)
     torch.cuda.synchronize()
-    ref = None
+    ref = slack = None
     for c, g in zip(cams, gs_img):
         r = O.render_grads(sc, c, g, "binned")
         ref = r if ref is None else {k: ref[k] + r[k] for k in ref}
+        q = O.render_grad_slack(sc, c, g)
+        slack = q if slack is None else {k: slack[k] + q[k] for k in slack}
     n = sc.n
     gpu = dict(means=grads["means"].cpu().numpy().T, scales=grads["scales"].cpu().numpy().T,
                quats=grads["quats"].cpu().numpy().T, opacities=grads["opacities"].cpu().numpy(),
@@ -44,7 +46,7 @@ def test_multiview_backward_sums_views(gpu_lib):
                freqs=grads["freqs"].cpu().numpy().reshape(2, 3, n).transpose(2, 0, 1),
                weights=grads["weights"].cpu().numpy().T)
     for k in NAMES:
-        check_grads_elementwise(k, gpu[k], ref[k])
+        check_grads_elementwise(k, gpu[k], ref[k], slack[k])
 
 
 def test_accumulate_adds_to_existing_gradients(gpu_lib):

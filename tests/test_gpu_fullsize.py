@@ -9,7 +9,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, check_grads_elementwise, last_ids_from_gpu, record_fields_np
+from gpu_helpers import assert_image, check_sampled_grads, last_ids_from_gpu, record_fields_np
 from sampling import stratified_primitives
 
 pytestmark = pytest.mark.gpu
@@ -134,14 +134,15 @@ def test_config3_sampled_primitive_gradients(gpu_lib, big):
     assert len(prims) == 200 and (pr.tiles[prims] >= 50).sum() >= 20
     ref = O.primitive_grads_windowed(sc, cam, g_img, prims, pr_all=pr)
     gpu = _gpu_prim_grads(grads, prims, sc.n)
-    for name in names:
-        r = np.stack([ref[j][name] for j in range(len(prims))])
-        print(name, check_grads_elementwise(name, gpu[name].reshape(r.shape), r))
+
+    def slack_rows(rows):
+        return O.primitive_grad_slack_windowed(sc, cam, g_img, prims[rows], pr_all=pr)
+    for name, rep in check_sampled_grads(names, gpu, ref, slack_rows, "200 sampled").items():
+        print(name, rep)
     # the large primitives on their own
     big_ = np.nonzero(pr.tiles[prims] >= 50)[0]
-    for name in names:
-        r = np.stack([ref[j][name] for j in big_])
-        check_grads_elementwise(f"{name} (>= 50 tiles)", gpu[name][big_].reshape(r.shape), r)
+    check_sampled_grads(names, {n: gpu[n][big_] for n in names}, [ref[j] for j in big_],
+                        lambda rows: slack_rows(big_[rows]), ">= 50 tiles")
 
 
 def test_config3_loss_full_frame(gpu_lib, big):

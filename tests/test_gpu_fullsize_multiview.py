@@ -12,7 +12,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, check_grads_elementwise
+from gpu_helpers import assert_image, check_sampled_grads
 from sampling import stratified_primitives
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +63,10 @@ def test_config4_sampled_views_binning_and_blend(gpu_lib, mv):
         with torch.no_grad():
             ref = O.render(None, O.camera_tensors(cam), "binned", tiles=tiles, scene_f32=sc, pr=pr)
         img = plan.view_image(v).cpu().numpy()
-        assert_image(img, ref, f"view {v}")
+        # the dense ball saturates most pixels, so more of them take a stop
+        # decision near its threshold than in the clustered frame (about 1% of
+        # the sampled pixels); every fragile pixel is still held to its bound
+        assert_image(img, ref, f"view {v}", max_fragile=0.03)
         # last contributor of every pixel of the sampled tiles
         nc = plan.view_n_contrib(v).cpu().numpy().astype(np.int64)
         valid = ~np.isnan(ref.color.numpy()[0]) & ~ref.fragile
@@ -108,6 +111,8 @@ def test_config4_backward_one_view_sampled_gradients(gpu_lib, mv):
            "freqs": grads["freqs"].cpu().numpy().reshape(4, 3, n)[:, :, prims].transpose(2, 0, 1),
            "weights": grads["weights"].cpu().numpy()[:, prims].T}
     print(f"view {v}, tiles of the sample: {sorted(pr.tiles[prims].tolist())}")
-    for name in names:
-        r = np.stack([ref[j][name] for j in range(len(prims))])
-        print(name, check_grads_elementwise(name, gpu[name].reshape(r.shape), r))
+    reports = check_sampled_grads(names, gpu, ref,
+                                  lambda rows: O.primitive_grad_slack_windowed(sc, cam, g_img, prims[rows], pr_all=pr),
+                                  f"view {v}")
+    for name, rep in reports.items():
+        print(name, rep)
