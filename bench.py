@@ -192,7 +192,7 @@ def main():
     render_flops = flops_env * e_env + flops_full * e_full
     ranges = plan.ranges[:cam.num_tiles].to(torch.int64)
     p_read = int((ranges[:, 1] - ranges[:, 0]).sum().item())
-    rec_bytes = 4 * (10 + 3 * K)  # record floats the blend uses
+    rec_bytes = 4 * (12 + 3 * K)  # record floats the blend uses (fields + the mean's rounding residuals)
     render_bytes = p_read * (4 + rec_bytes) + pix * (12 + 4 + 4) + cam.num_tiles * 8
     stage_ms = dict(stage)
     dom = max(stage_ms, key=stage_ms.get)
@@ -202,7 +202,7 @@ def main():
     # pass-aware algorithmic bytes of the whole forward (byte model in the design doc)
     N, V = scene.n, vis
     params_visible = 4 * (3 + 4 + 1 + 48 + 4 * K)
-    b_pre = 12 * N + params_visible * V + 4 * (10 + 3 * K) * V + 4 * 4 * N
+    b_pre = 12 * N + params_visible * V + 4 * (12 + 3 * K) * V + 4 * 4 * N
     b_scan = 8 * N
     b_dup = 16 * V + 12 * P
     b_sort = 8 * P + 24 * P * 6

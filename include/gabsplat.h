@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 3
+#define GABSPLAT_ABI_VERSION 4
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
@@ -149,6 +149,10 @@ typedef struct {
  *            [10+3j .. 12+3j]  2D frequency (cycles/pixel, x then y) and
  *                   weight of component j's cosine (w_j, times its
  *                   attenuation when GABSPLAT_FLAG_ATTENUATION is set)
+ *            [10+3k, 11+3k]  residuals of mu2d's float32 rounding: the mean
+ *                   is mu2d + residual (a float pair, computed in double),
+ *                   which holds it to ~1e-6 px where a float alone holds
+ *                   ~1e-4 px (at coordinates near 1000)
  *          so o * G(p) = exp2(q(p - mu2d) + rec[5]).
  *   depth  [items] fp32 camera z, computed as ((r20 x + r21 y) + r22 z) + t2
  *          with one IEEE rounding per operation

@@ -76,7 +76,11 @@ __host__ __device__ inline const SceneEntry* table_scenes(const void* t, int num
                                              sizeof(ViewEntry) * (size_t)num_views);
 }
 
-inline int record_floats(int k) { return (10 + 3 * k + 3) & ~3; }
+// Render record: the fields of gabsplat_geom.rec (10 + 3k floats, the mean's
+// float32 rounding residuals at 10 + 3k and 11 + 3k), padded to float4s.
+__host__ __device__ constexpr int record_stride(int k) { return (12 + 3 * k + 3) & ~3; }
+__host__ __device__ constexpr int record_mean_lo(int k) { return 10 + 3 * k; }
+inline int record_floats(int k) { return record_stride(k); }
 __host__ __device__ inline int grad2d_floats(int k) { return (10 + 3 * k + 3) & ~3; }
 __host__ __device__ inline int grad2d_stride(int k, int grad_flags) {
   return (grad_flags & GABSPLAT_GRAD_ABS_MEAN2D) ? (12 + 3 * k + 3) & ~3 : grad2d_floats(k);

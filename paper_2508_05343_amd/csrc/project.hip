@@ -192,6 +192,82 @@ __device__ __forceinline__ void geometry(const ViewEntry& V, float mx, float my,
   }
 }
 
+// Camera-space position of a mean in double precision from the float32
+// inputs (the same transform as the depth key, unrounded).
+__device__ __forceinline__ void camera_point_f64(const ViewEntry& V, float mx, float my, float mz, double (&t)[3]) {
+  const float* R = V.R;
+  const double X = mx, Y = my, Z = mz;
+  t[0] = (double)R[0] * X + (double)R[1] * Y + (double)R[2] * Z + (double)V.t[0];
+  t[1] = (double)R[3] * X + (double)R[4] * Y + (double)R[5] * Z + (double)V.t[1];
+  t[2] = (double)R[6] * X + (double)R[7] * Y + (double)R[8] * Z + (double)V.t[2];
+}
+
+// The image-plane mean of one item in double precision.  In float32 the mean
+// is only held to an ulp of its pixel coordinates (1.2e-4 px near x = 1000),
+// which moves alpha by up to ~1e-3 relative at the steep edge of a small
+// footprint; the record keeps the mean as a float pair (rounded value +
+// residual) and the blend forms the tile-relative offset from both.
+__device__ __forceinline__ void precise_mean(const ViewEntry& V, float mx, float my, float mz, double (&mu)[2]) {
+  double t[3];
+  camera_point_f64(V, mx, my, mz, t);
+  const double iz = 1.0 / t[2];
+  mu[0] = (double)V.fx * t[0] * iz + (double)V.cx;
+  mu[1] = (double)V.fy * t[1] * iz + (double)V.cy;
+}
+
+// The frequency basis (v_x, v_y) of geometry() in double precision (the
+// camera-space depth unrounded): the frequency dot products v . f cancel in
+// float32 to ~1e-5 of their terms, in double they are exact to the final
+// rounding.  Returns false when the raw 2D covariance is singular (the
+// frequencies are then zero).
+__device__ __forceinline__ bool precise_frequency_basis(const ViewEntry& V, float mx, float my, float mz,
+                                                        const float* q, const float* s, double (&vx)[3],
+                                                        double (&vy)[3]) {
+  const float* R = V.R;
+  double t[3];
+  camera_point_f64(V, mx, my, mz, t);
+  const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
+  const double iz = 1.0 / t[2];
+  const double Wd = V.width, Hd = V.height;
+  const double uxc = fmin(fmax(t[0] * iz, (-0.15 * Wd - cx) / fx), (1.15 * Wd - cx) / fx);
+  const double uyc = fmin(fmax(t[1] * iz, (-0.15 * Hd - cy) / fy), (1.15 * Hd - cy) / fy);
+  const double a0 = fx * iz, a1 = fy * iz;
+  const double T0[3] = {a0 * (R[0] - uxc * R[6]), a0 * (R[1] - uxc * R[7]), a0 * (R[2] - uxc * R[8])};
+  const double T1[3] = {a1 * (R[3] - uyc * R[6]), a1 * (R[4] - uyc * R[7]), a1 * (R[5] - uyc * R[8])};
+  const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  const double iq = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * iq, x = qx * iq, y = qy * iq, z = qz * iq;
+  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  double M[3][3], r0[3], r1[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[i][j] = Rq[i][j] * (double)s[j];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    r0[j] = T0[0] * M[0][j] + T0[1] * M[1][j] + T0[2] * M[2][j];
+    r1[j] = T1[0] * M[0][j] + T1[1] * M[1][j] + T1[2] * M[2][j];
+  }
+  const double c[3] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2], r0[0] * r1[1] - r0[1] * r1[0]};
+  const double D = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  if (!(D > 0.0)) {
+    vx[0] = vx[1] = vx[2] = vy[0] = vy[1] = vy[2] = 0.0;
+    return false;
+  }
+  // r1 x c and c x r0, mapped through M, over |c|^2
+  const double ux[3] = {r1[1] * c[2] - r1[2] * c[1], r1[2] * c[0] - r1[0] * c[2], r1[0] * c[1] - r1[1] * c[0]};
+  const double uy[3] = {c[1] * r0[2] - c[2] * r0[1], c[2] * r0[0] - c[0] * r0[2], c[0] * r0[1] - c[1] * r0[0]};
+  const double iD = 1.0 / D;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vx[i] = (M[i][0] * ux[0] + M[i][1] * ux[1] + M[i][2] * ux[2]) * iD;
+    vy[i] = (M[i][0] * uy[0] + M[i][1] * uy[1] + M[i][2] * uy[2]) * iD;
+  }
+  return true;
+}
+
 constexpr float kTwoPiSq = 19.739208802178716f;  // 2 pi^2
 
 __device__ __forceinline__ V3 mat_vec(const float (&M)[3][3], V3 x) {
@@ -254,7 +330,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
                                                     float* __restrict__ depth_out,
                                                     uint32_t* __restrict__ rect_out,
                                                     uint32_t* __restrict__ tiles_out) {
-  constexpr int RF = (10 + 3 * K + 3) & ~3;
+  constexpr int RF = record_stride(K);
   __shared__ uint16_t s_cand[kPreBlock];
   __shared__ uint32_t s_wave[4];
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -352,8 +428,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     Geo g;
     geometry(V, mx, my, mz, tz, q, sc, dil, g);
     if (mip2d) oe *= sqrtf(fmaxf(g.D / g.det, kMip2dMinRatio));
-    const float mux = fmaf(V.fx * g.tx, g.inv_tz, V.cx);
-    const float muy = fmaf(V.fy * g.ty, g.inv_tz, V.cy);
+    double mu_d[2];
+    precise_mean(V, mx, my, mz, mu_d);
+    const float mux = (float)mu_d[0], muy = (float)mu_d[1];
+    const float mux_lo = (float)(mu_d[0] - (double)mux), muy_lo = (float)(mu_d[1] - (double)muy);
     // exact support of o G >= 1/255: d^T C d <= 2 ln(255 o)
     const float kk = sqrtf(fmaxf(2.0f * kLn2 * log2f(255.0f * oe), 0.0f));
     const float rx = kk * sqrtf(g.ra + dil), ry = kk * sqrtf(g.rc + dil);
@@ -372,10 +450,29 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       float r[RF];
       r[0] = mux;
       r[1] = muy;
+      r[record_mean_lo(K)] = mux_lo;
+      r[record_mean_lo(K) + 1] = muy_lo;
       r[2] = -0.5f * kLog2e * g.conic[0];
       r[3] = -kLog2e * g.conic[1];
       r[4] = -0.5f * kLog2e * g.conic[2];
       r[5] = log2f(oe);
+      // frequencies first: their double-precision basis is dead before the colour row is loaded
+      float wsum = 0.f;
+      const bool atten = (S.flags & GABSPLAT_FLAG_ATTENUATION) != 0;
+      const V3 u = mat_vec(g.M, g.c);
+      double vx_d[3], vy_d[3];
+      precise_frequency_basis(V, mx, my, mz, q, sc, vx_d, vy_d);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
+                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
+        const float wk = S.weights[(int64_t)k * n + i];
+        r[10 + 3 * k] = (float)(vx_d[0] * f.x + vx_d[1] * f.y + vx_d[2] * f.z);
+        r[11 + 3 * k] = (float)(vy_d[0] * f.x + vy_d[1] * f.y + vy_d[2] * f.z);
+        r[12 + 3 * k] = atten ? wk * __expf(-kTwoPiSq * ray_variance(g, u, f)) : wk;
+        wsum += wk;
+      }
+      r[9] = 1.0f - wsum;
       if (S.sh_degree >= 0) {
         const V3 d = v3(mx - V.campos[0], my - V.campos[1], mz - V.campos[2]);
         const float il = 1.0f / sqrtf(dot3(d, d));
@@ -401,22 +498,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         r[7] = S.colors[3 * i + 1];
         r[8] = S.colors[3 * i + 2];
       }
-      float wsum = 0.f;
-      const bool atten = (S.flags & GABSPLAT_FLAG_ATTENUATION) != 0;
-      const V3 u = mat_vec(g.M, g.c);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
-                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
-        const float wk = S.weights[(int64_t)k * n + i];
-        r[10 + 3 * k] = dot3(g.vx, f);
-        r[11 + 3 * k] = dot3(g.vy, f);
-        r[12 + 3 * k] = atten ? wk * __expf(-kTwoPiSq * ray_variance(g, u, f)) : wk;
-        wsum += wk;
-      }
-      r[9] = 1.0f - wsum;
-#pragma unroll
-      for (int jj = 10 + 3 * K; jj < RF; ++jj) r[jj] = 0.f;
+      for (int jj = record_mean_lo(K) + 2; jj < RF; ++jj) r[jj] = 0.f;
       float4* dst = reinterpret_cast<float4*>(rec + item * RF);
 #pragma unroll
       for (int jj = 0; jj < RF / 4; ++jj) dst[jj] = make_float4(r[4 * jj], r[4 * jj + 1], r[4 * jj + 2], r[4 * jj + 3]);

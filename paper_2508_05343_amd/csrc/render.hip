@@ -96,11 +96,15 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float ox
 }
 
 // A record as staged in LDS for one tile, relative to the tile origin (ox, oy):
-// with the pixel's in-tile centre (u, v) = (px - ox + 0.5, py - oy + 0.5) and
-// m = (mu_x - ox, mu_y - oy), the envelope exponent q(d) + log2 o (d = (u, v) - m)
-// is the quadratic A u^2 + B u v + C v^2 + D u + E v + F, and the phase of
-// component k is fx_k u + fy_k v + G_k.  Floats (3 + K float4s):
-//   [A B C F] [D E m_x m_y] [r g b w0] then per component [fx fy G w'].
+// m = (mu_x - ox, mu_y - oy) is the mean in the tile's frame, and a pixel with
+// in-tile centre (u, v) = (px - ox + 0.5, py - oy + 0.5) sits at the offset
+// d = (u, v) - m from it.  The envelope exponent q(d) + log2 o is evaluated as
+// dx (A dx + B dy) + C dy^2 + log2 o and the phase of component k as
+// fx_k dx + fy_k dy, both at the offset itself: expanded around the tile
+// origin instead, the constant term A |m|^2 of a sharp footprint centred far
+// from the origin cancels against the pixel terms and leaves errors of ~1e-5
+// of the result.  Floats (3 + K float4s):
+//   [A B C log2o] [m_x m_y 0 0] [r g b w0] then per component [fx fy w' 0].
 template <int K>
 struct Staged {
   static constexpr int S4 = 3 + K;
@@ -109,35 +113,36 @@ struct Staged {
 template <int K>
 __device__ __forceinline__ void stage_record(const float4* q, float ox, float oy, float4* dst) {
   // record fields (gabsplat_geom.rec): mu 0-1, conic terms 2-4, log2 o 5,
-  // rgb 6-8, w0 9, component k at 10 + 3k (fx, fy, w')
-  constexpr int R4 = (10 + 3 * K + 3) / 4;
+  // rgb 6-8, w0 9, component k at 10 + 3k (fx, fy, w'), then the residuals
+  // of the mean's float32 rounding
+  constexpr int R4 = record_stride(K) / 4;
   float f[4 * R4];
 #pragma unroll
   for (int j = 0; j < R4; ++j) {
     f[4 * j] = q[j].x; f[4 * j + 1] = q[j].y; f[4 * j + 2] = q[j].z; f[4 * j + 3] = q[j].w;
   }
-  const float A = f[2], B = f[3], C = f[4];
-  const float mx = f[0] - ox, my = f[1] - oy;
-  const float D = -fmaf(2.0f * A, mx, B * my);
-  const float E = -fmaf(B, mx, 2.0f * C * my);
-  const float F = fmaf(A * mx, mx, fmaf(B * mx, my, fmaf(C * my, my, f[5])));
-  dst[0] = make_float4(A, B, C, F);
-  dst[1] = make_float4(D, E, mx, my);
+  // tile-relative mean: f[0] - ox is exact whenever the offset is no larger
+  // in magnitude than f[0] (both are multiples of the ulp of f[0]), so the
+  // residual restores the precision the absolute coordinate could not hold;
+  // a larger offset (a wide footprint centred far from the tile) is rounded
+  // at its own ulp
+  const float mx = (f[0] - ox) + f[record_mean_lo(K)], my = (f[1] - oy) + f[record_mean_lo(K) + 1];
+  dst[0] = make_float4(f[2], f[3], f[4], f[5]);
+  dst[1] = make_float4(mx, my, 0.f, 0.f);
   dst[2] = make_float4(f[6], f[7], f[8], f[9]);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float fxk = f[10 + 3 * k], fyk = f[11 + 3 * k];
-    dst[3 + k] = make_float4(fxk, fyk, -fmaf(fxk, mx, fyk * my), f[12 + 3 * k]);
-  }
+  for (int k = 0; k < K; ++k) dst[3 + k] = make_float4(f[10 + 3 * k], f[11 + 3 * k], f[12 + 3 * k], 0.f);
 }
 
-// Envelope exponent of a staged record at in-tile pixel centre (u, v).
-__device__ __forceinline__ float staged_power(float4 s0, float4 s1, float u, float v) {
-  return fmaf(u, fmaf(s0.x, u, fmaf(s0.y, v, s1.x)), fmaf(v, fmaf(s0.z, v, s1.y), s0.w));
+// Envelope exponent q(d) + log2 o of a staged record at the offset d = (dx, dy)
+// of a pixel centre from its mean (the forward and the backward evaluate it
+// with these operations in this order, so their alphas agree bit for bit).
+__device__ __forceinline__ float staged_power(float4 s0, float dx, float dy) {
+  return fmaf(dx, fmaf(s0.x, dx, s0.y * dy), fmaf(s0.z * dy, dy, s0.w));
 }
 
-// Phase (cycles) of a staged component (fx, fy, G) at (u, v).
-__device__ __forceinline__ float staged_phase(float4 c, float u, float v) { return fmaf(c.x, u, fmaf(c.y, v, c.z)); }
+// Phase (cycles) f . d of a staged component (fx, fy, w') at the offset d.
+__device__ __forceinline__ float staged_phase(float4 c, float dx, float dy) { return fmaf(c.x, dx, c.y * dy); }
 
 // --------------------------------------------------------------------- K6
 // The ANALYSIS variant (never the timed one) can also report, per pixel, how
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
                                                        uint32_t* __restrict__ eval_counts,
                                                        float* __restrict__ freq_map,
                                                        const int32_t* __restrict__ d_overflow) {
-  constexpr int RF = (10 + 3 * K + 3) & ~3;
+  constexpr int RF = record_stride(K);
   constexpr int R4 = RF / 4;
   constexpr int S4 = Staged<K>::S4;
   __shared__ float4 s_rec[kBatchFwd * S4];
@@ -205,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         const int j = c0 + __builtin_ctzll(bits);
         bits &= bits - 1;
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
-        const float pw = staged_power(s0, s1, u, v);
+        const float dx = u - s1.x, dy = v - s1.y;
+        const float pw = staged_power(s0, dx, dy);
         // o G < 1/255 with B <= 1 means alpha < 1/255: no full evaluation
         const bool env = !(pw < kLog2AlphaMin);
         if ((__builtin_amdgcn_ballot_w64(env) & act) == 0ull) continue;
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const float4 c = s_rec[j * S4 + 3 + k];
-          Bv = fmaf(c.w, cos_rev(staged_phase(c, u, v)), Bv);
+          Bv = fmaf(c.z, cos_rev(staged_phase(c, dx, dy)), Bv);
         }
         const float alpha = fminf(kAlphaMax, E * Bv);
         live = live && !(alpha < kAlphaMin);
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             const float4 c = s_rec[j * S4 + 3 + k];
-            phi = fmaf(c.w, sqrtf(c.x * c.x + c.y * c.y), phi);
+            phi = fmaf(c.z, sqrtf(c.x * c.x + c.y * c.y), phi);
           }
           Fm = fmaf(phi, wt, Fm);
         }
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
                                                        const float* __restrict__ dl_dimage,
                                                        float* __restrict__ grad2d,
                                                        const int32_t* __restrict__ d_overflow) {
-  constexpr int RF = (10 + 3 * K + 3) & ~3;
+  constexpr int RF = record_stride(K);
   constexpr int R4 = RF / 4;
   constexpr int S4 = Staged<K>::S4;
   constexpr int GS = 10 + 3 * K + (ABS ? 2 : 0);  // gradient components per pair (record fields [+ 2])
@@ -452,7 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         const int j = __builtin_amdgcn_readfirstlane(c0 + hb);  // wave-uniform: scalar addressing
         const uint32_t pos = lo + (uint32_t)j + 1;
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
-        const float pw = staged_power(s0, s1, u, v);
+        const float dx = u - s1.x, dy = v - s1.y;
+        const float pw = staged_power(s0, dx, dy);
         bool contrib = pos <= last && !(pw < kLog2AlphaMin);
         const uint64_t cb = __builtin_amdgcn_ballot_w64(contrib);
         if (cb == 0ull) continue;
@@ -466,10 +473,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         float Bv = col.w;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float fr = __builtin_amdgcn_fractf(staged_phase(cc[k], u, v));
+          const float fr = __builtin_amdgcn_fractf(staged_phase(cc[k], dx, dy));
           cs[k] = __builtin_amdgcn_cosf(fr);
           sn[k] = __builtin_amdgcn_sinf(fr);
-          Bv = fmaf(cc[k].w, cs[k], Bv);
+          Bv = fmaf(cc[k].z, cs[k], Bv);
         }
         const float EB = E * Bv;
         const float alpha = fminf(kAlphaMax, EB);
@@ -501,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         // with (ex, ey) = mean - pixel centre the mean gradient -(dL/d pixel
         // offset) is dp (2A ex + B ey, B ex + 2C ey) - sum_k dph_k f_k, where
         // dph_k = dL/d phase_k; nph = -dph_k
-        const float ex = s1.z - u, ey = s1.w - v;
+        const float ex = -dx, ey = -dy;
         const float px_ = dp * ex, py_ = dp * ey;
         gv[2] = px_ * ex;
         gv[3] = px_ * ey;
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         const float dB2pi = dB * 6.283185307179586f;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float nph = dB2pi * cc[k].w * sn[k];
+          const float nph = dB2pi * cc[k].z * sn[k];
           gv[10 + 3 * k] = nph * ex;  // = dph_k (u - mean_x)
           gv[11 + 3 * k] = nph * ey;
           gv[12 + 3 * k] = dB * cs[k];

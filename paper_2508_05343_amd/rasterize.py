@@ -337,7 +337,8 @@ class RenderPlan:
         r = self.rec[:self.items]
         k = self.k
         log2e = 1.0 / math.log(2.0)
-        out = dict(mu2d=r[:, 0:2], conic=torch.stack([r[:, 2] / (-0.5 * log2e), r[:, 3] / (-log2e),
+        lo = 10 + 3 * k  # residuals of the mean's float32 rounding
+        out = dict(mu2d=r[:, 0:2].double() + r[:, lo:lo + 2].double(), conic=torch.stack([r[:, 2] / (-0.5 * log2e), r[:, 3] / (-log2e),
                                                       r[:, 4] / (-0.5 * log2e)], 1),
                    opacity=torch.exp2(r[:, 5]), rgb=r[:, 6:9], w0=r[:, 9])
         if k:

@@ -67,7 +67,7 @@ def scratch_bytes(n_items: int, pixels: int, pairs: int, k: int = 4) -> int:
     """Device scratch of one job: per-item geometry (record + depth + rect +
     tiles), pair buffers (values, two key/value ping-pong buffers, per-partition
     counts) and the image, transmittance and contribution-count outputs."""
-    rec = 4 * ((10 + 3 * k + 3) // 4 * 4)
+    rec = 4 * ((12 + 3 * k + 3) // 4 * 4)  # gabsplat_record_floats(k)
     per_item = rec + 4 + 8 + 4 + 4 * 5 + 1024 * 4 // 4096
     per_pair = 4 * 4 + 256 * 4 * 4 // 4096 + 4
     per_pixel = 12 + 4 + 4

@@ -35,8 +35,8 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_helpers(L):
-    assert L.gabsplat_abi_version() == 3
-    assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 16
+    assert L.gabsplat_abi_version() == 4
+    assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 20
     assert L.gabsplat_record_floats(4) == 24 and L.gabsplat_record_floats(8) == 36
     assert L.gabsplat_record_floats(9) == -1
     assert L.gabsplat_grad2d_floats(4) == 24 and L.gabsplat_grad2d_floats(2) == 16
