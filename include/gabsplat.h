@@ -64,7 +64,8 @@ typedef enum {
   GABSPLAT_ERR_WORKSPACE_TOO_SMALL = 2,
   GABSPLAT_ERR_CAPACITY_EXCEEDED = 3,
   GABSPLAT_ERR_HIP = 4,
-  GABSPLAT_ERR_UNSUPPORTED_DEVICE = 5
+  GABSPLAT_ERR_UNSUPPORTED_DEVICE = 5,
+  GABSPLAT_ERR_SCRATCH_LIMIT = 6
 } gabsplat_status;
 
 /* A set of N primitives (Sec. 3.2: mean, covariance via scale and rotation,
@@ -317,6 +318,29 @@ size_t gabsplat_loss_workspace_size(int32_t channels, int32_t height, int32_t wi
 gabsplat_status gabsplat_loss_l1_dssim(const float* x, const float* y, int32_t channels,
                                        int32_t height, int32_t width, float lambda, float* d_loss,
                                        float* dl_dx, void* ws, size_t ws_bytes, void* stream);
+
+/* Size of the library's static scratch for gabsplat_loss_l1_dssim_noalloc
+ * (80 MiB per GPU): problems with gabsplat_loss_workspace_size(c, H, W) up
+ * to this, e.g. three channels of 1920x1080. */
+#define GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES ((size_t)83886080)
+
+/* gabsplat_loss_l1_dssim for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving or training loops, harnesses
+ * that forbid allocation.  Same arguments, results and kernels, without the
+ * workspace: its scratch is a static device array of
+ * GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds from the first call on it until the process ends (the first call on a
+ * GPU looks up that GPU's copy; later calls allocate and free nothing).  The
+ * kernels clear what they count with themselves, so no memset is recorded.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on a
+ * GPU (concurrent streams, or host threads) race and corrupt each other's
+ * results, so the caller serialises them.  x, y, d_loss, dl_dx and the stream
+ * are on the same GPU.  GABSPLAT_ERR_SCRATCH_LIMIT (before any device work)
+ * when gabsplat_loss_workspace_size(channels, height, width) exceeds the
+ * scratch; GABSPLAT_ERR_INVALID_ARGUMENT as gabsplat_loss_l1_dssim. */
+gabsplat_status gabsplat_loss_l1_dssim_noalloc(const float* x, const float* y, int32_t channels,
+                                               int32_t height, int32_t width, float lambda, float* d_loss,
+                                               float* dl_dx, void* stream);
 
 /* ------------------------------------------------ density control (Sec. 3.4.2)
  * The paper densifies as 3DGS does (clone small / split large primitives whose

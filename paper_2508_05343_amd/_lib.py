@@ -25,10 +25,12 @@ EXPORTS = (
     "gabsplat_loss_workspace_size", "gabsplat_loss_l1_dssim", "gabsplat_read_overflow",
     "gabsplat_densify_stats", "gabsplat_densify_workspace_size", "gabsplat_densify",
     "gabsplat_reset_frequency_weights", "gabsplat_grad2d_stride", "gabsplat_mip_filter3d_workspace_size",
-    "gabsplat_mip_filter3d",
+    "gabsplat_mip_filter3d", "gabsplat_loss_l1_dssim_noalloc",
 )
 
-OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE = range(6)
+OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE, SCRATCH_LIMIT = range(7)
+# GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES
+LOSS_NOALLOC_SCRATCH_BYTES = 83886080
 FLAG_ATTENUATION = 1
 FLAG_MIP_2D = 2
 FLAG_MIP_3D = 4
@@ -124,6 +126,9 @@ def lib() -> ctypes.CDLL:
     L.gabsplat_loss_l1_dssim.restype = c_int32
     L.gabsplat_loss_l1_dssim.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p,
                                          c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gabsplat_loss_l1_dssim_noalloc.restype = c_int32
+    L.gabsplat_loss_l1_dssim_noalloc.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p,
+                                                 c_void_p, c_void_p]
     L.gabsplat_read_overflow.restype = c_int32
     L.gabsplat_read_overflow.argtypes = [c_void_p, c_void_p]
     L.gabsplat_densify_stats.restype = c_int32
@@ -241,11 +246,36 @@ def gabsplat_render_bwd(scenes: Sequence[Scene], scene_of_view, cams: Sequence[C
                                      ptr(d_overflow), stream_handle(stream)), "gabsplat_render_bwd")
 
 
+def _loss_args(x, y, d_loss, dl_dx):
+    """Layout checks of the loss bindings: x, y and dl_dx contiguous float32
+    [channels][H][W] device tensors of one shape on one device, d_loss at least
+    one float32 there."""
+    import torch
+    for name, t in (("x", x), ("y", y), ("dl_dx", dl_dx), ("d_loss", d_loss)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+        if t.device != x.device:
+            raise ValueError(f"{name} is on {t.device}, x on {x.device}")
+    if x.dim() != 3 or y.shape != x.shape or dl_dx.shape != x.shape:
+        raise ValueError(f"x, y and dl_dx must share one [channels, H, W] shape, got {tuple(x.shape)}, "
+                         f"{tuple(y.shape)}, {tuple(dl_dx.shape)}")
+    if d_loss.numel() < 1:
+        raise ValueError("d_loss must hold one float")
+    return x.shape
+
+
 def gabsplat_loss_l1_dssim(x, y, lam: float, d_loss, dl_dx, ws, stream=None):
-    c, h, w = x.shape
+    c, h, w = _loss_args(x, y, d_loss, dl_dx)
     _check(lib().gabsplat_loss_l1_dssim(ptr(x), ptr(y), c, h, w, float(lam), ptr(d_loss), ptr(dl_dx), ptr(ws),
                                         ws.numel() * ws.element_size(), stream_handle(stream)),
            "gabsplat_loss_l1_dssim")
+
+
+def gabsplat_loss_l1_dssim_noalloc(x, y, lam: float, d_loss, dl_dx, stream=None):
+    c, h, w = _loss_args(x, y, d_loss, dl_dx)
+    _check(lib().gabsplat_loss_l1_dssim_noalloc(ptr(x), ptr(y), c, h, w, float(lam), ptr(d_loss), ptr(dl_dx),
+                                                stream_handle(stream)),
+           "gabsplat_loss_l1_dssim_noalloc")
 
 
 def gabsplat_densify_stats(geom: Geom, cams: Sequence[Camera], n: int, grad2d, grad_flags: int, accum, accum_abs,

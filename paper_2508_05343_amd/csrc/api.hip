@@ -168,6 +168,7 @@ const char* gabsplat_status_string(gabsplat_status s) {
     case GABSPLAT_ERR_CAPACITY_EXCEEDED: return "pair capacity exceeded";
     case GABSPLAT_ERR_HIP: return "HIP runtime error";
     case GABSPLAT_ERR_UNSUPPORTED_DEVICE: return "unsupported device (gfx950 required)";
+    case GABSPLAT_ERR_SCRATCH_LIMIT: return "problem larger than the static scratch of the allocation-free entry point";
   }
   return "unknown status";
 }

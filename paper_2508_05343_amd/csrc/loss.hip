@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "gs_internal.h"
 
@@ -305,3 +306,63 @@ hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, floa
 }
 
 }  // namespace gs
+
+// ------------------------------------------------ allocation-free entry point
+// The scratch of gabsplat_loss_l1_dssim_noalloc (the workspace of launch_loss:
+// SSIM maps, per-tile partial sums, completion counter).  The code object
+// holds one copy per GPU; in host code `scratch` names no device memory, so
+// the host only ever uses the address hipGetSymbolAddress returns for the
+// current GPU, looked up once per GPU and kept.
+static __device__ __align__(256) unsigned char scratch[GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of GPU `dev`'s scratch: looked up with that GPU current the
+// first time, then kept.
+hipError_t device_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" gabsplat_status gabsplat_loss_l1_dssim_noalloc(const float* x, const float* y, int32_t channels,
+                                                          int32_t height, int32_t width, float lambda,
+                                                          float* d_loss, float* dl_dx, void* stream) {
+  try {
+    if (!x || !y || !d_loss || !dl_dx || channels < 1 || height < 1 || width < 1 || height > 65535 * 16 ||
+        width > 65535 * 16 || channels > 65535 || !(lambda >= 0.f && lambda <= 1.f))
+      return GABSPLAT_ERR_INVALID_ARGUMENT;
+    if (gs::loss_workspace_bytes(channels, height, width) > GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES)
+      return GABSPLAT_ERR_SCRATCH_LIMIT;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) return GABSPLAT_ERR_HIP;
+    void* ws = nullptr;
+    if (device_scratch(dev, &ws) != hipSuccess) return GABSPLAT_ERR_HIP;
+    return gs::launch_loss(x, y, channels, height, width, lambda, d_loss, dl_dx, ws, s) == hipSuccess
+               ? GABSPLAT_OK
+               : GABSPLAT_ERR_HIP;
+  } catch (...) {
+    return GABSPLAT_ERR_HIP;
+  }
+}

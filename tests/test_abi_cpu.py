@@ -79,6 +79,15 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert st == L.INVALID_ARGUMENT
     st = lib.gabsplat_loss_l1_dssim(None, None, 3, 4, 4, 0.2, None, None, None, 0, None)
     assert st == L.INVALID_ARGUMENT
+    st = lib.gabsplat_loss_l1_dssim_noalloc(None, None, 3, 4, 4, 0.2, None, None, None)
+    assert st == L.INVALID_ARGUMENT
+    # beyond the static scratch: refused before any device work (the
+    # pointers are never dereferenced)
+    fake = 256
+    assert lib.gabsplat_loss_workspace_size(3, 1440, 2560) > L.LOSS_NOALLOC_SCRATCH_BYTES
+    st = lib.gabsplat_loss_l1_dssim_noalloc(fake, fake, 3, 1440, 2560, 0.2, fake, fake, None)
+    assert st == L.SCRATCH_LIMIT
+    assert b"static scratch" in lib.gabsplat_status_string(st)
     assert lib.gabsplat_read_overflow(None, None) == L.INVALID_ARGUMENT
     # 3D filter flag without variances
     sc.flags = L.FLAG_MIP_3D
