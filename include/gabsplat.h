@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 4
+#define GABSPLAT_ABI_VERSION 5
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
@@ -251,7 +251,10 @@ gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_sc
  *   vals [pair_capacity]      sorted item ids (output)
  *   keys [pair_capacity]      sorted 64-bit keys tile << 32 | depth bits, or
  *                             NULL to skip writing them
- *   tile_ranges [total_tiles][2] (output)
+ *   tile_ranges [3 * total_tiles] (output): [total_tiles][2] ranges, then
+ *                the order in which gabsplat_render_fwd / _bwd dispatch the
+ *                tiles (tile ids by decreasing list length, in geometric
+ *                buckets 2^(1/8) apart; empty tiles last)
  *   d_num_pairs  device int64 (output): number of pairs
  *   d_overflow   device int32 (output): 1 if pairs > pair_capacity, else 0.
  *                On overflow vals/keys/ranges are undefined and

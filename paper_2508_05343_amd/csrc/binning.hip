@@ -697,6 +697,52 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tke
     keys[i] = ((uint64_t)tkeys[i] << 32) | (uint64_t)depth_bits[vals[i]];
 }
 
+// ------------------------------------------------------ blend dispatch order
+// The blend kernels give workgroup b the tile order[b], with the tiles in
+// decreasing order of their list length (geometric buckets 2^(1/8) apart,
+// arbitrary order inside a bucket; empty tiles last).  The hardware starts
+// workgroups in index order as slots free up, so the longest tiles start
+// first and the last workgroups to start are short ones: dispatched in image
+// order, the densest tiles could start last and run with most of the GPU idle
+// around them.  One workgroup; order lives after the ranges in tile_ranges.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 160;
+
+__device__ __forceinline__ int order_bucket(uint32_t len) {
+  if (len == 0u) return 0;
+  // 1 + floor(8 log2 len), from the bit length and the next three mantissa bits
+  const int lz = 31 - __builtin_clz(len);
+  const uint32_t frac = lz >= 3 ? (len >> (lz - 3)) & 7u : (len << (3 - lz)) & 7u;
+  const int b = 1 + 8 * lz + (int)frac;
+  return b < kOrderBuckets ? b : kOrderBuckets - 1;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
+                                                              const uint32_t* __restrict__ counters,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderBuckets];
+  if (counters[C_OVERFLOW]) return;
+  const int t = threadIdx.x;
+  for (int b = t; b < kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0;
+  __syncthreads();
+  for (int i = t; i < ntiles; i += kOrderThreads)
+    atomicAdd(&s_cnt[order_bucket(ranges[2 * (size_t)i + 1] - ranges[2 * (size_t)i])], 1u);
+  __syncthreads();
+  if (t == 0) {  // bucket starts, longest bucket first
+    uint32_t run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      const uint32_t c = s_cnt[b];
+      s_cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < ntiles; i += kOrderThreads) {
+    const int b = order_bucket(ranges[2 * (size_t)i + 1] - ranges[2 * (size_t)i]);
+    order[atomicAdd(&s_cnt[b], 1u)] = (uint32_t)i;
+  }
+}
+
 // ---------------------------------------------------------- tile-count path
 // For frames with at most kTcMaxTiles tiles the pairs are binned without a
 // global radix sort: per-block tile histograms (LDS), per-tile column offsets
@@ -1169,6 +1215,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
                          depth_bits, nt, cnt, tstart, counters, pa);
       hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, pa, pb, vals, keys);
+      hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, nt, counters, ranges + 2 * (size_t)nt);
     }
     return hipGetLastError();
   }
@@ -1244,6 +1291,9 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
   const int64_t rbk = (p.capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys);
   const unsigned rblocks = (unsigned)(rbk < 1 ? 1 : (rbk > 65536 ? 65536 : rbk));
   hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tk_final, counters, ranges);
+  if (p.total_tiles > 0)
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, p.total_tiles, counters,
+                       ranges + 2 * (size_t)p.total_tiles);
   if (keys)
     hipLaunchKernelGGL(k_keys64, dim3(pblocks), dim3(256), 0, s, tk_final, vals, depth_bits, counters, keys);
   return hipGetLastError();

@@ -2,10 +2,10 @@
 //
 // One 256-lane workgroup per 16x16 tile; wave w covers the 8x8 quadrant
 // (w & 1, w >> 1) of the tile so that a wave's pixels are spatially compact.
-// Batches of 256 render records are staged in LDS (one record per lane) and
-// every lane walks them in order.  Workgroups are mapped to tiles so that the
-// 8 XCDs (which receive workgroup ids round-robin) get interleaved groups of
-// adjacent tiles: balanced work, shared records within a group.
+// Batches of render records are staged in LDS (one record per lane) and
+// every lane walks them in order.  Workgroup b renders the tile the binning
+// put at position b of its dispatch order (longest tile lists first), so that
+// the GPU never ends with a few long tiles running on an otherwise idle chip.
 //
 // The forward and the backward evaluate alpha with the same sequence of
 // operations and only explicit fused multiply-adds (the library is built
@@ -17,27 +17,11 @@
 
 namespace gs {
 
-constexpr int kNumXcd = 8;
-constexpr int kTileGroup = 4;
 // records staged in LDS per batch (<= kBlock): the forward's smaller batch
 // lowers its LDS use so that more wavefronts fit on a CU (measured faster);
 // the backward is not LDS-limited in the same way
 constexpr int kBatchFwd = 192;
 constexpr int kBatchBwd = 256;
-
-// Workgroup ids reach the 8 XCDs round-robin (id % 8).  Tiles are dealt to
-// the XCDs in groups of kTileGroup consecutive tiles, round-robin: XCD x
-// renders groups x, x + 8, ...  Adjacent tiles of a group share most of their
-// records in that XCD's L2, and the fine interleave spreads the dense parts
-// of the image evenly over the XCDs (contiguous bands of tile rows per XCD
-// leave the XCD with the densest band working ~1.5x longer than the mean).
-// The blocks past the last full round of groups map to themselves.
-__device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
-  const int full = nb / (kNumXcd * kTileGroup) * (kNumXcd * kTileGroup);
-  if (bid >= full) return bid;
-  const int x = bid % kNumXcd, j = bid / kNumXcd;
-  return ((j / kTileGroup) * kNumXcd + x) * kTileGroup + j % kTileGroup;
-}
 
 __device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv, int tile) {
   int lo = 0, hi = nv - 1;
@@ -169,7 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  // longest tile lists first (the order gabsplat_bin_sort writes after the ranges)
+  const int tile = (int)ranges[2 * (size_t)gridDim.x + blockIdx.x];
   const ViewEntry& V = views[find_view_by_tile(views, hdr->num_views, tile)];
   const int lt = tile - V.tile_offset;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
@@ -391,7 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
   const ViewEntry* views = table_views(table);
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  // longest tile lists first (the order gabsplat_bin_sort writes after the ranges)
+  const int tile = (int)ranges[2 * (size_t)gridDim.x + blockIdx.x];
   const ViewEntry& V = views[find_view_by_tile(views, hdr->num_views, tile)];
   const int lt = tile - V.tile_offset;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;

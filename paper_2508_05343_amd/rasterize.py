@@ -215,7 +215,9 @@ class RenderPlan:
         self.geom.rec, self.geom.depth = _lib.ptr(self.rec), _lib.ptr(self.depth)
         self.geom.rect, self.geom.tiles = _lib.ptr(self.rect), _lib.ptr(self.tiles_touched)
         self.geom.views = _lib.ptr(self.views)
-        self.ranges = torch.empty((max(tiles, 1), 2), dtype=torch.int32, device=device)
+        # [tiles][2] ranges, then the blend's dispatch order of the tiles
+        self.ranges_buf = torch.empty(3 * max(tiles, 1), dtype=torch.int32, device=device)
+        self.ranges = self.ranges_buf[:2 * max(tiles, 1)].view(max(tiles, 1), 2)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         self.image = torch.empty(max(3 * pix, 1), dtype=torch.float32, device=device)
@@ -260,11 +262,11 @@ class RenderPlan:
     def bin_sort(self, stream=None):
         self.generation += 1
         _lib.gabsplat_bin_sort(self.geom, self.c_cams, self.items, self.ws, self.keys, self.vals, self.capacity,
-                               self.ranges, self.num_pairs, self.overflow, stream)
+                               self.ranges_buf, self.num_pairs, self.overflow, stream)
 
     def render_fwd(self, stream=None, eval_counts=None, freq_map=None):
         self.generation += 1
-        _lib.gabsplat_render_fwd(self.geom, self.vals, self.ranges, self.c_cams, self.image, self.final_T,
+        _lib.gabsplat_render_fwd(self.geom, self.vals, self.ranges_buf, self.c_cams, self.image, self.final_T,
                                  self.n_contrib, self.overflow, stream, eval_counts=eval_counts, freq_map=freq_map)
 
     def forward(self, check_overflow=True, stream=None):
@@ -309,7 +311,7 @@ class RenderPlan:
                 setattr(c, name, _lib.ptr(t))
             c.grad2d = _lib.ptr(self.grad2d)
             gs.append(c)
-        _lib.gabsplat_render_bwd(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals, self.ranges,
+        _lib.gabsplat_render_bwd(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals, self.ranges_buf,
                                  self.final_T, self.n_contrib, dl_dimage, gs, self.overflow, stream)
 
     # ----- views of the outputs

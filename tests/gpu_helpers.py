@@ -138,3 +138,28 @@ def check_sampled_grads(names, gpu, ref_rows, slack_rows, label=""):
     print(f"{label}: slack evaluated for {len(need)} of {m} primitives")
     return {n: check_grads_elementwise(f"{label} {n}", np.asarray(gpu[n]).reshape(ref[n].shape), ref[n], slack[n])
             for n in names}
+
+
+def order_bucket(lengths):
+    """Dispatch bucket of a tile list length: 0 for an empty list, else
+    1 + 8 floor(log2 L) + the three bits of L after its leading one (capped at
+    159), i.e. geometric buckets 2^(1/8) apart."""
+    L = np.asarray(lengths, np.int64)
+    out = np.zeros(L.shape, np.int64)
+    nz = L > 0
+    # exact bit length (log2 rounding cannot be trusted at powers of two)
+    lz = np.array([int(x).bit_length() - 1 if x > 0 else 0 for x in L.ravel()], np.int64).reshape(L.shape)
+    frac = np.where(lz >= 3, (L >> np.maximum(lz - 3, 0)) & 7, (L << np.maximum(3 - lz, 0)) & 7)
+    out[nz] = np.minimum(1 + 8 * lz[nz] + frac[nz], 159)
+    return out
+
+
+def assert_dispatch_order(plan):
+    """The blend's dispatch order after the ranges: a permutation of the tile
+    ids whose list-length buckets never increase."""
+    T = plan.tiles
+    buf = plan.ranges_buf.cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges, order = buf[:2 * T].reshape(T, 2), buf[2 * T:3 * T]
+    assert np.array_equal(np.sort(order), np.arange(T))
+    b = order_bucket(ranges[:, 1] - ranges[:, 0])[order]
+    assert (np.diff(b) <= 0).all()

@@ -7,7 +7,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, gpu_plan, last_ids_from_gpu, oracle_project, record_fields_np
+from gpu_helpers import assert_image, gpu_plan, last_ids_from_gpu, oracle_project, record_fields_np, assert_dispatch_order
 
 pytestmark = pytest.mark.gpu
 
@@ -142,6 +142,7 @@ def test_bin_sort_end_to_end_config1(gpu_lib):
     else:
         assert (plan.ranges.cpu().numpy().view(np.uint32)[:cam.num_tiles] == ranges_o).all()
     assert (kg == keys_o).all() and (vg == vals_o).all()
+    assert_dispatch_order(plan)
 
 
 def test_render_forward_config1(gpu_lib):

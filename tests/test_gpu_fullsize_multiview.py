@@ -12,7 +12,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, check_sampled_grads
+from gpu_helpers import assert_dispatch_order, assert_image, check_sampled_grads
 from sampling import stratified_primitives
 
 pytestmark = pytest.mark.gpu
@@ -44,6 +44,7 @@ def _tile_lists(plan, v, cam, tiles):
 def test_config4_sampled_views_binning_and_blend(gpu_lib, mv):
     sc, cams, plan = mv
     assert sum(c.num_tiles for c in cams) > 8192  # the radix path
+    assert_dispatch_order(plan)
     rng = np.random.Generator(np.random.PCG64(4004))
     for v in rng.choice(len(cams), size=3, replace=False):
         v = int(v)
