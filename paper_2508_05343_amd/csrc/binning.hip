@@ -923,7 +923,8 @@ __global__ __launch_bounds__(256) void k_tc_colscan(uint32_t* __restrict__ cnt, 
 }
 
 // One block: exclusive scan of the tile totals -> tile starts, ranges ((0, 0)
-// for empty tiles), pair count and overflow flag.
+// for empty tiles), pair count and overflow flag; then the dispatch order of
+// the segment sort and the blend (as k_tile_order) after the ranges.
 __global__ __launch_bounds__(kSortThreads) void k_tc_tilescan(const uint32_t* __restrict__ tot, int ntiles,
                                                              uint32_t capacity, uint32_t* __restrict__ tstart,
                                                              uint32_t* __restrict__ ranges,
@@ -945,6 +946,23 @@ __global__ __launch_bounds__(kSortThreads) void k_tc_tilescan(const uint32_t* __
     ranges[2 * (size_t)i + 1] = c ? run + c : 0u;
     run += c;
   }
+  // dispatch order: tiles by decreasing length bucket
+  __shared__ uint32_t s_cnt[kOrderBuckets];
+  for (int b = t; b < kOrderBuckets; b += kSortThreads) s_cnt[b] = 0;
+  __syncthreads();
+  for (int i = t0; i < t1; ++i) atomicAdd(&s_cnt[order_bucket(tot[i])], 1u);
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      const uint32_t c = s_cnt[b];
+      s_cnt[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  uint32_t* order = ranges + 2 * (size_t)ntiles;
+  for (int i = t0; i < t1; ++i) order[atomicAdd(&s_cnt[order_bucket(tot[i])], 1u)] = (uint32_t)i;
   if (t == 0) {
     const uint32_t ov = total > capacity ? 1u : 0u;
     counters[C_NUM_PAIRS] = total;
@@ -1086,8 +1104,9 @@ __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ran
                                                 uint64_t* __restrict__ pb, uint32_t* __restrict__ vals,
                                                 uint64_t* __restrict__ keys) {
   if (counters[C_OVERFLOW]) return;
-  const int tile = blockIdx.x;
-  if (tile >= ntiles) return;
+  if ((int)blockIdx.x >= ntiles) return;
+  // longest segments first (the blend's dispatch order, after the ranges)
+  const int tile = (int)ranges[2 * (size_t)ntiles + blockIdx.x];
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
   const uint32_t n = end - start;
   if (n == 0) return;
@@ -1215,7 +1234,6 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
                          depth_bits, nt, cnt, tstart, counters, pa);
       hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, pa, pb, vals, keys);
-      hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, nt, counters, ranges + 2 * (size_t)nt);
     }
     return hipGetLastError();
   }
