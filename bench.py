@@ -302,8 +302,48 @@ def main():
                                "kind": "oracle",
                                "sample": f"fp64 projection of all {N} primitives ({t_proj:.1f} s, charged pro rata) "
                                          f"+ blend of {len(tiles)} seeded tiles of {cam.num_tiles} ({spix} px, "
-                                         f"{t_blend:.1f} s)"}
+                                         f"{t_blend:.1f} s)",
+                               "host": host_cpu(), "fp32": oracle_fp32_rate(O, torch, np, scene, cam, pix, tiles)}
     print(json.dumps(out))
+
+
+def host_cpu():
+    """The host the CPU baseline ran on: logical CPUs the OS reports and the
+    processor model (the oracle's threads are `cores`)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def oracle_fp32_rate(O, torch, np, scene, cam, pix, tiles):
+    """The same oracle evaluated in float32 (its arithmetic type switched, the
+    decisions it takes on float32 data unchanged) on a quarter of the sampled
+    tiles: Mpix/s, projection charged pro rata as above."""
+    sub = tiles[: max(1, len(tiles) // 4)]
+    saved = O.DT
+    O.DT = torch.float32
+    try:
+        t = time.perf_counter()
+        with torch.no_grad():
+            pr = O.project(O.scene_tensors(scene), O.camera_tensors(cam), scene)
+        t_proj = time.perf_counter() - t
+        t = time.perf_counter()
+        with torch.no_grad():
+            O.render(None, O.camera_tensors(cam), "binned", tiles=sub, scene_f32=scene, pr=pr)
+        t_blend = time.perf_counter() - t
+    finally:
+        O.DT = saved
+    spix = sum(min(16, cam.width - 16 * tx) * min(16, cam.height - 16 * ty) for tx, ty in sub)
+    return {"value": round(spix / (t_blend + t_proj * spix / pix) / 1e6, 5), "unit": "Mpix/s",
+            "sample": f"fp32 projection of all primitives ({t_proj:.1f} s, pro rata) + blend of {len(sub)} tiles "
+                      f"({spix} px, {t_blend:.1f} s)"}
 
 
 def multiview_step(args, torch, synth, DeviceScene, RenderPlan, LossBuffers):
@@ -373,7 +413,7 @@ def serving_run(args, torch, synth):
         sm = st.summary()
         res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
     res["workload"] = (f"8 resident scenes ({sum(sizes)} primitives), {len(reqs)} Poisson requests at "
-                       f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB scratch budget")
+                       f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB budget for job buffers")
     sweep = []
     for q in [float(x) for x in args.serve_sweep.split(",") if x]:
         rq = synth.config5_requests(scenes, n_requests=600, qps=q, seed=1005 + int(q))
