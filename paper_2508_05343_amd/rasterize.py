@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -168,6 +168,84 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 # ------------------------------------------------------------------ plans
+_ITEMSIZE = {torch.float32: 4, torch.int32: 4, torch.int64: 8}
+
+
+def plan_buffer_specs(k: int, items: int, pixels: int, tiles: int, n_views: int, n_scenes: int, capacity: int,
+                      want_keys: bool = False) -> Dict[str, tuple]:
+    """The device buffers a RenderPlan allocates for its forward: name ->
+    (shape, dtype).  The plan allocates exactly these, so their sum is the
+    plan's device footprint (serving admits batches by it)."""
+    rf = _lib.gabsplat_record_floats(k)
+    vb = _lib.gabsplat_views_bytes(n_views, n_scenes)
+    it, px, tl, cap = max(items, 1), max(pixels, 1), max(tiles, 1), max(int(capacity), 1)
+    wsb = _lib.gabsplat_bin_sort_workspace_size(items, int(capacity), tiles)
+    f32, i32, i64 = torch.float32, torch.int32, torch.int64
+    specs = dict(rec=((it, rf), f32), depth=((it,), f32), rect=((it, 2), i32), tiles_touched=((it,), i32),
+                 views=(((vb + 15) // 16 * 4,), i32), ranges_buf=((3 * tl,), i32), num_pairs=((1,), i64),
+                 overflow=((1,), i32), image=((3 * px,), f32), final_T=((px,), f32), n_contrib=((px,), i32),
+                 vals=((cap,), i32), ws=(((wsb + 255) // 256 * 64,), i32))
+    if want_keys:
+        specs["keys"] = ((cap,), i64)
+    return specs
+
+
+def specs_nbytes(specs: Dict[str, tuple]) -> int:
+    return sum(math.prod(shape) * _ITEMSIZE[dt] for shape, dt in specs.values())
+
+
+def block_bytes(nbytes: int) -> int:
+    """Upper bound of the device bytes torch's caching allocator charges for
+    one buffer of `nbytes`: requests round up to 512 bytes, and one above
+    1 MiB served from a larger cached block keeps up to 1 MiB of that block
+    unsplit."""
+    r = (max(int(nbytes), 1) + 511) // 512 * 512
+    return r + ((1 << 20) if r > (1 << 20) else 0)
+
+
+def specs_block_bytes(specs: Dict[str, tuple]) -> int:
+    """Allocator-charged bytes (block_bytes) of a set of buffer specs."""
+    return sum(block_bytes(math.prod(shape) * _ITEMSIZE[dt]) for shape, dt in specs.values())
+
+
+class DeviceArena:
+    """Grow-only device buffers that successive plans reuse (serving keeps one
+    per stream): a plan takes each of its buffers as a view of the arena's
+    buffer of the same name, which is reallocated only when it is too small.
+    A plan built on an arena must be done with (its results copied out)
+    before the next plan takes the same arena."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.bufs: Dict[str, torch.Tensor] = {}
+        self.allocations = 0  # buffers allocated (first use or growth) so far
+
+    def take(self, name: str, shape: tuple, dtype) -> torch.Tensor:
+        numel = math.prod(shape)
+        b = self.bufs.get(name)
+        if b is None or b.dtype != dtype or b.numel() < numel:
+            self.bufs.pop(name, None)  # freed first: the old and new buffer are never both held
+            b = torch.empty(numel, dtype=dtype, device=self.device)
+            self.bufs[name] = b
+            self.allocations += 1
+        return b[:numel].view(shape)
+
+    def nbytes(self) -> int:
+        """Allocator-charged bytes (block_bytes) of the buffers held."""
+        return sum(block_bytes(b.numel() * b.element_size()) for b in self.bufs.values())
+
+    def nbytes_after(self, specs: Dict[str, tuple]) -> int:
+        """Allocator-charged bytes held once a plan with these buffer specs
+        has taken its buffers."""
+        held = {n: b.numel() * b.element_size() for n, b in self.bufs.items()}
+        for n, (shape, dt) in specs.items():
+            held[n] = max(held.get(n, 0), math.prod(shape) * _ITEMSIZE[dt])
+        return sum(block_bytes(v) for v in held.values())
+
+    def release(self):
+        self.bufs.clear()
+
+
 @dataclass
 class ViewLayout:
     width: int
@@ -184,7 +262,9 @@ class RenderPlan:
     per-step calls."""
 
     def __init__(self, scenes: Sequence[DeviceScene], cams: Sequence, scene_of_view: Optional[Sequence[int]] = None,
-                 pair_capacity: Optional[int] = None, device="cuda", want_keys=False, abs_mean2d=False):
+                 pair_capacity: Optional[int] = None, device="cuda", want_keys=False, abs_mean2d=False,
+                 arena: Optional[DeviceArena] = None):
+        self.arena = arena
         self.scenes = list(scenes)
         # backward flags: abs_mean2d adds the AbsGS per-pixel absolute mean gradients to grad2d
         self.grad_flags = _lib.GRAD_ABS_MEAN2D if abs_mean2d else 0
@@ -203,29 +283,23 @@ class RenderPlan:
             pix += c.width * c.height
             tiles += ((c.width + TILE - 1) // TILE) * ((c.height + TILE - 1) // TILE)
         self.items, self.pixels, self.tiles = items, pix, tiles
-        rf = _lib.gabsplat_record_floats(self.k)
-        self.rec = torch.empty((max(items, 1), rf), dtype=torch.float32, device=device)
-        self.depth = torch.empty(max(items, 1), dtype=torch.float32, device=device)
-        self.rect = torch.empty((max(items, 1), 2), dtype=torch.int32, device=device)
-        self.tiles_touched = torch.empty(max(items, 1), dtype=torch.int32, device=device)
-        vb = _lib.gabsplat_views_bytes(len(self.cams), len(self.scenes))
-        self.views = torch.empty((vb + 15) // 16 * 4, dtype=torch.int32, device=device)
+        self.want_keys = want_keys
+        self.capacity = int(pair_capacity if pair_capacity is not None else max(1 << 16, 8 * items))
+        specs = plan_buffer_specs(self.k, items, pix, tiles, len(self.cams), len(self.scenes), self.capacity,
+                                  want_keys)
+        for name, (shape, dt) in specs.items():
+            setattr(self, name, self._take(name, shape, dt))
+        # [tiles][2] ranges, then the blend's dispatch order of the tiles
+        self.ranges = self.ranges_buf[:2 * max(tiles, 1)].view(max(tiles, 1), 2)
+        self.num_pairs.zero_()
+        self.overflow.zero_()
+        if not want_keys:
+            self.keys = None
         self.geom = _lib.Geom()
         self.geom.k = self.k
         self.geom.rec, self.geom.depth = _lib.ptr(self.rec), _lib.ptr(self.depth)
         self.geom.rect, self.geom.tiles = _lib.ptr(self.rect), _lib.ptr(self.tiles_touched)
         self.geom.views = _lib.ptr(self.views)
-        # [tiles][2] ranges, then the blend's dispatch order of the tiles
-        self.ranges_buf = torch.empty(3 * max(tiles, 1), dtype=torch.int32, device=device)
-        self.ranges = self.ranges_buf[:2 * max(tiles, 1)].view(max(tiles, 1), 2)
-        self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
-        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
-        self.image = torch.empty(max(3 * pix, 1), dtype=torch.float32, device=device)
-        self.final_T = torch.empty(max(pix, 1), dtype=torch.float32, device=device)
-        self.n_contrib = torch.empty(max(pix, 1), dtype=torch.int32, device=device)
-        self.want_keys = want_keys
-        self.capacity = 0
-        self._alloc_pairs(pair_capacity if pair_capacity is not None else max(1 << 16, 8 * items))
         self.grad2d = None
         # bumped by every stage that rewrites the buffers a backward reads
         # (records, pair lists, final_T, n_contrib); an autograd graph keeps
@@ -246,13 +320,25 @@ class RenderPlan:
         self.scenes[index] = scene
         self.c_scenes[index] = scene.cstruct()
 
+    def _take(self, name: str, shape: tuple, dtype) -> torch.Tensor:
+        if self.arena is not None:
+            return self.arena.take(name, shape, dtype)
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def buffer_specs(self, capacity: Optional[int] = None) -> Dict[str, tuple]:
+        """This plan's buffer specs (plan_buffer_specs), at another pair
+        capacity if given."""
+        return plan_buffer_specs(self.k, self.items, self.pixels, self.tiles, len(self.cams), len(self.scenes),
+                                 self.capacity if capacity is None else capacity, self.want_keys)
+
     def _alloc_pairs(self, cap: int):
         cap = int(cap)
         self.capacity = cap
-        self.vals = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
-        self.keys = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device) if self.want_keys else None
-        wsb = _lib.gabsplat_bin_sort_workspace_size(self.items, cap, self.tiles)
-        self.ws = torch.empty((wsb + 255) // 256 * 64, dtype=torch.int32, device=self.device)
+        specs = self.buffer_specs(cap)
+        for name in ("vals", "keys", "ws"):
+            if name in specs:
+                setattr(self, name, None)  # the old buffer is freed before the larger one is taken
+                setattr(self, name, self._take(name, *specs[name]))
 
     # ----- stages
     def preprocess(self, stream=None):

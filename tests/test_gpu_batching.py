@@ -91,6 +91,37 @@ def test_serving_mix_equals_alone(gpu_lib):
         assert torch.equal(alone[:mixed.numel()], mixed), r.rid
 
 
+def test_serving_device_memory_within_budget(gpu_lib):
+    """The scheduler charges the bytes its executor really holds: with a
+    budget of three of the largest single-request footprints, the device
+    memory the allocator reports at the peak of the run (resident scenes
+    excluded) stays within the budget, every batch's plan fits in the arena
+    it took its buffers from, and later batches reuse those buffers."""
+    from paper_2508_05343_amd.rasterize import DeviceScene
+    from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
+    scenes = [synth.clustered_scene(3200 + s, n, k=4, sh_degree=3) for s, n in enumerate((20000, 60000))]
+    dss = [DeviceScene.from_host(s) for s in scenes]
+    reqs = synth.config5_requests(scenes, n_requests=48, qps=20000.0, seed=11,
+                                  resolutions=((64, 64), (128, 96), (200, 160)))
+    jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
+    sizes = [s.n for s in scenes]
+    ex = GpuExecutor(dss, 2)
+    sch0 = Scheduler(sizes, 1 << 40)
+    one = max(ex.bytes_for([j], sch0.estimates([j])) for j in jobs)
+    budget = 3 * one
+    sch = Scheduler(sizes, budget, max_slots=16, max_batch=8, max_inflight=2)
+    st = serve(jobs, ex, sch)
+    print(f"budget {budget} charged {st.max_bytes_in_use} measured {st.peak_bytes_measured} "
+          f"batches {st.batches} allocations {sum(a.allocations for a in ex.arenas)}")
+    assert st.requests == 48 and sch.slots_used == 0
+    assert 0 < st.peak_bytes_measured <= budget
+    assert st.max_bytes_in_use <= budget
+    assert len(ex.batch_bytes) == st.batches
+    for plan_bytes, arena_bytes in ex.batch_bytes:
+        assert plan_bytes <= arena_bytes
+    assert sum(a.allocations for a in ex.arenas) < 14 * st.batches
+
+
 def test_serving_alone_matches_oracle(gpu_lib):
     """A served request (different scene per job in one launch) matches the
     oracle render of its own scene and camera."""

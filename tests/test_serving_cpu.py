@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import synth
-from paper_2508_05343_amd.serving import FakeExecutor, Job, Scheduler, scratch_bytes, serve
+from paper_2508_05343_amd.serving import FakeExecutor, Job, Scheduler, serve
 
 
 class VClock:
@@ -35,24 +35,27 @@ def trace(n=120, qps=400.0, seed=3, sizes=(1000, 5000, 20000)):
 def test_all_requests_complete_in_fifo_batches_within_budget():
     jobs, sizes = trace()
     clk = VClock()
-    ex = FakeExecutor(clk, n_streams=2)
-    budget = 8 * scratch_bytes(20000, 256 * 256, 200000)
+    ex = FakeExecutor(clk, n_streams=2, scene_sizes=sizes)
+    budget = 8 * ex.bytes_for(jobs[:1], [200000])
     sch = Scheduler(sizes, budget, max_slots=16, max_batch=8, max_inflight=2)
     st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
     assert st.requests == len(jobs) and len(st.latencies_ms) == len(jobs)
     assert st.max_bytes_in_use <= budget
-    assert sch.in_use == 0 and sch.slots_used == 0
+    assert 0 < st.peak_bytes_measured <= budget
+    assert sch.slots_used == 0
     order = [r for b in ex.submitted for r in b]
     assert order == sorted(order), "admission is FIFO"
     assert all(len(b) <= 8 for b in ex.submitted)
     assert all(j.done_s >= j.arrival_s for j in jobs)
     assert st.max_inflight_jobs <= 16
+    s = st.summary()
+    assert s["batches"] == len(ex.submitted) and s["host_ms_per_batch_p50"] == 0.0
 
 
 def test_requests_arriving_during_a_batch_join_the_next_one():
     jobs, sizes = trace(n=60, qps=5000.0)
     clk = VClock()
-    ex = FakeExecutor(clk, n_streams=1, fixed_s=0.01)
+    ex = FakeExecutor(clk, n_streams=1, fixed_s=0.01, scene_sizes=sizes)
     sch = Scheduler(sizes, 1 << 40, max_slots=64, max_batch=64, max_inflight=1)
     serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
     # with one stream busy for 10 ms, later arrivals accumulate into large batches
@@ -61,14 +64,20 @@ def test_requests_arriving_during_a_batch_join_the_next_one():
 
 
 def test_small_budget_defers_but_never_overcommits():
+    """Budget for about one and a half of the largest jobs: the held bytes
+    (buffers kept per stream between batches) never exceed it, idle streams
+    give theirs back so the next batch fits, and the work spreads over many
+    small batches."""
     jobs, sizes = trace(n=40)
     clk = VClock()
-    ex = FakeExecutor(clk, n_streams=4)
-    one = max(Scheduler(sizes, 1 << 40).job_bytes(j) for j in jobs)
-    sch = Scheduler(sizes, int(one * 1.5), max_slots=16, max_batch=16, max_inflight=4)
+    ex = FakeExecutor(clk, n_streams=4, scene_sizes=sizes)
+    sch0 = Scheduler(sizes, 1 << 40)
+    one = max(ex.bytes_for([j], sch0.estimates([j])) for j in jobs)
+    budget = int(one * 1.5)
+    sch = Scheduler(sizes, budget, max_slots=16, max_batch=16, max_inflight=4)
     st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
     assert st.requests == 40
-    assert st.max_bytes_in_use <= int(one * 1.5)
+    assert st.max_bytes_in_use <= budget and st.peak_bytes_measured <= budget
     # the budget holds at most a couple of jobs: work is spread over many batches
     assert st.batches >= 20
 
@@ -78,13 +87,50 @@ def test_request_larger_than_budget_is_rejected():
     clk = VClock()
     sch = Scheduler(sizes, 1000)
     with pytest.raises(ValueError):
-        serve(jobs, FakeExecutor(clk), sch, clock=clk, sleep=clk.sleep)
+        serve(jobs, FakeExecutor(clk, scene_sizes=sizes), sch, clock=clk, sleep=clk.sleep)
 
 
 def test_sequential_baseline_is_one_job_per_batch():
     jobs, sizes = trace(n=30)
     clk = VClock()
-    ex = FakeExecutor(clk, n_streams=1)
+    ex = FakeExecutor(clk, n_streams=1, scene_sizes=sizes)
     sch = Scheduler(sizes, 1 << 40, max_slots=1, max_batch=1, max_inflight=1)
     st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
     assert all(len(b) == 1 for b in ex.submitted) and st.batches == 30
+
+
+def test_pair_overflow_is_retried_with_grown_buffers_within_budget():
+    """A batch whose pair count outgrew its buffer is run again with larger
+    pair buffers once they fit; every request still completes and the held
+    bytes stay within the budget."""
+    jobs, sizes = trace(n=50)
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=2, scene_sizes=sizes, overflow_every=3)
+    sch0 = Scheduler(sizes, 1 << 40)
+    one = max(ex.bytes_for([j], [2 * e + 4096 for e in sch0.estimates([j])]) for j in jobs)
+    budget = 6 * one
+    sch = Scheduler(sizes, budget, max_slots=16, max_batch=4, max_inflight=2)
+    st = serve(jobs, ex, sch, clock=clk, sleep=clk.sleep)
+    assert st.requests == 50 and len(st.latencies_ms) == 50
+    assert st.retries >= 1
+    assert st.peak_bytes_measured <= budget and st.max_bytes_in_use <= budget
+    assert sch.slots_used == 0
+
+
+def test_idle_buffers_are_released_only_when_needed():
+    """Buffers stay with their stream between batches (no reallocation per
+    batch) until a batch on another stream needs the memory."""
+    sizes = [1000, 1000]
+    cam = synth.pinhole_camera(64, 64, 60.0, (0, 0, -3), (0, 0, 0))
+    clk = VClock()
+    ex = FakeExecutor(clk, n_streams=2, scene_sizes=sizes)
+    sch = Scheduler(sizes, 1 << 40)
+    j = [Job(0, 0, cam, 0.0)]
+    need = ex.bytes_for(j, sch.estimates(j))
+    h = ex.submit(j, sch.estimates(j), 0)
+    ex.release(h)
+    assert ex.bytes_held() == need  # kept for the next batch on stream 0
+    roomy = Scheduler(sizes, 3 * need)
+    assert roomy.fits(ex, 1, j, sch.estimates(j)) and ex.bytes_held() == need
+    tight = Scheduler(sizes, need + need // 2)
+    assert tight.fits(ex, 1, j, sch.estimates(j)) and ex.bytes_held() == 0
