@@ -224,7 +224,10 @@ class DeviceArena:
         numel = math.prod(shape)
         b = self.bufs.get(name)
         if b is None or b.dtype != dtype or b.numel() < numel:
-            self.bufs.pop(name, None)  # freed first: the old and new buffer are never both held
+            # the old buffer is dropped (its last reference included) before
+            # the new one is allocated: the two are never held together
+            b = None
+            self.bufs.pop(name, None)
             b = torch.empty(numel, dtype=dtype, device=self.device)
             self.bufs[name] = b
             self.allocations += 1

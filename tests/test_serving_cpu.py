@@ -134,3 +134,30 @@ def test_idle_buffers_are_released_only_when_needed():
     assert roomy.fits(ex, 1, j, sch.estimates(j)) and ex.bytes_held() == need
     tight = Scheduler(sizes, need + need // 2)
     assert tight.fits(ex, 1, j, sch.estimates(j)) and ex.bytes_held() == 0
+
+
+def test_arena_frees_a_buffer_before_growing_it(monkeypatch):
+    """When a buffer of a DeviceArena grows, the old one has lost its last
+    reference before the new one is allocated, so the two never coexist
+    (the bytes the serving scheduler charges are then the allocator's peak)."""
+    import weakref
+
+    import torch
+
+    from paper_2508_05343_amd.rasterize import DeviceArena
+    ar = DeviceArena(device="cpu")
+    small = ar.take("vals", (100,), torch.int32)
+    old = weakref.ref(ar.bufs["vals"])
+    del small
+    seen = []
+    real_empty = torch.empty
+
+    def empty(*a, **kw):
+        seen.append(old() is None)
+        return real_empty(*a, **kw)
+    monkeypatch.setattr(torch, "empty", empty)
+    big = ar.take("vals", (1000,), torch.int32)
+    assert seen == [True] and big.numel() == 1000 and ar.allocations == 2
+    again = ar.take("vals", (500,), torch.int32)  # fits: reused, no allocation
+    assert seen == [True] and ar.allocations == 2 and again.data_ptr() == big.data_ptr()
+    assert ar.nbytes() == 4096 and ar.nbytes_after({"vals": ((2000,), torch.int32)}) == 8192
