@@ -717,6 +717,35 @@ __device__ __forceinline__ int order_bucket(uint32_t len) {
   return b < kOrderBuckets ? b : kOrderBuckets - 1;
 }
 
+// Bucket counts -> bucket starts, longest bucket first: an exclusive scan of
+// s_cnt in decreasing bucket order by the first wavefront (three buckets per
+// lane, one shuffle scan).  The caller brackets it with barriers.
+__device__ __forceinline__ void order_bucket_starts(uint32_t* s_cnt) {
+  static_assert(kOrderBuckets <= 3 * 64, "three buckets per lane");
+  if (threadIdx.x >= 64) return;
+  const int l = threadIdx.x;
+  uint32_t c[3], sum = 0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int b = kOrderBuckets - 1 - (3 * l + r);
+    c[r] = b >= 0 ? s_cnt[b] : 0u;
+    sum += c[r];
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, 64);
+    if (l >= d) inc += o;
+  }
+  uint32_t run = inc - sum;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int b = kOrderBuckets - 1 - (3 * l + r);
+    if (b >= 0) s_cnt[b] = run;
+    run += c[r];
+  }
+}
+
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
                                                               const uint32_t* __restrict__ counters,
                                                               uint32_t* __restrict__ order) {
@@ -728,14 +757,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
   for (int i = t; i < ntiles; i += kOrderThreads)
     atomicAdd(&s_cnt[order_bucket(ranges[2 * (size_t)i + 1] - ranges[2 * (size_t)i])], 1u);
   __syncthreads();
-  if (t == 0) {  // bucket starts, longest bucket first
-    uint32_t run = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      const uint32_t c = s_cnt[b];
-      s_cnt[b] = run;
-      run += c;
-    }
-  }
+  order_bucket_starts(s_cnt);
   __syncthreads();
   for (int i = t; i < ntiles; i += kOrderThreads) {
     const int b = order_bucket(ranges[2 * (size_t)i + 1] - ranges[2 * (size_t)i]);
@@ -924,45 +946,77 @@ __global__ __launch_bounds__(256) void k_tc_colscan(uint32_t* __restrict__ cnt, 
 
 // One block: exclusive scan of the tile totals -> tile starts, ranges ((0, 0)
 // for empty tiles), pair count and overflow flag; then the dispatch order of
-// the segment sort and the blend (as k_tile_order) after the ranges.
-__global__ __launch_bounds__(kSortThreads) void k_tc_tilescan(const uint32_t* __restrict__ tot, int ntiles,
+// the segment sort and the blend (as k_tile_order) after the ranges.  The
+// totals are staged in LDS with coalesced loads; each thread then scans
+// kTileScanPer consecutive tiles held in registers (no dependent global loads)
+// and the starts and ranges go out coalesced from LDS again.
+constexpr int kTileScanThreads = 1024;
+constexpr int kTileScanPer = kTcMaxTiles / kTileScanThreads;
+__global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(const uint32_t* __restrict__ tot, int ntiles,
                                                              uint32_t capacity, uint32_t* __restrict__ tstart,
                                                              uint32_t* __restrict__ ranges,
                                                              uint32_t* __restrict__ counters,
                                                              int64_t* __restrict__ d_num_pairs,
                                                              int32_t* __restrict__ d_overflow) {
-  __shared__ uint32_t s_wave[kSortThreads / 64];
-  const int t = threadIdx.x;
-  const int per = (ntiles + kSortThreads - 1) / kSortThreads;
-  const int t0 = min(ntiles, t * per), t1 = min(ntiles, t0 + per);
-  uint32_t sum = 0;
-  for (int i = t0; i < t1; ++i) sum += tot[i];
-  uint32_t total;
-  uint32_t run = block_excl_scan(sum, s_wave, &total);
-  for (int i = t0; i < t1; ++i) {
-    const uint32_t c = tot[i];
-    tstart[i] = run;
-    ranges[2 * (size_t)i] = c ? run : 0u;
-    ranges[2 * (size_t)i + 1] = c ? run + c : 0u;
-    run += c;
-  }
-  // dispatch order: tiles by decreasing length bucket
+  __shared__ uint32_t s_v[kTcMaxTiles];
+  __shared__ uint32_t s_wave[kTileScanThreads / 64];
   __shared__ uint32_t s_cnt[kOrderBuckets];
-  for (int b = t; b < kOrderBuckets; b += kSortThreads) s_cnt[b] = 0;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r) {
+    const int i = r * kTileScanThreads + t;
+    if (i < ntiles) s_v[i] = tot[i];
+  }
+  for (int b = t; b < kOrderBuckets; b += kTileScanThreads) s_cnt[b] = 0;
   __syncthreads();
-  for (int i = t0; i < t1; ++i) atomicAdd(&s_cnt[order_bucket(tot[i])], 1u);
+  const int i0 = t * kTileScanPer;
+  uint32_t c[kTileScanPer], sum = 0;
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r) {
+    c[r] = i0 + r < ntiles ? s_v[i0 + r] : 0u;
+    sum += c[r];
+  }
+  // tiles per length bucket (dispatch order, longest bucket first)
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r)
+    if (i0 + r < ntiles) atomicAdd(&s_cnt[order_bucket(c[r])], 1u);
+  uint32_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, 64);
+    if (l >= d) inc += o;
+  }
+  if (l == 63) s_wave[w] = inc;
   __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      const uint32_t c = s_cnt[b];
-      s_cnt[b] = acc;
-      acc += c;
-    }
+  uint32_t run = inc - sum, total = 0;
+#pragma unroll
+  for (int q = 0; q < kTileScanThreads / 64; ++q) {
+    const uint32_t x = s_wave[q];
+    run += q < w ? x : 0u;
+    total += x;
+  }
+  order_bucket_starts(s_cnt);
+  // every read of the totals in s_v is done: the starts replace them
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r) {
+    if (i0 + r < ntiles) s_v[i0 + r] = run;
+    run += c[r];
   }
   __syncthreads();
   uint32_t* order = ranges + 2 * (size_t)ntiles;
-  for (int i = t0; i < t1; ++i) order[atomicAdd(&s_cnt[order_bucket(tot[i])], 1u)] = (uint32_t)i;
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r)
+    if (i0 + r < ntiles) order[atomicAdd(&s_cnt[order_bucket(c[r])], 1u)] = (uint32_t)(i0 + r);
+#pragma unroll
+  for (int r = 0; r < kTileScanPer; ++r) {
+    const int i = r * kTileScanThreads + t;
+    if (i < ntiles) {
+      const uint32_t st = s_v[i], nx = i + 1 < ntiles ? s_v[i + 1] : total;
+      tstart[i] = st;
+      ranges[2 * (size_t)i] = nx > st ? st : 0u;
+      ranges[2 * (size_t)i + 1] = nx > st ? nx : 0u;
+    }
+  }
   if (t == 0) {
     const uint32_t ov = total > capacity ? 1u : 0u;
     counters[C_NUM_PAIRS] = total;
@@ -1228,7 +1282,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
       hipLaunchKernelGGL(k_tc_colscan, dim3((unsigned)((nt + kColTiles - 1) / kColTiles)), dim3(256), 0, s, cnt, nt,
                          tot);
     }
-    hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kSortThreads), 0, s, tot, nt, (uint32_t)p.capacity, tstart,
+    hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kTileScanThreads), 0, s, tot, nt, (uint32_t)p.capacity, tstart,
                        ranges, counters, d_num_pairs, d_overflow);
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
