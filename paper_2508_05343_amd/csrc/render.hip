@@ -32,9 +32,8 @@ __device__ __forceinline__ int find_view_by_tile(const ViewEntry* views, int nv,
   return lo;
 }
 
-// cos(2 pi x) and sin(2 pi x); the hardware units take revolutions
+// cos(2 pi x) of any x; the hardware unit takes revolutions
 __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(x)); }
-__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(x)); }
 // 2^x on the hardware unit.  Every result that is used has x >= log2(1/255);
 // lanes with smaller x (whose results are discarded) get 0 or a denormal.
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -83,19 +82,34 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float ox
 // m = (mu_x - ox, mu_y - oy) is the mean in the tile's frame, and a pixel with
 // in-tile centre (u, v) = (px - ox + 0.5, py - oy + 0.5) sits at the offset
 // d = (u, v) - m from it.  The envelope exponent q(d) + log2 o is evaluated as
-// dx (A dx + B dy) + C dy^2 + log2 o and the phase of component k as
-// fx_k dx + fy_k dy, both at the offset itself: expanded around the tile
-// origin instead, the constant term A |m|^2 of a sharp footprint centred far
-// from the origin cancels against the pixel terms and leaves errors of ~1e-5
-// of the result.  Floats (3 + K float4s):
-//   [A B C log2o] [m_x m_y 0 0] [r g b w0] then per component [fx fy w' 0].
+// dx (A dx + B dy) + C dy^2 + log2 o at the offset itself: expanded around the
+// tile origin instead, the constant term A |m|^2 of a sharp footprint centred
+// far from the origin cancels against the pixel terms and leaves errors of
+// ~1e-5 of the result.
+//
+// The phase f_k . d of component k (cycles) is evaluated as
+// f_k . (p - c) + phi_k, with p - c = (u - 8, v - 8) the pixel centre's offset
+// from the tile centre (at most 7.5 per axis) and phi_k = f_k . (c - m)
+// reduced to [-1/2, 1/2]: equal to f_k . d up to a whole number of cycles,
+// and to the same rounding (phi_k carries the large part, rounded once).  The
+// hardware cosine and sine take revolutions and reduce them exactly, so these
+// small phases need no fract() per pixel; a record whose
+// 7.5 (|fx| + |fy|) + 1/2 could leave kPhaseRaw ("wide") has its phases
+// reduced per pixel all the same.  Floats (3 + K float4s):
+//   [A B C log2o] [m_x m_y 0 0] [r g b w0] then per component [fx fy w' phi].
 template <int K>
 struct Staged {
   static constexpr int S4 = 3 + K;
 };
 
+constexpr float kTileHalf = 0.5f * kTile;
+constexpr float kPhaseRaw = 250.0f;
+// bit of the staged quadrant mask that flags a wide record
+constexpr uint32_t kWideBit = 16u;
+
+// Stages record q for the tile at (ox, oy) into dst; returns whether it is wide.
 template <int K>
-__device__ __forceinline__ void stage_record(const float4* q, float ox, float oy, float4* dst) {
+__device__ __forceinline__ bool stage_record(const float4* q, float ox, float oy, float4* dst) {
   // record fields (gabsplat_geom.rec): mu 0-1, conic terms 2-4, log2 o 5,
   // rgb 6-8, w0 9, component k at 10 + 3k (fx, fy, w'), then the residuals
   // of the mean's float32 rounding
@@ -114,8 +128,15 @@ __device__ __forceinline__ void stage_record(const float4* q, float ox, float oy
   dst[0] = make_float4(f[2], f[3], f[4], f[5]);
   dst[1] = make_float4(mx, my, 0.f, 0.f);
   dst[2] = make_float4(f[6], f[7], f[8], f[9]);
+  bool wide = false;
 #pragma unroll
-  for (int k = 0; k < K; ++k) dst[3 + k] = make_float4(f[10 + 3 * k], f[11 + 3 * k], f[12 + 3 * k], 0.f);
+  for (int k = 0; k < K; ++k) {
+    const float fx = f[10 + 3 * k], fy = f[11 + 3 * k];
+    const float c = fmaf(fx, kTileHalf - mx, fy * (kTileHalf - my));
+    wide = wide || !(fmaf(kTileHalf - 0.5f, fabsf(fx) + fabsf(fy), 0.5f) <= kPhaseRaw);
+    dst[3 + k] = make_float4(fx, fy, f[12 + 3 * k], c - rintf(c));
+  }
+  return wide;
 }
 
 // Envelope exponent q(d) + log2 o of a staged record at the offset d = (dx, dy)
@@ -125,8 +146,9 @@ __device__ __forceinline__ float staged_power(float4 s0, float dx, float dy) {
   return fmaf(dx, fmaf(s0.x, dx, s0.y * dy), fmaf(s0.z * dy, dy, s0.w));
 }
 
-// Phase (cycles) f . d of a staged component (fx, fy, w') at the offset d.
-__device__ __forceinline__ float staged_phase(float4 c, float dx, float dy) { return fmaf(c.x, dx, c.y * dy); }
+// Phase (cycles, up to whole cycles) of a staged component (fx, fy, w', phi)
+// at the pixel whose centre is (pu, pv) from the tile centre.
+__device__ __forceinline__ float staged_phase(float4 c, float pu, float pv) { return fmaf(c.x, pu, fmaf(c.y, pv, c.w)); }
 
 // --------------------------------------------------------------------- K6
 // The ANALYSIS variant (never the timed one) can also report, per pixel, how
@@ -163,6 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
   const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
+  const float pu = u - kTileHalf, pv = v - kTileHalf;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
 
@@ -179,8 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
       float4 q[R4];
 #pragma unroll
       for (int j = 0; j < R4; ++j) q[j] = src[j];
-      stage_record<K>(q, ox, oy, &s_rec[t * S4]);
-      m = quadrant_mask(q[0], q[1], ox, oy);
+      const bool wide = stage_record<K>(q, ox, oy, &s_rec[t * S4]);
+      m = quadrant_mask(q[0], q[1], ox, oy) | (wide ? kWideBit : 0u);
     }
     if (t < kBatchFwd) s_mask[t] = m;
     __syncthreads();
@@ -190,9 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
       // the chunk only makes the skip test below less strict)
       const uint64_t act = __builtin_amdgcn_ballot_w64(!done);
       if (act == 0ull) break;
-      uint64_t bits = __ballot(c0 + l < cnt && ((s_mask[c0 + l] >> w) & 1u));
+      const uint32_t ml = c0 + l < cnt ? s_mask[c0 + l] : 0u;
+      uint64_t bits = __ballot((ml >> w) & 1u);
+      const uint64_t wide_bits = __ballot((ml & kWideBit) != 0u);
       while (bits) {
-        const int j = c0 + __builtin_ctzll(bits);
+        const int jj = __builtin_ctzll(bits);
+        const int j = c0 + jj;
+        const bool wide = (wide_bits >> jj) & 1ull;
         bits &= bits - 1;
         const float4 s0 = s_rec[j * S4], s1 = s_rec[j * S4 + 1];
         const float dx = u - s1.x, dy = v - s1.y;
@@ -206,10 +233,18 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         // straight-line update: lanes that do not take the record keep their state
         const float E = exp2_hw(pw);
         float Bv = col.w;
+        if (wide) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float4 c = s_rec[j * S4 + 3 + k];
-          Bv = fmaf(c.z, cos_rev(staged_phase(c, dx, dy)), Bv);
+          for (int k = 0; k < K; ++k) {
+            const float4 c = s_rec[j * S4 + 3 + k];
+            Bv = fmaf(c.z, cos_rev(staged_phase(c, pu, pv)), Bv);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float4 c = s_rec[j * S4 + 3 + k];
+            Bv = fmaf(c.z, __builtin_amdgcn_cosf(staged_phase(c, pu, pv)), Bv);
+          }
         }
         const float alpha = fminf(kAlphaMax, E * Bv);
         live = live && !(alpha < kAlphaMin);
@@ -386,6 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
   const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   const bool inside = px < V.width && py < V.height;
   const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
+  const float pu = u - kTileHalf, pv = v - kTileHalf;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
   const uint32_t start = ranges[2 * (size_t)tile];
   bool red_writer;
@@ -429,17 +465,20 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
       float4 q[R4];
 #pragma unroll
       for (int j = 0; j < R4; ++j) q[j] = src[j];
-      stage_record<K>(q, ox, oy, &s_rec[t * S4]);
-      m = quadrant_mask(q[0], q[1], ox, oy);
+      const bool wide = stage_record<K>(q, ox, oy, &s_rec[t * S4]);
+      m = quadrant_mask(q[0], q[1], ox, oy) | (wide ? kWideBit : 0u);
     }
     if (t < kBatchBwd) s_mask[t] = m;
     __syncthreads();
     // chunks of 64 records, newest first; records past the wave's last contributor are skipped
     for (int c0 = ((int)cnt - 1) & ~63; c0 >= 0; c0 -= 64) {
       const uint32_t pos_l = lo + (uint32_t)(c0 + l) + 1;
-      uint64_t bits = __ballot(c0 + l < (int)cnt && pos_l <= wlast && ((s_mask[c0 + l] >> w) & 1u));
+      const uint32_t ml = c0 + l < (int)cnt && pos_l <= wlast ? s_mask[c0 + l] : 0u;
+      uint64_t bits = __ballot((ml >> w) & 1u);
+      const uint64_t wide_bits = __ballot((ml & kWideBit) != 0u);
       while (bits) {
         const int hb = 63 - __builtin_clzll(bits);
+        const bool wide = (wide_bits >> hb) & 1ull;
         bits &= ~(1ull << hb);
         const int j = __builtin_amdgcn_readfirstlane(c0 + hb);  // wave-uniform: scalar addressing
         const uint32_t pos = lo + (uint32_t)j + 1;
@@ -457,13 +496,23 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const void* __restrict__ 
         const float E = exp2_hw(pw);
         float cs[K > 0 ? K : 1], sn[K > 0 ? K : 1];
         float Bv = col.w;
+        if (wide) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float fr = __builtin_amdgcn_fractf(staged_phase(cc[k], dx, dy));
-          cs[k] = __builtin_amdgcn_cosf(fr);
-          sn[k] = __builtin_amdgcn_sinf(fr);
-          Bv = fmaf(cc[k].z, cs[k], Bv);
+          for (int k = 0; k < K; ++k) {
+            const float fr = __builtin_amdgcn_fractf(staged_phase(cc[k], pu, pv));
+            cs[k] = __builtin_amdgcn_cosf(fr);
+            sn[k] = __builtin_amdgcn_sinf(fr);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float ph = staged_phase(cc[k], pu, pv);
+            cs[k] = __builtin_amdgcn_cosf(ph);
+            sn[k] = __builtin_amdgcn_sinf(ph);
+          }
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) Bv = fmaf(cc[k].z, cs[k], Bv);
         const float EB = E * Bv;
         const float alpha = fminf(kAlphaMax, EB);
         // the ballot of the alpha compare alone, masked in scalar registers
