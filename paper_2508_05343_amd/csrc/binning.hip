@@ -875,8 +875,11 @@ __device__ __forceinline__ void for_each_pair(const ViewEntry* views, int nv, co
 }
 
 // The items are split into kTcBlocks contiguous ranges, one per block of the
-// histogram and scatter kernels (the same ranges in both).
+// histogram and scatter kernels (the same ranges in both).  The number of
+// blocks sets the size of the count matrix (kTcBlocks x tiles); wide blocks
+// keep enough wavefronts in flight to cover the load latency of their items.
 constexpr int kTcBlocks = 512;
+constexpr int kTcThreads = 1024;
 
 __device__ __forceinline__ void tc_item_range(int64_t items, int64_t* i0, int64_t* i1) {
   const int64_t per = (items + kTcBlocks - 1) / kTcBlocks;
@@ -885,7 +888,7 @@ __device__ __forceinline__ void tc_item_range(int64_t items, int64_t* i0, int64_
 }
 
 // Per-block tile histograms in LDS, written as row blockIdx.x of cnt[kTcBlocks][T].
-__global__ __launch_bounds__(256) void k_tc_hist(const void* __restrict__ table, int64_t items,
+__global__ __launch_bounds__(kTcThreads) void k_tc_hist(const void* __restrict__ table, int64_t items,
                                                  const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rect,
                                                  int ntiles, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t s_h[kTcMaxTiles];
@@ -1030,7 +1033,7 @@ __global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(const uint32_t
 // key (depth bits << 32 | item): block b owns the positions tstart[t] +
 // cnt[b][t] onwards of each tile (LDS cursors, so the order inside a segment
 // is arbitrary; the segment sort fixes it).
-__global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ table, int64_t items,
+__global__ __launch_bounds__(kTcThreads) void k_tc_scatter(const void* __restrict__ table, int64_t items,
                                                     const uint32_t* __restrict__ tiles,
                                                     const uint32_t* __restrict__ rect,
                                                     const uint32_t* __restrict__ depth_bits, int ntiles,
@@ -1057,13 +1060,13 @@ __global__ __launch_bounds__(256) void k_tc_scatter(const void* __restrict__ tab
 
 
 // Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of x
-// into out at o0, by the whole block (each lane a contiguous slice of the
+// into out at o0, by one wavefront (each lane a contiguous slice of the
 // output, split points by merge-path binary search; keys are unique).
-__device__ void block_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
-                            uint64_t* __restrict__ out, uint32_t o0) {
+__device__ void wave_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
+                           uint64_t* __restrict__ out, uint32_t o0) {
   const uint32_t n = na + nb;
-  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-  const uint32_t d0 = min(n, threadIdx.x * per), d1 = min(n, d0 + per);
+  const uint32_t per = (n + 63) / 64;
+  const uint32_t d0 = min(n, (uint32_t)__lane_id() * per), d1 = min(n, d0 + per);
   if (d0 >= d1) return;
   uint32_t lo = d0 > nb ? d0 - nb : 0u, hi = min(d0, na);
   while (lo < hi) {  // number of elements of a among the first d0 outputs
@@ -1088,7 +1091,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
 
 template <int E>
 __device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
-  const int lane = threadIdx.x;
+  const int lane = __lane_id();
   constexpr int N = 64 * E;
 #pragma unroll
   for (int k = 2; k <= N; k <<= 1) {
@@ -1126,7 +1129,7 @@ template <int E, bool TO_VALS>
 __device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ pa, uint32_t start, uint32_t n,
                                                uint32_t tile, uint32_t* __restrict__ vals,
                                                uint64_t* __restrict__ keys) {
-  const int lane = threadIdx.x;
+  const int lane = __lane_id();
   uint64_t x[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1148,23 +1151,37 @@ __device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ pa, uint32
   }
 }
 
-// One wavefront per tile: sorts the tile's segment of (depth bits, item) keys
-// and writes the item ids to vals (and the 64-bit keys when asked for).
-// Segments of up to kSegCap pairs are sorted in registers; longer ones as
-// register-sorted runs of kSegCap merged pairwise through the ping-pong
-// buffer pb.
-__global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
-                                                const uint32_t* __restrict__ counters, uint64_t* __restrict__ pa,
-                                                uint64_t* __restrict__ pb, uint32_t* __restrict__ vals,
-                                                uint64_t* __restrict__ keys) {
+// Global-memory writes of one wavefront made visible to its own later reads
+// from other lanes (a workgroup-scope release and acquire around the point
+// where the lanes trade data).
+__device__ __forceinline__ void wave_memory_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wavefront per tile, kSortWaves tiles per workgroup (independent
+// wavefronts, no barrier), tiles in the blend's dispatch order (longest
+// first): sorts the tile's segment of (depth bits, item) keys and writes the
+// item ids to vals (and the 64-bit keys when asked for).  Segments of up to
+// kSegCap pairs are sorted in registers; longer ones as register-sorted runs
+// of kSegCap merged pairwise through the ping-pong buffer pb.
+constexpr int kSortWaves = 4;
+__global__ __launch_bounds__(64 * kSortWaves) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
+                                                            const uint32_t* __restrict__ counters,
+                                                            uint64_t* __restrict__ pa, uint64_t* __restrict__ pb,
+                                                            uint32_t* __restrict__ vals,
+                                                            uint64_t* __restrict__ keys) {
+  const int slot = (int)blockIdx.x * kSortWaves + (int)(threadIdx.x >> 6);
+  if (slot >= ntiles) return;
+  // the order is written whether or not the pairs overflowed: read it
+  // alongside the overflow flag
+  const int tile = (int)ranges[2 * (size_t)ntiles + slot];
   if (counters[C_OVERFLOW]) return;
-  if ((int)blockIdx.x >= ntiles) return;
-  // longest segments first (the blend's dispatch order, after the ranges)
-  const int tile = (int)ranges[2 * (size_t)ntiles + blockIdx.x];
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
   const uint32_t n = end - start;
   if (n == 0) return;
-  const int t = threadIdx.x;
+  const int lane = __lane_id();
   static_assert(kSegCap == 1024, "register sort sizes");
   if (n <= 64) return tile_sort_regs<1, true>(pa, start, n, tile, vals, keys);
   if (n <= 128) return tile_sort_regs<2, true>(pa, start, n, tile, vals, keys);
@@ -1174,18 +1191,18 @@ __global__ __launch_bounds__(64) void k_tc_sort(const uint32_t* __restrict__ ran
   // long segment: sorted runs in place, then pairwise merges pa <-> pb
   for (uint32_t r0 = 0; r0 < n; r0 += kSegCap)
     tile_sort_regs<16, false>(pa, start + r0, min((uint32_t)kSegCap, n - r0), tile, vals, keys);
-  __syncthreads();
+  wave_memory_sync();
   uint64_t *src = pa, *dst = pb;
   for (uint32_t width = kSegCap; width < n; width <<= 1) {
     for (uint32_t lo = 0; lo < n; lo += 2 * width) {
       const uint32_t na = min(width, n - lo);
       const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
-      block_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo);
+      wave_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo);
     }
-    __syncthreads();
+    wave_memory_sync();
     uint64_t* tmp = src; src = dst; dst = tmp;
   }
-  for (uint32_t i = t; i < n; i += blockDim.x) {
+  for (uint32_t i = lane; i < n; i += 64) {
     const uint64_t x = src[start + i];
     vals[start + i] = (uint32_t)x;
     if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
@@ -1278,16 +1295,17 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     const int nt = p.total_tiles;
     // no counter clear: the tile scan writes the only counters this path reads
     if (nt > 0) {
-      hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
+      hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(kTcThreads), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
       hipLaunchKernelGGL(k_tc_colscan, dim3((unsigned)((nt + kColTiles - 1) / kColTiles)), dim3(256), 0, s, cnt, nt,
                          tot);
     }
     hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kTileScanThreads), 0, s, tot, nt, (uint32_t)p.capacity, tstart,
                        ranges, counters, d_num_pairs, d_overflow);
     if (nt > 0) {
-      hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(256), 0, s, g.views, p.items, g.tiles, g.rect,
+      hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(kTcThreads), 0, s, g.views, p.items, g.tiles, g.rect,
                          depth_bits, nt, cnt, tstart, counters, pa);
-      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)nt), dim3(64), 0, s, ranges, nt, counters, pa, pb, vals, keys);
+      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)((nt + kSortWaves - 1) / kSortWaves)), dim3(64 * kSortWaves), 0, s,
+                         ranges, nt, counters, pa, pb, vals, keys);
     }
     return hipGetLastError();
   }
