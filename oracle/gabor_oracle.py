@@ -582,11 +582,14 @@ def tile_candidates(pr: Projected, order: np.ndarray, tx: int, ty: int) -> np.nd
 
 def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binned",
            tiles: Optional[Sequence[tuple]] = None, scene_f32=None, pr: Optional[Projected] = None,
-           chunk: int = 4096, attenuation: bool = False, mip2d: bool = False, filter3d=None) -> Image:
+           chunk: int = 4096, attenuation: bool = False, mip2d: bool = False, filter3d=None,
+           tau_alpha: float = 1e-4, tau_T: float = 1e-3) -> Image:
     """Render the whole image (or only the listed tiles; other pixels are NaN).
     mode 'brute': every visible primitive at every pixel; 'binned': per-tile
     candidate lists from the tile rects (exact culling: the rect covers every
-    pixel where o G >= 1/255)."""
+    pixel where o G >= 1/255).  tau_alpha / tau_T: relative width of the
+    bands around the alpha and stop thresholds inside which a decision is
+    reported fragile (blend_pixels); they change no rendered value."""
     if pr is None:
         pr = project(p, cam, scene_f32, attenuation, mip2d, filter3d)
     W, H = cam["W"], cam["H"]
@@ -618,7 +621,7 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
     cols, fts, idxs, fms = [], [], [], []
     for gx, gy, cand in parts:
         res = blend_pixels(pr, cand, torch.from_numpy(gx + 0.5).to(DT),
-                           torch.from_numpy(gy + 0.5).to(DT), bg)
+                           torch.from_numpy(gy + 0.5).to(DT), bg, tau_alpha=tau_alpha, tau_T=tau_T)
         idx = gy * W + gx
         cols.append(res.color); fts.append(res.final_T); idxs.append(torch.from_numpy(idx)); fms.append(res.freq_map)
         last[idx] = res.last_id
@@ -639,11 +642,12 @@ def render(p: Dict[str, torch.Tensor], cam: Dict[str, object], mode: str = "binn
                  fbound.reshape(H, W))
 
 
-def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False, mip2d=False, filter3d=None) -> Image:
+def render_scene(scene, cam, mode="binned", tiles=None, attenuation=False, mip2d=False, filter3d=None,
+                 tau_alpha: float = 1e-4, tau_T: float = 1e-3) -> Image:
     """Convenience: numpy scene/camera objects -> fp64 image."""
     with torch.no_grad():
         return render(scene_tensors(scene), camera_tensors(cam), mode, tiles, scene_f32=scene,
-                      attenuation=attenuation, mip2d=mip2d, filter3d=filter3d)
+                      attenuation=attenuation, mip2d=mip2d, filter3d=filter3d, tau_alpha=tau_alpha, tau_T=tau_T)
 
 
 # --------------------------------------------------------------------------

@@ -7,7 +7,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, check_grads_elementwise, gpu_plan
+from gpu_helpers import assert_image, check_grads_elementwise, gpu_plan, oracle_project
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +80,39 @@ def test_forward_and_backward_every_component_count(gpu_lib, k):
     ref = O.render_scene(sc, cam, "binned")
     assert_image(plan.view_image(0).cpu().numpy(), ref, f"k{k}")
     _check_grads(sc, cam, 70 + k, scene_name=f"k{k}")
+
+
+def test_wide_frequency_records(gpu_lib):
+    """Records whose image-plane frequencies reach 45 cycles/px (|fx| + |fy|
+    above 33, so a tile's phases can leave [-256, 256] cycles) take the
+    blend's per-pixel phase reduction; the rest take the unreduced phases.
+    Both kinds in one frame: image and gradients against the oracle.  Phases
+    of ~340 cycles carry ~2e-5 cycles of float32 rounding (~1.3e-4 in a
+    cosine, up to ~3% of the 1/255 alpha threshold), so decisions within 5%
+    of a threshold are fragile here and the bounds are scaled to that error."""
+    sc = synth.uniform_scene(71, 300, 2, sh_degree=1, log_scale_mu=-2.6)
+    cam = synth.pinhole_camera(64, 48, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0), bg=(0.1, 0.2, 0.3))
+    pr = oracle_project(sc, cam)
+    m = np.abs(pr.f2d.numpy()).sum(-1).max(1)  # per primitive, max_k |fx| + |fy| (cycles/px)
+    sel = np.random.default_rng(0).random(sc.n) < 0.5
+    sc.freqs = (sc.freqs * np.where(sel, 45.0 / np.maximum(m, 1e-6), 1.0)[:, None, None]).astype(np.float32)
+    pr = oracle_project(sc, cam)
+    m = np.abs(pr.f2d.numpy()).sum(-1).max(1)
+    vis = pr.visible.numpy()
+    wide = 7.5 * m + 0.5 > 250.0
+    assert (wide & vis).sum() > 50 and (~wide & vis).sum() > 50
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    ref = O.render_scene(sc, cam, "binned", tau_alpha=0.05)
+    assert_image(plan.view_image(0).cpu().numpy(), ref, "wide frequencies", atol=1e-3, max_fragile=0.25)
+    g_img = synth.random_dl_dimage(72, (3, cam.height, cam.width))
+    gg = _gpu_grads(ds, plan, g_img)
+    rg = O.render_grads(sc, cam, g_img, "binned")
+    report = {}
+    for name, t in gg.items():
+        report[name] = check_grads_elementwise(name, _to_aos(name, t, sc.n, sc.k), rg[name], rel=1e-2,
+                                               max_outlier_frac=0.05, norm_tol=2e-2)
+    print("wide", {k: f"out {v[0]} worst {v[1]:.2f} l2 {v[2]:.2e}" for k, v in report.items()})
 
 
 def test_loss_matches_oracle(gpu_lib):
