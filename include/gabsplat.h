@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 5
+#define GABSPLAT_ABI_VERSION 6
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
@@ -250,7 +250,15 @@ gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_sc
  * global tile's [start, end) range (empty tiles = (0, 0)).
  *   vals [pair_capacity]      sorted item ids (output)
  *   keys [pair_capacity]      sorted 64-bit keys tile << 32 | depth bits, or
- *                             NULL to skip writing them
+ *                             NULL to skip writing them.  Without keys, a
+ *                             frame of at most 8192 tiles (and a capacity
+ *                             below 2^31) may leave a tile's list of up to
+ *                             1024 ids grouped but unordered, marked by bit
+ *                             31 of its end in tile_ranges (the range is
+ *                             [start, end & 0x7fffffff)); gabsplat_render_fwd
+ *                             orders such a list in place in vals and clears
+ *                             the bit before blending it, so after it vals
+ *                             and tile_ranges are exactly as with keys
  *   tile_ranges [3 * total_tiles] (output): [total_tiles][2] ranges, then
  *                the order in which gabsplat_render_fwd / _bwd dispatch the
  *                tiles (tile ids by decreasing list length, in geometric
@@ -287,9 +295,14 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
  *             the record's cosine weights) blended with the weights alpha T of
  *             its colour, without background
  *   (eval_counts / freq_map select a separate, slower analysis variant.)
+ *   vals, tile_ranges  from gabsplat_bin_sort (device); a list marked
+ *             unordered (bit 31 of its end) is first ordered in place by
+ *             (fp32 depth bits of geom->depth, id) and its mark cleared, so
+ *             both are read and written; geom->depth must be the depths of
+ *             the gabsplat_preprocess that the bin sort read
  *   d_overflow  from gabsplat_bin_sort (device). */
-gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals,
-                                    const uint32_t* tile_ranges, const gabsplat_camera* cams,
+gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, uint32_t* vals,
+                                    uint32_t* tile_ranges, const gabsplat_camera* cams,
                                     int32_t num_views, float* image, float* final_T,
                                     uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map,
                                     const int32_t* d_overflow, void* stream);

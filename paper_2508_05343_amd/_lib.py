@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgabsplat.so")
 # the argument layouts this binding marshals (GABSPLAT_ABI_VERSION)
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 EXPORTS = (
     "gabsplat_abi_version", "gabsplat_status_string", "gabsplat_record_floats", "gabsplat_grad2d_floats",

@@ -246,12 +246,12 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
   }
 }
 
-gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, const uint32_t* vals, const uint32_t* tile_ranges,
+gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, uint32_t* vals, uint32_t* tile_ranges,
                                     const gabsplat_camera* cams, int32_t num_views, float* image, float* final_T,
                                     uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map,
                                     const int32_t* d_overflow, void* stream) {
   try {
-    if (!geom || !geom->views || !geom->rec || geom->k < 0 || geom->k > GABSPLAT_MAX_K || !cams ||
+    if (!geom || !geom->views || !geom->rec || !geom->depth || geom->k < 0 || geom->k > GABSPLAT_MAX_K || !cams ||
         num_views < 1 || num_views > GABSPLAT_MAX_VIEWS || !tile_ranges || !image || !final_T || !n_contrib)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     for (int v = 0; v < num_views; ++v)

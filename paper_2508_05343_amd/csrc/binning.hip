@@ -8,7 +8,12 @@
 // of (depth bits << 32 | item) into each tile's segment through per-block
 // LDS cursors, and a sort of every segment by that unique key (one wavefront
 // per tile, bitonic in registers; runs of 1024 merged for longer segments).
-// Five launches, no global radix passes and no global atomics.
+// Five launches, no global radix passes and no global atomics.  When the
+// caller does not ask for the keys, the scatter writes the item ids of each
+// segment straight into vals and leaves their order to the forward blend,
+// which sorts each list of up to kBlendSortCap pairs in LDS before blending
+// it (sorted there, it costs no separate pass over the pairs); only longer
+// lists are sorted here.
 //
 // Larger batches (many views) take the radix path: an LSD radix sort over
 // the same key that first sorts by the 32 depth bits and then, stably, by
@@ -27,6 +32,7 @@
 
 #include "gs_block.h"
 #include "gs_internal.h"
+#include "gs_sort.h"
 
 namespace gs {
 
@@ -49,6 +55,7 @@ enum {
   C_NUM_VISIBLE = 16,
   C_NUM_PAIRS = 17,
   C_OVERFLOW = 18,
+  C_LONG_TILES = 19,  // tile-count path without keys: lists longer than the blend sorts
   C_COUNT = 64
 };
 
@@ -952,11 +959,16 @@ __global__ __launch_bounds__(256) void k_tc_colscan(uint32_t* __restrict__ cnt, 
 // the segment sort and the blend (as k_tile_order) after the ranges.  The
 // totals are staged in LDS with coalesced loads; each thread then scans
 // kTileScanPer consecutive tiles held in registers (no dependent global loads)
-// and the starts and ranges go out coalesced from LDS again.
+// and the starts and ranges go out coalesced from LDS again.  With `direct`
+// (no keys: the scatter writes ids and the blend orders the lists) every
+// list of two or more pairs is marked unsorted (kUnsortedBit on its end) and
+// the lists longer than kBlendSortCap are listed, into `tot` (whose totals are
+// in LDS by then), for k_tc_sort_long.
 constexpr int kTileScanThreads = 1024;
 constexpr int kTileScanPer = kTcMaxTiles / kTileScanThreads;
-__global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(const uint32_t* __restrict__ tot, int ntiles,
-                                                             uint32_t capacity, uint32_t* __restrict__ tstart,
+__global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(uint32_t* __restrict__ tot, int ntiles,
+                                                             uint32_t capacity, int direct,
+                                                             uint32_t* __restrict__ tstart,
                                                              uint32_t* __restrict__ ranges,
                                                              uint32_t* __restrict__ counters,
                                                              int64_t* __restrict__ d_num_pairs,
@@ -964,12 +976,14 @@ __global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(const uint32_t
   __shared__ uint32_t s_v[kTcMaxTiles];
   __shared__ uint32_t s_wave[kTileScanThreads / 64];
   __shared__ uint32_t s_cnt[kOrderBuckets];
+  __shared__ uint32_t s_long;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
 #pragma unroll
   for (int r = 0; r < kTileScanPer; ++r) {
     const int i = r * kTileScanThreads + t;
     if (i < ntiles) s_v[i] = tot[i];
   }
+  if (t == 0) s_long = 0;
   for (int b = t; b < kOrderBuckets; b += kTileScanThreads) s_cnt[b] = 0;
   __syncthreads();
   const int i0 = t * kTileScanPer;
@@ -1017,22 +1031,30 @@ __global__ __launch_bounds__(kTileScanThreads) void k_tc_tilescan(const uint32_t
       const uint32_t st = s_v[i], nx = i + 1 < ntiles ? s_v[i + 1] : total;
       tstart[i] = st;
       ranges[2 * (size_t)i] = nx > st ? st : 0u;
-      ranges[2 * (size_t)i + 1] = nx > st ? nx : 0u;
+      ranges[2 * (size_t)i + 1] = nx > st ? (nx | (direct && nx - st > 1u ? kUnsortedBit : 0u)) : 0u;
     }
   }
+  if (direct) {
+#pragma unroll
+    for (int r = 0; r < kTileScanPer; ++r)
+      if (i0 + r < ntiles && c[r] > (uint32_t)kBlendSortCap) tot[atomicAdd(&s_long, 1u)] = (uint32_t)(i0 + r);
+  }
+  __syncthreads();
   if (t == 0) {
     const uint32_t ov = total > capacity ? 1u : 0u;
     counters[C_NUM_PAIRS] = total;
     counters[C_OVERFLOW] = ov;
+    counters[C_LONG_TILES] = s_long;
     *d_num_pairs = (int64_t)total;
     *d_overflow = (int32_t)ov;
   }
 }
 
-// Scatter of every (item, tile) pair into its tile's segment as the 64-bit
-// key (depth bits << 32 | item): block b owns the positions tstart[t] +
-// cnt[b][t] onwards of each tile (LDS cursors, so the order inside a segment
-// is arbitrary; the segment sort fixes it).
+// Scatter of every (item, tile) pair into its tile's segment, as the 64-bit
+// key (depth bits << 32 | item) into spair, or (ids given) as the item id
+// straight into ids: block b owns the positions tstart[t] + cnt[b][t]
+// onwards of each tile (LDS cursors, so the order inside a segment is
+// arbitrary; the segment sort, or the blend, fixes it).
 __global__ __launch_bounds__(kTcThreads) void k_tc_scatter(const void* __restrict__ table, int64_t items,
                                                     const uint32_t* __restrict__ tiles,
                                                     const uint32_t* __restrict__ rect,
@@ -1040,7 +1062,8 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_scatter(const void* __restric
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ tstart,
                                                     const uint32_t* __restrict__ counters,
-                                                    uint64_t* __restrict__ spair) {
+                                                    uint64_t* __restrict__ spair,
+                                                    uint32_t* __restrict__ ids) {
   __shared__ uint32_t s_cur[kTcMaxTiles];
   if (counters[C_OVERFLOW]) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -1054,74 +1077,11 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_scatter(const void* __restric
   for (int64_t b = i0; b < i1; b += (int64_t)kTcItems * blockDim.x)
     for_each_pair(views, nv, tiles, rect, b, i1, [&](uint32_t item, uint32_t t) {
       const uint32_t pos = atomicAdd(&s_cur[t], 1u);
-      spair[pos] = ((uint64_t)depth_bits[item] << 32) | item;  // the sort key (depth bits, item)
+      if (ids) ids[pos] = item;  // ordered later by (depth bits, item)
+      else spair[pos] = ((uint64_t)depth_bits[item] << 32) | item;  // the sort key (depth bits, item)
     });
 }
 
-
-// Merge of the sorted runs a = [a0, a0 + na) and b = [b0, b0 + nb) of x
-// into out at o0, by one wavefront (each lane a contiguous slice of the
-// output, split points by merge-path binary search; keys are unique).
-__device__ void wave_merge(const uint64_t* __restrict__ x, uint32_t a0, uint32_t na, uint32_t b0, uint32_t nb,
-                           uint64_t* __restrict__ out, uint32_t o0) {
-  const uint32_t n = na + nb;
-  const uint32_t per = (n + 63) / 64;
-  const uint32_t d0 = min(n, (uint32_t)__lane_id() * per), d1 = min(n, d0 + per);
-  if (d0 >= d1) return;
-  uint32_t lo = d0 > nb ? d0 - nb : 0u, hi = min(d0, na);
-  while (lo < hi) {  // number of elements of a among the first d0 outputs
-    const uint32_t m = (lo + hi) >> 1;
-    if (x[a0 + m] <= x[b0 + d0 - 1 - m]) lo = m + 1; else hi = m;
-  }
-  uint32_t ia = lo, ib = d0 - lo;
-  for (uint32_t o = d0; o < d1; ++o) {
-    const bool takea = ib >= nb || (ia < na && x[a0 + ia] <= x[b0 + ib]);
-    out[o0 + o] = takea ? x[a0 + ia++] : x[b0 + ib++];
-  }
-}
-
-// Bitonic sort of 64 E keys held in registers, E consecutive keys per lane
-// (key i = lane E + r).  Steps whose partner distance j is below E pair keys of
-// one lane; the others pair key r of lanes l and l ^ (j / E) through a lane
-// shuffle, each side keeping the minimum or the maximum.  No LDS, no barrier.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
-  const int lo = __shfl_xor((int)(uint32_t)x, m, 64), hi = __shfl_xor((int)(uint32_t)(x >> 32), m, 64);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
-  const int lane = __lane_id();
-  constexpr int N = 64 * E;
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j < E) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          if ((r & j) == 0) {
-            const bool up = (((lane * E + r) & k) == 0);
-            const uint64_t a = x[r], b = x[r | j];
-            const bool sw = (a > b) == up;
-            x[r] = sw ? b : a;
-            x[r | j] = sw ? a : b;
-          }
-        }
-      } else {
-        const int m = j / E;
-        const bool lower = (lane & m) == 0;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const bool up = (((lane * E + r) & k) == 0);
-          const uint64_t y = shfl_xor_u64(x[r], m);
-          const bool take_min = lower == up;
-          x[r] = take_min ? (x[r] < y ? x[r] : y) : (x[r] > y ? x[r] : y);
-        }
-      }
-    }
-  }
-}
 
 // Sorts the n <= 64 E keys at pa[start ..) and writes them either as item ids
 // (+ 64-bit tile keys) to vals / keys, or (TO_VALS = false) back to pa.
@@ -1160,12 +1120,38 @@ __device__ __forceinline__ void wave_memory_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Sorts the long segment pa[start, start + n) (n > kSegCap) of tile `tile` as
+// register-sorted runs of kSegCap merged pairwise through the ping-pong
+// buffer pb, by one wavefront, and writes the item ids to vals (and the
+// 64-bit keys when asked for).
+__device__ void sort_long_segment(uint64_t* __restrict__ pa, uint64_t* __restrict__ pb, uint32_t start, uint32_t n,
+                                  uint32_t tile, uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap)
+    tile_sort_regs<16, false>(pa, start + r0, min((uint32_t)kSegCap, n - r0), tile, vals, keys);
+  wave_memory_sync();
+  uint64_t *src = pa, *dst = pb;
+  for (uint32_t width = kSegCap; width < n; width <<= 1) {
+    for (uint32_t lo = 0; lo < n; lo += 2 * width) {
+      const uint32_t na = min(width, n - lo);
+      const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
+      merge_runs<false>(src, start + lo, na, start + lo + na, nb, dst, nullptr, start + lo, 0u,
+                        (uint32_t)__lane_id(), 64u);
+    }
+    wave_memory_sync();
+    uint64_t* tmp = src; src = dst; dst = tmp;
+  }
+  for (uint32_t i = __lane_id(); i < n; i += 64) {
+    const uint64_t x = src[start + i];
+    vals[start + i] = (uint32_t)x;
+    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
+  }
+}
+
 // One wavefront per tile, kSortWaves tiles per workgroup (independent
 // wavefronts, no barrier), tiles in the blend's dispatch order (longest
 // first): sorts the tile's segment of (depth bits, item) keys and writes the
 // item ids to vals (and the 64-bit keys when asked for).  Segments of up to
-// kSegCap pairs are sorted in registers; longer ones as register-sorted runs
-// of kSegCap merged pairwise through the ping-pong buffer pb.
+// kSegCap pairs are sorted in registers, longer ones by sort_long_segment.
 constexpr int kSortWaves = 4;
 __global__ __launch_bounds__(64 * kSortWaves) void k_tc_sort(const uint32_t* __restrict__ ranges, int ntiles,
                                                             const uint32_t* __restrict__ counters,
@@ -1181,31 +1167,45 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_tc_sort(const uint32_t* __r
   const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
   const uint32_t n = end - start;
   if (n == 0) return;
-  const int lane = __lane_id();
   static_assert(kSegCap == 1024, "register sort sizes");
   if (n <= 64) return tile_sort_regs<1, true>(pa, start, n, tile, vals, keys);
   if (n <= 128) return tile_sort_regs<2, true>(pa, start, n, tile, vals, keys);
   if (n <= 256) return tile_sort_regs<4, true>(pa, start, n, tile, vals, keys);
   if (n <= 512) return tile_sort_regs<8, true>(pa, start, n, tile, vals, keys);
   if (n <= 1024) return tile_sort_regs<16, true>(pa, start, n, tile, vals, keys);
-  // long segment: sorted runs in place, then pairwise merges pa <-> pb
-  for (uint32_t r0 = 0; r0 < n; r0 += kSegCap)
-    tile_sort_regs<16, false>(pa, start + r0, min((uint32_t)kSegCap, n - r0), tile, vals, keys);
-  wave_memory_sync();
-  uint64_t *src = pa, *dst = pb;
-  for (uint32_t width = kSegCap; width < n; width <<= 1) {
-    for (uint32_t lo = 0; lo < n; lo += 2 * width) {
-      const uint32_t na = min(width, n - lo);
-      const uint32_t nb = n - lo > width ? min(width, n - lo - width) : 0u;
-      wave_merge(src, start + lo, na, start + lo + na, nb, dst, start + lo);
+  sort_long_segment(pa, pb, start, n, tile, vals, keys);
+}
+
+// Without keys the scatter writes item ids straight into vals and the blend
+// orders every list of up to kBlendSortCap pairs itself; this kernel orders
+// the longer ones, listed by the tile scan (counters[C_LONG_TILES] of them in
+// `long_tiles`): each wavefront takes listed tiles in turn, builds the keys
+// (depth bits, item) in pa, sorts them and writes the ids back, then clears
+// the tile's unsorted bit.  A small fixed grid: with no long tile every
+// wavefront reads the count and ends.
+constexpr int kLongSortBlocks = 64;
+__global__ __launch_bounds__(64 * kSortWaves) void k_tc_sort_long(uint32_t* __restrict__ ranges,
+                                                                 const uint32_t* __restrict__ long_tiles,
+                                                                 const uint32_t* __restrict__ counters,
+                                                                 const uint32_t* __restrict__ depth_bits,
+                                                                 uint64_t* __restrict__ pa,
+                                                                 uint64_t* __restrict__ pb,
+                                                                 uint32_t* __restrict__ vals) {
+  if (counters[C_OVERFLOW]) return;
+  const uint32_t count = counters[C_LONG_TILES];
+  const uint32_t waves = gridDim.x * kSortWaves;
+  for (uint32_t li = blockIdx.x * kSortWaves + (threadIdx.x >> 6); li < count; li += waves) {
+    const uint32_t tile = long_tiles[li];
+    const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1] & ~kUnsortedBit;
+    const uint32_t n = end - start;
+    for (uint32_t i = __lane_id(); i < n; i += 64) {
+      const uint32_t id = vals[start + i];
+      pa[start + i] = ((uint64_t)depth_bits[id] << 32) | id;
     }
     wave_memory_sync();
-    uint64_t* tmp = src; src = dst; dst = tmp;
-  }
-  for (uint32_t i = lane; i < n; i += 64) {
-    const uint64_t x = src[start + i];
-    vals[start + i] = (uint32_t)x;
-    if (keys) keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
+    if (n <= kSegCap) tile_sort_regs<16, true>(pa, start, n, tile, vals, nullptr);
+    else sort_long_segment(pa, pb, start, n, tile, vals, nullptr);
+    if (__lane_id() == 0) ranges[2 * (size_t)tile + 1] = end;
   }
 }
 
@@ -1293,19 +1293,26 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
     uint64_t* pa = reinterpret_cast<uint64_t*>(w + p.off_tcpair_a);
     uint64_t* pb = reinterpret_cast<uint64_t*>(w + p.off_tcpair_b);
     const int nt = p.total_tiles;
-    // no counter clear: the tile scan writes the only counters this path reads
+    // no counter clear: the tile scan writes the only counters this path reads.
+    // Without keys (and with pair positions below the unsorted bit) the
+    // lists are left for the blend to order.
+    const int direct = (keys == nullptr && p.capacity < (int64_t)kUnsortedBit) ? 1 : 0;
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_hist, dim3(kTcBlocks), dim3(kTcThreads), 0, s, g.views, p.items, g.tiles, g.rect, nt, cnt);
       hipLaunchKernelGGL(k_tc_colscan, dim3((unsigned)((nt + kColTiles - 1) / kColTiles)), dim3(256), 0, s, cnt, nt,
                          tot);
     }
-    hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kTileScanThreads), 0, s, tot, nt, (uint32_t)p.capacity, tstart,
-                       ranges, counters, d_num_pairs, d_overflow);
+    hipLaunchKernelGGL(k_tc_tilescan, dim3(1), dim3(kTileScanThreads), 0, s, tot, nt, (uint32_t)p.capacity, direct,
+                       tstart, ranges, counters, d_num_pairs, d_overflow);
     if (nt > 0) {
       hipLaunchKernelGGL(k_tc_scatter, dim3(kTcBlocks), dim3(kTcThreads), 0, s, g.views, p.items, g.tiles, g.rect,
-                         depth_bits, nt, cnt, tstart, counters, pa);
-      hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)((nt + kSortWaves - 1) / kSortWaves)), dim3(64 * kSortWaves), 0, s,
-                         ranges, nt, counters, pa, pb, vals, keys);
+                         depth_bits, nt, cnt, tstart, counters, pa, direct ? vals : nullptr);
+      if (direct)
+        hipLaunchKernelGGL(k_tc_sort_long, dim3(kLongSortBlocks), dim3(64 * kSortWaves), 0, s, ranges, tot, counters,
+                           depth_bits, pa, pb, vals);
+      else
+        hipLaunchKernelGGL(k_tc_sort, dim3((unsigned)((nt + kSortWaves - 1) / kSortWaves)), dim3(64 * kSortWaves), 0,
+                           s, ranges, nt, counters, pa, pb, vals, keys);
     }
     return hipGetLastError();
   }

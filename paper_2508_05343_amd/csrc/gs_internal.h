@@ -16,6 +16,12 @@ constexpr float kTMin = 1e-4f;                 // transmittance stop
 constexpr float kDilation = 0.3f;              // px^2 added to the 2D covariance
 constexpr float kMip2dVariance = 0.1f;         // px^2 of the 2D anti-aliasing filter
 constexpr float kMip2dMinRatio = 1e-6f;        // floor of det S / det(S + 0.1 I)
+// Bit 31 of a tile's end in the tile ranges: the tile's list is grouped by
+// the bin sort but not yet in depth order.  The tile-count bin sort without
+// keys leaves lists of up to kBlendSortCap pairs so marked, and the forward
+// blend orders such a list (in place in vals) before blending it.
+constexpr uint32_t kUnsortedBit = 0x80000000u;
+constexpr int kBlendSortCap = 1024;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 // log2(1/255): o G < 1/255  <=>  q + log2 o < kLog2AlphaMin
@@ -120,7 +126,7 @@ hipError_t launch_bin_sort(const gabsplat_geom& g, const BinSortPlan& p, void* w
                            hipStream_t s);
 
 hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g,
-                             int k, const uint32_t* vals, const uint32_t* ranges, float* image,
+                             int k, uint32_t* vals, uint32_t* ranges, float* image,
                              float* final_T, uint32_t* n_contrib, uint32_t* eval_counts,
                              float* freq_map, const int32_t* d_overflow, hipStream_t s);
 

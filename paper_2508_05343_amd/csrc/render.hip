@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gs_internal.h"
+#include "gs_sort.h"
 
 namespace gs {
 
@@ -150,6 +151,83 @@ __device__ __forceinline__ float staged_power(float4 s0, float dx, float dy) {
 // at the pixel whose centre is (pu, pv) from the tile centre.
 __device__ __forceinline__ float staged_phase(float4 c, float pu, float pv) { return fmaf(c.x, pu, fmaf(c.y, pv, c.w)); }
 
+// ------------------------------------------------- list order in the blend
+// A tile list the bin sort left unsorted (kUnsortedBit on its end) is put in
+// depth order by the tile's own workgroup before blending: the ids
+// vals[start, start + n), 2 <= n <= kBlendSortCap, are sorted in place by the
+// unique key (depth bits << 32 | id).  Up to 256 ids: the first wavefront
+// sorts them in registers.  More: each wavefront sorts a quarter (64 E keys,
+// E = 2 or 4) in registers and two rounds of merge-path merges in LDS (2
+// kBlendSortCap keys in `lds`) join the quarters.  Called by the whole
+// workgroup; ends with a barrier, after which the sorted ids are visible to
+// every wavefront of it.
+template <int E>
+__device__ __forceinline__ void load_list_keys(const uint32_t* vals, const uint32_t* depth_bits, uint32_t start,
+                                               uint32_t base, uint32_t n, uint64_t (&x)[E]) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = base + (uint32_t)(lane * E + r);
+    uint64_t key = ~0ull;
+    if (i < n) {
+      const uint32_t id = vals[start + i];
+      key = ((uint64_t)depth_bits[id] << 32) | id;
+    }
+    x[r] = key;
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort_list(uint32_t* vals, const uint32_t* depth_bits, uint32_t start,
+                                               uint32_t n) {
+  uint64_t x[E];
+  load_list_keys<E>(vals, depth_bits, start, 0u, n, x);
+  wave_bitonic<E>(x);
+  const int lane = __lane_id();
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = (uint32_t)(lane * E + r);
+    if (i < n) vals[start + i] = (uint32_t)x[r];
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void block_sort_quarters(uint32_t* vals, const uint32_t* depth_bits, uint32_t start,
+                                                    uint32_t n, uint64_t* lds) {
+  constexpr uint32_t C = 64 * E;
+  static_assert(4 * C <= (uint32_t)kBlendSortCap, "quarters fit the sort buffer");
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  uint64_t x[E];
+  load_list_keys<E>(vals, depth_bits, start, (uint32_t)w * C, n, x);
+  wave_bitonic<E>(x);
+#pragma unroll
+  for (int r = 0; r < E; ++r) lds[(uint32_t)w * C + (uint32_t)(lane * E + r)] = x[r];
+  __syncthreads();
+  // quarters (0, 1) and (2, 3), 128 threads each, into the second half
+  uint64_t* b = lds + kBlendSortCap;
+  const uint32_t h = (uint32_t)t >> 7;
+  merge_runs<false>(lds, 2 * C * h, C, 2 * C * h + C, C, b, nullptr, 2 * C * h, 0u, (uint32_t)t & 127u, 128u);
+  __syncthreads();
+  merge_runs<true>(b, 0u, 2 * C, 2 * C, 2 * C, nullptr, vals + start, 0u, n, (uint32_t)t, (uint32_t)kBlock);
+}
+
+__device__ __forceinline__ void block_sort_list(uint32_t* vals, const uint32_t* depth_bits, uint32_t start,
+                                                uint32_t n, uint64_t* lds) {
+  static_assert(kBlock == 256 && kBlendSortCap == 1024, "four wavefronts, quarters of up to 256 keys");
+  if (n <= 256) {
+    if (threadIdx.x < 64) {
+      if (n <= 64) wave_sort_list<1>(vals, depth_bits, start, n);
+      else if (n <= 128) wave_sort_list<2>(vals, depth_bits, start, n);
+      else wave_sort_list<4>(vals, depth_bits, start, n);
+    }
+  } else if (n <= 512) {
+    block_sort_quarters<2>(vals, depth_bits, start, n, lds);
+  } else {
+    block_sort_quarters<4>(vals, depth_bits, start, n, lds);
+  }
+  __syncthreads();
+}
+
 // --------------------------------------------------------------------- K6
 // The ANALYSIS variant (never the timed one) can also report, per pixel, how
 // far down its tile list the blend had to go (the stopping position, or the
@@ -160,8 +238,9 @@ __device__ __forceinline__ float staged_phase(float4 c, float pu, float pv) { re
 template <int K, bool ANALYSIS>
 __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ table,
                                                        const float* __restrict__ rec,
-                                                       const uint32_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ depth_bits,
+                                                       uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ ranges,
                                                        float* __restrict__ image, float* __restrict__ final_T,
                                                        uint32_t* __restrict__ n_contrib,
                                                        uint32_t* __restrict__ eval_counts,
@@ -170,7 +249,9 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   constexpr int RF = record_stride(K);
   constexpr int R4 = RF / 4;
   constexpr int S4 = Staged<K>::S4;
-  __shared__ float4 s_rec[kBatchFwd * S4];
+  // the staged records; before the first batch, the list sort's keys
+  constexpr int kRecF4 = kBatchFwd * S4, kSortF4 = kBlendSortCap;  // 2 u64 keys per float4
+  __shared__ float4 s_rec[kRecF4 > kSortF4 ? kRecF4 : kSortF4];
   __shared__ uint32_t s_mask[kBatchFwd];
   if (d_overflow != nullptr && *d_overflow != 0) return;
   const ViewTableHeader* hdr = reinterpret_cast<const ViewTableHeader*>(table);
@@ -187,7 +268,12 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
   const float u = (float)((w & 1) * 8 + (l & 7)) + 0.5f, v = (float)((w >> 1) * 8 + (l >> 3)) + 0.5f;
   const float pu = u - kTileHalf, pv = v - kTileHalf;
   const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
-  const uint32_t start = ranges[2 * (size_t)tile], end = ranges[2 * (size_t)tile + 1];
+  const uint32_t start = ranges[2 * (size_t)tile], end_word = ranges[2 * (size_t)tile + 1];
+  const uint32_t end = end_word & ~kUnsortedBit;
+  if (end_word & kUnsortedBit) {  // the same for the whole workgroup
+    block_sort_list(vals, depth_bits, start, end - start, reinterpret_cast<uint64_t*>(s_rec));
+    if (t == 0) ranges[2 * (size_t)tile + 1] = end;
+  }
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0, stop_pos = end - start, n_full = 0;
@@ -605,21 +691,22 @@ hipError_t launch_clear_grad2d(const uint32_t* tiles, float* grad2d, int64_t ite
 
 // --------------------------------------------------------------- launchers
 template <int K>
-static hipError_t fwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, const uint32_t* vals,
-                        const uint32_t* ranges, float* image, float* final_T, uint32_t* n_contrib,
+static hipError_t fwd_k(const void* d_table, const HostTable& h, const gabsplat_geom& g, uint32_t* vals,
+                        uint32_t* ranges, float* image, float* final_T, uint32_t* n_contrib,
                         uint32_t* eval_counts, float* freq_map, const int32_t* ov, hipStream_t s) {
   if (h.hdr.total_tiles == 0) return hipSuccess;
+  const uint32_t* depth_bits = reinterpret_cast<const uint32_t*>(g.depth);
   if (eval_counts || freq_map)
     hipLaunchKernelGGL((k_render_fwd<K, true>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table, g.rec,
-                       vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
+                       depth_bits, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
   else
     hipLaunchKernelGGL((k_render_fwd<K, false>), dim3((unsigned)h.hdr.total_tiles), dim3(kBlock), 0, s, d_table,
-                       g.rec, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
+                       g.rec, depth_bits, vals, ranges, image, final_T, n_contrib, eval_counts, freq_map, ov);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(const void* d_table, const HostTable& h, const gabsplat_geom& g, int k,
-                             const uint32_t* vals, const uint32_t* ranges, float* image, float* final_T,
+                             uint32_t* vals, uint32_t* ranges, float* image, float* final_T,
                              uint32_t* n_contrib, uint32_t* eval_counts, float* freq_map, const int32_t* ov,
                              hipStream_t s) {
   switch (k) {

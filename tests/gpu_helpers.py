@@ -7,7 +7,7 @@ import synth
 from oracle import gabor_oracle as O
 
 
-def gpu_plan(scenes, cams, scene_of_view=None, want_keys=True, capacity=None):
+def gpu_plan(scenes, cams, scene_of_view=None, want_keys=False, capacity=None):
     from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
     if not isinstance(scenes, (list, tuple)):
         scenes = [scenes]

@@ -35,7 +35,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_helpers(L):
-    assert L.gabsplat_abi_version() == 5
+    assert L.gabsplat_abi_version() == 6
     assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 20
     assert L.gabsplat_record_floats(4) == 24 and L.gabsplat_record_floats(8) == 36
     assert L.gabsplat_record_floats(9) == -1

@@ -58,11 +58,11 @@ def _write_synthetic_geom(plan, rect, depth, vis):
     plan.tiles_touched.copy_(torch.from_numpy(t).cuda())
 
 
-def _bin_sort_case(n, views, seed, width=200, height=150, hot_share=0.0):
+def _bin_sort_case(n, views, seed, width=200, height=150, hot_share=0.0, want_keys=True):
     sc = synth.uniform_scene(seed, n, 1)
     cams = [synth.pinhole_camera(width + 37 * v, height + 11 * v, 60.0, (0, 0, -3), (0, 0, 0)) for v in range(views)]
     # capacity for the largest rectangles (6 x 6 tiles) of every item
-    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * views, capacity=36 * n * views + 1024)
+    ds, plan = gpu_plan(sc, cams, scene_of_view=[0] * views, capacity=36 * n * views + 1024, want_keys=want_keys)
     plan.preprocess()  # writes the view table
     rects, depths, viss = [], [], []
     for v, c in enumerate(cams):
@@ -97,27 +97,91 @@ def test_bin_sort_bit_exact_on_synthetic_geometry(gpu_lib, n, views, seed, width
     torch.cuda.synchronize()
     P = int(plan.num_pairs.item())
     assert int(plan.overflow.item()) == 0
-    keys_o, vals_o, ranges_o = [], [], []
-    for v, c in enumerate(cams):
-        sl = slice(v * n, (v + 1) * n)
-        k, vv, rg = O.bin_sort(rect[sl], depth[sl], vis[sl], c.tiles_x, c.num_tiles,
-                               tile_offset=plan.layout[v].tile_offset, index_offset=v * n)
-        keys_o.append(k); vals_o.append(vv); ranges_o.append(rg + (sum(len(x) for x in keys_o[:-1])) * (rg[:, 1:] > 0))
-    keys_o = np.concatenate(keys_o)
-    vals_o = np.concatenate(vals_o)
+    keys_o, vals_o, exp = _expected_bin_sort(cams, plan, rect, depth, vis, n)
     assert P == len(keys_o)
     kg = plan.keys.cpu().numpy()[:P].view(np.uint64)
     vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
     assert (kg == keys_o).all()
     assert (vg == vals_o).all()
     rg = plan.ranges.cpu().numpy().view(np.uint32)
+    assert (rg[:plan.tiles] == exp).all()
+
+
+def _expected_bin_sort(cams, plan, rect, depth, vis, n):
+    """The oracle's library stable sort of the synthetic pairs of every view:
+    global keys, item ids and per-tile [start, end) ranges."""
+    keys_o, vals_o = [], []
+    for v, c in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        k, vv, _ = O.bin_sort(rect[sl], depth[sl], vis[sl], c.tiles_x, c.num_tiles,
+                              tile_offset=plan.layout[v].tile_offset, index_offset=v * n)
+        keys_o.append(k); vals_o.append(vv)
+    keys_o = np.concatenate(keys_o)
+    vals_o = np.concatenate(vals_o)
     # global ranges: recompute from the oracle's global key order
     tl = (keys_o >> np.uint64(32)).astype(np.int64)
     exp = np.zeros((plan.tiles, 2), np.uint32)
     for t_ in np.unique(tl):
         idx = np.nonzero(tl == t_)[0]
         exp[t_] = (idx[0], idx[-1] + 1)
-    assert (rg[:plan.tiles] == exp).all()
+    return keys_o, vals_o, exp
+
+
+@pytest.mark.parametrize("n,seed,hot", [(500, 11, 0.0), (3000, 12, 0.0), (9000, 13, 0.0), (20000, 14, 0.0),
+                                        (20000, 15, 0.7)])
+def test_blend_orders_the_lists_it_is_given_unsorted(gpu_lib, n, seed, hot):
+    """Without keys the tile-count bin sort leaves every list of two or more
+    pairs grouped but unordered, marked by bit 31 of its end, and sorts only
+    the lists longer than 1024 itself; the forward blend orders the others
+    (one wavefront up to 256 ids, quarters merged in LDS up to 1024) before
+    blending them.  After the blend, vals and the ranges equal the oracle's
+    stable sort exactly, for lists of every length class (500 items: tens of
+    pairs per tile; 3000: hundreds; 9000: up to ~1000; 20000: beyond 1024;
+    hot: one list of ~11,000)."""
+    cams, plan, rect, depth, vis = _bin_sort_case(n, 1, seed, hot_share=hot, want_keys=False)
+    _write_synthetic_geom(plan, rect, depth, vis)
+    plan.bin_sort()
+    torch.cuda.synchronize()
+    P = int(plan.num_pairs.item())
+    assert int(plan.overflow.item()) == 0
+    keys_o, vals_o, exp = _expected_bin_sort(cams, plan, rect, depth, vis, n)
+    assert P == len(keys_o)
+    rg = plan.ranges.cpu().numpy().view(np.uint32)[:plan.tiles].copy()
+    lens = exp[:, 1] - exp[:, 0]
+    marked = (rg[:, 1] & 0x80000000) != 0
+    # marked: exactly the lists of 2..1024 pairs; the bin sort ordered the longer ones
+    assert (marked == ((lens >= 2) & (lens <= 1024))).all()
+    assert (rg[:, 0] == exp[:, 0]).all() and ((rg[:, 1] & 0x7FFFFFFF) == exp[:, 1]).all()
+    vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
+    long_ = lens > 1024
+    for t_ in np.nonzero(long_)[0]:
+        assert (vg[exp[t_, 0]:exp[t_, 1]] == vals_o[exp[t_, 0]:exp[t_, 1]]).all(), t_
+    for t_ in np.nonzero(marked)[0]:  # the same ids, grouped by tile
+        a, b = exp[t_]
+        assert (np.sort(vg[a:b]) == np.sort(vals_o[a:b])).all(), t_
+    print("lists", int(marked.sum()), "marked,", int(long_.sum()), "long; max", int(lens.max()))
+    plan.render_fwd()
+    torch.cuda.synchronize()
+    vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
+    assert (vg == vals_o).all()
+    assert (plan.ranges.cpu().numpy().view(np.uint32)[:plan.tiles] == exp).all()
+
+
+def test_unsorted_lists_render_exactly_like_sorted_ones(gpu_lib):
+    """Config 1's K1 output binned with keys (every list sorted by the bin
+    sort) and without (lists ordered by the blend): identical images, final
+    transmittances, contributor counts, lists and ranges, bit for bit."""
+    sc, cam = synth.config1_scene(), synth.config1_camera()
+    outs = []
+    for want_keys in (True, False):
+        ds, plan = gpu_plan(sc, [cam], want_keys=want_keys)
+        plan.forward()
+        torch.cuda.synchronize()
+        P = int(plan.num_pairs.item())
+        outs.append((plan.image.cpu().numpy(), plan.final_T.cpu().numpy(), plan.n_contrib.cpu().numpy(),
+                     plan.vals.cpu().numpy()[:P], plan.ranges.cpu().numpy()[:plan.tiles]))
+    for a, b in zip(*outs):
+        assert a.shape == b.shape and (a.view(np.uint32) == b.view(np.uint32)).all()
 
 
 def test_bin_sort_end_to_end_config1(gpu_lib):
@@ -125,7 +189,7 @@ def test_bin_sort_end_to_end_config1(gpu_lib):
     (no primitive of this scene sits within the rect tolerance of a tile
     boundary, so the comparison is exact)."""
     sc, cam = synth.config1_scene(), synth.config1_camera()
-    ds, plan = gpu_plan(sc, [cam])
+    ds, plan = gpu_plan(sc, [cam], want_keys=True)
     plan.preprocess()
     plan.bin_sort()
     torch.cuda.synchronize()

@@ -52,7 +52,7 @@ def test_config2_heaviest_tiles_binned_order(gpu_lib, big):
     for x0, y0, x1, y1 in pr.rect[vis]:
         cnt[y0:y1, x0:x1] += 1
     heavy = np.argsort(cnt.ravel())[::-1][:6]
-    assert cnt.ravel()[heavy[0]] > 512  # the longest segments take the 1024-key register sort
+    assert cnt.ravel()[heavy[0]] > 512  # the longest lists take the blend's merged-quarter sort
     order = O.depth_order(pr.depth32, vis)
     ranges = plan.ranges.cpu().numpy().view(np.uint32)
     vals = plan.vals.cpu().numpy().view(np.uint32)
