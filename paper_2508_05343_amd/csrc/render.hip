@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const void* __restrict__ 
         }
         const float alpha = fminf(kAlphaMax, E * Bv);
         live = live && !(alpha < kAlphaMin);
-        const float Tn = T * (1.0f - alpha);
+        const float Tn = fmaf(-alpha, T, T);  // T (1 - alpha), rounded once
         const bool stop = live && Tn < kTMin;
         const bool take = live && !stop;
         if (ANALYSIS && stop) stop_pos = b - start + (uint32_t)j + 1;
