@@ -324,6 +324,24 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
                                     const float* dl_dimage, const gabsplat_scene_grads* grads,
                                     const int32_t* d_overflow, void* stream);
 
+/* The backward above in its two stages, for callers that time or schedule
+ * them apart (same arguments and checks as gabsplat_render_bwd, plus):
+ *   stages  GABSPLAT_BWD_BLEND: clear the grad2d rows of the items that
+ *           touch a tile and run K7 (the image-plane gradients into
+ *           grads->grad2d); GABSPLAT_BWD_PROJECT: K8 only, chaining the
+ *           grad2d an earlier blend stage left (unchanged since) into the
+ *           scene gradients; both bits: gabsplat_render_bwd.  Any other
+ *           value is an invalid argument. */
+#define GABSPLAT_BWD_BLEND 1
+#define GABSPLAT_BWD_PROJECT 2
+gabsplat_status gabsplat_render_bwd_stages(const gabsplat_scene* scenes, int32_t num_scenes,
+                                           const int32_t* scene_of_view, const gabsplat_camera* cams,
+                                           int32_t num_views, const gabsplat_geom* geom,
+                                           const uint32_t* vals, const uint32_t* tile_ranges,
+                                           const float* final_T, const uint32_t* n_contrib,
+                                           const float* dl_dimage, const gabsplat_scene_grads* grads,
+                                           const int32_t* d_overflow, int32_t stages, void* stream);
+
 /* K9, photometric loss of Sec. 3.4.1 for one image: L = (1 - lambda) mean|x - y|
  * + lambda (1 - mean SSIM(x, y)), SSIM with an 11x11 Gaussian window
  * (sigma 1.5), zero-padded, C1 = 0.01^2, C2 = 0.03^2, means over all channels

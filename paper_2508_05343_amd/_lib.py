@@ -25,12 +25,14 @@ EXPORTS = (
     "gabsplat_loss_workspace_size", "gabsplat_loss_l1_dssim", "gabsplat_read_overflow",
     "gabsplat_densify_stats", "gabsplat_densify_workspace_size", "gabsplat_densify",
     "gabsplat_reset_frequency_weights", "gabsplat_grad2d_stride", "gabsplat_mip_filter3d_workspace_size",
-    "gabsplat_mip_filter3d", "gabsplat_loss_l1_dssim_noalloc",
+    "gabsplat_mip_filter3d", "gabsplat_loss_l1_dssim_noalloc", "gabsplat_render_bwd_stages",
 )
 
 OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE, SCRATCH_LIMIT = range(7)
 # GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES
 LOSS_NOALLOC_SCRATCH_BYTES = 83886080
+# GABSPLAT_BWD_BLEND, GABSPLAT_BWD_PROJECT
+BWD_BLEND, BWD_PROJECT = 1, 2
 FLAG_ATTENUATION = 1
 FLAG_MIP_2D = 2
 FLAG_MIP_3D = 4
@@ -121,6 +123,10 @@ def lib() -> ctypes.CDLL:
     L.gabsplat_render_bwd.argtypes = [POINTER(Scene), c_int32, POINTER(c_int32), POINTER(Camera), c_int32,
                                       POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       POINTER(SceneGrads), c_void_p, c_void_p]
+    L.gabsplat_render_bwd_stages.restype = c_int32
+    L.gabsplat_render_bwd_stages.argtypes = [POINTER(Scene), c_int32, POINTER(c_int32), POINTER(Camera), c_int32,
+                                             POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                             POINTER(SceneGrads), c_void_p, c_int32, c_void_p]
     L.gabsplat_loss_workspace_size.restype = c_size_t
     L.gabsplat_loss_workspace_size.argtypes = [c_int32, c_int32, c_int32]
     L.gabsplat_loss_l1_dssim.restype = c_int32
@@ -244,6 +250,19 @@ def gabsplat_render_bwd(scenes: Sequence[Scene], scene_of_view, cams: Sequence[C
     _check(lib().gabsplat_render_bwd(sa, len(scenes), sv, ca, len(cams), ctypes.byref(geom), ptr(vals),
                                      ptr(tile_ranges), ptr(final_T), ptr(n_contrib), ptr(dl_dimage), ga,
                                      ptr(d_overflow), stream_handle(stream)), "gabsplat_render_bwd")
+
+
+def gabsplat_render_bwd_stages(scenes: Sequence[Scene], scene_of_view, cams: Sequence[Camera], geom: Geom, vals,
+                               tile_ranges, final_T, n_contrib, dl_dimage, grads: Sequence[SceneGrads], d_overflow,
+                               stages: int, stream=None):
+    sa = _arr(Scene, scenes)
+    sv = None if scene_of_view is None else _arr(c_int32, scene_of_view)
+    ca = _arr(Camera, cams)
+    ga = _arr(SceneGrads, grads)
+    _check(lib().gabsplat_render_bwd_stages(sa, len(scenes), sv, ca, len(cams), ctypes.byref(geom), ptr(vals),
+                                            ptr(tile_ranges), ptr(final_T), ptr(n_contrib), ptr(dl_dimage), ga,
+                                            ptr(d_overflow), int(stages), stream_handle(stream)),
+           "gabsplat_render_bwd_stages")
 
 
 def _loss_args(x, y, d_loss, dl_dx):

@@ -275,9 +275,22 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
                                     const uint32_t* vals, const uint32_t* tile_ranges, const float* final_T,
                                     const uint32_t* n_contrib, const float* dl_dimage,
                                     const gabsplat_scene_grads* grads, const int32_t* d_overflow, void* stream) {
+  return gabsplat_render_bwd_stages(scenes, num_scenes, scene_of_view, cams, num_views, geom, vals, tile_ranges,
+                                    final_T, n_contrib, dl_dimage, grads, d_overflow,
+                                    GABSPLAT_BWD_BLEND | GABSPLAT_BWD_PROJECT, stream);
+}
+
+gabsplat_status gabsplat_render_bwd_stages(const gabsplat_scene* scenes, int32_t num_scenes,
+                                           const int32_t* scene_of_view, const gabsplat_camera* cams,
+                                           int32_t num_views, const gabsplat_geom* geom, const uint32_t* vals,
+                                           const uint32_t* tile_ranges, const float* final_T,
+                                           const uint32_t* n_contrib, const float* dl_dimage,
+                                           const gabsplat_scene_grads* grads, const int32_t* d_overflow,
+                                           int32_t stages, void* stream) {
   try {
     if (!geom || !geom->views || !geom->rec || !geom->tiles || !grads || !tile_ranges || !final_T || !n_contrib || !dl_dimage)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
+    if (stages < 1 || (stages & ~(GABSPLAT_BWD_BLEND | GABSPLAT_BWD_PROJECT)) != 0) return GABSPLAT_ERR_INVALID_ARGUMENT;
     TableBuild tb;
     gabsplat_status st = build_table(scenes, num_scenes, scene_of_view, cams, num_views, tb);
     if (st != GABSPLAT_OK) return st;
@@ -294,15 +307,19 @@ gabsplat_status gabsplat_render_bwd(const gabsplat_scene* scenes, int32_t num_sc
     hipStream_t s = static_cast<hipStream_t>(stream);
     HostTable h = tb.host();
     const bool abs_mean2d = (grads[0].flags & GABSPLAT_GRAD_ABS_MEAN2D) != 0;
-    hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items,
-                                       grad2d_stride(geom->k, grads[0].flags), s);
-    if (e != hipSuccess) return GABSPLAT_ERR_HIP;
-    e = launch_render_bwd(geom->views, h, *geom, geom->k, vals, tile_ranges, final_T, n_contrib, dl_dimage,
-                          grads[0].grad2d, abs_mean2d, d_overflow, s);
-    if (e != hipSuccess) return GABSPLAT_ERR_HIP;
-    for (int i = 0; i < num_scenes; ++i) {
-      e = launch_preprocess_bwd(geom->views, h, *geom, i, grads[i], d_overflow, s);
+    if (stages & GABSPLAT_BWD_BLEND) {
+      hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items,
+                                         grad2d_stride(geom->k, grads[0].flags), s);
       if (e != hipSuccess) return GABSPLAT_ERR_HIP;
+      e = launch_render_bwd(geom->views, h, *geom, geom->k, vals, tile_ranges, final_T, n_contrib, dl_dimage,
+                            grads[0].grad2d, abs_mean2d, d_overflow, s);
+      if (e != hipSuccess) return GABSPLAT_ERR_HIP;
+    }
+    if (stages & GABSPLAT_BWD_PROJECT) {
+      for (int i = 0; i < num_scenes; ++i) {
+        const hipError_t e = launch_preprocess_bwd(geom->views, h, *geom, i, grads[i], d_overflow, s);
+        if (e != hipSuccess) return GABSPLAT_ERR_HIP;
+      }
     }
     return GABSPLAT_OK;
   } catch (...) {

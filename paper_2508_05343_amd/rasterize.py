@@ -373,10 +373,13 @@ class RenderPlan:
         self.render_fwd(stream)
         return self.image
 
-    def backward(self, dl_dimage, grads: Sequence[dict], stream=None, accumulate=True):
+    def backward(self, dl_dimage, grads: Sequence[dict], stream=None, accumulate=True, stages=None):
         """dl_dimage has the layout of self.image; grads[s] maps attribute name
         -> tensor (same layout as the scene) that receives the gradient, added
-        to it (accumulate=True) or overwriting it."""
+        to it (accumulate=True) or overwriting it.  stages (default both):
+        _lib.BWD_BLEND (the image-plane gradients into grad2d) and/or
+        _lib.BWD_PROJECT (grad2d through the projection into grads), to run
+        the two parts as separate calls."""
         if not isinstance(dl_dimage, torch.Tensor) or dl_dimage.numel() != 3 * self.pixels:
             raise ValueError(f"dl_dimage must hold the plan's {3 * self.pixels} image values")
         check_device_tensor("dl_dimage", dl_dimage, tuple(dl_dimage.shape), self.image.device)
@@ -400,8 +403,13 @@ class RenderPlan:
                 setattr(c, name, _lib.ptr(t))
             c.grad2d = _lib.ptr(self.grad2d)
             gs.append(c)
-        _lib.gabsplat_render_bwd(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals, self.ranges_buf,
-                                 self.final_T, self.n_contrib, dl_dimage, gs, self.overflow, stream)
+        if stages is None:
+            _lib.gabsplat_render_bwd(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals,
+                                     self.ranges_buf, self.final_T, self.n_contrib, dl_dimage, gs, self.overflow, stream)
+        else:
+            _lib.gabsplat_render_bwd_stages(self.c_scenes, self.scene_of_view, self.c_cams, self.geom, self.vals,
+                                            self.ranges_buf, self.final_T, self.n_contrib, dl_dimage, gs,
+                                            self.overflow, stages, stream)
 
     # ----- views of the outputs
     def view_image(self, v: int) -> torch.Tensor:

@@ -89,6 +89,16 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert st == L.SCRATCH_LIMIT
     assert b"static scratch" in lib.gabsplat_status_string(st)
     assert lib.gabsplat_read_overflow(None, None) == L.INVALID_ARGUMENT
+    # backward stages other than blend, project or both (checked before any
+    # pointer is dereferenced on the device)
+    gg = L.Geom()
+    gg.views = gg.rec = gg.tiles = fake
+    gr = L.SceneGrads()
+    gr.grad2d = fake
+    for stages in (0, 4, 7, -1):
+        st = lib.gabsplat_render_bwd_stages(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(gg), fake,
+                                            fake, fake, fake, fake, ctypes.byref(gr), None, stages, None)
+        assert st == L.INVALID_ARGUMENT, stages
     # 3D filter flag without variances
     sc.flags = L.FLAG_MIP_3D
     st = lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)

@@ -9,7 +9,7 @@ import torch
 import synth
 from oracle import gabor_oracle as O
 
-from gpu_helpers import assert_image, check_grads_elementwise
+from gpu_helpers import assert_image, check_grads_elementwise, gpu_plan
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,29 @@ def test_accumulate_adds_to_existing_gradients(gpu_lib):
         scale = float(a[n].abs().max())
         assert float((a[n] - b[n]).abs().max()) <= 1e-5 * scale, n  # no 7s left
         assert float((c[n] - 1.0 - a[n]).abs().max()) <= 1e-5 * scale + 1e-6, n
+
+
+def test_backward_in_two_stages_equals_one_call(gpu_lib):
+    """gabsplat_render_bwd_stages: the blend stage, then the projection stage,
+    as two calls, give the gradients of the one-call backward (up to the
+    rounding of fp32 atomics)."""
+    from paper_2508_05343_amd import _lib
+    sc = synth.uniform_scene(81, 2000, 4, sh_degree=3, log_scale_mu=-2.9)
+    cam = synth.pinhole_camera(96, 72, 60.0, (0.2, -0.1, -3.0), (0, 0, 0), bg=(0.3, 0.2, 0.1))
+    ds, plan = gpu_plan(sc, [cam])
+    plan.forward()
+    g = torch.from_numpy(synth.random_dl_dimage(82, (3, cam.height, cam.width)).reshape(-1)).cuda()
+    d = ds[0]
+    one = {n: torch.zeros_like(getattr(d, n)) for n in NAMES}
+    plan.backward(g, [one], accumulate=False)
+    two = {n: torch.zeros_like(getattr(d, n)) for n in NAMES}
+    plan.backward(g, [two], accumulate=False, stages=_lib.BWD_BLEND)
+    plan.backward(g, [two], accumulate=False, stages=_lib.BWD_PROJECT)
+    torch.cuda.synchronize()
+    for n in NAMES:
+        scale = float(one[n].abs().max())
+        assert scale > 0, n
+        assert float((one[n] - two[n]).abs().max()) <= 1e-5 * scale, n
 
 
 def test_serving_mix_equals_alone(gpu_lib):
