@@ -27,38 +27,67 @@ HBM_PEAK_GBS = 8000.0
 # without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 78.6
 
-# HBM traffic of one k_render_fwd<4, false> launch on the default workload,
-# from two rocprofv3 --pmc runs of `bench.py --profile --no-train` (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch, mean over the dispatches), each scaled by
-# what the same counter reads for the 256 MiB device copy that run also makes
-# (FETCH_SIZE reads 131,088 KiB for 262,144 KiB moved: x2.0; WRITE_SIZE reads
-# 262,144 KiB: x1.0).  Valid only for the kernel source the counters were
-# taken on (hash of the blend's source text); otherwise traffic is null.
+# Counters of one launch of each blend kernel on the default workload, from
+# rocprofv3 --pmc runs of `bench.py --profile` (means over the dispatches):
+#   fetch_kib / write_kib  FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each
+#       scaled by what the same counter reads for the 256 MiB device copy the
+#       same run makes (fetch_scale, write_scale: bytes moved / counter bytes)
+#   valu_busy  SQ_ACTIVE_INST_VALU x 4 / (SIMDs x GRBM_GUI_ACTIVE / XCDs)
+#       (GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU sums,
+#       per wavefront, the quad-cycles with a VALU instruction in flight, so a
+#       saturated SIMD whose transcendental instructions overlap the next
+#       wavefront's issue reads above 1)
+#   valu_util  SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU): active lanes
+#       per issued VALU instruction
+#   lds_bank_conflict  SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: conflict
+#       cycles per LDS access cycle
+# Valid only for the kernel source they were taken on (hash of the kernel's
+# source text); otherwise the bench reports them as null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "b56fc39df842dc3654e89ecae82461f7b80cdfb0bb53605143543575fc7eab52",
-    "fetch_kib": 43673.4, "write_kib": 23990.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "source_sha256": "54a9bb7ef43b5af4dbceb596efccb5dbbe190bc5d31afefef99316c79c021032",
+    "fetch_kib": 84085.0, "write_kib": 34441.2, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 0.9248, "valu_util": 0.9841, "lds_bank_conflict": 0.0043,
+}
+RENDER_BWD_COUNTERS = {
+    "source_sha256": "1d415270baf92c596a019c1b9ed4aae33be3f2257f7a0ef56306343a19495d18",
+    "fetch_kib": 85003.3, "write_kib": 113938.6, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 1.0431, "valu_util": 0.9779, "lds_bank_conflict": 0.0,
 }
 
+_SPLIT = "// ------------------------------------------------- wave reduce-scatter-add"
 
-def render_fwd_source_sha():
-    """sha256 over the blend kernel's source: render.hip up to the backward
-    helpers, plus the shared internal header."""
+
+def _render_source_sha(part):
+    """sha256 over the source of one blend kernel: render.hip before (forward)
+    or from (backward) the backward's helpers, plus the internal headers."""
     import hashlib
     base = os.path.join(ROOT, "paper_2508_05343_amd", "csrc")
     with open(os.path.join(base, "render.hip")) as f:
         txt = f.read()
-    cut = txt.index("// ------------------------------------------------- wave reduce-scatter-add")
-    h = hashlib.sha256(txt[:cut].encode())
-    with open(os.path.join(base, "gs_internal.h")) as f:
-        h.update(f.read().encode())
+    cut = txt.index(_SPLIT)
+    h = hashlib.sha256((txt[:cut] if part == "fwd" else txt[cut:]).encode())
+    for hdr in ("gs_internal.h", "gs_sort.h"):
+        with open(os.path.join(base, hdr)) as f:
+            h.update(f.read().encode())
     return h.hexdigest()
 
 
-def render_fwd_traffic():
-    c = RENDER_FWD_COUNTERS
-    if render_fwd_source_sha() != c["source_sha256"]:
-        return None
-    return int(1024 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]))
+def render_fwd_source_sha():
+    return _render_source_sha("fwd")
+
+
+def render_bwd_source_sha():
+    return _render_source_sha("bwd")
+
+
+def kernel_counters(table, sha):
+    """(traffic bytes per launch or None, {valu_busy, valu_util,
+    lds_bank_conflict} or Nones) for a counter table, if taken on this source."""
+    keys = ("valu_busy", "valu_util", "lds_bank_conflict")
+    if sha != table["source_sha256"] or table["fetch_kib"] is None:
+        return None, {k: None for k in keys}
+    traffic = int(1024 * (table["fetch_kib"] * table["fetch_scale"] + table["write_kib"] * table["write_scale"]))
+    return traffic, {k: table[k] for k in keys}
 
 
 def parse():
@@ -191,6 +220,7 @@ def main():
     flops_env, flops_full = 10, 12 + 7 * K  # per evaluation, FMA = 2
     render_flops = flops_env * e_env + flops_full * e_full
     ranges = plan.ranges[:cam.num_tiles].to(torch.int64)
+    bwd_walk = int(plan.n_contrib[:pix].to(torch.int64).sum().item())
     p_read = int((ranges[:, 1] - ranges[:, 0]).sum().item())
     rec_bytes = 4 * (12 + 3 * K)  # record floats the blend uses (fields + the mean's rounding residuals)
     render_bytes = p_read * (4 + rec_bytes) + pix * (12 + 4 + 4) + cam.num_tiles * 8
@@ -209,6 +239,7 @@ def main():
     b_ranges = 8 * P + 8 * cam.num_tiles
     b_fwd = b_pre + b_scan + b_dup + b_sort + b_ranges + render_bytes
     hbm_frac_fwd = (b_fwd / 1e9) / (ms_step_clean * 1e-3) / HBM_PEAK_GBS
+    fwd_traffic, fwd_ctr = kernel_counters(RENDER_FWD_COUNTERS, render_fwd_source_sha())
     out = {
         "metric": "Mpix/s fwd, fwd+bwd step ms @1M Gabor prims; serve p50/p99 latency",
         "value": round(pix / (ms_step_clean * 1e-3) / 1e6, 3),
@@ -230,7 +261,7 @@ def main():
         "fwd_hbm_fraction": round(hbm_frac_fwd, 4),
         "roofline": {"kernel": "k_render_fwd<4>", "bound": "alu", "achieved": round(render_tflops, 3),
                      "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(render_tflops / VALU_PEAK_TFLOPS, 4),
-                     "traffic": render_fwd_traffic(), "evaluations": e_env, "full_evaluations": e_full,
+                     "traffic": fwd_traffic, **fwd_ctr, "evaluations": e_env, "full_evaluations": e_full,
                      "flops_per_launch": int(render_flops), "kernel_ms": round(stage_ms["render_fwd"], 4),
                      "hbm_gbs": round(render_gbs, 1), "hbm_frac": round(render_gbs / HBM_PEAK_GBS, 4),
                      "dominant_stage": dom},
@@ -270,6 +301,43 @@ def main():
         torch.cuda.synchronize()
         out["train_step_ms"] = round(t0.elapsed_time(t1) / ts, 4)
         out["train_loss"] = round(float(lossb.loss.item()), 6)
+
+        # the same steps with HIP events between the backward's two stages
+        # (the blend stage is the grad2d row clear + k_render_bwd)
+        btimer = StageTimer(torch, ["loss", "render_bwd", "project_bwd"])
+
+        def train_step_staged():
+            fwd_step(False)
+            a, b = btimer.pair("loss"); a.record(stream)
+            lossb(img, target)
+            b.record(stream); a, b = btimer.pair("render_bwd"); a.record(stream)
+            plan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_BLEND)
+            b.record(stream); a, b = btimer.pair("project_bwd"); a.record(stream)
+            plan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_PROJECT)
+            b.record(stream)
+
+        for _ in range(ts):
+            train_step_staged()
+        torch.cuda.synchronize()
+        bst = {k: v / ts for k, v in btimer.totals_ms().items()}
+        out["train_stages_ms"] = {k: round(v, 4) for k, v in bst.items()}
+        # algorithmic work of k_render_bwd<4>: each pixel walks its list back
+        # from its last contributor (n_contrib): an envelope test per pair
+        # (10 flops, as the forward) and, for the pairs that pass it (the
+        # forward's count up to its stop: at most the stopping pair more), the
+        # alpha of the forward (12 + 7K) and its gradient (46 + 13K flops:
+        # transmittance recovery, colour and opacity terms, conic, mean and
+        # per-component phase terms, and the sum over pixels of the 10 + 3K
+        # record gradients)
+        bwd_flops = 10 * bwd_walk + (58 + 20 * K) * e_full
+        t_bwd = bst["render_bwd"] * 1e-3
+        bwd_tflops = bwd_flops / t_bwd / 1e12
+        bwd_traffic, bwd_ctr = kernel_counters(RENDER_BWD_COUNTERS, render_bwd_source_sha())
+        out["roofline_bwd"] = {"kernel": "k_render_bwd<4>", "bound": "alu", "achieved": round(bwd_tflops, 3),
+                               "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(bwd_tflops / VALU_PEAK_TFLOPS, 4), "traffic": bwd_traffic, **bwd_ctr,
+                               "walked_pairs": bwd_walk, "full_evaluations": e_full,
+                               "flops_per_launch": int(bwd_flops), "kernel_ms": round(bst["render_bwd"], 4)}
 
     # ---- multi-view training step: 64 views of 800x800, one launch per stage
     if not args.no_multiview:
