@@ -428,6 +428,12 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     Geo g;
     geometry(V, mx, my, mz, tz, q, sc, dil, g);
     if (mip2d) oe *= sqrtf(fmaxf(g.D / g.det, kMip2dMinRatio));
+    // compiler-only barriers around the double-precision part: the loads of
+    // the frequencies, weights and colour row stay after it instead of being
+    // hoisted above it, which keeps the kernel within 128 VGPRs (four
+    // wavefronts per SIMD, the whole grid resident at once; 147 VGPRs and
+    // three wavefronts without them)
+    asm volatile("" ::: "memory");
     double mu_d[2];
     precise_mean(V, mx, my, mz, mu_d);
     const float mux = (float)mu_d[0], muy = (float)mu_d[1];
@@ -462,6 +468,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       const V3 u = mat_vec(g.M, g.c);
       double vx_d[3], vy_d[3];
       precise_frequency_basis(V, mx, my, mz, q, sc, vx_d, vy_d);
+      asm volatile("" ::: "memory");
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
