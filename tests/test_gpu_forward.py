@@ -167,6 +167,44 @@ def test_blend_orders_the_lists_it_is_given_unsorted(gpu_lib, n, seed, hot):
     assert (plan.ranges.cpu().numpy().view(np.uint32)[:plan.tiles] == exp).all()
 
 
+def test_blend_list_sort_at_every_size_boundary(gpu_lib):
+    """Lists of exactly the lengths where the list sort changes method (one
+    wavefront with 1, 2 or 4 keys per lane up to 64, 128 and 256 ids; merged
+    quarters of 2 and 4 keys per lane up to 512 and 1024; the bin sort's
+    long-list kernel beyond) and one either side, with a fifth of the depths
+    drawn from three values so that equal depths are ordered by item: after
+    the blend every list equals the oracle's stable sort."""
+    lens = [1, 2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2049]
+    n = int(sum(lens))
+    sc = synth.uniform_scene(16, n, 1)
+    cam = synth.pinhole_camera(160, 48, 60.0, (0, 0, -3), (0, 0, 0))  # 10 x 3 tiles
+    ds, plan = gpu_plan(sc, [cam], capacity=n + 1024)
+    plan.preprocess()
+    rng = np.random.Generator(np.random.PCG64(17))
+    tile_of = np.repeat(np.arange(len(lens)), lens)
+    rng.shuffle(tile_of)
+    tx, ty = tile_of % cam.tiles_x, tile_of // cam.tiles_x
+    rect = np.stack([tx, ty, tx + 1, ty + 1], 1).astype(np.int32)
+    depth = rng.uniform(0.2, 50.0, size=n).astype(np.float32)
+    ties = rng.uniform(size=n) < 0.2
+    depth[ties] = rng.choice(np.array([1.0, 2.5, 7.25], np.float32), size=int(ties.sum()))
+    vis = np.ones(n, bool)
+    _write_synthetic_geom(plan, rect, depth, vis)
+    plan.bin_sort()
+    plan.render_fwd()
+    torch.cuda.synchronize()
+    assert int(plan.overflow.item()) == 0
+    P = int(plan.num_pairs.item())
+    keys_o, vals_o, exp = _expected_bin_sort([cam], plan, rect, depth, vis, n)
+    assert P == n == len(vals_o)
+    assert (plan.ranges.cpu().numpy().view(np.uint32)[:plan.tiles] == exp).all()
+    vg = plan.vals.cpu().numpy()[:P].view(np.uint32)
+    for t_ in range(len(lens)):
+        a, b = exp[t_]
+        assert b - a == lens[t_]
+        assert (vg[a:b] == vals_o[a:b]).all(), (t_, lens[t_])
+
+
 def test_unsorted_lists_render_exactly_like_sorted_ones(gpu_lib):
     """Config 1's K1 output binned with keys (every list sorted by the bin
     sort) and without (lists ordered by the blend): identical images, final
