@@ -218,20 +218,29 @@ class DeviceArena:
     def __init__(self, device="cuda"):
         self.device = device
         self.bufs: Dict[str, torch.Tensor] = {}
+        self.views: Dict[str, tuple] = {}  # name -> (shape, view) last handed out
         self.allocations = 0  # buffers allocated (first use or growth) so far
 
     def take(self, name: str, shape: tuple, dtype) -> torch.Tensor:
+        shape = tuple(shape)
         numel = math.prod(shape)
         b = self.bufs.get(name)
         if b is None or b.dtype != dtype or b.numel() < numel:
-            # the old buffer is dropped (its last reference included) before
-            # the new one is allocated: the two are never held together
+            # the old buffer (and the view of it) is dropped, its last
+            # reference included, before the new one is allocated: the two
+            # are never held together
             b = None
+            self.views.pop(name, None)
             self.bufs.pop(name, None)
             b = torch.empty(numel, dtype=dtype, device=self.device)
             self.bufs[name] = b
             self.allocations += 1
-        return b[:numel].view(shape)
+        v = self.views.get(name)
+        if v is not None and v[0] == shape:
+            return v[1]  # the same view again (no per-batch view construction)
+        view = b[:numel].view(shape)
+        self.views[name] = (shape, view)
+        return view
 
     def nbytes(self) -> int:
         """Allocator-charged bytes (block_bytes) of the buffers held."""
@@ -246,6 +255,7 @@ class DeviceArena:
         return sum(block_bytes(v) for v in held.values())
 
     def release(self):
+        self.views.clear()
         self.bufs.clear()
 
 
@@ -290,12 +300,16 @@ class RenderPlan:
         self.capacity = int(pair_capacity if pair_capacity is not None else max(1 << 16, 8 * items))
         specs = plan_buffer_specs(self.k, items, pix, tiles, len(self.cams), len(self.scenes), self.capacity,
                                   want_keys)
+        allocated = arena.allocations if arena is not None else None
         for name, (shape, dt) in specs.items():
             setattr(self, name, self._take(name, shape, dt))
         # [tiles][2] ranges, then the blend's dispatch order of the tiles
         self.ranges = self.ranges_buf[:2 * max(tiles, 1)].view(max(tiles, 1), 2)
-        self.num_pairs.zero_()
-        self.overflow.zero_()
+        # defined before the first bin sort (which rewrites both); buffers an
+        # arena hands out again already hold a bin sort's values
+        if arena is None or arena.allocations != allocated:
+            self.num_pairs.zero_()
+            self.overflow.zero_()
         if not want_keys:
             self.keys = None
         self.geom = _lib.Geom()
