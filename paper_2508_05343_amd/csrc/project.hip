@@ -303,16 +303,29 @@ __device__ __forceinline__ float ray_variance(const Geo& g, V3 u, V3 f) {
 constexpr int kPreItems = 4;
 constexpr int kPreBlock = 256 * kPreItems;
 
+// The scene attributes are device memory, but their pointers come out of the
+// view table, so the compiler cannot tell and emits flat loads (64-bit
+// addresses, waits on both memory counters).  gptr() states it: global loads.
+typedef const __attribute__((address_space(1))) float* gfloat_ptr;
+typedef const __attribute__((address_space(1))) float4* gfloat4_ptr;
+__device__ __forceinline__ gfloat_ptr gptr(const float* p) { return (gfloat_ptr)p; }
+
 // The nv (<= 48) colour values of primitive i, stored row by row, into
 // v[0..nv) (zeros after): 16-byte loads when every row starts on a 16-byte
 // boundary, else one float at a time.
-__device__ __forceinline__ void load_colour_row(const float* __restrict__ base, int64_t i, int nv, float (&v)[48]) {
-  const float* row = base + i * nv;
+template <typename P>
+__device__ __forceinline__ void load_colour_row(P base, int64_t i, int nv, float (&v)[48]) {
+  const P row = base + i * nv;
   if ((nv & 3) == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0) {
-    const float4* r4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
-      const float4 x = 4 * j < nv ? r4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (4 * j < nv) {
+        x.x = row[4 * j];
+        x.y = row[4 * j + 1];
+        x.z = row[4 * j + 2];
+        x.w = row[4 * j + 3];
+      }
       v[4 * j] = x.x;
       v[4 * j + 1] = x.y;
       v[4 * j + 2] = x.z;
@@ -352,14 +365,14 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     const int64_t i = base + j * 256 + t;
     if (i >= n) continue;
     const int64_t item = V.item_offset + i;
-    const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+    const float mx = gptr(S.means)[i], my = gptr(S.means)[n + i], mz = gptr(S.means)[2 * n + i];
     const float tz = depth_key(V.R, V.t, mx, my, mz);
     depth_out[item] = tz;
-    const float o = S.opac[i];
+    const float o = gptr(S.opac)[i];
     bool ok = (tz > V.near_plane) && (o * 255.0f > 1.0f);
     if (ok) {
-      float smax = fmaxf(fmaxf(S.scales[i], S.scales[n + i]), S.scales[2 * n + i]);
-      if (mip3d) smax = sqrtf(fmaf(smax, smax, S.filter3d[i]));
+      float smax = fmaxf(fmaxf(gptr(S.scales)[i], gptr(S.scales)[n + i]), gptr(S.scales)[2 * n + i]);
+      if (mip3d) smax = sqrtf(fmaf(smax, smax, gptr(S.filter3d)[i]));
       const float* R = V.R;
       const float tx = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
       const float ty = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
@@ -409,15 +422,15 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
   for (uint32_t c = t; c < total; c += 256) {
     const int64_t i = base + s_cand[c];
     const int64_t item = V.item_offset + i;
-    const float mx = S.means[i], my = S.means[n + i], mz = S.means[2 * n + i];
+    const float mx = gptr(S.means)[i], my = gptr(S.means)[n + i], mz = gptr(S.means)[2 * n + i];
     const float tz = depth_out[item];
-    const float o = S.opac[i];
-    const float q[4] = {S.quats[i], S.quats[n + i], S.quats[2 * n + i], S.quats[3 * n + i]};
-    float sc[3] = {S.scales[i], S.scales[n + i], S.scales[2 * n + i]};
+    const float o = gptr(S.opac)[i];
+    const float q[4] = {gptr(S.quats)[i], gptr(S.quats)[n + i], gptr(S.quats)[2 * n + i], gptr(S.quats)[3 * n + i]};
+    float sc[3] = {gptr(S.scales)[i], gptr(S.scales)[n + i], gptr(S.scales)[2 * n + i]};
     // filtered envelope: scales sqrt(s^2 + v), opacity times prod s / sqrt(s^2 + v)
     float oe = o;
     if (mip3d) {
-      const float fv = S.filter3d[i];
+      const float fv = gptr(S.filter3d)[i];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         const float sf = sqrtf(fmaf(sc[j], sc[j], fv));
@@ -471,9 +484,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       asm volatile("" ::: "memory");
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const V3 f = v3(S.freqs[(int64_t)(3 * k) * n + i], S.freqs[(int64_t)(3 * k + 1) * n + i],
-                        S.freqs[(int64_t)(3 * k + 2) * n + i]);
-        const float wk = S.weights[(int64_t)k * n + i];
+        const V3 f = v3(gptr(S.freqs)[(int64_t)(3 * k) * n + i], gptr(S.freqs)[(int64_t)(3 * k + 1) * n + i],
+                        gptr(S.freqs)[(int64_t)(3 * k + 2) * n + i]);
+        const float wk = gptr(S.weights)[(int64_t)k * n + i];
         r[10 + 3 * k] = (float)(vx_d[0] * f.x + vx_d[1] * f.y + vx_d[2] * f.z);
         r[11 + 3 * k] = (float)(vy_d[0] * f.x + vy_d[1] * f.y + vy_d[2] * f.z);
         r[12 + 3 * k] = atten ? wk * __expf(-kTwoPiSq * ray_variance(g, u, f)) : wk;
@@ -488,7 +501,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         sh_basis(d.x * il, d.y * il, d.z * il, deg, Y);
         const int nd = (deg + 1) * (deg + 1);
         float shv[48];
-        load_colour_row(S.sh, i, 3 * nd, shv);
+        load_colour_row(gptr(S.sh), i, 3 * nd, shv);
         float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
         for (int b = 0; b < 16; ++b) {  // compile-time bound keeps Y in registers
@@ -501,9 +514,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
         r[7] = fmaxf(col[1], 0.f);
         r[8] = fmaxf(col[2], 0.f);
       } else {
-        r[6] = S.colors[3 * i];
-        r[7] = S.colors[3 * i + 1];
-        r[8] = S.colors[3 * i + 2];
+        r[6] = gptr(S.colors)[3 * i];
+        r[7] = gptr(S.colors)[3 * i + 1];
+        r[8] = gptr(S.colors)[3 * i + 2];
       }
 #pragma unroll
       for (int jj = record_mean_lo(K) + 2; jj < RF; ++jj) r[jj] = 0.f;
