@@ -145,6 +145,35 @@ def test_serving_device_memory_within_budget(gpu_lib):
     assert sum(a.allocations for a in ex.arenas) < 14 * st.batches
 
 
+def test_serving_pair_overflow_is_rebinned(gpu_lib):
+    """Pair estimates far too small: batches overflow their pair buffers, wait
+    for larger ones within the budget and are binned again; every request
+    still renders exactly what it renders alone, and the device bytes stay
+    within the budget."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    from paper_2508_05343_amd.serving import GpuExecutor, Job, PairEstimator, Scheduler, serve
+    scenes = [synth.clustered_scene(3300 + s, n, k=4, sh_degree=3) for s, n in enumerate((30000, 60000))]
+    dss = [DeviceScene.from_host(s) for s in scenes]
+    reqs = synth.config5_requests(scenes, n_requests=24, qps=20000.0, seed=13,
+                                  resolutions=((128, 96), (256, 192), (320, 240)))
+    jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
+    sizes = [s.n for s in scenes]
+    sch = Scheduler(sizes, 1 << 30, max_slots=8, max_batch=4, max_inflight=2)
+    sch.est = PairEstimator(prior_pairs_per_pixel=0.001, safety=1.0)  # 4096 pairs per job: too few
+    ex = GpuExecutor(dss, 2)
+    st = serve(jobs, ex, sch, keep_results=True)
+    print(f"retries {st.retries} batches {st.batches} charged {st.max_bytes_in_use} measured {st.peak_bytes_measured}")
+    assert st.requests == 24 and st.retries > 0
+    # the measured peak also holds the images kept for the comparison below
+    kept = sum((t.numel() * t.element_size() + 511) // 512 * 512 for t in st.results.values())
+    assert st.max_bytes_in_use <= 1 << 30
+    assert 0 < st.peak_bytes_measured <= st.max_bytes_in_use + kept
+    for r in reqs:
+        plan = RenderPlan([dss[r.scene]], [r.camera])
+        alone = plan.forward().clone()
+        assert torch.equal(alone, st.results[r.rid].reshape(-1)), r.rid
+
+
 def test_serving_alone_matches_oracle(gpu_lib):
     """A served request (different scene per job in one launch) matches the
     oracle render of its own scene and camera."""
