@@ -58,6 +58,10 @@ extern "C" {
 /* gabsplat_scene_grads.flags */
 #define GABSPLAT_GRAD_ABS_MEAN2D 1
 
+/* Every entry point that launches device work checks its arguments first
+ * (GABSPLAT_ERR_INVALID_ARGUMENT, ..._WORKSPACE_TOO_SMALL, ..._SCRATCH_LIMIT
+ * need no device), then that the current HIP device is a gfx950
+ * (GABSPLAT_ERR_UNSUPPORTED_DEVICE otherwise; asked once per device). */
 typedef enum {
   GABSPLAT_OK = 0,
   GABSPLAT_ERR_INVALID_ARGUMENT = 1,

@@ -3,6 +3,7 @@
 // gabsplat_read_overflow, documented as synchronous).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <vector>
 
@@ -22,6 +23,21 @@ struct WordChunk {
 
 __global__ void k_store_words(uint32_t* __restrict__ dst, WordChunk c) {
   for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
+gabsplat_status device_status() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> cache[kMaxDevices];  // 0 unknown, 1 gfx950, 2 other
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GABSPLAT_ERR_HIP;
+  int c = (dev >= 0 && dev < kMaxDevices) ? cache[dev].load(std::memory_order_relaxed) : 0;
+  if (c == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GABSPLAT_ERR_HIP;
+    c = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    if (dev >= 0 && dev < kMaxDevices) cache[dev].store(c, std::memory_order_relaxed);
+  }
+  return c == 1 ? GABSPLAT_OK : GABSPLAT_ERR_UNSUPPORTED_DEVICE;
 }
 
 hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s) {
@@ -192,11 +208,7 @@ size_t gabsplat_bin_sort_workspace_size(int64_t items, int64_t pair_capacity, in
 
 gabsplat_status gabsplat_check_device(void) {
   try {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return GABSPLAT_ERR_HIP;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GABSPLAT_ERR_HIP;
-    return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? GABSPLAT_OK : GABSPLAT_ERR_UNSUPPORTED_DEVICE;
+    return device_status();
   } catch (...) {
     return GABSPLAT_ERR_HIP;
   }
@@ -217,6 +229,7 @@ gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_sc
     HostTable h = tb.host();
     hipError_t e = upload_table(geom->views, h, s);
     if (e != hipSuccess) return GABSPLAT_ERR_HIP;
+    GS_REQUIRE_DEVICE();
     return hip_status(launch_preprocess(geom->views, h, *geom, s));
   } catch (...) {
     return GABSPLAT_ERR_HIP;
@@ -239,6 +252,7 @@ gabsplat_status gabsplat_bin_sort(const gabsplat_geom* geom, const gabsplat_came
     if (items > 0 && (!geom->depth || !geom->rect || !geom->tiles)) return GABSPLAT_ERR_INVALID_ARGUMENT;
     const BinSortPlan p = plan_bin_sort(items, pair_capacity, (int32_t)tiles);
     if (!ws || ws_bytes < p.bytes) return GABSPLAT_ERR_WORKSPACE_TOO_SMALL;
+    GS_REQUIRE_DEVICE();
     return hip_status(launch_bin_sort(*geom, p, ws, keys, vals, tile_ranges, d_num_pairs, d_overflow,
                                       static_cast<hipStream_t>(stream)));
   } catch (...) {
@@ -262,6 +276,7 @@ gabsplat_status gabsplat_render_fwd(const gabsplat_geom* geom, uint32_t* vals, u
     HostTable h{};
     h.hdr.num_views = num_views;
     h.hdr.total_tiles = (int32_t)tiles;
+    GS_REQUIRE_DEVICE();
     return hip_status(launch_render_fwd(geom->views, h, *geom, geom->k, vals, tile_ranges, image, final_T,
                                         n_contrib, eval_counts, freq_map, d_overflow,
                                         static_cast<hipStream_t>(stream)));
@@ -307,6 +322,7 @@ gabsplat_status gabsplat_render_bwd_stages(const gabsplat_scene* scenes, int32_t
     hipStream_t s = static_cast<hipStream_t>(stream);
     HostTable h = tb.host();
     const bool abs_mean2d = (grads[0].flags & GABSPLAT_GRAD_ABS_MEAN2D) != 0;
+    GS_REQUIRE_DEVICE();
     if (stages & GABSPLAT_BWD_BLEND) {
       hipError_t e = launch_clear_grad2d(geom->tiles, grads[0].grad2d, tb.hdr.total_items,
                                          grad2d_stride(geom->k, grads[0].flags), s);
@@ -340,6 +356,7 @@ gabsplat_status gabsplat_loss_l1_dssim(const float* x, const float* y, int32_t c
         width > 65535 * 16 || channels > 65535 || !(lambda >= 0.f && lambda <= 1.f))
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (!ws || ws_bytes < loss_workspace_bytes(channels, height, width)) return GABSPLAT_ERR_WORKSPACE_TOO_SMALL;
+    GS_REQUIRE_DEVICE();
     return hip_status(launch_loss(x, y, channels, height, width, lambda, d_loss, dl_dx, ws,
                                   static_cast<hipStream_t>(stream)));
   } catch (...) {

@@ -241,6 +241,7 @@ gabsplat_status gabsplat_densify_stats(const gabsplat_geom* geom, const gabsplat
         (grad_flags & ~GABSPLAT_GRAD_ABS_MEAN2D) != 0 || (abs_stat && !accum_abs))
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (n == 0) return GABSPLAT_OK;
+    GS_REQUIRE_DEVICE();
     hipLaunchKernelGGL(k_densify_stats, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), geom->views, n, geom->tiles, grad2d,
                        grad2d_stride(geom->k, grad_flags), abs_stat ? 10 + 3 * geom->k : -1, accum, accum_abs,
@@ -273,6 +274,7 @@ gabsplat_status gabsplat_densify(const gabsplat_scene* in, const float* accum, c
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (in->n > 0 && prm->abs_grad_threshold > 0.f && !accum_abs) return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (!ws || ws_bytes < gabsplat_densify_workspace_size(in->n)) return GABSPLAT_ERR_WORKSPACE_TOO_SMALL;
+    GS_REQUIRE_DEVICE();
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nblocks = (int)((in->n + kDenBlock - 1) / kDenBlock);
     uint32_t* counts = static_cast<uint32_t*>(ws);
@@ -298,6 +300,7 @@ gabsplat_status gabsplat_reset_frequency_weights(const gabsplat_scene_out* scene
         (scene->n > 0 && (!scene->opacities || (scene->k > 0 && !scene->weights))))
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (scene->n == 0) return GABSPLAT_OK;
+    GS_REQUIRE_DEVICE();
     hipLaunchKernelGGL(k_reset_weights, dim3((unsigned)((scene->n + 255) / 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), *scene, weight_value, opacity_cap);
     return hipGetLastError() == hipSuccess ? GABSPLAT_OK : GABSPLAT_ERR_HIP;

@@ -99,6 +99,17 @@ struct HostTable {
   SceneEntry* scenes;  // host array [num_scenes]
 };
 
+// Whether the current HIP device is a gfx950 (GABSPLAT_OK), is not
+// (GABSPLAT_ERR_UNSUPPORTED_DEVICE), or cannot be queried (GABSPLAT_ERR_HIP).
+// Asked once per device; every entry point that launches work checks it after
+// its argument checks (so invalid arguments are reported without a device).
+gabsplat_status device_status();
+#define GS_REQUIRE_DEVICE()                                       \
+  do {                                                            \
+    const gabsplat_status ds_ = ::gs::device_status();             \
+    if (ds_ != GABSPLAT_OK) return ds_;                           \
+  } while (0)
+
 // --- launchers (each returns hipSuccess or the first launch error) ---------
 hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s);
 // Copies `bytes` (a multiple of 4) of host memory to device memory with small

@@ -354,6 +354,7 @@ extern "C" gabsplat_status gabsplat_loss_l1_dssim_noalloc(const float* x, const 
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (gs::loss_workspace_bytes(channels, height, width) > GABSPLAT_LOSS_NOALLOC_SCRATCH_BYTES)
       return GABSPLAT_ERR_SCRATCH_LIMIT;
+    GS_REQUIRE_DEVICE();
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = -1;
     if (hipStreamGetDevice(s, &dev) != hipSuccess) return GABSPLAT_ERR_HIP;

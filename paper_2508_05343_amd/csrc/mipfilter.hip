@@ -108,6 +108,7 @@ gabsplat_status gabsplat_mip_filter3d(const float* means, int64_t n, const gabsp
         return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (n == 0) return GABSPLAT_OK;
     if (!ws || ws_bytes < gabsplat_mip_filter3d_workspace_size(n, num_cams)) return GABSPLAT_ERR_WORKSPACE_TOO_SMALL;
+    GS_REQUIRE_DEVICE();
     std::vector<MipCam> table((size_t)num_cams);
     for (int c = 0; c < num_cams; ++c) {
       const gabsplat_camera& g = cams[c];

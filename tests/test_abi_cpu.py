@@ -171,3 +171,17 @@ def test_device_scene_rejects_bad_layouts():
         DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(27, n), z(9, n), colors=z(n, 3))
     with pytest.raises(ValueError, match="exactly one"):
         DeviceScene(z(3, n), z(3, n), z(4, n), z(n), z(3 * k, n), z(k, n))
+
+
+def test_no_launch_without_a_gfx950(L):
+    """Arguments that pass every check stop at the device check when the
+    current device is not a gfx950 (here: no device), before any launch."""
+    lib = L.lib()
+    st0 = lib.gabsplat_check_device()
+    if st0 == L.OK:
+        pytest.skip("a gfx950 is present: the calls below would launch with placeholder pointers")
+    assert st0 in (L.HIP_ERROR, L.UNSUPPORTED_DEVICE)
+    fake = 256  # never dereferenced: the call returns before any device work
+    wsb = lib.gabsplat_loss_workspace_size(3, 4, 4)
+    assert lib.gabsplat_loss_l1_dssim(fake, fake, 3, 4, 4, 0.2, fake, fake, fake, wsb, None) == st0
+    assert lib.gabsplat_loss_l1_dssim_noalloc(fake, fake, 3, 4, 4, 0.2, fake, fake, None) == st0
