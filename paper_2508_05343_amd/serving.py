@@ -163,8 +163,11 @@ class Scheduler:
 
 
 def serve(requests: Sequence[Job], executor, scheduler: Scheduler, clock=time.perf_counter,
-          keep_results=False, sleep=time.sleep) -> ServeStats:
-    """Run the request trace in real time (arrival_s relative to the start)."""
+          keep_results=False, sleep=time.sleep, spin_s=3e-4) -> ServeStats:
+    """Run the request trace in real time (arrival_s relative to the start).
+    While idle it sleeps until spin_s before the next arrival and polls from
+    there: a sleep overshoots by tens of microseconds, which would be added
+    to that request's latency."""
     queue = deque(sorted(requests, key=lambda j: (j.arrival_s, j.rid)))
     inflight = []  # [handle, jobs, pair capacities of a pending retry or None]
     t0 = clock()
@@ -219,8 +222,8 @@ def serve(requests: Sequence[Job], executor, scheduler: Scheduler, clock=time.pe
         if not inflight and queue:
             # idle until the next arrival
             wait = queue[0].arrival_s - (clock() - t0)
-            if wait > 0:
-                sleep(min(wait, 0.001))
+            if wait > spin_s:
+                sleep(min(wait - spin_s, 0.001))
     wall = clock() - t0
     st = ServeStats(lat, wall, len(requests), pixels, batches, max_jobs, scheduler.max_in_use, retries,
                     executor.peak_bytes_measured(), list(executor.host_ms))
