@@ -84,6 +84,32 @@ __device__ __forceinline__ void load_run(const float* row, float (&v)[kRunIn]) {
   v[13] = t.y;
 }
 
+// Output tile of a block.  Consecutive workgroups go to the GPU's 8 XCDs in
+// turn and each XCD has its own L2, while the staged halos of neighbouring
+// tiles overlap: neighbours should run on one XCD.  Workgroup b (linear id,
+// x fastest) runs on XCD b % 8, so the blocks with b % 8 = j take the j-th
+// contiguous run of tiles (runs of ceil(n/8) tiles, then of floor(n/8)): a
+// permutation of the tiles, whatever order the dispatch actually uses.
+constexpr uint32_t kXcds = 8;
+struct TileId {
+  int x, y, c;
+  uint32_t linear;
+};
+
+__device__ __forceinline__ TileId xcd_tile() {
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  const uint32_t n = gx * gy * gridDim.z;
+  const uint32_t b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t q = n / kXcds, r = n % kXcds, j = b % kXcds, k = b / kXcds;
+  const uint32_t t = j < r ? j * (q + 1) + k : r * (q + 1) + (j - r) * q + k;
+  TileId id;
+  id.x = (int)(t % gx);
+  id.y = (int)((t / gx) % gy);
+  id.c = (int)(t / (gx * gy));
+  id.linear = t;
+  return id;
+}
+
 // pass 1: moments, SSIM map, per-pixel factors for the backward, partial sums
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Window win, float lambda, float inv_n,
@@ -93,8 +119,9 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
   if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *counter = 0u;
   __shared__ __align__(16) float s_h[5][kSY][kTX];
   __shared__ float s_red[4];
-  const int c = blockIdx.z;
-  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY;
+  const TileId tid = xcd_tile();
+  const int c = tid.c;
+  const int ox = tid.x * kTX, oy = tid.y * kTY;
   const size_t plane = (size_t)H * W;
   const float* const src[2] = {x + c * plane, y + c * plane};
   stage_planes<2>(src, H, W, ox, oy, s_in);
@@ -174,9 +201,8 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
   const float ts = block_sum(ssim, s_red);
   const float tl = block_sum(l1, s_red);
   if (threadIdx.x == 0) {
-    const size_t bi = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    partial[2 * bi] = tl;
-    partial[2 * bi + 1] = ts;
+    partial[2 * (size_t)tid.linear] = tl;
+    partial[2 * (size_t)tid.linear + 1] = ts;
   }
 }
 
@@ -186,8 +212,9 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
                                                   const float* __restrict__ f3, float* __restrict__ dl_dx) {
   __shared__ __align__(16) float s_f[3][kSY][kSP];
   __shared__ __align__(16) float s_h[3][kSY][kTX];
-  const int c = blockIdx.z;
-  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY;
+  const TileId tid = xcd_tile();
+  const int c = tid.c;
+  const int ox = tid.x * kTX, oy = tid.y * kTY;
   const size_t plane = (size_t)H * W;
   const size_t nn = plane * gridDim.z;
   const float* const src[3] = {f3 + c * plane, f3 + nn + c * plane, f3 + 2 * nn + c * plane};
