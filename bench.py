@@ -44,14 +44,14 @@ VALU_PEAK_TFLOPS = 78.6
 # Valid only for the kernel source they were taken on (hash of the kernel's
 # source text); otherwise the bench reports them as null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "54a9bb7ef43b5af4dbceb596efccb5dbbe190bc5d31afefef99316c79c021032",
-    "fetch_kib": 84145.0, "write_kib": 34449.2, "fetch_scale": 2.0, "write_scale": 1.0,
-    "valu_busy": 0.9252, "valu_util": 0.9841, "lds_bank_conflict": 0.0043,
+    "source_sha256": "4a95decdab2a09777db791a6d0d789c745b0de8e86b445f4bbd7d3b70931bad4",
+    "fetch_kib": 84168.8, "write_kib": 34427.3, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 0.9279, "valu_util": 0.9841, "lds_bank_conflict": 0.0043,
 }
 RENDER_BWD_COUNTERS = {
-    "source_sha256": "1d415270baf92c596a019c1b9ed4aae33be3f2257f7a0ef56306343a19495d18",
-    "fetch_kib": 85006.3, "write_kib": 113938.6, "fetch_scale": 2.0, "write_scale": 1.0,
-    "valu_busy": 1.0462, "valu_util": 0.9779, "lds_bank_conflict": 0.0,
+    "source_sha256": "13e95d96bb60104b2ef59e9757cf8fe751159972945532a92e030271fd151b49",
+    "fetch_kib": 85144.0, "write_kib": 113938.6, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 1.0399, "valu_util": 0.9779, "lds_bank_conflict": 0.0,
 }
 
 _SPLIT = "// ------------------------------------------------- wave reduce-scatter-add"
