@@ -133,8 +133,9 @@ class StageTimer:
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this rasterizer build has no multi-GPU path "
-              "(see the sharding note in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the rasterizer has no multi-GPU path "
+              "(one GPU renders its own views; a batch of views would shard across GPUs by view); "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.profile:
         args.steps, args.warmup, args.no_cpu_baseline = min(args.steps, 5), min(args.warmup, 2), True
@@ -157,8 +158,8 @@ def main():
               flush=True)
         return
 
-    scene = synth.config2_scene()
-    cam = synth.config2_camera()
+    scene = synth.scene_1m_k4_sh3()
+    cam = synth.camera_1297x840()
     ds = DeviceScene.from_host(scene)
     plan = RenderPlan([ds], [cam])
     # establish the pair capacity (host sync allowed outside the timed region)
@@ -217,7 +218,10 @@ def main():
     e_env = int(counts[:, 0].to(torch.int64).sum().item())
     e_full = int(counts[:, 1].to(torch.int64).sum().item())
     K = plan.k
-    flops_env, flops_full = 10, 12 + 7 * K  # per evaluation, FMA = 2
+    # per evaluation, an FMA counting 2 and a transcendental 1: the envelope test
+    # (2 subtractions, 3 multiplies, 3 FMAs) and the full evaluation (exp2; per
+    # component 2 FMAs for the phase, cos and an FMA; clamp, T - aT, aT, 3 colour FMAs)
+    flops_env, flops_full = 10, 12 + 7 * K
     render_flops = flops_env * e_env + flops_full * e_full
     ranges = plan.ranges[:cam.num_tiles].to(torch.int64)
     bwd_walk = int(plan.n_contrib[:pix].to(torch.int64).sum().item())
@@ -229,7 +233,9 @@ def main():
     t_render = stage_ms["render_fwd"] * 1e-3
     render_tflops = render_flops / t_render / 1e12
     render_gbs = (render_bytes / 1e9) / t_render
-    # pass-aware algorithmic bytes of the whole forward (byte model in the design doc)
+    # pass-aware algorithmic bytes of the whole forward: preprocess (means of all,
+    # parameters of the visible, records written, depth/rect/tiles of all), compaction,
+    # duplication, a six-pass 8-bit sort of the pairs, ranges, and the blend
     N, V = scene.n, vis
     params_visible = 4 * (3 + 4 + 1 + 48 + 4 * K)
     b_pre = 12 * N + params_visible * V + 4 * (12 + 3 * K) * V + 4 * 4 * N
@@ -418,8 +424,8 @@ def multiview_step(args, torch, synth, DeviceScene, RenderPlan, LossBuffers):
     """300k primitives, K=4, SH3, 64 cameras on an orbit at 800x800: forward
     over all views (one launch per stage), loss over all views (one launch),
     backward over all views with the gradients summed over views in fp32."""
-    scene = synth.config4_scene()
-    cams = synth.config4_cameras()
+    scene = synth.scene_300k_k4_sh3()
+    cams = synth.orbit_cameras_64x800()
     ds = DeviceScene.from_host(scene)
     plan = RenderPlan([ds], cams, [0] * len(cams), pair_capacity=12 * scene.n * len(cams))
     plan.forward(check_overflow=True)
@@ -461,9 +467,9 @@ def serving_run(args, torch, synth):
     cameras and resolutions; continuous batching vs one request at a time."""
     from paper_2508_05343_amd.rasterize import DeviceScene
     from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
-    scenes = synth.config5_scenes()
+    scenes = synth.serving_scenes()
     dss = [DeviceScene.from_host(s) for s in scenes]
-    reqs = synth.config5_requests(scenes, n_requests=args.serve_requests, qps=args.serve_qps)
+    reqs = synth.serving_requests(scenes, n_requests=args.serve_requests, qps=args.serve_qps)
     sizes = [s.n for s in scenes]
     budget = 6 << 30
 
@@ -484,7 +490,7 @@ def serving_run(args, torch, synth):
                        f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB budget for job buffers")
     sweep = []
     for q in [float(x) for x in args.serve_sweep.split(",") if x]:
-        rq = synth.config5_requests(scenes, n_requests=600, qps=q, seed=1005 + int(q))
+        rq = synth.serving_requests(scenes, n_requests=600, qps=q, seed=1005 + int(q))
         row = {"qps": q}
         for mode, sch, ns in (("continuous", Scheduler(sizes, budget, max_slots=16, max_batch=16, max_inflight=2), 2),
                               ("sequential", Scheduler(sizes, budget, max_slots=1, max_batch=1, max_inflight=1), 1)):

@@ -9,14 +9,14 @@ from .scenes import (  # noqa: F401
     Scene,
     look_at,
     pinhole_camera,
-    config1_scene,
-    config1_camera,
-    config2_scene,
-    config2_camera,
-    config4_scene,
-    config4_cameras,
-    config5_scenes,
-    config5_requests,
+    scene_1k_k2_rgb,
+    camera_128,
+    scene_1m_k4_sh3,
+    camera_1297x840,
+    scene_300k_k4_sh3,
+    orbit_cameras_64x800,
+    serving_scenes,
+    serving_requests,
     clustered_scene,
     uniform_scene,
     random_geom,

@@ -237,32 +237,32 @@ def _random_orthonormal(rng, m):
 # --------------------------------------------------------------------------
 # the named workloads
 # --------------------------------------------------------------------------
-def config1_scene(seed=1001) -> Scene:
+def scene_1k_k2_rgb(seed=1001) -> Scene:
     """1,000 primitives, K=2, RGB colour, means U[-1,1]^3, log-scales N(-3,0.5)."""
     return uniform_scene(seed, 1000, 2, sh_degree=-1)
 
 
-def config1_camera() -> Camera:
+def camera_128() -> Camera:
     """128x128, 60 degree horizontal FOV, at distance 3 looking at the origin."""
     return pinhole_camera(128, 128, 60.0, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0))
 
 
-def config2_scene(seed=1002, n=1_000_000) -> Scene:
+def scene_1m_k4_sh3(seed=1002, n=1_000_000) -> Scene:
     """1M primitives, K=4, SH degree 3, 64 clusters in a 20-unit box."""
     return clustered_scene(seed, n, k=4, sh_degree=3)
 
 
-def config2_camera() -> Camera:
+def camera_1297x840() -> Camera:
     """1297x840 pinhole inside the scene at (0,0,-6) looking along +z."""
     return pinhole_camera(1297, 840, 60.0, eye=(0.0, 0.0, -6.0), target=(0.0, 0.0, 0.0))
 
 
-def config4_scene(seed=1004, n=300_000) -> Scene:
+def scene_300k_k4_sh3(seed=1004, n=300_000) -> Scene:
     """300k primitives, K=4, SH3, means uniform in the unit ball."""
     return ball_scene(seed, n, 4, sh_degree=3)
 
 
-def config4_cameras(n_views=64, res=800, radius=4.0, elev_deg=30.0, hfov=40.0) -> List[Camera]:
+def orbit_cameras_64x800(n_views=64, res=800, radius=4.0, elev_deg=30.0, hfov=40.0) -> List[Camera]:
     """Orbit of cameras at 30 degree elevation looking at the origin, white bg."""
     cams = []
     el = math.radians(elev_deg)
@@ -275,12 +275,12 @@ def config4_cameras(n_views=64, res=800, radius=4.0, elev_deg=30.0, hfov=40.0) -
     return cams
 
 
-CONFIG5_SIZES = (100_000, 250_000, 500_000, 1_000_000, 1_000_000, 1_500_000,
-                 2_000_000, 2_000_000)
-CONFIG5_RESOLUTIONS = ((256, 256), (800, 800), (1297, 840), (1920, 1080))
+SERVING_SCENE_SIZES = (100_000, 250_000, 500_000, 1_000_000, 1_000_000, 1_500_000,
+                       2_000_000, 2_000_000)
+SERVING_RESOLUTIONS = ((256, 256), (800, 800), (1297, 840), (1920, 1080))
 
 
-def config5_scenes(sizes: Sequence[int] = CONFIG5_SIZES, base_seed=1005) -> List[Scene]:
+def serving_scenes(sizes: Sequence[int] = SERVING_SCENE_SIZES, base_seed=1005) -> List[Scene]:
     return [clustered_scene(base_seed + 2000 + s, int(n), k=4, sh_degree=3)
             for s, n in enumerate(sizes)]
 
@@ -293,8 +293,8 @@ class Request:
     camera: Camera
 
 
-def config5_requests(scenes: Sequence[Scene], n_requests=2000, qps=200.0, seed=1005,
-                     resolutions=CONFIG5_RESOLUTIONS) -> List[Request]:
+def serving_requests(scenes: Sequence[Scene], n_requests=2000, qps=200.0, seed=1005,
+                     resolutions=SERVING_RESOLUTIONS) -> List[Request]:
     """Poisson arrivals; scene uniform; resolution uniform; random camera in the
     box looking at a random cluster centre of the chosen scene."""
     rng = np.random.Generator(np.random.PCG64(seed))

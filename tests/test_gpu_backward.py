@@ -57,8 +57,8 @@ def test_backward_small_sh_scene(gpu_lib, deg):
     _check_grads(sc, cam, 5, scene_name=f"sh{deg} k2")
 
 
-def test_backward_config1(gpu_lib):
-    _check_grads(synth.config1_scene(), synth.config1_camera(), 6, scene_name="config1")
+def test_backward_1k_scene(gpu_lib):
+    _check_grads(synth.scene_1k_k2_rgb(), synth.camera_128(), 6, scene_name="1k scene")
 
 
 def test_backward_k4_sh3_rotated_camera(gpu_lib):

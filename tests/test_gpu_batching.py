@@ -101,7 +101,7 @@ def test_serving_mix_equals_alone(gpu_lib):
     from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
     scenes = [synth.clustered_scene(3000 + s, n, k=4, sh_degree=3) for s, n in enumerate((20000, 50000, 30000))]
     dss = [DeviceScene.from_host(s) for s in scenes]
-    reqs = synth.config5_requests(scenes, n_requests=40, qps=20000.0, seed=9,
+    reqs = synth.serving_requests(scenes, n_requests=40, qps=20000.0, seed=9,
                                   resolutions=((64, 64), (100, 75), (160, 96)))
     jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
     sch = Scheduler([s.n for s in scenes], 1 << 33, max_slots=16, max_batch=8, max_inflight=2)
@@ -124,7 +124,7 @@ def test_serving_device_memory_within_budget(gpu_lib):
     from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
     scenes = [synth.clustered_scene(3200 + s, n, k=4, sh_degree=3) for s, n in enumerate((20000, 60000))]
     dss = [DeviceScene.from_host(s) for s in scenes]
-    reqs = synth.config5_requests(scenes, n_requests=48, qps=20000.0, seed=11,
+    reqs = synth.serving_requests(scenes, n_requests=48, qps=20000.0, seed=11,
                                   resolutions=((64, 64), (128, 96), (200, 160)))
     jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
     sizes = [s.n for s in scenes]
@@ -154,7 +154,7 @@ def test_serving_pair_overflow_is_rebinned(gpu_lib):
     from paper_2508_05343_amd.serving import GpuExecutor, Job, PairEstimator, Scheduler, serve
     scenes = [synth.clustered_scene(3300 + s, n, k=4, sh_degree=3) for s, n in enumerate((30000, 60000))]
     dss = [DeviceScene.from_host(s) for s in scenes]
-    reqs = synth.config5_requests(scenes, n_requests=24, qps=20000.0, seed=13,
+    reqs = synth.serving_requests(scenes, n_requests=24, qps=20000.0, seed=13,
                                   resolutions=((128, 96), (256, 192), (320, 240)))
     jobs = [Job(r.rid, r.scene, r.camera, r.arrival_s) for r in reqs]
     sizes = [s.n for s in scenes]

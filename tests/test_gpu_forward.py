@@ -16,8 +16,8 @@ def _rel(a, b, floor):
     return np.abs(a - b) / (np.abs(b) + floor)
 
 
-def test_preprocess_matches_oracle_config1(gpu_lib):
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+def test_preprocess_matches_oracle_1k_scene(gpu_lib):
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     ds, plan = gpu_plan(sc, [cam])
     plan.preprocess()
     torch.cuda.synchronize()
@@ -206,10 +206,10 @@ def test_blend_list_sort_at_every_size_boundary(gpu_lib):
 
 
 def test_unsorted_lists_render_exactly_like_sorted_ones(gpu_lib):
-    """Config 1's K1 output binned with keys (every list sorted by the bin
+    """The 1000-primitive scene's K1 output binned with keys (every list sorted by the bin
     sort) and without (lists ordered by the blend): identical images, final
     transmittances, contributor counts, lists and ranges, bit for bit."""
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     outs = []
     for want_keys in (True, False):
         ds, plan = gpu_plan(sc, [cam], want_keys=want_keys)
@@ -222,11 +222,11 @@ def test_unsorted_lists_render_exactly_like_sorted_ones(gpu_lib):
         assert a.shape == b.shape and (a.view(np.uint32) == b.view(np.uint32)).all()
 
 
-def test_bin_sort_end_to_end_config1(gpu_lib):
-    """K1 + K2-K5 on config 1: the GPU's sorted keys equal the oracle's
+def test_bin_sort_end_to_end_1k_scene(gpu_lib):
+    """K1 + K2-K5 on the 1000-primitive scene: the GPU's sorted keys equal the oracle's
     (no primitive of this scene sits within the rect tolerance of a tile
     boundary, so the comparison is exact)."""
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     ds, plan = gpu_plan(sc, [cam], want_keys=True)
     plan.preprocess()
     plan.bin_sort()
@@ -247,14 +247,14 @@ def test_bin_sort_end_to_end_config1(gpu_lib):
     assert_dispatch_order(plan)
 
 
-def test_render_forward_config1(gpu_lib):
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+def test_render_forward_1k_scene(gpu_lib):
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     ds, plan = gpu_plan(sc, [cam])
     plan.forward()
     torch.cuda.synchronize()
     ref = O.render_scene(sc, cam, "binned")
     img = plan.view_image(0).cpu().numpy()
-    assert_image(img, ref, "config1")
+    assert_image(img, ref, "1k scene")
     T = plan.view_final_T(0).cpu().numpy()
     ok = ~ref.fragile
     assert np.abs(T - ref.final_T.numpy())[ok].max() <= 1e-4
@@ -276,7 +276,7 @@ def test_render_forward_high_frequency(gpu_lib):
     """Frequencies scaled so that |f2d| reaches ~0.5 cycles/px."""
     sc = synth.uniform_scene(32, 2000, 3, sh_degree=-1, log_scale_mu=-2.8)
     sc.freqs *= 12.0
-    cam = synth.config1_camera()
+    cam = synth.camera_128()
     ds, plan = gpu_plan(sc, [cam])
     plan.forward()
     pr = oracle_project(sc, cam)
@@ -314,7 +314,7 @@ def test_render_forward_empty_and_culled(gpu_lib):
 
 
 def test_forward_is_deterministic(gpu_lib):
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     ds, plan = gpu_plan(sc, [cam])
     a = plan.forward().clone()
     b = plan.forward().clone()
@@ -324,7 +324,7 @@ def test_forward_is_deterministic(gpu_lib):
 def test_capacity_overflow_and_retry(gpu_lib):
     """A pair capacity that is too small sets the device flag; the plan grows
     its buffers and reaches the same image."""
-    sc, cam = synth.config1_scene(), synth.config1_camera()
+    sc, cam = synth.scene_1k_k2_rgb(), synth.camera_128()
     ds, plan = gpu_plan(sc, [cam], capacity=100)
     plan.preprocess()
     plan.bin_sort()

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def big():
     from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
-    sc, cam = synth.config2_scene(), synth.config2_camera()
+    sc, cam = synth.scene_1m_k4_sh3(), synth.camera_1297x840()
     ds = DeviceScene.from_host(sc)
     plan = RenderPlan([ds], [cam])
     plan.forward()
@@ -28,7 +28,7 @@ def big():
     return sc, cam, ds, plan, pr
 
 
-def test_config2_depth_keys_and_visibility(gpu_lib, big):
+def test_1m_frame_depth_keys_and_visibility(gpu_lib, big):
     sc, cam, ds, plan, pr = big
     d = plan.depth.cpu().numpy()[:sc.n]
     assert (d.view(np.uint32) == pr.depth32.view(np.uint32)).all()
@@ -42,7 +42,7 @@ def test_config2_depth_keys_and_visibility(gpu_lib, big):
     print(f"visible {vis_o.sum()} pairs {P} fragile rects {pr.fragile_rect.sum()}")
 
 
-def test_config2_heaviest_tiles_binned_order(gpu_lib, big):
+def test_1m_frame_heaviest_tiles_binned_order(gpu_lib, big):
     """The tiles with the most pairs (chosen from the oracle's rects) come out
     of the GPU binning in the oracle's (depth, index) order, item for item
     (items with a fragile rect are left out of both lists)."""
@@ -65,7 +65,7 @@ def test_config2_heaviest_tiles_binned_order(gpu_lib, big):
         assert np.array_equal(got, ref), (tx, ty, len(got), len(ref))
 
 
-def test_config2_records_of_every_visible_primitive(gpu_lib, big):
+def test_1m_frame_records_of_every_visible_primitive(gpu_lib, big):
     """K1 at full size: the render record of every visible primitive (mean,
     conic, opacity, colour, 2D frequencies and weights) against the oracle's
     projection, within 1e-5 relative (conic and frequencies relative to the
@@ -92,7 +92,7 @@ def test_config2_records_of_every_visible_primitive(gpu_lib, big):
     assert (np.abs(f["w0"][:sc.n][m] - w0) <= 1e-6).all()
 
 
-def test_config2_whole_frame_forward(gpu_lib, big):
+def test_1m_frame_whole_frame_forward(gpu_lib, big):
     """Every pixel of the 1297x840 frame (all 4346 tiles, ragged edge tiles
     included) against the oracle's binned fp64 blend, and the last blended
     primitive of every non-fragile pixel."""
@@ -100,7 +100,7 @@ def test_config2_whole_frame_forward(gpu_lib, big):
     with torch.no_grad():
         ref = O.render(None, O.camera_tensors(cam), "binned", scene_f32=sc, pr=pr)
     img = plan.view_image(0).cpu().numpy()
-    assert_image(img, ref, "config2 whole frame")
+    assert_image(img, ref, "1M frame")
     ok = ~ref.fragile
     T = plan.view_final_T(0).cpu().numpy()
     assert np.abs(T - ref.final_T.numpy())[ok].max() <= 1e-4
@@ -118,7 +118,7 @@ def _gpu_prim_grads(grads, prims, n):
             "weights": grads["weights"].cpu().numpy()[:, prims].T}
 
 
-def test_config3_sampled_primitive_gradients(gpu_lib, big):
+def test_1m_frame_sampled_primitive_gradients(gpu_lib, big):
     """render_bwd at full size with a seeded image gradient: every attribute
     gradient of 200 seeded visible primitives, drawn from every tile-count
     class (30 with one tile ... 24 with 50 to 400 tiles, whose gradients sum
@@ -145,7 +145,7 @@ def test_config3_sampled_primitive_gradients(gpu_lib, big):
                         lambda rows: slack_rows(big_[rows]), ">= 50 tiles")
 
 
-def test_config3_loss_full_frame(gpu_lib, big):
+def test_1m_frame_loss_full_frame(gpu_lib, big):
     from paper_2508_05343_amd.rasterize import LossBuffers
     sc, cam, ds, plan, pr = big
     # seeded image and target of the full frame size (no input comes from the GPU path)

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def mv():
     from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
-    sc, cams = synth.config4_scene(), synth.config4_cameras()
+    sc, cams = synth.scene_300k_k4_sh3(), synth.orbit_cameras_64x800()
     ds = DeviceScene.from_host(sc)
     plan = RenderPlan([ds], cams)
     plan.forward(check_overflow=True)
@@ -41,7 +41,7 @@ def _tile_lists(plan, v, cam, tiles):
     return out
 
 
-def test_config4_sampled_views_binning_and_blend(gpu_lib, mv):
+def test_64_views_sampled_views_binning_and_blend(gpu_lib, mv):
     sc, cams, plan = mv
     assert sum(c.num_tiles for c in cams) > 8192  # the radix path
     assert_dispatch_order(plan)
@@ -79,7 +79,7 @@ def test_config4_sampled_views_binning_and_blend(gpu_lib, mv):
             assert (ids[ok] == ref.last_id[ys, xs][ok]).all(), (v, tx, ty)
 
 
-def test_config4_backward_one_view_sampled_gradients(gpu_lib, mv):
+def test_64_views_backward_one_view_sampled_gradients(gpu_lib, mv):
     """The backward over all 64 views at full size, with a seeded image
     gradient on one seeded view and zero on the others: the summed gradients
     of 24 seeded primitives that view sees, drawn from every tile-count class

@@ -23,7 +23,7 @@ STEP = dict(means=1e-6, scales=1e-6, quats=1e-6, opacities=1e-6, sh=1e-5, freqs=
 
 @pytest.fixture(scope="module")
 def frame():
-    sc, cam = synth.config2_scene(), synth.config2_camera()
+    sc, cam = synth.scene_1m_k4_sh3(), synth.camera_1297x840()
     with torch.no_grad():
         pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     g_img = synth.random_dl_dimage(1003, (3, cam.height, cam.width))

@@ -140,8 +140,8 @@ def test_paper_two_step_frequency_formula(completion):
     """f_proj = (JW)^-T f (Sec. 3.3.1) then f2d = f_proj,xy - S_xy,z/S_zz f_proj,z
     with S the inverse of J W Sigma W^T J^T (Sec. 3.3.2), for two different
     completions of J's third row, equals the oracle's 2D frequency."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     ct = O.camera_tensors(cam)
     pr = O.project(O.scene_tensors(sc), ct, sc)
     R = cam.R.astype(np.float64)
@@ -173,8 +173,8 @@ def test_ray_space_quadrature_of_the_gabor_kernel():
     the 2D covariance is the oracle's raw covariance (supplementary A.2, whose
     final formula keeps only the phase; its C2 factor carries the wrong sign)."""
     from scipy.integrate import quad
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     R = cam.R.astype(np.float64)
     rng = np.random.Generator(np.random.PCG64(5))
@@ -205,8 +205,8 @@ def test_ray_space_quadrature_of_the_gabor_kernel():
 def test_covariance_uses_the_perspective_jacobian():
     """The 2D covariance equals J Sigma J^T with J the finite-difference
     Jacobian of the pixel projection t -> (fx tx/tz + cx, fy ty/tz + cy)."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     R = cam.R.astype(np.float64)
     proj = lambda t: np.array([cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy])  # noqa: E731
@@ -346,12 +346,12 @@ def _gaussian_splat_loop(pr, order, x, y, bg):
 def test_reduces_to_gaussian_splatting(which):
     """With every frequency weight zero, or every frequency zero, the
     primitive is the 3DGS Gaussian (Sec. 3.2.2)."""
-    sc = synth.config1_scene()
+    sc = synth.scene_1k_k2_rgb()
     if which == "weights_zero":
         sc.weights[:] = 0
     else:
         sc.freqs[:] = 0
-    cam = synth.config1_camera()
+    cam = synth.camera_128()
     img = O.render_scene(sc, cam, "binned")
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     order = O.depth_order(pr.depth32, pr.visible.numpy())
@@ -365,8 +365,8 @@ def test_reduces_to_gaussian_splatting(which):
 def test_transmittance_and_convexity():
     """T is in (0, 1]; the colour is a convex combination of the primitive
     colours and the background (weights a_i T_i and T_final sum to one)."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     cam.bg = (0.0, 0.0, 0.0)
     img = O.render_scene(sc, cam, "binned")
     T = img.final_T.numpy()
@@ -383,8 +383,8 @@ def test_transmittance_and_convexity():
 
 def test_transmittance_monotone_along_the_walk():
     """The final T of ever longer front-to-back candidate prefixes never grows."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     order = O.depth_order(pr.depth32, pr.visible.numpy())
     rng = np.random.Generator(np.random.PCG64(6))
@@ -399,8 +399,8 @@ def test_transmittance_monotone_along_the_walk():
 
 
 def test_brute_equals_binned_and_loop():
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     a = O.render_scene(sc, cam, "brute")
     b = O.render_scene(sc, cam, "binned")
     assert float((a.color - b.color).abs().max()) < 1e-14
@@ -416,8 +416,8 @@ def test_brute_equals_binned_and_loop():
 
 
 def test_frequency_sign_and_component_permutation_invariance():
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     base = O.render_scene(sc, cam, "binned")
     s2 = sc.subset(np.arange(sc.n))
     s2.freqs = -s2.freqs
@@ -431,8 +431,8 @@ def test_rigid_motion_invariance():
     """Moving scene (means, orientations, frequency vectors) and camera by the
     same rigid motion leaves the image unchanged: the frequency projection of
     Sec. 3.3.1 transforms covariantly."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     base = O.render_scene(sc, cam, "binned")
     rng = np.random.Generator(np.random.PCG64(8))
     qm = rng.normal(size=4)
@@ -659,8 +659,8 @@ def test_attenuated_primitive_equals_the_exact_z_integral():
     per-component factor), up to the common factor sqrt(2 pi / S_zz) that the
     opacity absorbs: checked by fp64 quadrature of the whole filter bank."""
     from scipy.integrate import quad
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc, attenuation=True)
     R = cam.R.astype(np.float64)
     rng = np.random.Generator(np.random.PCG64(12))
@@ -717,8 +717,8 @@ def test_frequency_map_is_a_blended_channel():
     """The frequency map equals rendering the scene with every primitive's
     colour set to its weighted frequency sum_k w_k |f2d_k| on a black
     background (same blending weights); for one primitive it is alpha * phi."""
-    sc = synth.config1_scene()
-    cam = synth.config1_camera()
+    sc = synth.scene_1k_k2_rgb()
+    cam = synth.camera_128()
     img = O.render_scene(sc, cam, "binned")
     pr = O.project(O.scene_tensors(sc), O.camera_tensors(cam), sc)
     phi = (pr.w * torch.linalg.norm(pr.f2d, dim=-1)).sum(-1).numpy()
