@@ -934,8 +934,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_preprocess_bwd(const void* __rest
 // primitive.  Visible lanes read their own colour row (the colour arrays hold
 // one row per primitive), run the chain rule and leave the gradient row in
 // LDS; the wavefront then writes its 64 rows -- one contiguous run -- with
-// consecutive lanes on consecutive floats (zeros for the primitives no view
-// sees, unless accumulating).
+// consecutive lanes on consecutive float4s, or floats where rows are not whole
+// float4s (zeros for the primitives no view sees, unless accumulating).
 constexpr int kColBlock = 64;
 
 template <int DEG>
