@@ -49,9 +49,10 @@ def test_multiview_backward_sums_views(gpu_lib):
         check_grads_elementwise(k, gpu[k], ref[k], slack[k])
 
 
-def test_accumulate_adds_to_existing_gradients(gpu_lib):
+@pytest.mark.parametrize("deg", [0, 1, 3])  # colour rows of 3, 12 and 48 floats (scalar and float4 writes)
+def test_accumulate_adds_to_existing_gradients(gpu_lib, deg):
     from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
-    sc = synth.uniform_scene(52, 300, 2, sh_degree=0)
+    sc = synth.uniform_scene(52, 301, 2, sh_degree=deg)
     cam = synth.pinhole_camera(40, 40, 60.0, (0.0, 0.0, -3.0), (0, 0, 0))
     ds = DeviceScene.from_host(sc)
     plan = RenderPlan([ds], [cam])
