@@ -161,3 +161,30 @@ def test_arena_frees_a_buffer_before_growing_it(monkeypatch):
     again = ar.take("vals", (500,), torch.int32)  # fits: reused, no allocation
     assert seen == [True] and ar.allocations == 2 and again.data_ptr() == big.data_ptr()
     assert ar.nbytes() == 4096 and ar.nbytes_after({"vals": ((2000,), torch.int32)}) == 8192
+
+
+def test_idle_loop_never_sleeps_into_the_next_arrival():
+    """While idle the loop sleeps only until spin_s before the next arrival
+    (a sleep may overshoot) and polls from there, so a request is picked up
+    at most one poll after it arrives."""
+    jobs, sizes = trace(n=40, qps=50.0)
+    clk = VClock(dt=1e-6)
+    arrivals = sorted(j.arrival_s for j in jobs)
+    spin = 3e-4
+    ends = []
+
+    def sleep(s):
+        assert s > 0
+        clk.sleep(s)
+        ends.append(clk.t)
+
+    ex = FakeExecutor(clk, n_streams=1, fixed_s=1e-4, per_mpix_s=0.0, scene_sizes=sizes)
+    sch = Scheduler(sizes, 1 << 40, max_slots=1, max_batch=1, max_inflight=1)
+    st = serve(jobs, ex, sch, clock=clk, sleep=sleep, spin_s=spin)
+    assert st.requests == len(jobs) and ends
+    for t in ends:  # serve's clock starts near 0: times here are arrival times
+        nxt = min((a for a in arrivals if a >= t - 1e-5), default=None)
+        assert nxt is None or t <= nxt - spin + 1e-5
+    # picked up promptly: a one-at-a-time batch starts within a few polls of
+    # its arrival (the batch itself takes fixed_s)
+    assert max(st.latencies_ms) < 1e3 * (1e-4 + 1e-3)
