@@ -206,12 +206,61 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
   }
 }
 
+// Sum of the per-tile partials, folded into the SSIM backward (which runs
+// after the forward wrote every partial): its first nparts blocks, by linear
+// block id, each reduce a contiguous slice; the last of them to finish
+// (completion counter, zeroed by k_ssim_fwd and again by that block) adds the
+// slice sums in slice order, so the result does not depend on which finishes
+// last.  Slice sums are published and read with agent-scope atomics (the
+// XCDs' L2s are not coherent).
+constexpr int kFinalBlocks = 256;
+constexpr int kFinalSlice = 2048;  // partial pairs per slice (before the cap)
+
+__device__ __forceinline__ void loss_final_part(const float* __restrict__ partial, int nb, float lambda,
+                                                float inv_n, float* __restrict__ part2,
+                                                uint32_t* __restrict__ counter, float* __restrict__ d_loss,
+                                                int part, int nparts, float* s_red, int* s_last) {
+  const int per = (nb + nparts - 1) / nparts;
+  const int b0 = part * per, b1 = min(nb, b0 + per);
+  float l1 = 0.f, ss = 0.f;
+  for (int i = b0 + (int)threadIdx.x; i < b1; i += 256) {
+    l1 += partial[2 * i];
+    ss += partial[2 * i + 1];
+  }
+  l1 = block_sum(l1, s_red);
+  ss = block_sum(ss, s_red);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&part2[2 * part], l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&part2[2 * part + 1], ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = done == (uint32_t)nparts - 1;
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  float a = 0.f, b = 0.f;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    a += __hip_atomic_load(&part2[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b += __hip_atomic_load(&part2[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  a = block_sum(a, s_red);
+  b = block_sum(b, s_red);
+  if (threadIdx.x == 0) {
+    *d_loss = (1.f - lambda) * a * inv_n + lambda * (1.f - b * inv_n);
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // pass 2: filter the three factor maps and combine
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, Window win, float lambda, float inv_n,
-                                                  const float* __restrict__ f3, float* __restrict__ dl_dx) {
+                                                  const float* __restrict__ f3, float* __restrict__ dl_dx,
+                                                  const float* __restrict__ partial, int nb, int nfin,
+                                                  float* __restrict__ part2, uint32_t* __restrict__ counter,
+                                                  float* __restrict__ d_loss) {
   __shared__ __align__(16) float s_f[3][kSY][kSP];
   __shared__ __align__(16) float s_h[3][kSY][kTX];
+  __shared__ float s_red[4];
+  __shared__ int s_last;
   const TileId tid = xcd_tile();
   const int c = tid.c;
   const int ox = tid.x * kTX, oy = tid.y * kTY;
@@ -261,49 +310,9 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
       dl_dx[off] = (1.f - lambda) * inv_n * sgn + m[0][o] + 2.f * xv * m[1][o] + yv * m[2][o];
     }
   }
-}
-
-// Sum of the per-tile partials: up to kFinalBlocks blocks reduce contiguous
-// slices; the last block to finish (completion counter, zeroed by k_ssim_fwd
-// and again by that block) adds the block sums in block order, so the result
-// does not depend on which block finishes last.  Block sums are published
-// and read with agent-scope atomics (the XCDs' L2s are not coherent).
-constexpr int kFinalBlocks = 256;
-constexpr int kFinalSlice = 2048;  // partial pairs per block (before the cap)
-
-__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ partial, int nb, float lambda,
-                                                    float inv_n, float* __restrict__ part2,
-                                                    uint32_t* __restrict__ counter, float* __restrict__ d_loss) {
-  __shared__ float s_red[4];
-  __shared__ int s_last;
-  const int per = (nb + (int)gridDim.x - 1) / (int)gridDim.x;
-  const int b0 = (int)blockIdx.x * per, b1 = min(nb, b0 + per);
-  float l1 = 0.f, ss = 0.f;
-  for (int i = b0 + (int)threadIdx.x; i < b1; i += 256) {
-    l1 += partial[2 * i];
-    ss += partial[2 * i + 1];
-  }
-  l1 = block_sum(l1, s_red);
-  ss = block_sum(ss, s_red);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&part2[2 * blockIdx.x], l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&part2[2 * blockIdx.x + 1], ss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = done == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  float a = 0.f, b = 0.f;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += 256) {
-    a += __hip_atomic_load(&part2[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b += __hip_atomic_load(&part2[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  a = block_sum(a, s_red);
-  b = block_sum(b, s_red);
-  if (threadIdx.x == 0) {
-    *d_loss = (1.f - lambda) * a * inv_n + lambda * (1.f - b * inv_n);
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  const uint32_t lb = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (lb < (uint32_t)nfin)
+    loss_final_part(partial, nb, lambda, inv_n, part2, counter, d_loss, (int)lb, nfin, s_red, &s_last);
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -327,8 +336,8 @@ hipError_t launch_loss(const float* x, const float* y, int c, int h, int w, floa
   int nfin = (nb + kFinalSlice - 1) / kFinalSlice;
   nfin = nfin < 1 ? 1 : (nfin > kFinalBlocks ? kFinalBlocks : nfin);
   hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, partial, counter);
-  hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, dl_dx);
-  hipLaunchKernelGGL(k_loss_final, dim3(nfin), dim3(256), 0, s, partial, nb, lambda, inv_n, part2, counter, d_loss);
+  hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, x, y, h, w, win, lambda, inv_n, f3, dl_dx, partial, nb, nfin,
+                     part2, counter, d_loss);
   return hipGetLastError();
 }
 
