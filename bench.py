@@ -161,7 +161,9 @@ def main():
     scene = synth.scene_1m_k4_sh3()
     cam = synth.camera_1297x840()
     ds = DeviceScene.from_host(scene)
-    plan = RenderPlan([ds], [cam])
+    # the rendered scene stays fixed: its quaternions, frequencies and weights
+    # are also packed row by row (one line per primitive) for the projection
+    plan = RenderPlan([ds.with_rows()], [cam])
     # establish the pair capacity (host sync allowed outside the timed region)
     plan.forward(check_overflow=True)
     torch.cuda.synchronize()
@@ -283,18 +285,25 @@ def main():
         out["calibration_copy_bytes"] = src.numel() * 4
         del src, dst
 
-    # ---- training step (forward + loss + backward)
+    # ---- training step (forward + loss + backward).  Training changes the
+    # attributes every step, so its plan reads the planes only (no rows).
     if not args.no_train:
         target = torch.from_numpy(synth.random_target(1003, (3, cam.height, cam.width))).to(dev)
         lossb = LossBuffers(3, cam.height, cam.width)
         grads = {n: torch.zeros_like(getattr(ds, n)) for n in
                  ("means", "scales", "quats", "opacities", "sh", "freqs", "weights")}
-        img = plan.view_image(0)
+        tplan = RenderPlan([ds], [cam], pair_capacity=plan.capacity)
+        img = tplan.view_image(0)
+
+        def tfwd_step():
+            tplan.preprocess()
+            tplan.bin_sort()
+            tplan.render_fwd()
 
         def train_step():
-            fwd_step(False)
+            tfwd_step()
             lossb(img, target)
-            plan.backward(lossb.grad.view(-1), [grads], accumulate=False)
+            tplan.backward(lossb.grad.view(-1), [grads], accumulate=False)
 
         for _ in range(max(2, args.warmup // 2)):
             train_step()
@@ -313,13 +322,13 @@ def main():
         btimer = StageTimer(torch, ["loss", "render_bwd", "project_bwd"])
 
         def train_step_staged():
-            fwd_step(False)
+            tfwd_step()
             a, b = btimer.pair("loss"); a.record(stream)
             lossb(img, target)
             b.record(stream); a, b = btimer.pair("render_bwd"); a.record(stream)
-            plan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_BLEND)
+            tplan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_BLEND)
             b.record(stream); a, b = btimer.pair("project_bwd"); a.record(stream)
-            plan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_PROJECT)
+            tplan.backward(lossb.grad.view(-1), [grads], accumulate=False, stages=_lib.BWD_PROJECT)
             b.record(stream)
 
         for _ in range(ts):
@@ -468,7 +477,8 @@ def serving_run(args, torch, synth):
     from paper_2508_05343_amd.rasterize import DeviceScene
     from paper_2508_05343_amd.serving import GpuExecutor, Job, Scheduler, serve
     scenes = synth.serving_scenes()
-    dss = [DeviceScene.from_host(s) for s in scenes]
+    # resident scenes stay fixed: each also carries its packed rows
+    dss = [DeviceScene.from_host(s).with_rows() for s in scenes]
     reqs = synth.serving_requests(scenes, n_requests=args.serve_requests, qps=args.serve_qps)
     sizes = [s.n for s in scenes]
     budget = 6 << 30
@@ -487,7 +497,8 @@ def serving_run(args, torch, synth):
         sm = st.summary()
         res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
     res["workload"] = (f"8 resident scenes ({sum(sizes)} primitives), {len(reqs)} Poisson requests at "
-                       f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB budget for job buffers")
+                       f"{args.serve_qps:g} QPS, resolutions 256^2..1920x1080, 6 GiB budget for job buffers "
+                       "(scenes resident with packed rows)")
     sweep = []
     for q in [float(x) for x in args.serve_sweep.split(",") if x]:
         rq = synth.serving_requests(scenes, n_requests=600, qps=q, seed=1005 + int(q))

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GABSPLAT_ABI_VERSION 6
+#define GABSPLAT_ABI_VERSION 7
 #define GABSPLAT_TILE 16
 #define GABSPLAT_MAX_K 8
 #define GABSPLAT_MAX_SH_DEGREE 3
@@ -107,8 +107,19 @@ typedef enum {
  *   filter3d  [n] variance of the 3D filter (world units squared, >= 0), e.g.
  *             from gabsplat_mip_filter3d; read only with GABSPLAT_FLAG_MIP_3D
  *             (may be NULL otherwise).
+ *   rows      [n][gabsplat_row_floats(k)] or NULL: a row-major copy of each
+ *             primitive's quaternion, frequencies and weights, as
+ *             gabsplat_pack_rows writes it from the planes above (16-byte
+ *             aligned).  When given, gabsplat_preprocess reads those three
+ *             attributes of the primitives it projects from their rows: one
+ *             aligned row per primitive instead of 4 + 4k planes, whose
+ *             lines hold mostly culled neighbours.  The planes must still be
+ *             given (the backward and density control read them), and the
+ *             rows must be packed again after any change to them: the rows
+ *             are for scenes that stay fixed across frames (serving).
  * Limits: 0 <= k <= GABSPLAT_MAX_K, sh_degree in [0, 3] when sh != NULL,
- * 0 <= n < 2^31.  All scenes of one call share k, the colour mode and flags. */
+ * 0 <= n < 2^31.  All scenes of one call share k, the colour mode, the flags
+ * and whether rows are given. */
 typedef struct {
   int64_t n;
   int32_t k;
@@ -124,6 +135,7 @@ typedef struct {
   const float* freqs;
   const float* weights;
   const float* filter3d;
+  const float* rows;
 } gabsplat_scene;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point x
@@ -214,6 +226,11 @@ int32_t gabsplat_abi_version(void);
 const char* gabsplat_status_string(gabsplat_status s);
 /* Floats per render record for k components: round_up(10 + 3k, 4). */
 int32_t gabsplat_record_floats(int32_t k);
+/* Floats per row of gabsplat_scene.rows: round_up(4 + 4k, 32) (rows of whole
+ * 128-byte lines): quaternion (w, x, y, z), then the 3k frequencies
+ * (component-major: f_j at 4 + 3j), then the k weights (w_j at 4 + 3k + j),
+ * then zeros; -1 if k is invalid. */
+int32_t gabsplat_row_floats(int32_t k);
 /* Floats per item of the image-plane gradient: round_up(10 + 3k, 4). */
 int32_t gabsplat_grad2d_floats(int32_t k);
 /* Row stride of grad2d for gabsplat_scene_grads.flags: round_up(10 + 3k, 4),
@@ -246,6 +263,14 @@ gabsplat_status gabsplat_check_device(void);
 gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_scenes,
                                     const int32_t* scene_of_view, const gabsplat_camera* cams,
                                     int32_t num_views, const gabsplat_geom* geom, void* stream);
+
+/* Writes scene->rows' layout (gabsplat_row_floats(k) floats per primitive)
+ * into `rows` (device, n rows, 16-byte aligned; 128-byte alignment puts every
+ * row on its own cache line) from the scene's quats, freqs and weights
+ * planes, the attributes K1 reads for every primitive it projects (Sec. 3.1,
+ * 3.3.2).  The scene's own `rows` field is ignored.  Enqueued on `stream`.
+ * INVALID_ARGUMENT for an invalid scene or a NULL or misaligned `rows`. */
+gabsplat_status gabsplat_pack_rows(const gabsplat_scene* scene, float* rows, void* stream);
 
 /* K2-K5, binning: compact the visible items, stably sort them by fp32 depth
  * bits, emit one (global tile, item) pair per overlapped tile, stably sort the

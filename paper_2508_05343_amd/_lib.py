@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgabsplat.so")
 # the argument layouts this binding marshals (GABSPLAT_ABI_VERSION)
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 EXPORTS = (
     "gabsplat_abi_version", "gabsplat_status_string", "gabsplat_record_floats", "gabsplat_grad2d_floats",
@@ -26,6 +26,7 @@ EXPORTS = (
     "gabsplat_densify_stats", "gabsplat_densify_workspace_size", "gabsplat_densify",
     "gabsplat_reset_frequency_weights", "gabsplat_grad2d_stride", "gabsplat_mip_filter3d_workspace_size",
     "gabsplat_mip_filter3d", "gabsplat_loss_l1_dssim_noalloc", "gabsplat_render_bwd_stages",
+    "gabsplat_row_floats", "gabsplat_pack_rows",
 )
 
 OK, INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, CAPACITY_EXCEEDED, HIP_ERROR, UNSUPPORTED_DEVICE, SCRATCH_LIMIT = range(7)
@@ -49,7 +50,7 @@ class Scene(ctypes.Structure):
     _fields_ = [("n", c_int64), ("k", c_int32), ("sh_degree", c_int32), ("flags", c_int32), ("pad", c_int32),
                 ("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
                 ("sh", c_void_p), ("colors", c_void_p), ("freqs", c_void_p), ("weights", c_void_p),
-                ("filter3d", c_void_p)]
+                ("filter3d", c_void_p), ("rows", c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -101,6 +102,10 @@ def lib() -> ctypes.CDLL:
     L.gabsplat_status_string.argtypes = [c_int32]
     L.gabsplat_record_floats.restype = c_int32
     L.gabsplat_record_floats.argtypes = [c_int32]
+    L.gabsplat_row_floats.restype = c_int32
+    L.gabsplat_row_floats.argtypes = [c_int32]
+    L.gabsplat_pack_rows.restype = c_int32
+    L.gabsplat_pack_rows.argtypes = [POINTER(Scene), c_void_p, c_void_p]
     L.gabsplat_grad2d_floats.restype = c_int32
     L.gabsplat_grad2d_floats.argtypes = [c_int32]
     L.gabsplat_grad2d_stride.restype = c_int32
@@ -190,6 +195,10 @@ def gabsplat_record_floats(k: int) -> int:
     return int(lib().gabsplat_record_floats(k))
 
 
+def gabsplat_row_floats(k: int) -> int:
+    return int(lib().gabsplat_row_floats(k))
+
+
 def gabsplat_grad2d_floats(k: int) -> int:
     return int(lib().gabsplat_grad2d_floats(k))
 
@@ -222,6 +231,10 @@ def gabsplat_preprocess(scenes: Sequence[Scene], scene_of_view: Optional[Sequenc
     ca = _arr(Camera, cams)
     _check(lib().gabsplat_preprocess(sa, len(scenes), sv, ca, len(cams), ctypes.byref(geom),
                                      stream_handle(stream)), "gabsplat_preprocess")
+
+
+def gabsplat_pack_rows(scene: Scene, rows, stream=None):
+    _check(lib().gabsplat_pack_rows(ctypes.byref(scene), ptr(rows), stream_handle(stream)), "gabsplat_pack_rows")
 
 
 def gabsplat_bin_sort(geom: Geom, cams: Sequence[Camera], items: int, ws, keys, vals, pair_capacity: int,

@@ -94,6 +94,7 @@ bool valid_scene(const gabsplat_scene& s) {
   if (s.sh && (s.sh_degree < 0 || s.sh_degree > GABSPLAT_MAX_SH_DEGREE)) return false;
   if (s.k > 0 && (!s.freqs || !s.weights)) return false;
   if ((s.flags & GABSPLAT_FLAG_MIP_3D) && !s.filter3d) return false;
+  if (s.rows && (reinterpret_cast<uintptr_t>(s.rows) & 15) != 0) return false;
   return true;
 }
 
@@ -118,12 +119,14 @@ gabsplat_status build_table(const gabsplat_scene* scenes, int32_t num_scenes, co
     const gabsplat_scene& s = scenes[i];
     if (!valid_scene(s)) return GABSPLAT_ERR_INVALID_ARGUMENT;
     if (s.k != k || (s.sh != nullptr) != use_sh || (use_sh && s.sh_degree != deg) || s.flags != flags ||
+        (s.rows != nullptr) != (scenes[0].rows != nullptr) ||
         (s.flags & ~(GABSPLAT_FLAG_ATTENUATION | GABSPLAT_FLAG_MIP_2D | GABSPLAT_FLAG_MIP_3D)) != 0)
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     SceneEntry& e = tb.scenes[i];
     e.means = s.means; e.scales = s.scales; e.quats = s.quats; e.opac = s.opacities;
     e.sh = s.sh; e.colors = s.colors; e.freqs = s.freqs; e.weights = s.weights;
     e.filter3d = (s.flags & GABSPLAT_FLAG_MIP_3D) ? s.filter3d : nullptr;
+    e.rows = s.rows;
     e.n = s.n; e.k = s.k; e.sh_degree = deg; e.flags = s.flags; e.pad = 0;
   }
   tb.views.resize(num_views);
@@ -190,6 +193,7 @@ const char* gabsplat_status_string(gabsplat_status s) {
 }
 
 int32_t gabsplat_record_floats(int32_t k) { return (k < 0 || k > GABSPLAT_MAX_K) ? -1 : record_floats(k); }
+int32_t gabsplat_row_floats(int32_t k) { return (k < 0 || k > GABSPLAT_MAX_K) ? -1 : row_stride(k); }
 int32_t gabsplat_grad2d_floats(int32_t k) { return (k < 0 || k > GABSPLAT_MAX_K) ? -1 : grad2d_floats(k); }
 int32_t gabsplat_grad2d_stride(int32_t k, int32_t grad_flags) {
   if (k < 0 || k > GABSPLAT_MAX_K || (grad_flags & ~GABSPLAT_GRAD_ABS_MEAN2D) != 0) return -1;
@@ -227,10 +231,24 @@ gabsplat_status gabsplat_preprocess(const gabsplat_scene* scenes, int32_t num_sc
       return GABSPLAT_ERR_INVALID_ARGUMENT;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HostTable h = tb.host();
+    GS_REQUIRE_DEVICE();
     hipError_t e = upload_table(geom->views, h, s);
     if (e != hipSuccess) return GABSPLAT_ERR_HIP;
-    GS_REQUIRE_DEVICE();
     return hip_status(launch_preprocess(geom->views, h, *geom, s));
+  } catch (...) {
+    return GABSPLAT_ERR_HIP;
+  }
+}
+
+gabsplat_status gabsplat_pack_rows(const gabsplat_scene* scene, float* rows, void* stream) {
+  try {
+    if (!scene || !rows || (reinterpret_cast<uintptr_t>(rows) & 15) != 0) return GABSPLAT_ERR_INVALID_ARGUMENT;
+    gabsplat_scene sc = *scene;
+    sc.rows = nullptr;  // the scene's own rows are not read
+    if (!valid_scene(sc)) return GABSPLAT_ERR_INVALID_ARGUMENT;
+    if (sc.n == 0) return GABSPLAT_OK;
+    GS_REQUIRE_DEVICE();
+    return hip_status(launch_pack_rows(sc, rows, static_cast<hipStream_t>(stream)));
   } catch (...) {
     return GABSPLAT_ERR_HIP;
   }

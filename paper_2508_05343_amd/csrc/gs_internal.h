@@ -38,6 +38,7 @@ struct SceneEntry {
   const float* freqs;
   const float* weights;
   const float* filter3d;  // [n] 3D filter variance (GABSPLAT_FLAG_MIP_3D)
+  const float* rows;      // [n][row_floats(k)] quats, freqs, weights by primitive, or null
   int64_t n;
   int32_t k;
   int32_t sh_degree;  // -1 for precomputed colours
@@ -87,6 +88,8 @@ __host__ __device__ inline const SceneEntry* table_scenes(const void* t, int num
 __host__ __device__ constexpr int record_stride(int k) { return (12 + 3 * k + 3) & ~3; }
 __host__ __device__ constexpr int record_mean_lo(int k) { return 10 + 3 * k; }
 inline int record_floats(int k) { return record_stride(k); }
+// floats per row of gabsplat_scene.rows: quaternion, 3k frequencies, k weights, zeros to whole 128-byte lines
+__host__ __device__ constexpr int row_stride(int k) { return (4 + 4 * k + 31) & ~31; }
 __host__ __device__ inline int grad2d_floats(int k) { return (10 + 3 * k + 3) & ~3; }
 __host__ __device__ inline int grad2d_stride(int k, int grad_flags) {
   return (grad_flags & GABSPLAT_GRAD_ABS_MEAN2D) ? (12 + 3 * k + 3) & ~3 : grad2d_floats(k);
@@ -116,6 +119,7 @@ hipError_t upload_table(void* d_table, const HostTable& h, hipStream_t s);
 // kernels whose arguments carry the data (no copy engine, no host sync).
 hipError_t upload_words(void* d_dst, const void* h_src, size_t bytes, hipStream_t s);
 
+hipError_t launch_pack_rows(const gabsplat_scene& sc, float* rows, hipStream_t s);
 hipError_t launch_preprocess(const void* d_table, const HostTable& h, const gabsplat_geom& g,
                              hipStream_t s);
 

@@ -337,7 +337,37 @@ __device__ __forceinline__ void load_colour_row(P base, int64_t i, int nv, float
   }
 }
 
-template <int K>
+// The quaternion of primitive i of S: from its row (ROWS, one 16-byte load)
+// or its four planes.
+template <bool ROWS>
+__device__ __forceinline__ void load_quat(const SceneEntry& S, int64_t n, int64_t i, int rs, float (&q)[4]) {
+  if constexpr (ROWS) {
+    const gfloat_ptr r = gptr(S.rows) + i * rs;  // 16-byte aligned: adjacent loads merge
+    q[0] = r[0]; q[1] = r[1]; q[2] = r[2]; q[3] = r[3];
+  } else {
+    q[0] = gptr(S.quats)[i]; q[1] = gptr(S.quats)[n + i]; q[2] = gptr(S.quats)[2 * n + i];
+    q[3] = gptr(S.quats)[3 * n + i];
+  }
+}
+
+// The frequencies (3K, component-major) then the weights (K) of primitive i
+// of S: from its row (ROWS, K 16-byte loads after the quaternion) or the planes.
+template <int K, bool ROWS>
+__device__ __forceinline__ void load_freq_weights(const SceneEntry& S, int64_t n, int64_t i, int rs,
+                                                  float (&fw)[K > 0 ? 4 * K : 1]) {
+  if constexpr (ROWS) {
+    const gfloat_ptr r = gptr(S.rows) + i * rs + 4;
+#pragma unroll
+    for (int j = 0; j < 4 * K; ++j) fw[j] = r[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) fw[j] = gptr(S.freqs)[(int64_t)j * n + i];
+#pragma unroll
+    for (int j = 0; j < K; ++j) fw[3 * K + j] = gptr(S.weights)[(int64_t)j * n + i];
+  }
+}
+
+template <int K, bool ROWS>
 __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ table,
                                                     float* __restrict__ rec,
                                                     float* __restrict__ depth_out,
@@ -425,7 +455,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
     const float mx = gptr(S.means)[i], my = gptr(S.means)[n + i], mz = gptr(S.means)[2 * n + i];
     const float tz = depth_out[item];
     const float o = gptr(S.opac)[i];
-    const float q[4] = {gptr(S.quats)[i], gptr(S.quats)[n + i], gptr(S.quats)[2 * n + i], gptr(S.quats)[3 * n + i]};
+    float q[4];
+    load_quat<ROWS>(S, n, i, row_stride(K), q);
     float sc[3] = {gptr(S.scales)[i], gptr(S.scales)[n + i], gptr(S.scales)[2 * n + i]};
     // filtered envelope: scales sqrt(s^2 + v), opacity times prod s / sqrt(s^2 + v)
     float oe = o;
@@ -482,11 +513,12 @@ __global__ __launch_bounds__(256) void k_preprocess(const void* __restrict__ tab
       double vx_d[3], vy_d[3];
       precise_frequency_basis(V, mx, my, mz, q, sc, vx_d, vy_d);
       asm volatile("" ::: "memory");
+      float fw[K > 0 ? 4 * K : 1];
+      load_freq_weights<K, ROWS>(S, n, i, row_stride(K), fw);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const V3 f = v3(gptr(S.freqs)[(int64_t)(3 * k) * n + i], gptr(S.freqs)[(int64_t)(3 * k + 1) * n + i],
-                        gptr(S.freqs)[(int64_t)(3 * k + 2) * n + i]);
-        const float wk = gptr(S.weights)[(int64_t)k * n + i];
+        const V3 f = v3(fw[3 * k], fw[3 * k + 1], fw[3 * k + 2]);
+        const float wk = fw[3 * K + k];
         r[10 + 3 * k] = (float)(vx_d[0] * f.x + vx_d[1] * f.y + vx_d[2] * f.z);
         r[11 + 3 * k] = (float)(vy_d[0] * f.x + vy_d[1] * f.y + vy_d[2] * f.z);
         r[12 + 3 * k] = atten ? wk * __expf(-kTwoPiSq * ray_variance(g, u, f)) : wk;
@@ -1036,7 +1068,30 @@ static hipError_t pre_k(const void* d_table, const HostTable& h, const gabsplat_
   }
   if (max_n == 0) return hipSuccess;
   dim3 grid((unsigned)((max_n + kPreBlock - 1) / kPreBlock), (unsigned)h.hdr.num_views);
-  hipLaunchKernelGGL(k_preprocess<K>, grid, dim3(256), 0, s, d_table, g.rec, g.depth, g.rect, g.tiles);
+  if (h.scenes[0].rows != nullptr)  // every scene of the call has rows or none has
+    hipLaunchKernelGGL((k_preprocess<K, true>), grid, dim3(256), 0, s, d_table, g.rec, g.depth, g.rect, g.tiles);
+  else
+    hipLaunchKernelGGL((k_preprocess<K, false>), grid, dim3(256), 0, s, d_table, g.rec, g.depth, g.rect, g.tiles);
+  return hipGetLastError();
+}
+
+// gabsplat_pack_rows: thread i writes primitive i's row (row_stride(k) floats).
+__global__ __launch_bounds__(256) void k_pack_rows(const float* __restrict__ quats, const float* __restrict__ freqs,
+                                                   const float* __restrict__ weights, int64_t n, int k, int rs,
+                                                   float* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float* r = rows + i * rs;
+  for (int a = 0; a < 4; ++a) r[a] = quats[(int64_t)a * n + i];
+  for (int a = 0; a < 3 * k; ++a) r[4 + a] = freqs[(int64_t)a * n + i];
+  for (int a = 0; a < k; ++a) r[4 + 3 * k + a] = weights[(int64_t)a * n + i];
+  for (int a = 4 + 4 * k; a < rs; ++a) r[a] = 0.f;
+}
+
+hipError_t launch_pack_rows(const gabsplat_scene& sc, float* rows, hipStream_t s) {
+  const int64_t blocks = (sc.n + 255) / 256;  // n < 2^31: fewer than 2^23 blocks
+  hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)blocks), dim3(256), 0, s, sc.quats, sc.freqs, sc.weights, sc.n,
+                     (int)sc.k, row_stride(sc.k), rows);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ transposes are needed.
 """
 from __future__ import annotations
 
+import copy
 import math
 from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence
@@ -93,6 +94,20 @@ class DeviceScene:
         self.means, self.scales, self.quats, self.opacities = means, scales, quats, opacities
         self.freqs, self.weights, self.sh, self.colors = freqs, weights, sh, colors
         self.filter3d = filter3d
+        self.rows = None  # row-major quats/freqs/weights (with_rows), read by the projection when set
+
+    def with_rows(self, stream=None) -> "DeviceScene":
+        """The same scene (the same tensors) plus a row-major copy of every
+        primitive's quaternion, frequencies and weights (gabsplat_pack_rows,
+        one 128-byte line per primitive for K <= 7), which the projection
+        reads instead of their planes: the planes' lines hold mostly culled
+        neighbours of each visible primitive.  For scenes that stay fixed
+        (serving): the copy is not updated when the planes change."""
+        ds = copy.copy(self)
+        rs = _lib.gabsplat_row_floats(self.k)
+        ds.rows = torch.empty((max(self.n, 1), rs), dtype=torch.float32, device=self.means.device)
+        _lib.gabsplat_pack_rows(self.cstruct(), ds.rows, stream)
+        return ds
 
     @staticmethod
     def from_host(scene, device="cuda", attenuation=False, mip2d=False) -> "DeviceScene":
@@ -145,10 +160,12 @@ class DeviceScene:
         s.sh = _lib.ptr(self.sh) if self.sh is not None else None
         s.colors = _lib.ptr(self.colors) if self.colors is not None else None
         s.freqs, s.weights = _lib.ptr(self.freqs), _lib.ptr(self.weights)
+        s.rows = _lib.ptr(self.rows) if self.rows is not None else None
         return s
 
     def nbytes(self) -> int:
-        return sum(t.numel() * 4 for t in self.tensors() if t is not None)
+        rows = self.rows.numel() * 4 if self.rows is not None else 0
+        return sum(t.numel() * 4 for t in self.tensors() if t is not None) + rows
 
 
 def camera_struct(cam) -> _lib.Camera:

@@ -35,10 +35,13 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_helpers(L):
-    assert L.gabsplat_abi_version() == 6
+    assert L.gabsplat_abi_version() == 7
     assert L.gabsplat_record_floats(0) == 12 and L.gabsplat_record_floats(2) == 20
     assert L.gabsplat_record_floats(4) == 24 and L.gabsplat_record_floats(8) == 36
     assert L.gabsplat_record_floats(9) == -1
+    # rows of whole 128-byte lines: quaternion, 3k frequencies, k weights
+    assert L.gabsplat_row_floats(0) == 32 and L.gabsplat_row_floats(4) == 32 and L.gabsplat_row_floats(7) == 32
+    assert L.gabsplat_row_floats(8) == 64 and L.gabsplat_row_floats(9) == -1 and L.gabsplat_row_floats(-1) == -1
     assert L.gabsplat_grad2d_floats(4) == 24 and L.gabsplat_grad2d_floats(2) == 16
     # the AbsGS columns follow the record's fields
     assert L.gabsplat_grad2d_stride(4, 0) == 24 and L.gabsplat_grad2d_stride(4, L.GRAD_ABS_MEAN2D) == 24
@@ -105,6 +108,28 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert st == L.INVALID_ARGUMENT
     st = lib.gabsplat_mip_filter3d(None, 10, ctypes.byref(cam), 1, 0.2, 0.15, None, None, 0, None)
     assert st == L.INVALID_ARGUMENT
+    # packed rows: NULL or misaligned destination, invalid scene; a
+    # misaligned rows pointer in a scene; scenes of one call that disagree on
+    # having rows (all checked before any device work)
+    sc.flags = 0
+    ok = L.Scene()
+    ok.n, ok.k, ok.sh_degree = 10, 2, 0
+    ok.means = ok.scales = ok.quats = ok.opacities = ok.sh = ok.freqs = ok.weights = fake
+    assert lib.gabsplat_pack_rows(ctypes.byref(ok), None, None) == L.INVALID_ARGUMENT
+    assert lib.gabsplat_pack_rows(ctypes.byref(ok), fake + 4, None) == L.INVALID_ARGUMENT
+    assert lib.gabsplat_pack_rows(ctypes.byref(sc), fake, None) == L.INVALID_ARGUMENT
+    assert lib.gabsplat_pack_rows(None, fake, None) == L.INVALID_ARGUMENT
+    g.views = fake
+    ok.rows = fake + 8
+    st = lib.gabsplat_preprocess(ctypes.byref(ok), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    two = (L.Scene * 2)(ok, ok)
+    two[0].rows, two[1].rows = fake, None
+    cams2 = (L.Camera * 2)(cam, cam)
+    sv = (ctypes.c_int32 * 2)(0, 1)
+    st = lib.gabsplat_preprocess(two, 2, sv, cams2, 2, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT
+    g.views = None
     # AbsGS statistic requested without its output
     g.views = g.tiles = 1
     st = lib.gabsplat_densify_stats(ctypes.byref(g), ctypes.byref(cam), 1, 10, 1, L.GRAD_ABS_MEAN2D, 1, None, 1, None)
@@ -185,3 +210,19 @@ def test_no_launch_without_a_gfx950(L):
     wsb = lib.gabsplat_loss_workspace_size(3, 4, 4)
     assert lib.gabsplat_loss_l1_dssim(fake, fake, 3, 4, 4, 0.2, fake, fake, fake, wsb, None) == st0
     assert lib.gabsplat_loss_l1_dssim_noalloc(fake, fake, 3, 4, 4, 0.2, fake, fake, None) == st0
+    # a scene whose rows pass the checks reaches the device check too, where
+    # the same scene with misaligned rows was refused as an invalid argument
+    sc = L.Scene()
+    sc.n, sc.k, sc.sh_degree = 10, 2, 0
+    sc.means = sc.scales = sc.quats = sc.opacities = sc.sh = sc.freqs = sc.weights = fake
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy = 16, 16, 10.0, 10.0
+    g = L.Geom()
+    g.k, g.views = 2, fake
+    g.rec = g.depth = g.rect = g.tiles = fake
+    sc.rows = fake
+    assert lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None) == st0
+    assert lib.gabsplat_pack_rows(ctypes.byref(sc), fake, None) == st0
+    sc.rows = fake + 8
+    st = lib.gabsplat_preprocess(ctypes.byref(sc), 1, None, ctypes.byref(cam), 1, ctypes.byref(g), None)
+    assert st == L.INVALID_ARGUMENT

@@ -359,3 +359,38 @@ def test_frequency_map_and_eval_counts(gpu_lib):
     lens = (ranges[:, 1] - ranges[:, 0])[tile].reshape(-1)
     assert (c[:, 0] <= lens).all() and (c[:, 1] <= c[:, 0]).all()
     assert (c[:, 0] >= plan.view_n_contrib(0).cpu().numpy().reshape(-1)).all()
+
+
+@pytest.mark.parametrize("k,deg", [(4, 3), (2, 1), (8, 0)])
+def test_packed_rows_render_exactly_like_the_planes(gpu_lib, k, deg):
+    """gabsplat_pack_rows writes each primitive's quaternion, frequencies and
+    weights as one row (zeros after), and K1 reading those rows gives the
+    records, depths, rects, tile counts and images of the planar input, bit
+    for bit -- for one scene and for a batch of two scenes with rows."""
+    from paper_2508_05343_amd.rasterize import DeviceScene, RenderPlan
+    sc = synth.uniform_scene(90 + k, 3000, k, sh_degree=deg, log_scale_mu=-3.0)
+    sc2 = synth.uniform_scene(190 + k, 2000, k, sh_degree=deg, log_scale_mu=-2.8)
+    cam = synth.pinhole_camera(160, 120, 60.0, (0.1, 0.0, -3.0), (0, 0, 0))
+    cam2 = synth.pinhole_camera(96, 80, 55.0, (-0.8, 0.3, -2.6), (0, 0, 0), bg=(0.3, 0.3, 0.3))
+    ds, ds2 = DeviceScene.from_host(sc), DeviceScene.from_host(sc2)
+    dr, dr2 = ds.with_rows(), ds2.with_rows()
+    torch.cuda.synchronize()
+    rs = gpu_lib.gabsplat_row_floats(k)
+    rows = dr.rows.cpu().numpy()
+    assert rows.shape == (sc.n, rs) and dr.rows.data_ptr() % 128 == 0
+    assert np.array_equal(rows[:, 0:4], ds.quats.cpu().numpy().T)
+    assert np.array_equal(rows[:, 4:4 + 3 * k], ds.freqs.cpu().numpy().T)
+    assert np.array_equal(rows[:, 4 + 3 * k:4 + 4 * k], ds.weights.cpu().numpy().T)
+    assert not rows[:, 4 + 4 * k:].any()
+    for planar, packed, cams, sov in (([ds], [dr], [cam], None), ([ds, ds2], [dr, dr2], [cam, cam2, cam], [0, 1, 1])):
+        a = RenderPlan(planar, cams, sov)
+        b = RenderPlan(packed, cams, sov)
+        a.forward()
+        b.forward()
+        torch.cuda.synchronize()
+        for name in ("rec", "depth", "rect", "tiles_touched", "image", "final_T", "n_contrib"):
+            x, y = getattr(a, name).cpu().numpy(), getattr(b, name).cpu().numpy()
+            if name in ("rec", "depth", "rect"):  # rows of culled items are not written
+                vis = a.tiles_touched.cpu().numpy()[:a.items] > 0
+                x, y = x[:a.items][vis], y[:a.items][vis]
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (name, len(cams))
