@@ -1075,21 +1075,36 @@ static hipError_t pre_k(const void* d_table, const HostTable& h, const gabsplat_
   return hipGetLastError();
 }
 
-// gabsplat_pack_rows: thread i writes primitive i's row (row_stride(k) floats).
+// gabsplat_pack_rows: a block transposes 64 primitives through LDS -- loads
+// of consecutive primitives of one plane, then the 64 rows written as one
+// contiguous run (zeros after the 4 + 4k used floats of each row).
+constexpr int kPackRows = 64, kPackPitch = 65;  // row_stride(k) <= 64 columns; odd pitch
 __global__ __launch_bounds__(256) void k_pack_rows(const float* __restrict__ quats, const float* __restrict__ freqs,
                                                    const float* __restrict__ weights, int64_t n, int k, int rs,
                                                    float* __restrict__ rows) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  float* r = rows + i * rs;
-  for (int a = 0; a < 4; ++a) r[a] = quats[(int64_t)a * n + i];
-  for (int a = 0; a < 3 * k; ++a) r[4 + a] = freqs[(int64_t)a * n + i];
-  for (int a = 0; a < k; ++a) r[4 + 3 * k + a] = weights[(int64_t)a * n + i];
-  for (int a = 4 + 4 * k; a < rs; ++a) r[a] = 0.f;
+  __shared__ float s[kPackRows * kPackPitch];
+  const int64_t i0 = (int64_t)blockIdx.x * kPackRows;
+  const int nrow = (int)min((int64_t)kPackRows, n - i0);
+  const int used = 4 + 4 * k;
+  for (int e = threadIdx.x; e < used * kPackRows; e += 256) {
+    const int c = e / kPackRows, r = e - c * kPackRows;
+    if (r < nrow) {
+      const float* src = c < 4 ? quats + (int64_t)c * n
+                               : (c < 4 + 3 * k ? freqs + (int64_t)(c - 4) * n : weights + (int64_t)(c - 4 - 3 * k) * n);
+      s[r * kPackPitch + c] = src[i0 + r];
+    }
+  }
+  __syncthreads();
+  float* dst = rows + i0 * rs;
+  for (int e = threadIdx.x; e < nrow * rs; e += 256) {
+    const int r = e / rs, c = e - r * rs;
+    dst[e] = c < used ? s[r * kPackPitch + c] : 0.f;
+  }
 }
 
 hipError_t launch_pack_rows(const gabsplat_scene& sc, float* rows, hipStream_t s) {
-  const int64_t blocks = (sc.n + 255) / 256;  // n < 2^31: fewer than 2^23 blocks
+  static_assert(row_stride(GABSPLAT_MAX_K) <= kPackPitch - 1, "a row fits the LDS pitch");
+  const int64_t blocks = (sc.n + kPackRows - 1) / kPackRows;  // n < 2^31: fewer than 2^25 blocks
   hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)blocks), dim3(256), 0, s, sc.quats, sc.freqs, sc.weights, sc.n,
                      (int)sc.k, row_stride(sc.k), rows);
   return hipGetLastError();
