@@ -44,14 +44,14 @@ VALU_PEAK_TFLOPS = 78.6
 # Valid only for the kernel source they were taken on (hash of the kernel's
 # source text); otherwise the bench reports them as null.
 RENDER_FWD_COUNTERS = {
-    "source_sha256": "4a95decdab2a09777db791a6d0d789c745b0de8e86b445f4bbd7d3b70931bad4",
-    "fetch_kib": 84139.8, "write_kib": 34453.5, "fetch_scale": 2.0, "write_scale": 1.0,
-    "valu_busy": 0.9219, "valu_util": 0.9841, "lds_bank_conflict": 0.0043,
+    "source_sha256": "506d5085f64925d126f209cf5bc6d837a0d12e6e52d30ba98923271a612202bc",
+    "fetch_kib": 84231.7, "write_kib": 34440.4, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 0.9328, "valu_util": 0.9841, "lds_bank_conflict": 0.0043,
 }
 RENDER_BWD_COUNTERS = {
-    "source_sha256": "13e95d96bb60104b2ef59e9757cf8fe751159972945532a92e030271fd151b49",
-    "fetch_kib": 85042.6, "write_kib": 113938.6, "fetch_scale": 2.0, "write_scale": 1.0,
-    "valu_busy": 1.041, "valu_util": 0.9779, "lds_bank_conflict": 0.0,
+    "source_sha256": "725661bc35587c921f8df4c349ab0ba788771e215df09238b93172814cd618da",
+    "fetch_kib": 85130.4, "write_kib": 113938.6, "fetch_scale": 2.0, "write_scale": 1.0,
+    "valu_busy": 1.0492, "valu_util": 0.9779, "lds_bank_conflict": 0.0,
 }
 
 _SPLIT = "// ------------------------------------------------- wave reduce-scatter-add"
